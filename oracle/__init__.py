@@ -1,0 +1,280 @@
+"""CPU oracle for the LOD Gaussian-splatting renderer -- TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  The product library never loads it, and it never loads
+the product library: the two share only the seeded input generators in
+``synth``.
+
+The arithmetic lives in ``lodge_oracle.c`` (plain C, built twice: FP32 and
+FP64, ``-O2 -ffp-contract=off``).  This module only marshals numpy arrays
+into it and builds it with gcc on first use.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "lodge_oracle.c")
+BUILD = os.path.join(HERE, "_build")
+
+ALL, LOD_CAMERA, CHUNKED = 0, 1, 2
+TILE = 16
+
+
+def build(force: bool = False) -> None:
+    """Compile liblodge_oracle_{f32,f64}.so with gcc (no FMA contraction, no fast-math)."""
+    os.makedirs(BUILD, exist_ok=True)
+    for tag, real in (("f32", "float"), ("f64", "double")):
+        out = os.path.join(BUILD, f"liblodge_oracle_{tag}.so")
+        if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(SRC):
+            continue
+        tmp = out + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-Wall",
+                               "-fPIC", "-shared", f"-DREAL={real}", SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, out)
+
+
+_LIBS = {}
+
+
+def _lib(tag: str):
+    if tag not in _LIBS:
+        build()
+        lib = C.CDLL(os.path.join(BUILD, f"liblodge_oracle_{tag}.so"))
+        _LIBS[tag] = lib
+    return _LIBS[tag]
+
+
+def _structs(real):
+    class Level(C.Structure):
+        _fields_ = [("n", C.c_int64), ("mean", C.c_void_p), ("scale", C.c_void_p), ("quat", C.c_void_p),
+                    ("opacity", C.c_void_p), ("sh", C.c_void_p), ("sh_degree", C.c_int32),
+                    ("filter3d_var", real)]
+
+    class Camera(C.Structure):
+        _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", real), ("fy", real), ("cx", real),
+                    ("cy", real), ("R", real * 9), ("t", real * 3), ("pos", real * 3), ("znear", real),
+                    ("lim_x", real), ("lim_y", real), ("bg", real * 3)]
+
+    class Grads(C.Structure):
+        _fields_ = [("mean", C.c_void_p), ("scale", C.c_void_p), ("quat", C.c_void_p), ("opacity", C.c_void_p),
+                    ("sh", C.c_void_p)]
+
+    return Level, Camera, Grads
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+@dataclass
+class Projection:
+    depth: np.ndarray
+    uv: np.ndarray
+    conic: np.ndarray
+    o_eff: np.ndarray
+    rgb: np.ndarray
+    rect: np.ndarray
+    tiles: np.ndarray
+    radius: np.ndarray
+
+
+@dataclass
+class Binned:
+    tile: np.ndarray
+    dkey: np.ndarray
+    val: np.ndarray
+    ranges: np.ndarray
+    M: int
+
+
+class Oracle:
+    """The oracle in one precision ('f32' decides like the FP32 renderer; 'f64' for the adjoint)."""
+
+    def __init__(self, precision: str = "f32"):
+        assert precision in ("f32", "f64")
+        self.tag = precision
+        self.dt = np.float32 if precision == "f32" else np.float64
+        self.real = C.c_float if precision == "f32" else C.c_double
+        self.L, self.Cam, self.G = _structs(self.real)
+        self.lib = _lib(precision)
+        self._keep = []
+
+    # -- marshalling ---------------------------------------------------------
+    def _arr(self, a):
+        a = np.ascontiguousarray(a, dtype=self.dt)
+        self._keep.append(a)
+        return a
+
+    def levels(self, levels):
+        arr = (self.L * len(levels))()
+        for i, lv in enumerate(levels):
+            arr[i].n = lv.n
+            for f in ("mean", "scale", "quat", "opacity", "sh"):
+                setattr(arr[i], f, _p(self._arr(getattr(lv, f))))
+            arr[i].sh_degree = lv.sh_degree
+            arr[i].filter3d_var = lv.filter3d_var
+        return arr
+
+    def camera(self, cam):
+        c = self.Cam()
+        c.width, c.height = cam.width, cam.height
+        c.fx, c.fy, c.cx, c.cy = cam.fx, cam.fy, cam.cx, cam.cy
+        for i, v in enumerate(np.asarray(cam.R, np.float64).ravel()):
+            c.R[i] = v
+        for i in range(3):
+            c.t[i] = float(cam.t[i]); c.pos[i] = float(cam.pos[i]); c.bg[i] = float(cam.bg[i])
+        c.znear, c.lim_x, c.lim_y = cam.znear, cam.lim_x, cam.lim_y
+        return c
+
+    # -- steps ---------------------------------------------------------------
+    def chunk_pair(self, centers, band, pos):
+        centers = self._arr(centers)
+        f, o, t = C.c_int32(), C.c_int32(), self.real()
+        rc = self.lib.orc_chunk_pair(_p(centers), C.c_int32(len(centers)), self.real(band), _p(self._arr(pos)),
+                                     C.byref(f), C.byref(o), C.byref(t))
+        if rc != 0:
+            raise ValueError("chunk_pair: no chunks")
+        return f.value, o.value, t.value
+
+    def select(self, scene, mode: int, pos, cap: int | None = None):
+        lv = self.levels(scene.levels)
+        d = self._arr(np.asarray(scene.d if scene.d else [0.0]))
+        ch = scene.chunks
+        K = 0 if ch is None else len(ch.centers)
+        centers = self._arr(ch.centers if K else np.zeros((1, 3)))
+        offs = self._arr(ch.offsets if K else np.zeros(1))
+        band = ch.band if K else 0.0
+        if cap is None:
+            cap = scene.n_total
+        ids = np.empty(max(cap, 1), np.uint32)
+        w = np.empty(max(cap, 1), self.dt)
+        f, o, t = C.c_int32(), C.c_int32(), self.real()
+        fn = self.lib.orc_select
+        fn.restype = C.c_int64
+        n = fn(lv, C.c_int32(len(scene.levels)), _p(d), C.c_int32(mode), _p(centers), _p(offs), C.c_int32(K),
+               self.real(band), _p(self._arr(pos)), _p(ids), _p(w), C.c_int64(cap), C.byref(f), C.byref(o),
+               C.byref(t))
+        if n < 0:
+            raise ValueError("select: bad arguments")
+        return ids[:n].copy(), w[:n].copy(), (f.value, o.value, t.value)
+
+    def project(self, scene, ids, w, cam, s2d=0.3, compensate=True) -> Projection:
+        lv = self.levels(scene.levels)
+        n = len(ids)
+        ids = np.ascontiguousarray(ids, np.uint32)
+        w = self._arr(w)
+        out = Projection(depth=np.empty(n, self.dt), uv=np.empty((n, 2), self.dt), conic=np.empty((n, 3), self.dt),
+                         o_eff=np.empty(n, self.dt), rgb=np.empty((n, 3), self.dt), rect=np.empty((n, 4), np.int32),
+                         tiles=np.empty(n, np.uint32), radius=np.empty(n, self.dt))
+        c = self.camera(cam)
+        self.lib.orc_project(lv, C.c_int32(len(scene.levels)), _p(ids), _p(w), C.c_int64(n), C.byref(c),
+                             self.real(s2d), C.c_int32(int(compensate)), _p(out.depth), _p(out.uv), _p(out.conic),
+                             _p(out.o_eff), _p(out.rgb), _p(out.rect), _p(out.tiles), _p(out.radius))
+        return out
+
+    def bin_sort(self, proj: Projection, cam) -> Binned:
+        TX = (cam.width + TILE - 1) // TILE
+        TY = (cam.height + TILE - 1) // TILE
+        M = int(proj.tiles.astype(np.int64).sum())
+        tile = np.empty(max(M, 1), np.uint32)
+        dkey = np.empty(max(M, 1), np.uint64)
+        val = np.empty(max(M, 1), np.uint32)
+        ranges = np.empty((TX * TY, 2), np.uint32)
+        fn = self.lib.orc_bin_sort
+        fn.restype = C.c_int64
+        m = fn(C.c_int64(len(proj.depth)), _p(proj.depth), _p(proj.rect), _p(proj.tiles), C.c_int32(TX),
+               C.c_int32(TY), _p(tile), _p(dkey), _p(val), C.c_int64(M), _p(ranges))
+        assert m == M
+        return Binned(tile=tile[:M], dkey=dkey[:M], val=val[:M], ranges=ranges, M=M)
+
+    def composite(self, proj: Projection, binned: Binned, cam):
+        H, W = cam.height, cam.width
+        img = np.empty((3, H, W), self.dt)
+        T = np.empty((H, W), self.dt)
+        nc = np.empty((H, W), np.uint32)
+        nb = np.empty((H, W), np.uint32)
+        ne = np.empty((H, W), np.uint32)
+        near = np.empty((H, W), np.uint8)
+        c = self.camera(cam)
+        val = binned.val if binned.M else np.zeros(1, np.uint32)
+        self.lib.orc_composite(C.byref(c), _p(proj.uv), _p(proj.conic), _p(proj.o_eff), _p(proj.rgb),
+                               _p(binned.ranges), _p(val), _p(img), _p(T), _p(nc), _p(nb), _p(ne), _p(near))
+        return {"image": img, "final_T": T, "n_contrib": nc, "n_blend": nb, "n_eval": ne, "near": near}
+
+    def composite_brute(self, proj: Projection, cam):
+        H, W = cam.height, cam.width
+        img = np.empty((3, H, W), self.dt)
+        T = np.empty((H, W), self.dt)
+        nc = np.empty((H, W), np.uint32)
+        c = self.camera(cam)
+        self.lib.orc_composite_brute(C.byref(c), C.c_int64(len(proj.depth)), _p(proj.depth), _p(proj.rect),
+                                     _p(proj.tiles), _p(proj.uv), _p(proj.conic), _p(proj.o_eff), _p(proj.rgb),
+                                     _p(img), _p(T), _p(nc))
+        return {"image": img, "final_T": T, "n_contrib": nc}
+
+    def pixel_accept(self, proj: Projection, binned: Binned, cam, x: int, y: int, probe, tol: float) -> bool:
+        c = self.camera(cam)
+        probe = self._arr(np.asarray(probe))
+        val = binned.val if binned.M else np.zeros(1, np.uint32)
+        return bool(self.lib.orc_pixel_accept(C.byref(c), _p(proj.uv), _p(proj.conic), _p(proj.o_eff), _p(proj.rgb),
+                                              _p(binned.ranges), _p(val), C.c_int32(x), C.c_int32(y), _p(probe),
+                                              self.real(tol)))
+
+    def sh_basis(self, x, y, z):
+        Y = np.empty(16, self.dt)
+        self.lib.orc_sh_basis(self.real(x), self.real(y), self.real(z), _p(Y))
+        return Y
+
+    # -- adjoint ---------------------------------------------------------------
+    def grad2d(self, proj: Projection, binned: Binned, cam, dL_dimage):
+        g2 = np.zeros((len(proj.depth), 9), self.dt)
+        c = self.camera(cam)
+        dl = self._arr(dL_dimage)
+        val = binned.val if binned.M else np.zeros(1, np.uint32)
+        self.lib.orc_composite_grad2d(C.byref(c), _p(proj.uv), _p(proj.conic), _p(proj.o_eff), _p(proj.rgb),
+                                      _p(binned.ranges), _p(val), _p(dl), _p(g2))
+        return g2
+
+    def project_grad(self, scene, ids, w, cam, g2, s2d=0.3, compensate=True, grad_level=-1, grads=None):
+        lv = self.levels(scene.levels)
+        if grads is None:
+            grads = [{"mean": np.zeros((3, l.n), self.dt), "scale": np.zeros((3, l.n), self.dt),
+                      "quat": np.zeros((4, l.n), self.dt), "opacity": np.zeros(l.n, self.dt),
+                      "sh": np.zeros((16, 3, l.n), self.dt)} for l in scene.levels]
+        garr = (self.G * len(grads))()
+        for i, g in enumerate(grads):
+            for f in ("mean", "scale", "quat", "opacity", "sh"):
+                setattr(garr[i], f, _p(g[f]))
+        c = self.camera(cam)
+        ids = np.ascontiguousarray(ids, np.uint32)
+        self.lib.orc_project_grad(lv, C.c_int32(len(scene.levels)), _p(ids), _p(self._arr(w)), C.c_int64(len(ids)),
+                                  C.byref(c), self.real(s2d), C.c_int32(int(compensate)), _p(self._arr(g2)),
+                                  C.c_int32(grad_level), garr)
+        return grads
+
+    # -- whole frame -------------------------------------------------------------
+    def render(self, scene, cam, mode: int, s2d=0.3, compensate=True, brute=False):
+        """select -> project -> bin/sort -> composite, all intermediates returned."""
+        ids, w, fot = self.select(scene, mode, cam.pos)
+        proj = self.project(scene, ids, w, cam, s2d, compensate)
+        binned = self.bin_sort(proj, cam)
+        out = self.composite(proj, binned, cam)
+        out.update(ids=ids, w=w, fot=fot, proj=proj, binned=binned)
+        if brute:
+            out["brute"] = self.composite_brute(proj, cam)
+        self._keep.clear()
+        return out
+
+    def render_grad(self, scene, cam, mode: int, dL_dimage, s2d=0.3, compensate=True, grad_level=-1):
+        """Forward, then the adjoint of L = sum(dL_dimage * image) w.r.t. activated params."""
+        fwd = self.render(scene, cam, mode, s2d, compensate)
+        g2 = self.grad2d(fwd["proj"], fwd["binned"], cam, dL_dimage)
+        grads = self.project_grad(scene, fwd["ids"], fwd["w"], cam, g2, s2d, compensate, grad_level)
+        self._keep.clear()
+        return fwd, g2, grads

@@ -1,0 +1,533 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these retypes the oracle's own formulas: each checks a closed form
+of a special case, an invariant, hand-worked values, a library routine or a
+brute-force alternative, chosen so that a dropped term, a wrong sign or
+index, or a transposed operand in the oracle fails at least one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import Camera, Chunks, Level, Scene
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# helpers: hand-built scenes
+# ---------------------------------------------------------------------------
+
+def axis_camera(W=64, H=64, f=80.0, bg=(0.0, 0.0, 0.0), pos=(0.0, 0.0, 0.0)):
+    """Camera at `pos` looking down +z with identity rotation."""
+    pos = np.asarray(pos, np.float32)
+    return Camera(width=W, height=H, fx=f, fy=f, cx=W / 2.0, cy=H / 2.0, R=np.eye(3, dtype=np.float32),
+                  t=(-pos).astype(np.float32), pos=pos, znear=0.2, lim_x=1.3 * (W / 2.0) / f,
+                  lim_y=1.3 * (H / 2.0) / f, bg=bg)
+
+
+def make_level(means, scales, quats=None, opac=None, dc=None, var=0.0, sh=None):
+    means = np.asarray(means, np.float64).reshape(-1, 3)
+    n = len(means)
+    scales = np.broadcast_to(np.asarray(scales, np.float64), (n, 3)) if np.ndim(scales) else np.full((n, 3), scales)
+    if quats is None:
+        quats = np.tile([1.0, 0, 0, 0], (n, 1))
+    if opac is None:
+        opac = np.full(n, 0.5)
+    if sh is None:
+        sh = np.zeros((16, 3, n))
+        sh[0] = np.broadcast_to(np.asarray(dc if dc is not None else 0.5, np.float64).reshape(-1, 1), (3, n)) \
+            if np.ndim(dc) <= 1 else np.asarray(dc).T
+    return Level(mean=np.ascontiguousarray(means.T, np.float32), scale=np.ascontiguousarray(np.asarray(scales).T, np.float32),
+                 quat=np.ascontiguousarray(np.asarray(quats, np.float64).T, np.float32),
+                 opacity=np.asarray(opac, np.float32), sh=np.asarray(sh, np.float32), sh_degree=3,
+                 filter3d_var=float(np.float32(var)))
+
+
+def one_level_scene(level):
+    return Scene(levels=[level], d=[], chunks=None)
+
+
+C0 = 1.0 / (2.0 * math.sqrt(math.pi))
+
+
+# ---------------------------------------------------------------------------
+# Eq. 4: chunk pair and t
+# ---------------------------------------------------------------------------
+
+def test_chunk_pair_hand_worked_cases(oracle32, oracle64):
+    g = json.load(open(os.path.join(GOLDEN, "chunk_pair_cases.json")))
+    centers = np.asarray(g["centers"], np.float64)
+    for O in (oracle32, oracle64):
+        for case in g["cases"]:
+            f, o, t = O.chunk_pair(centers, case["band"], np.asarray(case["c"], np.float64))
+            assert (f, o) == (case["f"], case["o"]), case
+            assert t == case["t"], case
+
+
+def test_chunk_pair_nearest_two_by_enumeration(oracle32):
+    rng = np.random.default_rng(7)
+    for trial in range(200):
+        K = int(rng.integers(2, 20))
+        centers = rng.uniform(-50, 50, (K, 3)).astype(np.float32)
+        c = rng.uniform(-60, 60, 3).astype(np.float32)
+        f, o, t = oracle32.chunk_pair(centers, 0.0, c)
+        d = np.linalg.norm(centers.astype(np.float64) - c, axis=1)
+        order = np.argsort(d, kind="stable")
+        assert f == order[0] and o == order[1]
+        # the nearest chunk never weighs less than one half (its weights are "close to 1")
+        assert t >= 0.5
+        # t is the projection of c - m_o on the centre line, clamped (float64 reference within FP32 rounding)
+        g_ = centers[f].astype(np.float64) - centers[o]
+        tb = np.dot(c - centers[o].astype(np.float64), g_) / np.dot(g_, g_)
+        assert abs(t - min(1.0, max(0.0, tb))) <= 1e-5
+
+
+def test_chunk_pair_single_chunk_and_none(oracle32):
+    f, o, t = oracle32.chunk_pair(np.zeros((1, 3)), 0.0, np.ones(3))
+    assert (f, o, t) == (0, -1, 1.0)
+    with pytest.raises(ValueError):
+        oracle32.chunk_pair(np.zeros((0, 3)), 0.0, np.ones(3))
+
+
+# ---------------------------------------------------------------------------
+# Eq. 2: active set; chunk offsets
+# ---------------------------------------------------------------------------
+
+def test_lod_partition_identical_levels_select_each_gaussian_once(oracle32):
+    """L identical copies of one level, camera mode: [d_l, d_{l+1}) partitions
+    [0, inf), so each Gaussian is selected from exactly one copy, and the LOD
+    render equals the plain render of the single level bit for bit."""
+    base = synth.gaussians(3000, (901, 0), synth._cube(4.0), -3.0, 0.5, morton=False)
+    # three Gaussians exactly on the switch distances 2 and 4 (inclusive lower bound)
+    base.mean[:, 0] = [2.0, 0.0, 0.0]
+    base.mean[:, 1] = [0.0, 4.0, 0.0]
+    base.mean[:, 2] = [0.0, 0.0, 2.0]
+    lod = Scene(levels=[base, base, base], d=[2.0, 4.0])
+    cam = synth.look_at((0.0, 0.0, 0.0), (0.0, 0.0, 1.0), (0, -1, 0), 96, 80)
+    cam.pos = np.zeros(3, np.float32)
+    ids, w, _ = oracle32.select(lod, oracle.LOD_CAMERA, cam.pos)
+    n = base.n
+    local = ids % n
+    lvl = ids // n
+    assert np.array_equal(np.sort(local), np.arange(n)), "each Gaussian exactly once"
+    assert np.all(w == 1.0)
+    sel_level = dict(zip(local.tolist(), lvl.tolist()))
+    assert sel_level[0] == 1 and sel_level[2] == 1 and sel_level[1] == 2
+    dist = np.linalg.norm(base.mean.T.astype(np.float64), axis=1)
+    expect = np.where(dist < 2.0, 0, np.where(dist < 4.0, 1, 2))
+    assert np.array_equal(np.array([sel_level[i] for i in range(n)]), expect)
+    # image equality with the plain render
+    cam2 = synth.look_at((0.0, 0.5, -6.0), (0.0, 0.0, 0.0), (0, -1, 0), 96, 80)
+    r_lod = oracle32.render(lod, cam2, oracle.LOD_CAMERA)
+    r_one = oracle32.render(one_level_scene(base), cam2, oracle.ALL)
+    assert np.array_equal(r_lod["image"], r_one["image"])
+    assert np.array_equal(r_lod["final_T"], r_one["final_T"])
+
+
+def test_chunk_offsets_and_union_weights(oracle32):
+    """Two chunks 10 m apart with offset r = 10; level thresholds d = (3,):
+    level 0 about chunk k covers [0, 13), level 1 covers [13, inf)."""
+    rng = np.random.default_rng(3)
+    m = rng.uniform(-30, 30, (4000, 3))
+    m[0] = [13.0, 0.0, 0.0]   # exactly d_1 + r from chunk 0
+    lv0 = make_level(m, 0.05)
+    lv1 = make_level(m, 0.05)
+    ch = Chunks(centers=np.array([[0, 0, 0], [10, 0, 0]], np.float32), offsets=np.array([10, 10], np.float32))
+    sc = Scene(levels=[lv0, lv1], d=[3.0], chunks=ch)
+    pos = np.array([2.0, 1.0, 0.0], np.float32)   # tau = 1/5 -> t = 0.8
+    ids, w, (f, o, t) = oracle32.select(sc, oracle.CHUNKED, pos)
+    assert (f, o) == (0, 1) and t == np.float32(0.8)
+    n = len(m)
+    md = m.astype(np.float32).astype(np.float64)
+    dF = np.linalg.norm(md - [0, 0, 0], axis=1)
+    dO = np.linalg.norm(md - [10, 0, 0], axis=1)
+    inF = [dF < 13.0, dF >= 13.0]
+    inO = [dO < 13.0, dO >= 13.0]
+    exp_ids, exp_w = [], []
+    for l in range(2):
+        for i in range(n):
+            a, b = inF[l][i], inO[l][i]
+            if a or b:
+                exp_ids.append(l * n + i)
+                exp_w.append(1.0 if (a and b) else (np.float32(0.8) if a else np.float32(1) - np.float32(0.8)))
+    assert np.array_equal(ids, np.asarray(exp_ids, np.uint32))
+    assert np.array_equal(w, np.asarray(exp_w, np.float32))
+    # the Gaussian exactly at distance d_1 + r_0 from chunk 0 belongs to level 1 about chunk 0
+    assert n + 0 in set(ids.tolist())
+
+
+def test_camera_at_chunk_centre_renders_nearest_set_alone(oracle32):
+    """Camera at m_f: t = 1, so every Gaussian only in the other chunk's set
+    gets weight 0 and the image equals the render of A_f alone."""
+    sc = synth.lod_city_scene(counts=(6000, 1500), half_xy=20.0, d=(6.0,), grid=2, spacing=8.0, chunk_z=1.0,
+                              band=0.0, seed=11)
+    pos = sc.chunks.centers[0].astype(np.float64)
+    cam = synth.look_at(pos, pos + np.array([1.0, 0.2, -0.1]), (0, 0, 1), 128, 72)
+    cam.pos = sc.chunks.centers[0].copy()
+    r = oracle32.render(sc, cam, oracle.CHUNKED)
+    f, o, t = r["fot"]
+    assert f == 0 and t == 1.0
+    assert set(np.unique(r["w"]).tolist()) <= {0.0, 1.0}
+    # A_f alone: a scene whose only chunk is f
+    only_f = Scene(levels=sc.levels, d=sc.d, chunks=Chunks(centers=sc.chunks.centers[:1], offsets=sc.chunks.offsets[:1]))
+    r_f = oracle32.render(only_f, cam, oracle.CHUNKED)
+    assert set(r_f["ids"].tolist()) == set(r["ids"][r["w"] == 1.0].tolist())
+    assert np.array_equal(r["image"], r_f["image"])
+
+
+def test_storage_permutation_invariance(oracle32):
+    sc = synth.lod_city_scene(counts=(5000, 1200), half_xy=15.0, d=(5.0,), grid=2, spacing=6.0, chunk_z=1.0,
+                              band=3.0, seed=12)
+    cam = synth.look_at((-1.0, 0.5, 1.2), (10.0, 0.0, 0.0), (0, 0, 1), 112, 64)
+    r = oracle32.render(sc, cam, oracle.CHUNKED)
+    rng = np.random.default_rng(0)
+    perms = [rng.permutation(l.n) for l in sc.levels]
+    sp = Scene(levels=[synth.permuted(l, p) for l, p in zip(sc.levels, perms)], d=sc.d, chunks=sc.chunks)
+    rp = oracle32.render(sp, cam, oracle.CHUNKED)
+    # same selected set (mapped back to original storage) with the same weights
+    def keyed(res, perm_list):
+        out = {}
+        base = 0
+        bases = [0]
+        for l in sc.levels:
+            bases.append(bases[-1] + l.n)
+        for g, w in zip(res["ids"].tolist(), res["w"].tolist()):
+            l = max(i for i in range(len(sc.levels)) if bases[i] <= g)
+            i = g - bases[l]
+            orig = i if perm_list is None else int(perm_list[l][i])
+            out[(l, orig)] = w
+        return out
+    assert keyed(r, None) == keyed(rp, perms)
+    assert np.array_equal(r["image"], rp["image"])
+
+
+# ---------------------------------------------------------------------------
+# projection closed forms (EWA, Eq. 3, 2-D filter, SH)
+# ---------------------------------------------------------------------------
+
+def isotropic_expected(W, H, f, z, sigma, o, k_dc, s2d=0.3, var=0.0, X=0.0):
+    """Closed form of one isotropic Gaussian at (X, 0, z) seen by axis_camera:
+    J = [[f/z, 0, -f X / z^2], [0, f/z, 0]], Sigma' = (sigma^2 + var) J J^T + s2d I."""
+    v = sigma * sigma + var
+    a0 = v * ((f / z) ** 2 + (f * X / z ** 2) ** 2)
+    c0 = v * (f / z) ** 2
+    a, c = a0 + s2d, c0 + s2d
+    comp2 = math.sqrt(a0 * c0 / (a * c))
+    comp3 = (sigma * sigma / v) ** 1.5
+    u, vv = f * X / z + W / 2.0, H / 2.0
+    r = math.ceil(3.0 * math.sqrt(max(a, c)))
+    rgb = C0 * k_dc + 0.5
+    img = np.zeros((3, H, W))
+    T = np.ones((H, W))
+    TX, TY = (W + 15) // 16, (H + 15) // 16
+    x0, x1 = max(0, math.floor((u - r) / 16)), min(TX, math.floor((u + r) / 16) + 1)
+    y0, y1 = max(0, math.floor((vv - r) / 16)), min(TY, math.floor((vv + r) / 16) + 1)
+    for py in range(H):
+        for px in range(W):
+            if not (x0 <= px // 16 < x1 and y0 <= py // 16 < y1):
+                continue
+            dx, dy = u - (px + 0.5), vv - (py + 0.5)
+            alpha = min(0.99, o * comp3 * comp2 * math.exp(-0.5 * (dx * dx / a + dy * dy / c)))
+            if alpha < 1.0 / 255.0:
+                continue
+            img[:, py, px] = rgb * alpha
+            T[py, px] = 1.0 - alpha
+    return dict(a=a, c=c, u=u, v=vv, r=r, rect=(x0, y0, x1, y1), comp2=comp2, comp3=comp3, img=img, T=T, rgb=rgb)
+
+
+@pytest.mark.parametrize("X,var", [(0.0, 0.0), (0.0, 0.004), (1.5, 0.0), (-2.0, 0.002)])
+def test_isotropic_gaussian_closed_form(oracle64, oracle32, X, var):
+    W = H = 64
+    f, z, sigma, o, k = 80.0, 5.0, 0.1, 0.8, 0.7
+    lv = make_level([[X, 0.0, z]], sigma, opac=[o], dc=k, var=var)
+    # float32 inputs: use the values they round to in the closed form
+    X32, z32, s32 = float(np.float32(X)), float(np.float32(z)), float(np.float32(sigma))
+    e = isotropic_expected(W, H, f, z32, s32, float(np.float32(o)), float(np.float32(k)), var=float(np.float32(var)), X=X32)
+    cam = axis_camera(W, H, f)
+    for O, tol in ((oracle64, 1e-12), (oracle32, 2e-6)):
+        r = O.render(one_level_scene(lv), cam, oracle.ALL)
+        p = r["proj"]
+        assert tuple(p.rect[0]) == e["rect"]
+        assert p.radius[0] == e["r"]
+        assert abs(p.uv[0, 0] - e["u"]) <= tol * 100 and abs(p.uv[0, 1] - e["v"]) <= tol * 100
+        assert np.allclose(p.conic[0], [1 / e["a"], 0.0, 1 / e["c"]], rtol=tol * 10, atol=tol)
+        assert abs(p.o_eff[0] - float(np.float32(o)) * e["comp2"] * e["comp3"]) <= tol
+        assert np.allclose(p.rgb[0], e["rgb"], atol=tol)
+        assert np.abs(r["image"] - e["img"]).max() <= tol * 10
+        assert np.abs(r["final_T"] - e["T"]).max() <= tol * 10
+
+
+def test_quaternion_quarter_turn_swaps_axes(oracle64):
+    """q = (cos 45, 0, 0, sin 45) turns x into y: Sigma = diag(sy^2, sx^2, sz^2)."""
+    f, z, sx, sy = 80.0, 5.0, 0.2, 0.05
+    h = math.sqrt(0.5)
+    lv = make_level([[0.0, 0.0, z]], [[sx, sy, 0.1]], quats=[[h, 0.0, 0.0, h]], opac=[0.5])
+    cam = axis_camera(64, 64, f)
+    p = oracle64.render(one_level_scene(lv), cam, oracle.ALL)["proj"]
+    sx32, sy32 = float(np.float32(sx)), float(np.float32(sy))
+    a = (f / z) ** 2 * sy32 ** 2 + 0.3
+    c = (f / z) ** 2 * sx32 ** 2 + 0.3
+    assert np.allclose(p.conic[0], [1 / a, 0.0, 1 / c], rtol=1e-6, atol=1e-6)  # q rounded to float32
+    # an unrotated copy has the axes the other way round
+    lv2 = make_level([[0.0, 0.0, z]], [[sx, sy, 0.1]], opac=[0.5])
+    p2 = oracle64.render(one_level_scene(lv2), cam, oracle.ALL)["proj"]
+    assert np.allclose(p2.conic[0], [1 / c, 0.0, 1 / a], rtol=1e-6, atol=1e-6)
+
+
+def test_anisotropic_general_matches_matrix_product(oracle64):
+    """A random rotated anisotropic Gaussian: Sigma' from numpy's matrix
+    products of (J W) R S^2 R^T (J W)^T (library routine, not the oracle's sums)."""
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        mu = rng.uniform(-1, 1, 3) + [0, 0, 6]
+        s = np.exp(rng.normal(-2, 0.4, 3))
+        q = rng.normal(size=4); q /= np.linalg.norm(q)
+        lv = make_level([mu], [s], quats=[q], opac=[0.6], var=0.001)
+        cam = synth.look_at((0.3, -0.2, -1.0), (0.1, 0.0, 6.0), (0, -1, 0), 96, 64)
+        p = oracle64.render(one_level_scene(lv), cam, oracle.ALL)["proj"]
+        mu32 = lv.mean[:, 0].astype(np.float64); s32 = lv.scale[:, 0].astype(np.float64)
+        w, x, y, z = lv.quat[:, 0].astype(np.float64)
+        # rotation of a unit quaternion via scipy (independent formula)
+        from scipy.spatial.transform import Rotation
+        Rq = Rotation.from_quat([x, y, z, w]).as_matrix()
+        Sig = Rq @ np.diag(s32 ** 2 + np.float32(0.001)) @ Rq.T
+        Wc = cam.R.astype(np.float64)
+        tc = Wc @ mu32 + cam.t.astype(np.float64)
+        J = np.array([[cam.fx / tc[2], 0, -cam.fx * tc[0] / tc[2] ** 2], [0, cam.fy / tc[2], -cam.fy * tc[1] / tc[2] ** 2]])
+        Sp = J @ Wc @ Sig @ Wc.T @ J.T + 0.3 * np.eye(2)
+        inv = np.linalg.inv(Sp)
+        if p.tiles[0] == 0:
+            continue
+        assert np.allclose(p.conic[0], [inv[0, 0], inv[0, 1], inv[1, 1]], rtol=1e-5)
+        assert abs(p.depth[0] - tc[2]) < 1e-9
+
+
+def test_sh_basis_orthonormal_by_quadrature(oracle64):
+    """Integral of Y_i Y_j over the sphere is delta_ij (Gauss-Legendre in
+    cos(theta) x uniform phi; exact for these polynomial degrees)."""
+    xg, wg = np.polynomial.legendre.leggauss(12)
+    nphi = 24
+    G = np.zeros((16, 16))
+    for ct, wt in zip(xg, wg):
+        st = math.sqrt(1 - ct * ct)
+        for k in range(nphi):
+            ph = 2 * math.pi * k / nphi
+            Y = oracle64.sh_basis(st * math.cos(ph), st * math.sin(ph), ct)
+            G += wt * (2 * math.pi / nphi) * np.outer(Y, Y)
+    assert np.abs(G - np.eye(16)).max() < 1e-12
+
+
+def test_sh_addition_theorem(oracle64):
+    """sum_m Y_lm(u) Y_lm(v) = (2l+1)/(4 pi) P_l(u.v): fixes each band's span and scale."""
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        u = rng.normal(size=3); u /= np.linalg.norm(u)
+        v = rng.normal(size=3); v /= np.linalg.norm(v)
+        Yu, Yv = oracle64.sh_basis(*u), oracle64.sh_basis(*v)
+        for l in range(4):
+            sl = slice(l * l, (l + 1) * (l + 1))
+            lhs = float(np.dot(Yu[sl], Yv[sl]))
+            Pl = np.polynomial.legendre.Legendre.basis(l)(float(np.dot(u, v)))
+            assert abs(lhs - (2 * l + 1) / (4 * math.pi) * Pl) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# compositing (Eq. 1, front-to-back blending)
+# ---------------------------------------------------------------------------
+
+def test_blend_weights_plus_transmittance_is_one(oracle32, oracle64):
+    """With every colour 1 and bg 0, image = sum_k alpha_k T_k = 1 - T_final."""
+    sc = synth.plain_scene(n=3000, seed=21, width=96, height=80)
+    lv = sc.levels[0]
+    lv.sh[:] = 0.0
+    lv.sh[0] = 0.5 / C0
+    for O, tol in ((oracle32, 1e-5), (oracle64, 1e-12)):
+        r = O.render(sc, sc.cameras[0], oracle.ALL)
+        for ch in range(3):
+            c = r["proj"].rgb[0, ch]          # the float32-stored DC gives c = 1 up to rounding
+            assert np.all(r["proj"].rgb[:, ch] == c) and abs(c - 1.0) < 1e-6
+            assert np.abs(r["image"][ch] / c + r["final_T"] - 1.0).max() <= tol
+
+
+def test_tiled_equals_brute_force(oracle32):
+    sc = synth.plain_scene(n=2500, seed=22, width=80, height=72)
+    r = oracle32.render(sc, sc.cameras[0], oracle.ALL, brute=True)
+    b = r["brute"]
+    assert np.array_equal(r["image"], b["image"])
+    assert np.array_equal(r["final_T"], b["final_T"])
+    assert np.array_equal(r["n_contrib"], b["n_contrib"])
+
+
+def test_sort_order_and_ranges(oracle32):
+    sc = synth.plain_scene(n=2000, seed=23, width=96, height=64)
+    r = oracle32.render(sc, sc.cameras[0], oracle.ALL)
+    bn, p = r["binned"], r["proj"]
+    key = np.lexsort((bn.val, bn.dkey, bn.tile))      # numpy's sort of the same triples
+    assert np.array_equal(key, np.arange(bn.M))
+    assert np.array_equal(bn.dkey, p.depth[bn.val].view(np.uint32).astype(np.uint64))
+    for t in range(len(bn.ranges)):
+        s, e = bn.ranges[t]
+        assert np.all(bn.tile[s:e] == t)
+    assert int(bn.ranges[:, 1].max()) == bn.M
+    # instance count per Gaussian = rectangle area
+    cnt = np.bincount(bn.val, minlength=len(p.tiles))
+    assert np.array_equal(cnt, p.tiles)
+
+
+def test_special_cases_opaque_empty_two_layers(oracle64):
+    W = H = 64
+    f = 80.0
+    bg = (0.1, 0.2, 0.3)
+    cam = axis_camera(W, H, f, bg=bg)
+    # one near-opaque wide Gaussian at the centre: alpha clamps at 0.99
+    lv = make_level([[0.0, 0.0, 5.0]], 0.6, opac=[1.0], dc=0.5 / C0)
+    r = oracle64.render(one_level_scene(lv), cam, oracle.ALL, compensate=False)
+    assert abs(r["final_T"][32, 32] - 0.01) < 1e-12
+    # an empty frame is pure background
+    far = make_level([[0.0, 0.0, -5.0]], 0.1)     # behind the camera: culled
+    r2 = oracle64.render(one_level_scene(far), cam, oracle.ALL)
+    for ch in range(3):
+        assert np.all(r2["image"][ch] == bg[ch])
+    assert np.all(r2["final_T"] == 1.0) and np.all(r2["n_contrib"] == 0)
+    # two layers: C = c1 a1 + c2 a2 (1 - a1) (+ T bg); storage order back-to-front
+    s = 0.3
+    lv2 = make_level([[0.0, 0.0, 8.0], [0.0, 0.0, 4.0]], s, opac=[0.7, 0.6], dc=[[0.2, 0.2, 0.2], [0.9, 0.9, 0.9]])
+    r3 = oracle64.render(one_level_scene(lv2), cam, oracle.ALL, compensate=False)
+    px = py = 34
+    def alpha(z, o):
+        a = (f * float(np.float32(s)) / z) ** 2 + 0.3
+        d = 32 - (px + 0.5)
+        return min(0.99, float(np.float32(o)) * math.exp(-0.5 * (d * d / a + d * d / a)))
+    a1, a2 = alpha(4.0, 0.6), alpha(8.0, 0.7)
+    c1, c2 = C0 * float(np.float32(0.9)) + 0.5, C0 * float(np.float32(0.2)) + 0.5
+    T = (1 - a1) * (1 - a2)
+    assert a1 > 1 / 255 and a2 > 1 / 255
+    for ch in range(3):
+        assert abs(r3["image"][ch, py, px] - (c1 * a1 + c2 * a2 * (1 - a1) + T * bg[ch])) < 1e-12
+    assert r3["n_contrib"][py, px] == 2
+
+
+def test_early_termination(oracle64):
+    """Stacked wide opaque layers: T = prod (1 - alpha_k); the layer that would
+    push T below 1e-4 is not blended and ends the pixel."""
+    W = H = 32
+    cam = axis_camera(W, H, 40.0)
+    zs = [3.0 + 0.5 * k for k in range(10)]
+    lv = make_level([[0.0, 0.0, z] for z in zs[::-1]], 0.5, opac=[0.9] * 10, dc=0.5 / C0)
+    r = oracle64.render(one_level_scene(lv), cam, oracle.ALL, compensate=False)
+    px = py = 16
+    T, k_last = 1.0, 0
+    for k, z in enumerate(zs):
+        a = (40.0 * 0.5 / z) ** 2 + 0.3
+        d = 16 - (px + 0.5)
+        al = min(0.99, float(np.float32(0.9)) * math.exp(-0.5 * (2 * d * d / a)))
+        if T * (1 - al) < 1e-4:
+            break
+        T *= (1 - al)
+        k_last = k + 1
+    assert r["n_contrib"][py, px] == k_last < 10
+    assert abs(r["final_T"][py, px] - T) < 1e-12
+
+
+def test_f32_and_f64_oracles_agree(oracle32, oracle64):
+    sc = synth.plain_scene(n=1500, seed=24, width=64, height=64)
+    r32 = oracle32.render(sc, sc.cameras[0], oracle.ALL)
+    r64 = oracle64.render(sc, sc.cameras[0], oracle.ALL)
+    assert np.array_equal(r32["binned"].val, r64["binned"].val)
+    ok = (r32["near"] == 0)
+    assert np.abs(r32["image"] - r64["image"]).max(axis=0)[ok].max() < 1e-5
+
+
+# ---------------------------------------------------------------------------
+# adjoint vs central finite differences (FP64)
+# ---------------------------------------------------------------------------
+
+def _fd_check(O, sc, cam, params, rng, n_coords, mode=oracle.ALL, grad_level=-1):
+    H, W = cam.height, cam.width
+    dL = rng.normal(size=(3, H, W))
+    fwd, g2, grads = O.render_grad(sc, cam, mode, dL, grad_level=grad_level)
+    base_sig = (fwd["n_contrib"].copy(), fwd["n_blend"].copy(), fwd["proj"].tiles.copy(), fwd["proj"].rect.copy())
+
+    def loss_and_sig():
+        r = O.render(sc, cam, mode)
+        return float(np.sum(dL * r["image"])), (r["n_contrib"], r["n_blend"], r["proj"].tiles, r["proj"].rect)
+
+    report = {}
+    for name in params:
+        for l, lv in enumerate(sc.levels):
+            arr = getattr(lv, name)
+            flat = arr.reshape(-1)
+            idx = rng.choice(flat.size, size=min(n_coords, flat.size), replace=False)
+            fd, an = [], []
+            skipped = 0
+            for j in idx:
+                th = flat[j]
+                h = 1e-6 * max(1.0, abs(th))
+                flat[j] = th + h
+                lp, sp = loss_and_sig()
+                flat[j] = th - h
+                lm, sm = loss_and_sig()
+                flat[j] = th
+                if not all(np.array_equal(x, y) for x, y in zip(sp, base_sig)) or \
+                        not all(np.array_equal(x, y) for x, y in zip(sm, base_sig)):
+                    skipped += 1
+                    continue
+                fd.append((lp - lm) / (2 * h))
+                an.append(grads[l][name].reshape(-1)[j])
+            fd, an = np.asarray(fd), np.asarray(an)
+            report[(name, l)] = (fd, an, skipped)
+    return report
+
+
+@pytest.mark.parametrize("var", [0.0, 0.003])
+def test_adjoint_matches_central_differences(oracle64, var):
+    sc = synth.check_scene(n=64, width=32, height=32, filter3d_var=var)
+    lv = sc.levels[0]
+    for f in ("mean", "scale", "quat", "opacity", "sh"):
+        setattr(lv, f, getattr(lv, f).astype(np.float64))
+    cam = sc.cameras[0]
+    rng = np.random.default_rng(17)
+    rep = _fd_check(oracle64, sc, cam, ["mean", "scale", "quat", "opacity", "sh"], rng, n_coords=60)
+    for key, (fd, an, skipped) in rep.items():
+        assert len(fd) >= 20, (key, skipped)
+        nrm = np.linalg.norm(fd)
+        assert nrm > 0, key
+        rel = np.linalg.norm(fd - an) / nrm
+        assert rel <= 1e-3, (key, rel)
+        assert np.all(np.abs(fd - an) <= 1e-3 * (np.abs(fd) + np.sqrt(np.mean(fd ** 2)))), key
+
+
+def test_adjoint_level_mask(oracle64):
+    """grad_level restricts the update to one level's Gaussians."""
+    sc = synth.lod_city_scene(counts=(800, 200), half_xy=6.0, d=(3.0,), grid=1, spacing=1.0, chunk_z=1.0,
+                              band=0.0, seed=31)
+    for lv in sc.levels:
+        for f in ("mean", "scale", "quat", "opacity", "sh"):
+            setattr(lv, f, getattr(lv, f).astype(np.float64))
+    cam = synth.look_at((0.0, -8.0, 1.5), (0.0, 0.0, 0.0), (0, 0, 1), 48, 32)
+    dL = np.random.default_rng(2).normal(size=(3, 32, 48))
+    _, _, g_all = oracle64.render_grad(sc, cam, oracle.LOD_CAMERA, dL)
+    _, _, g_1 = oracle64.render_grad(sc, cam, oracle.LOD_CAMERA, dL, grad_level=1)
+    assert np.all(g_1[0]["mean"] == 0) and np.abs(g_all[0]["mean"]).max() > 0
+    assert np.array_equal(g_1[1]["mean"], g_all[1]["mean"])
+
+
+def test_sh_colour_uses_direction_from_camera_to_gaussian(oracle64):
+    """Colour is evaluated in the unit direction from the camera centre to the
+    mean: a Gaussian straight ahead (+z) with only the z-linear band set shows
+    0.5 + c1 k, one seen from behind (camera on the other side) 0.5 - c1 k."""
+    c1 = math.sqrt(3.0 / (4.0 * math.pi))
+    k = 0.25
+    sh = np.zeros((16, 3, 1)); sh[2, :, 0] = k
+    lv = make_level([[0.0, 0.0, 5.0]], 0.1, sh=sh)
+    p = oracle64.render(one_level_scene(lv), axis_camera(), oracle.ALL)["proj"]
+    assert np.allclose(p.rgb[0], 0.5 + c1 * float(np.float32(k)), atol=1e-12)
+    cam_back = synth.look_at((0.0, 0.0, 10.0), (0.0, 0.0, 0.0), (0, -1, 0), 64, 64)
+    p2 = oracle64.render(one_level_scene(lv), cam_back, oracle.ALL)["proj"]
+    assert np.allclose(p2.rgb[0], 0.5 - c1 * float(np.float32(k)), atol=1e-6)
