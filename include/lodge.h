@@ -1,0 +1,278 @@
+/*
+ * lodge.h -- C ABI of the MI355X (gfx950) per-frame renderer for
+ * level-of-detail Gaussian splatting (LODGE, arXiv 2505.23158).
+ *
+ * One frame is:  lodge_select  (two nearest chunks + Eq. 4 weight t, active
+ * set of Eq. 2 with per-chunk offset thresholds)  ->  lodge_render  (EWA
+ * projection with the Eq. 3 3-D filter and the renderer's 2-D filter, SH
+ * colour, 16x16 tile binning, per-tile sort on (depth, index), front-to-back
+ * alpha compositing of Eq. 1 with early termination).  lodge_render_backward
+ * is the adjoint of lodge_render for the per-level fine-tuning of the
+ * paper's supplementary material ("LOD structure optimization steps").
+ *
+ * Conventions shared by every call
+ *  - All functions return a lodge_status and never abort; the message of
+ *    the last failure on the calling thread is lodge_last_error().
+ *  - "device" pointers are HIP device memory owned by the caller; "host"
+ *    pointers are read during the call only unless stated otherwise.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls marked
+ *    ASYNC enqueue work on `stream` and return; they never synchronise the
+ *    host, never allocate device memory, and may be captured into a HIP
+ *    graph when the camera struct they are given lives in pinned host
+ *    memory (the capture records a copy of it that is re-read at replay).
+ *  - Every array of Gaussian parameters is a structure of arrays in FP32:
+ *    attribute-major planes of n floats each.
+ *  - Data-dependent sizes never return to the host inside a frame: device
+ *    counters bound every kernel.  Capacity overflows set device flags that
+ *    lodge_check() reports after the stream has been synchronised.
+ */
+#ifndef LODGE_H
+#define LODGE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+
+typedef enum {
+    LODGE_OK = 0,
+    LODGE_ERR_INVALID_ARG = 1,   /* a pointer, size or value outside its stated range */
+    LODGE_ERR_CAPACITY = 2,      /* a workspace / selection capacity was exceeded */
+    LODGE_ERR_HIP = 3,           /* the HIP runtime reported an error (see lodge_last_error) */
+    LODGE_ERR_UNSUPPORTED = 4    /* a valid request this build does not handle */
+} lodge_status;
+
+/* Static description of a status code. */
+const char* lodge_status_string(lodge_status s);
+/* Message of the last non-OK status returned on this thread ("" if none). */
+const char* lodge_last_error(void);
+/* Library version string. */
+const char* lodge_version(void);
+
+/* ------------------------------------------------------------ scene input */
+
+/* One LOD level G^(l) (Sec. 3 "Level of Detail (LOD) representation"):
+ * activated parameters, device memory, borrowed until lodge_scene_destroy.
+ *   mean    [3][n]   position mu
+ *   scale   [3][n]   linear per-axis scale s (covariance R diag(s^2) R^T)
+ *   quat    [4][n]   rotation quaternion (w, x, y, z), used as given
+ *   opacity [n]      o in [0, 1]
+ *   sh      [(d+1)^2][3][n]  real SH coefficients [basis][channel][n]
+ *   sh_degree d in 0..3
+ *   filter3d_var     variance of the level's 3-D smoothing filter (Eq. 3,
+ *                    Sec. 3 "Building LOD representation"), m^2, >= 0 */
+typedef struct {
+    int64_t n;
+    const float* mean;
+    const float* scale;
+    const float* quat;
+    const float* opacity;
+    const float* sh;
+    int32_t sh_degree;
+    float filter3d_var;
+} lodge_level;
+
+/* Chunks (Sec. 3 "Reducing memory with chunk-based rendering"): centres
+ * m_k and the offset r_k added to every switch distance for chunk k.
+ * Host memory, copied by lodge_scene_create.  1 <= k <= LODGE_MAX_CHUNKS.
+ * band > 0 narrows the Eq. 4 ramp to a strip of that width (metres)
+ * around the bisector of the two centres; band <= 0 is Eq. 4 as printed. */
+#define LODGE_MAX_CHUNKS 128
+typedef struct {
+    int32_t k;
+    const float* center;  /* host [k][3] */
+    const float* offset;  /* host [k]    */
+    float band;
+} lodge_chunks;
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward).  R is the
+ * world->camera rotation (row-major), t its translation, pos the camera
+ * centre (both sides of the renderer use pos as given).  Pixel (x, y) is
+ * sampled at (x + 0.5, y + 0.5).  Gaussians with camera depth <= znear are
+ * culled; the projection Jacobian is evaluated at the mean clamped to
+ * |x/z| <= lim_x, |y/z| <= lim_y.  bg is the background colour. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float R[9];
+    float t[3];
+    float pos[3];
+    float znear, lim_x, lim_y;
+    float bg[3];
+} lodge_camera;
+
+/* Opaque scene: the level pointers (borrowed), the switch distances and the
+ * chunk table (owned host copies).  Read-only after creation; one scene may
+ * be used by any number of concurrent frames on distinct workspaces. */
+typedef struct lodge_scene lodge_scene;
+
+#define LODGE_MAX_LEVELS 8
+
+/* Creates a scene of L levels (1 <= L <= LODGE_MAX_LEVELS).  d (host, L-1
+ * values) holds the switch distances d_1 < ... < d_{L-1} of Eq. 2 (d_0 = 0
+ * and d_L = infinity implicitly; d may be NULL when L = 1).  chunks may be
+ * NULL (then only LODGE_SELECT_ALL and LODGE_SELECT_LOD_CAMERA work).
+ * Validates: n >= 0, sum of n < 2^32, d strictly increasing and > 0,
+ * sh_degree in 0..3, non-NULL planes when n > 0, filter3d_var >= 0.
+ * Allocates host memory only.  *out is NULL on failure. */
+lodge_status lodge_scene_create(const lodge_level* levels, int32_t L, const float* d,
+                                const lodge_chunks* chunks, lodge_scene** out);
+void lodge_scene_destroy(lodge_scene* scene);
+/* Total number of Gaussians over all levels (global ids are
+ * id = sum_{j<l} n_j + i for Gaussian i of level l). */
+int64_t lodge_scene_total(const lodge_scene* scene);
+
+/* -------------------------------------------------------------- workspace */
+
+/* Caller-allocated device scratch for one frame in flight, laid out by the
+ * library from these fields.  A workspace serves one image size and is
+ * reused across frames; lodge_render_backward reads what lodge_render left
+ * in it, so a frame's backward must run before the workspace's next render.
+ * Frames on distinct workspaces may run concurrently on distinct streams. */
+typedef struct {
+    void* base;              /* device, >= lodge_workspace_size() bytes, 256-byte aligned */
+    size_t bytes;
+    int32_t width, height;   /* image size this workspace serves */
+    uint32_t max_active;     /* capacity for selected Gaussians (== the selection cap) */
+    uint64_t max_instances;  /* capacity for (Gaussian, tile) instances, < 2^32 */
+} lodge_workspace;
+
+lodge_status lodge_workspace_size(const lodge_scene* scene, int32_t width, int32_t height, uint32_t max_active,
+                                  uint64_t max_instances, size_t* bytes);
+
+/* -------------------------------------------------------------- selection */
+
+enum {
+    LODGE_SELECT_ALL = 0,        /* every Gaussian of every level, weight 1 (plain render) */
+    LODGE_SELECT_LOD_CAMERA = 1, /* Eq. 2 about the camera centre, weight 1 */
+    LODGE_SELECT_CHUNKED = 2     /* Eq. 2 about the two nearest chunk centres (offsets r_k), union
+                                    with the Eq. 4 opacity weights (Sec. 3 "Opacity blending") */
+};
+
+/* Output of lodge_select, device memory owned by the caller:
+ *   ids[cap]  global ids of the active Gaussians, strictly ascending
+ *   w[cap]    opacity weight of each: 1 in both chunk sets, t in the nearest
+ *             chunk's set only, 1 - t in the other's only
+ *   count[1]  number selected (may exceed cap: then only cap entries are
+ *             written, the overflow flag is set and the frame renders the
+ *             first cap entries) */
+typedef struct {
+    uint32_t* ids;
+    float* w;
+    uint32_t* count;
+    uint32_t cap;
+} lodge_selection;
+
+/* ASYNC.  Computes the chunk pair (f, o) and t (Eq. 4; ties go to the lower
+ * chunk index) on the device, then the active set (Eq. 2, with thresholds
+ * d_l + r_k about chunk k's centre; intervals [d_l, d_{l+1}) on squared
+ * FP32 distances).  sel->cap must equal ws->max_active. */
+lodge_status lodge_select(const lodge_scene* scene, const lodge_camera* cam, int32_t mode,
+                          const lodge_workspace* ws, lodge_selection* sel, void* stream);
+
+/* -------------------------------------------------------------- rendering */
+
+typedef struct {
+    float s2d;           /* screen-space filter variance (px^2) added to the 2-D covariance, >= 0 */
+    int32_t compensate;  /* 1: scale opacity by sqrt(det(S')/det(S' + s2d I)) (Mip-Splatting-style 2-D filter) */
+    void* const* stage_events;  /* NULL, or LODGE_STAGE_EVENTS hipEvent_t recorded on the stream before
+                                   projection, binning, sorting and compositing and after compositing */
+} lodge_render_opts;
+#define LODGE_STAGE_EVENTS 5
+
+/* ASYNC.  Renders the selection into caller device buffers:
+ *   image     [3][H][W]  C + T_final * bg
+ *   final_T   [H][W]     transmittance left after the last blended Gaussian
+ *   n_contrib [H][W]     1 + position (in its tile's sorted list) of the last
+ *                        blended Gaussian, 0 if none
+ * Stages: project (Eq. 3 filter, EWA, 2-D filter, SH, 3-sigma tile rect,
+ * depth), per-tile counting, instance emission, per-tile LDS sort on
+ * (depth bits, active index), compositing (Eq. 1; alpha = min(0.99, o G),
+ * entries with alpha < 1/255 skipped, stop before T(1 - alpha) < 1e-4).
+ * opts may be NULL (s2d = 0.3, compensate = 1). */
+lodge_status lodge_render(const lodge_scene* scene, const lodge_selection* sel, const lodge_camera* cam,
+                          const lodge_render_opts* opts, const lodge_workspace* ws, float* image, float* final_T,
+                          uint32_t* n_contrib, void* stream);
+
+/* Per-frame counters kept in the workspace (device) by select + render. */
+typedef struct {
+    uint32_t n_selected;     /* active set size (may exceed the capacity) */
+    uint32_t n_front;        /* selected Gaussians in front of the near plane */
+    uint32_t n_visible;      /* projected Gaussians with a non-empty tile rect */
+    uint32_t max_tile_len;   /* longest per-tile list */
+    uint64_t n_instances;    /* (Gaussian, tile) pairs */
+    uint64_t pairs_evaluated;/* (pixel, list entry) pairs visited before each pixel stopped */
+    uint64_t pairs_blended;  /* pairs that were alpha-blended */
+    uint32_t overflow;       /* bit 0 selection cap, bit 1 instance cap */
+    int32_t f, o;            /* chunk pair (-1 when unused) */
+    float t;                 /* Eq. 4 weight of the nearest chunk */
+    uint32_t n_long;         /* tiles whose list took the 16384-entry LDS sort */
+    uint32_t n_merge;        /* tiles whose list took the chunked merge sort */
+} lodge_frame_info;
+
+/* Synchronises `stream`, then copies the counters of the last frame on ws. */
+lodge_status lodge_frame_info_read(const lodge_workspace* ws, lodge_frame_info* out, void* stream);
+
+/* Synchronises `stream`; returns LODGE_ERR_CAPACITY if the last frame on ws
+ * overflowed a capacity, with the sizes it needed (either pointer may be NULL). */
+lodge_status lodge_check(const lodge_workspace* ws, uint32_t* needed_active, uint64_t* needed_instances,
+                         void* stream);
+
+/* Device views of the last frame's intermediates inside ws (valid until the
+ * next render on ws), for inspection and tests.  Any pointer may be NULL.
+ *   sorted_ids [n_instances]  active index of each instance, tile-major,
+ *                             each tile's run in ascending (depth bits, index)
+ *   tile_ranges[TX*TY][2]     [start, end) of each tile's run
+ *   proj       [max_active][12]  per active index: u, v, conic A, B, C, o_eff,
+ *                             r, g, b, depth, tile rect (x0 | y0 << 16, x1 | y1 << 16
+ *                             as two uint32 bit patterns); rect (0, 0) = culled */
+lodge_status lodge_debug_views(const lodge_workspace* ws, const uint32_t** sorted_ids, const uint32_t** tile_ranges,
+                               const float** proj);
+
+/* ---------------------------------------------------------- differentiation */
+
+/* Gradient planes of one level, device memory, same shapes as the level's
+ * parameters; the backward ADDS into them (the caller zeroes), so a batch of
+ * views accumulates.  Any pointer may be NULL to skip that parameter. */
+typedef struct {
+    float* mean;
+    float* scale;
+    float* quat;
+    float* opacity;
+    float* sh;
+} lodge_grads;
+
+/* ASYNC.  Adjoint of lodge_render for L = sum(dL_dimage * image):
+ * gradients w.r.t. the activated parameters of every selected Gaussian
+ * (grad_level >= 0: only Gaussians of that level, as the per-level
+ * fine-tuning updates G_l alone).  Walks each pixel's list back to front
+ * from n_contrib - 1, recovering the transmittance before each entry by
+ * division T_k = T_{k+1} / (1 - alpha_k) from final_T instead of storing it.
+ * ws must still hold the forward's intermediates (same scene, selection,
+ * camera and options).  grads is an array of L entries. */
+lodge_status lodge_render_backward(const lodge_scene* scene, const lodge_selection* sel, const lodge_camera* cam,
+                                   const lodge_render_opts* opts, const lodge_workspace* ws, const float* final_T,
+                                   const uint32_t* n_contrib, const float* dL_dimage, int32_t grad_level,
+                                   const lodge_grads* grads, void* stream);
+
+/* ASYNC.  3DGS parameter activation for n Gaussians (device planes):
+ * scale = exp(log_scale), quat = q / |q|, opacity = sigmoid(logit).
+ * Output planes have the shapes of the inputs. */
+lodge_status lodge_activate(int64_t n, const float* log_scale, const float* quat_raw, const float* opacity_logit,
+                            float* scale, float* quat, float* opacity, void* stream);
+
+/* ASYNC.  Chain rule through lodge_activate: given the activated values
+ * (scale, quat_raw, opacity) and gradients w.r.t. the activated parameters,
+ * ADDS gradients w.r.t. log_scale, quat_raw and the opacity logit. */
+lodge_status lodge_activate_backward(int64_t n, const float* quat_raw, const float* scale, const float* opacity,
+                                     const float* g_scale, const float* g_quat, const float* g_opacity,
+                                     float* g_log_scale, float* g_quat_raw, float* g_opacity_logit, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LODGE_H */

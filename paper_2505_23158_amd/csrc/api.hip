@@ -1,0 +1,432 @@
+// Host side of the C ABI declared in include/lodge.h: argument validation,
+// the workspace layout, and the per-frame launch sequences.  No call here
+// allocates device memory or synchronises the host except lodge_check and
+// lodge_frame_info_read, which say so.
+#include <string.h>
+
+#include <cmath>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "lodge_internal.hpp"
+
+struct lodge_scene {
+    lodge::LevelsArg levels;
+    lodge::ChunksArg chunks;
+    bool has_chunks;
+};
+
+namespace lodge {
+
+namespace {
+
+thread_local std::string g_last_error;
+
+lodge_status fail(lodge_status s, const std::string& msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+lodge_status hip_fail(hipError_t e, const char* where)
+{
+    return fail(LODGE_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+lodge_status check_ws(const lodge_scene* s, const lodge_workspace* ws)
+{
+    if (!ws || !ws->base) return fail(LODGE_ERR_INVALID_ARG, "workspace is NULL");
+    if (((uintptr_t)ws->base & 255) != 0) return fail(LODGE_ERR_INVALID_ARG, "workspace base not 256-byte aligned");
+    if (ws->width <= 0 || ws->height <= 0 || ws->width > 16384 || ws->height > 16384)
+        return fail(LODGE_ERR_INVALID_ARG, "workspace image size out of range");
+    if (ws->max_instances >= (1ull << 32)) return fail(LODGE_ERR_INVALID_ARG, "max_instances must be < 2^32");
+    if (ws->max_active >= (1u << 31)) return fail(LODGE_ERR_INVALID_ARG, "max_active must be < 2^31");
+    const Layout L = make_layout(s->levels.total, ws->width, ws->height, ws->max_active, ws->max_instances);
+    if (ws->bytes < L.total) return fail(LODGE_ERR_INVALID_ARG, "workspace smaller than lodge_workspace_size()");
+    return LODGE_OK;
+}
+
+lodge_status check_cam(const lodge_camera* c, const lodge_workspace* ws)
+{
+    if (!c) return fail(LODGE_ERR_INVALID_ARG, "camera is NULL");
+    if (ws && (c->width != ws->width || c->height != ws->height))
+        return fail(LODGE_ERR_INVALID_ARG, "camera size differs from the workspace's");
+    const float v[] = {c->fx, c->fy, c->cx, c->cy, c->znear, c->lim_x, c->lim_y};
+    for (float x : v)
+        if (!std::isfinite(x)) return fail(LODGE_ERR_INVALID_ARG, "camera has a non-finite intrinsic");
+    if (!(c->fx > 0) || !(c->fy > 0) || !(c->znear > 0) || !(c->lim_x > 0) || !(c->lim_y > 0))
+        return fail(LODGE_ERR_INVALID_ARG, "camera focal lengths, znear and limits must be > 0");
+    return LODGE_OK;
+}
+
+lodge_status check_sel(const lodge_selection* sel, const lodge_workspace* ws)
+{
+    if (!sel || !sel->ids || !sel->w || !sel->count) return fail(LODGE_ERR_INVALID_ARG, "selection buffers are NULL");
+    if (sel->cap != ws->max_active) return fail(LODGE_ERR_INVALID_ARG, "selection cap != workspace max_active");
+    return LODGE_OK;
+}
+
+}  // namespace
+
+Layout make_layout(uint32_t n_total, int32_t width, int32_t height, uint32_t max_active, uint64_t max_instances)
+{
+    Layout L{};
+    L.TX = (uint32_t)(width + kTile - 1) / kTile;
+    L.TY = (uint32_t)(height + kTile - 1) / kTile;
+    L.T = L.TX * L.TY;
+    L.sel_tiles = std::max<uint32_t>(1, (n_total + kSelTile - 1) / kSelTile);
+    L.scan_tiles = std::max<uint32_t>(1, (max_active + kScanTile - 1) / kScanTile);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t o = off; off += al(bytes); return o; };
+    L.params = take(sizeof(FrameParams));
+    L.info = take(sizeof(FrameInfo));
+    L.scan_flags = take(8ull * L.scan_tiles);
+    L.proj = take(48ull * max_active);
+    L.vis = take(4ull * max_active);
+    L.vtiles = take(4ull * max_active);
+    L.diff = take(4ull * (L.TX + 1) * (L.TY + 1));
+    L.ranges = take(8ull * L.T);
+    L.cursor = take(4ull * L.T);
+    L.order = take(4ull * L.T);
+    L.large = take(8ull * L.T);
+    L.sorted = take(4ull * max_instances);
+    L.temp = take(8ull * max_instances);
+    L.g2d = take(48ull * max_active);
+    L.sel_flags = take(8ull * L.sel_tiles);   // last: the only region whose size depends on the scene
+    L.total = off;
+    return L;
+}
+
+Views views_of(const lodge_workspace* ws, uint32_t n_total)
+{
+    Views v{};
+    v.lay = make_layout(n_total, ws->width, ws->height, ws->max_active, ws->max_instances);
+    char* b = static_cast<char*>(ws->base);
+    v.params = reinterpret_cast<FrameParams*>(b + v.lay.params);
+    v.info = reinterpret_cast<FrameInfo*>(b + v.lay.info);
+    v.sel_flags = reinterpret_cast<unsigned long long*>(b + v.lay.sel_flags);
+    v.scan_flags = reinterpret_cast<unsigned long long*>(b + v.lay.scan_flags);
+    v.proj = reinterpret_cast<float4*>(b + v.lay.proj);
+    v.vis = reinterpret_cast<uint32_t*>(b + v.lay.vis);
+    v.vtiles = reinterpret_cast<uint32_t*>(b + v.lay.vtiles);
+    v.diff = reinterpret_cast<int32_t*>(b + v.lay.diff);
+    v.ranges = reinterpret_cast<uint2*>(b + v.lay.ranges);
+    v.cursor = reinterpret_cast<uint32_t*>(b + v.lay.cursor);
+    v.order = reinterpret_cast<uint32_t*>(b + v.lay.order);
+    v.large = reinterpret_cast<uint32_t*>(b + v.lay.large);
+    v.sorted = reinterpret_cast<uint32_t*>(b + v.lay.sorted);
+    v.temp = reinterpret_cast<unsigned long long*>(b + v.lay.temp);
+    v.g2d = reinterpret_cast<float*>(b + v.lay.g2d);
+    v.max_active = ws->max_active;
+    v.max_instances = ws->max_instances;
+    return v;
+}
+
+// Clears the render counters, the difference grid and the scan flags, and
+// records the options; one small kernel so a captured graph holds no memset.
+namespace {
+__global__ void k_render_setup(FrameParams* fp, FrameInfo* info, int32_t* diff, uint32_t ndiff,
+                               unsigned long long* flags, uint32_t nflags, float s2d, int32_t compensate, int32_t TX,
+                               int32_t TY)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+    for (uint32_t k = i; k < ndiff; k += stride) diff[k] = 0;
+    for (uint32_t k = i; k < nflags; k += stride) flags[k] = 0ull;
+    if (i == 0) {
+        fp->s2d = s2d;
+        fp->compensate = compensate;
+        fp->TX = TX;
+        fp->TY = TY;
+        info->n_front = 0;
+        info->n_visible = 0;
+        info->n_instances = 0;
+        info->pairs_evaluated = 0;
+        info->pairs_blended = 0;
+        info->max_tile_len = 0;
+        info->overflow &= kOvfSelect;
+        info->n_large = 0;
+        info->n_huge = 0;
+        info->scan_ticket = 0;
+    }
+}
+}  // namespace
+
+hipError_t launch_render_setup(const lodge_render_opts& o, const Views& v, hipStream_t st)
+{
+    const uint32_t ndiff = (v.lay.TX + 1) * (v.lay.TY + 1);
+    const uint32_t n = std::max(ndiff, v.lay.scan_tiles);
+    uint32_t blocks = std::min<uint32_t>(256, (n + 255) / 256);
+    k_render_setup<<<std::max<uint32_t>(blocks, 1), 256, 0, st>>>(v.params, v.info, v.diff, ndiff, v.scan_flags,
+                                                                   v.lay.scan_tiles, o.s2d, o.compensate,
+                                                                   (int32_t)v.lay.TX, (int32_t)v.lay.TY);
+    return hipGetLastError();
+}
+
+}  // namespace lodge
+
+using namespace lodge;
+
+extern "C" {
+
+const char* lodge_status_string(lodge_status s)
+{
+    switch (s) {
+    case LODGE_OK: return "ok";
+    case LODGE_ERR_INVALID_ARG: return "invalid argument";
+    case LODGE_ERR_CAPACITY: return "capacity exceeded";
+    case LODGE_ERR_HIP: return "HIP runtime error";
+    case LODGE_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* lodge_last_error(void) { return g_last_error.c_str(); }
+
+const char* lodge_version(void) { return "lodge-gfx950 0.1"; }
+
+lodge_status lodge_scene_create(const lodge_level* levels, int32_t L, const float* d, const lodge_chunks* chunks,
+                                lodge_scene** out)
+{
+    if (!out) return fail(LODGE_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!levels || L < 1 || L > LODGE_MAX_LEVELS) return fail(LODGE_ERR_INVALID_ARG, "need 1..8 levels");
+    if (L > 1 && !d) return fail(LODGE_ERR_INVALID_ARG, "switch distances are NULL");
+    lodge_scene* s = new lodge_scene();
+    memset(s, 0, sizeof(*s));
+    uint64_t total = 0;
+    for (int l = 0; l < L; l++) {
+        const lodge_level& v = levels[l];
+        if (v.n < 0) { delete s; return fail(LODGE_ERR_INVALID_ARG, "negative level size"); }
+        if (v.sh_degree < 0 || v.sh_degree > 3) { delete s; return fail(LODGE_ERR_INVALID_ARG, "sh_degree must be 0..3"); }
+        if (!(v.filter3d_var >= 0.0f) || !std::isfinite(v.filter3d_var)) {
+            delete s;
+            return fail(LODGE_ERR_INVALID_ARG, "filter3d_var must be finite and >= 0");
+        }
+        if (v.n > 0 && (!v.mean || !v.scale || !v.quat || !v.opacity || !v.sh)) {
+            delete s;
+            return fail(LODGE_ERR_INVALID_ARG, "level has a NULL parameter plane");
+        }
+        LevelDev& dv = s->levels.lv[l];
+        dv.mean = v.mean; dv.scale = v.scale; dv.quat = v.quat; dv.opacity = v.opacity; dv.sh = v.sh;
+        dv.n = (uint32_t)v.n;
+        dv.base = (uint32_t)total;
+        dv.sh_degree = v.sh_degree;
+        dv.var = v.filter3d_var;
+        total += (uint64_t)v.n;
+        if (total >= (1ull << 32)) { delete s; return fail(LODGE_ERR_INVALID_ARG, "more than 2^32 - 1 Gaussians"); }
+    }
+    // unused level slots never match: base beyond every id
+    for (int l = L; l < LODGE_MAX_LEVELS; l++) s->levels.lv[l].base = 0xffffffffu;
+    for (int l = 0; l + 1 < L; l++) {
+        if (!(d[l] > 0.0f) || !std::isfinite(d[l]) || (l > 0 && !(d[l] > d[l - 1]))) {
+            delete s;
+            return fail(LODGE_ERR_INVALID_ARG, "switch distances must be finite, > 0 and strictly increasing");
+        }
+        s->levels.d[l] = d[l];
+    }
+    s->levels.L = L;
+    s->levels.total = (uint32_t)total;
+    if (chunks) {
+        if (chunks->k < 1 || chunks->k > LODGE_MAX_CHUNKS || !chunks->center || !chunks->offset) {
+            delete s;
+            return fail(LODGE_ERR_INVALID_ARG, "chunks: need 1..128 centres and offsets");
+        }
+        s->chunks.K = chunks->k;
+        s->chunks.band = chunks->band;
+        for (int k = 0; k < chunks->k; k++) {
+            for (int j = 0; j < 3; j++) s->chunks.c[k][j] = chunks->center[3 * k + j];
+            s->chunks.r[k] = chunks->offset[k];
+            if (!std::isfinite(s->chunks.r[k]) || s->chunks.r[k] < 0.0f) {
+                delete s;
+                return fail(LODGE_ERR_INVALID_ARG, "chunk offsets must be finite and >= 0");
+            }
+        }
+        s->has_chunks = true;
+    }
+    *out = s;
+    return LODGE_OK;
+}
+
+void lodge_scene_destroy(lodge_scene* scene) { delete scene; }
+
+int64_t lodge_scene_total(const lodge_scene* scene) { return scene ? (int64_t)scene->levels.total : -1; }
+
+lodge_status lodge_workspace_size(const lodge_scene* scene, int32_t width, int32_t height, uint32_t max_active,
+                                  uint64_t max_instances, size_t* bytes)
+{
+    if (!scene || !bytes) return fail(LODGE_ERR_INVALID_ARG, "scene or bytes is NULL");
+    if (width <= 0 || height <= 0 || width > 16384 || height > 16384)
+        return fail(LODGE_ERR_INVALID_ARG, "image size out of range");
+    if (max_instances >= (1ull << 32)) return fail(LODGE_ERR_INVALID_ARG, "max_instances must be < 2^32");
+    if (max_active >= (1u << 31)) return fail(LODGE_ERR_INVALID_ARG, "max_active must be < 2^31");
+    *bytes = make_layout(scene->levels.total, width, height, max_active, max_instances).total;
+    return LODGE_OK;
+}
+
+lodge_status lodge_select(const lodge_scene* scene, const lodge_camera* cam, int32_t mode, const lodge_workspace* ws,
+                          lodge_selection* sel, void* stream)
+{
+    if (!scene) return fail(LODGE_ERR_INVALID_ARG, "scene is NULL");
+    lodge_status s;
+    if ((s = check_ws(scene, ws)) != LODGE_OK) return s;
+    if ((s = check_cam(cam, nullptr)) != LODGE_OK) return s;
+    if ((s = check_sel(sel, ws)) != LODGE_OK) return s;
+    if (mode < LODGE_SELECT_ALL || mode > LODGE_SELECT_CHUNKED) return fail(LODGE_ERR_INVALID_ARG, "unknown mode");
+    if (mode == LODGE_SELECT_CHUNKED && !scene->has_chunks)
+        return fail(LODGE_ERR_INVALID_ARG, "chunked selection on a scene without chunks");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Views v = views_of(ws, scene->levels.total);
+    hipError_t e = hipMemcpyAsync(&v.params->cam, cam, sizeof(lodge_camera), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "lodge_select: camera upload");
+    if ((e = launch_select_setup(scene->levels, scene->chunks, mode, v, st)) != hipSuccess)
+        return hip_fail(e, "lodge_select: setup");
+    if ((e = launch_select(scene->levels, v, *sel, st)) != hipSuccess) return hip_fail(e, "lodge_select");
+    return LODGE_OK;
+}
+
+lodge_status lodge_render(const lodge_scene* scene, const lodge_selection* sel, const lodge_camera* cam,
+                          const lodge_render_opts* opts, const lodge_workspace* ws, float* image, float* final_T,
+                          uint32_t* n_contrib, void* stream)
+{
+    if (!scene) return fail(LODGE_ERR_INVALID_ARG, "scene is NULL");
+    lodge_status s;
+    if ((s = check_ws(scene, ws)) != LODGE_OK) return s;
+    if ((s = check_cam(cam, ws)) != LODGE_OK) return s;
+    if ((s = check_sel(sel, ws)) != LODGE_OK) return s;
+    if (!image || !final_T || !n_contrib) return fail(LODGE_ERR_INVALID_ARG, "output buffers are NULL");
+    lodge_render_opts o{0.3f, 1, nullptr};
+    if (opts) o = *opts;
+    if (!(o.s2d >= 0.0f) || !std::isfinite(o.s2d)) return fail(LODGE_ERR_INVALID_ARG, "s2d must be finite and >= 0");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Views v = views_of(ws, scene->levels.total);
+    hipError_t e = hipMemcpyAsync(&v.params->cam, cam, sizeof(lodge_camera), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "lodge_render: camera upload");
+    auto mark = [&](int k) -> hipError_t {
+        return o.stage_events ? hipEventRecord(static_cast<hipEvent_t>(o.stage_events[k]), st) : hipSuccess;
+    };
+    if ((e = launch_render_setup(o, v, st)) != hipSuccess) return hip_fail(e, "lodge_render: setup");
+    if ((e = mark(0)) != hipSuccess) return hip_fail(e, "lodge_render: event");
+    if ((e = launch_project(scene->levels, *sel, v, st)) != hipSuccess) return hip_fail(e, "lodge_render: project");
+    if ((e = mark(1)) != hipSuccess) return hip_fail(e, "lodge_render: event");
+    if ((e = launch_bin(v, st)) != hipSuccess) return hip_fail(e, "lodge_render: bin");
+    if ((e = mark(2)) != hipSuccess) return hip_fail(e, "lodge_render: event");
+    if ((e = launch_sort(v, st)) != hipSuccess) return hip_fail(e, "lodge_render: sort");
+    if ((e = mark(3)) != hipSuccess) return hip_fail(e, "lodge_render: event");
+    if ((e = launch_composite(v, image, final_T, n_contrib, st)) != hipSuccess)
+        return hip_fail(e, "lodge_render: composite");
+    if ((e = mark(4)) != hipSuccess) return hip_fail(e, "lodge_render: event");
+    return LODGE_OK;
+}
+
+lodge_status lodge_frame_info_read(const lodge_workspace* ws, lodge_frame_info* out, void* stream)
+{
+    if (!ws || !ws->base || !out) return fail(LODGE_ERR_INVALID_ARG, "workspace or out is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "lodge_frame_info_read: sync");
+    FrameInfo fi;
+    // the info block sits right after the params block
+    const size_t off = al(sizeof(FrameParams));
+    e = hipMemcpy(&fi, static_cast<const char*>(ws->base) + off, sizeof(fi), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "lodge_frame_info_read: copy");
+    out->n_selected = fi.n_selected;
+    out->n_front = fi.n_front;
+    out->n_visible = fi.n_visible;
+    out->max_tile_len = fi.max_tile_len;
+    out->n_instances = fi.n_instances;
+    out->pairs_evaluated = fi.pairs_evaluated;
+    out->pairs_blended = fi.pairs_blended;
+    out->overflow = fi.overflow;
+    out->f = fi.f;
+    out->o = fi.o;
+    out->t = fi.t;
+    out->n_long = fi.n_large;
+    out->n_merge = fi.n_huge;
+    return LODGE_OK;
+}
+
+lodge_status lodge_check(const lodge_workspace* ws, uint32_t* needed_active, uint64_t* needed_instances, void* stream)
+{
+    lodge_frame_info fi;
+    lodge_status s = lodge_frame_info_read(ws, &fi, stream);
+    if (s != LODGE_OK) return s;
+    if (needed_active) *needed_active = fi.n_selected;
+    if (needed_instances) *needed_instances = fi.n_instances;
+    if (fi.overflow & (kOvfSelect | kOvfInstances)) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "capacity exceeded: selected %u (cap %u), instances %llu (cap %llu)", fi.n_selected,
+                 ws->max_active, (unsigned long long)fi.n_instances, (unsigned long long)ws->max_instances);
+        return fail(LODGE_ERR_CAPACITY, buf);
+    }
+    return LODGE_OK;
+}
+
+lodge_status lodge_debug_views(const lodge_workspace* ws, const uint32_t** sorted_ids, const uint32_t** tile_ranges,
+                               const float** proj)
+{
+    if (!ws || !ws->base) return fail(LODGE_ERR_INVALID_ARG, "workspace is NULL");
+    // every region but the trailing selection flags is independent of the scene size
+    const Views v = views_of(ws, 0);
+    if (sorted_ids) *sorted_ids = v.sorted;
+    if (tile_ranges) *tile_ranges = reinterpret_cast<const uint32_t*>(v.ranges);
+    if (proj) *proj = reinterpret_cast<const float*>(v.proj);
+    return LODGE_OK;
+}
+
+lodge_status lodge_render_backward(const lodge_scene* scene, const lodge_selection* sel, const lodge_camera* cam,
+                                   const lodge_render_opts* opts, const lodge_workspace* ws, const float* final_T,
+                                   const uint32_t* n_contrib, const float* dL_dimage, int32_t grad_level,
+                                   const lodge_grads* grads, void* stream)
+{
+    if (!scene) return fail(LODGE_ERR_INVALID_ARG, "scene is NULL");
+    lodge_status s;
+    if ((s = check_ws(scene, ws)) != LODGE_OK) return s;
+    if ((s = check_cam(cam, ws)) != LODGE_OK) return s;
+    if ((s = check_sel(sel, ws)) != LODGE_OK) return s;
+    if (!final_T || !n_contrib || !dL_dimage || !grads)
+        return fail(LODGE_ERR_INVALID_ARG, "final_T, n_contrib, dL_dimage and grads must be non-NULL");
+    if (grad_level < -1 || grad_level >= scene->levels.L) return fail(LODGE_ERR_INVALID_ARG, "grad_level out of range");
+    lodge_render_opts o{0.3f, 1, nullptr};
+    if (opts) o = *opts;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Views v = views_of(ws, scene->levels.total);
+    // the forward's options and camera are in ws; refresh them in case the caller changed nothing else
+    hipError_t e = hipMemcpyAsync(&v.params->cam, cam, sizeof(lodge_camera), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "lodge_render_backward: camera upload");
+    if ((e = launch_backward(scene->levels, *sel, v, final_T, n_contrib, dL_dimage, grad_level, grads, st)) !=
+        hipSuccess)
+        return hip_fail(e, "lodge_render_backward");
+    return LODGE_OK;
+}
+
+lodge_status lodge_activate(int64_t n, const float* log_scale, const float* quat_raw, const float* opacity_logit,
+                            float* scale, float* quat, float* opacity, void* stream)
+{
+    if (n < 0) return fail(LODGE_ERR_INVALID_ARG, "n < 0");
+    if (n == 0) return LODGE_OK;
+    if (!log_scale || !quat_raw || !opacity_logit || !scale || !quat || !opacity)
+        return fail(LODGE_ERR_INVALID_ARG, "activate: NULL plane");
+    const hipError_t e = launch_activate(n, log_scale, quat_raw, opacity_logit, scale, quat, opacity,
+                                         static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LODGE_OK : hip_fail(e, "lodge_activate");
+}
+
+lodge_status lodge_activate_backward(int64_t n, const float* quat_raw, const float* scale, const float* opacity,
+                                     const float* g_scale, const float* g_quat, const float* g_opacity,
+                                     float* g_log_scale, float* g_quat_raw, float* g_opacity_logit, void* stream)
+{
+    if (n < 0) return fail(LODGE_ERR_INVALID_ARG, "n < 0");
+    if (n == 0) return LODGE_OK;
+    if ((g_scale && (!scale || !g_log_scale)) || (g_quat && (!quat_raw || !g_quat_raw)) ||
+        (g_opacity && (!opacity || !g_opacity_logit)))
+        return fail(LODGE_ERR_INVALID_ARG, "activate_backward: a gradient is given without its inputs/outputs");
+    const hipError_t e = launch_activate_backward(n, quat_raw, scale, opacity, g_scale, g_quat, g_opacity,
+                                                  g_log_scale, g_quat_raw, g_opacity_logit,
+                                                  static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LODGE_OK : hip_fail(e, "lodge_activate_backward");
+}
+
+}  // extern "C"

@@ -1,0 +1,422 @@
+// Adjoint of lodge_render (the rasterizer's backward pass used by the
+// per-level fine-tuning of the paper's supplementary "LOD structure
+// optimization steps": only the parameters of G_l are updated).
+//
+// k_bwd_setup      zero the per-active 2-D gradient records.
+// k_composite_bwd  one 256-thread block per tile, one pixel per thread,
+//                  walking the tile's sorted run back to front from the
+//                  largest n_contrib of the tile.  The transmittance before
+//                  entry k is recovered from the stored final T by division,
+//                  T_k = T_{k+1} / (1 - alpha_k), rather than stored per pair.
+//                  With S_k the colour behind entry k (plus T_final * bg):
+//                    dC/dc_k = alpha_k T_k,  dC/dalpha_k = c_k T_k - S_k / (1 - alpha_k).
+//                  Per entry the 256 pixels' gradients are summed with wave
+//                  reductions (only in waves where some pixel contributed)
+//                  and one atomic add per wave.
+// k_project_bwd    one thread per visible active Gaussian: the chain rule from
+//                  (u, v, conic, o_eff, rgb) back through the 2-D filter, the
+//                  EWA covariance, the camera and the Eq. 3 filter to the
+//                  activated parameters; each Gaussian occurs once per frame,
+//                  so its gradient is added without atomics.
+#include "lodge_internal.hpp"
+#include "splat.hpp"
+
+namespace lodge {
+
+namespace {
+
+constexpr int kBatch = 256;
+constexpr int kG2 = 12;   // floats per 2-D gradient record: u, v, A, B, C, o, r, g, b (+3 pad)
+
+__global__ void k_bwd_setup(float* __restrict__ g2d, const uint32_t* __restrict__ count, uint32_t cap)
+{
+    const uint32_t n = min(*count, cap) * (uint32_t)kG2;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) g2d[i] = 0.0f;
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_composite_bwd(const FrameParams* __restrict__ fp,
+                                                       const uint2* __restrict__ ranges,
+                                                       const uint32_t* __restrict__ sorted,
+                                                       const float4* __restrict__ proj,
+                                                       const float* __restrict__ final_T,
+                                                       const uint32_t* __restrict__ n_contrib,
+                                                       const float* __restrict__ dL, float* __restrict__ g2d,
+                                                       uint32_t cap)
+{
+    __shared__ float4 s_geo[kBatch];
+    __shared__ float4 s_col[kBatch];
+    __shared__ float2 s_gb[kBatch];
+    __shared__ uint32_t s_a[kBatch];
+    __shared__ uint32_t s_max;
+
+    const int32_t W = fp->cam.width, H = fp->cam.height, TX = fp->TX;
+    const uint32_t tile = blockIdx.x;
+    const uint32_t tx = tile % (uint32_t)TX, ty = tile / (uint32_t)TX;
+    const uint32_t x = tx * kTile + (threadIdx.x & 15), y = ty * kTile + (threadIdx.x >> 4);
+    const bool inside = (int32_t)x < W && (int32_t)y < H;
+    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+    const uint2 rg = ranges[tile];
+    const uint32_t lane = threadIdx.x & 63;
+
+    const size_t HW = (size_t)W * H, p = (size_t)y * W + x;
+    uint32_t last = 0;
+    float T = 1.0f, dC0 = 0.0f, dC1 = 0.0f, dC2 = 0.0f;
+    if (inside) {
+        last = n_contrib[p];
+        T = final_T[p];
+        dC0 = dL[p];
+        dC1 = dL[HW + p];
+        dC2 = dL[2 * HW + p];
+    }
+    const float* bg = fp->cam.bg;
+    float S0 = T * bg[0], S1 = T * bg[1], S2 = T * bg[2];   // colour behind the current entry
+
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
+    atomicMax(&s_max, last);
+    __syncthreads();
+    const uint32_t end = min(s_max, rg.y - rg.x);
+
+    for (uint32_t e = end; e > 0;) {
+        const uint32_t b0 = e > (uint32_t)kBatch ? e - kBatch : 0u;
+        const uint32_t nb = e - b0;
+        if (threadIdx.x < nb) {
+            uint32_t a = sorted[rg.x + b0 + threadIdx.x];
+            a = a < cap ? a : 0u;
+            s_a[threadIdx.x] = a;
+            stage_splat(proj, a, s_geo[threadIdx.x], s_col[threadIdx.x], s_gb[threadIdx.x]);
+        }
+        __syncthreads();
+        for (int j = (int)nb - 1; j >= 0; j--) {
+            const uint32_t k = b0 + (uint32_t)j;
+            float g[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            bool contrib = false;
+            if (k < last) {
+                const float4 geo = s_geo[j];
+                const float4 col = s_col[j];
+                float dx, dy, G;
+                bool clamped = false;
+                const float alpha = splat_alpha(geo, col, px, py, dx, dy, G, clamped);
+                if (alpha >= 0.0f) {
+                    contrib = true;
+                    const float om = 1.0f - alpha;
+                    T = T / om;                       // transmittance before this entry
+                    const float2 gb = s_gb[j];
+                    const float c0 = col.w, c1 = gb.x, c2 = gb.y;
+                    const float wgt = alpha * T;
+                    g[6] = wgt * dC0;
+                    g[7] = wgt * dC1;
+                    g[8] = wgt * dC2;
+                    const float dalpha = dC0 * (c0 * T - S0 / om) + dC1 * (c1 * T - S1 / om) +
+                                         dC2 * (c2 * T - S2 / om);
+                    S0 += c0 * wgt;
+                    S1 += c1 * wgt;
+                    S2 += c2 * wgt;
+                    if (!clamped) {
+                        const float o = col.y;
+                        g[5] = dalpha * G;
+                        const float dpow = dalpha * o * G;
+                        // power = -A/2 dx^2 - C/2 dy^2 - B dx dy, staged as geo.z = -A/2, geo.w = -B, col.x = -C/2
+                        const float A = -2.0f * geo.z, B = -geo.w, C = -2.0f * col.x;
+                        g[2] = -0.5f * dx * dx * dpow;
+                        g[3] = -dx * dy * dpow;
+                        g[4] = -0.5f * dy * dy * dpow;
+                        g[0] = (-A * dx - B * dy) * dpow;
+                        g[1] = (-C * dy - B * dx) * dpow;
+                    }
+                }
+            }
+            if (__ballot(contrib) != 0ull) {
+                float* dst = g2d + (size_t)s_a[j] * kG2;
+#pragma unroll
+                for (int q = 0; q < 9; q++) {
+                    const float sum = wave_sum(g[q]);
+                    if (lane == 0 && sum != 0.0f) atomicAdd(dst + q, sum);
+                }
+            }
+        }
+        __syncthreads();
+        e = b0;
+    }
+}
+
+// Real SH basis to degree 3 (same convention as the projection kernel) and
+// its derivatives with respect to the (unnormalised) direction components.
+constexpr float kC0 = 0.28209479177387814f;
+constexpr float kC1 = 0.4886025119029199f;
+constexpr float kC2a = 1.0925484305920792f;
+constexpr float kC2b = 0.31539156525252005f;
+constexpr float kC2c = 0.5462742152960396f;
+constexpr float kC3a = 0.5900435899266435f;
+constexpr float kC3b = 2.890611442640554f;
+constexpr float kC3c = 0.4570457994644658f;
+constexpr float kC3d = 0.3731763325901154f;
+constexpr float kC3e = 1.445305721320277f;
+
+__device__ __forceinline__ void sh_basis_grad(float x, float y, float z, float* Y, float (*dY)[3])
+{
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[0] = kC0;                                   dY[0][0] = 0; dY[0][1] = 0; dY[0][2] = 0;
+    Y[1] = -kC1 * y;                              dY[1][0] = 0; dY[1][1] = -kC1; dY[1][2] = 0;
+    Y[2] = kC1 * z;                               dY[2][0] = 0; dY[2][1] = 0; dY[2][2] = kC1;
+    Y[3] = -kC1 * x;                              dY[3][0] = -kC1; dY[3][1] = 0; dY[3][2] = 0;
+    Y[4] = kC2a * x * y;                          dY[4][0] = kC2a * y; dY[4][1] = kC2a * x; dY[4][2] = 0;
+    Y[5] = -kC2a * y * z;                         dY[5][0] = 0; dY[5][1] = -kC2a * z; dY[5][2] = -kC2a * y;
+    Y[6] = kC2b * (2.0f * zz - xx - yy);          dY[6][0] = -2.0f * kC2b * x; dY[6][1] = -2.0f * kC2b * y;
+                                                  dY[6][2] = 4.0f * kC2b * z;
+    Y[7] = -kC2a * x * z;                         dY[7][0] = -kC2a * z; dY[7][1] = 0; dY[7][2] = -kC2a * x;
+    Y[8] = kC2c * (xx - yy);                      dY[8][0] = 2.0f * kC2c * x; dY[8][1] = -2.0f * kC2c * y; dY[8][2] = 0;
+    Y[9] = -kC3a * y * (3.0f * xx - yy);          dY[9][0] = -6.0f * kC3a * x * y;
+                                                  dY[9][1] = -3.0f * kC3a * (xx - yy); dY[9][2] = 0;
+    Y[10] = kC3b * x * y * z;                     dY[10][0] = kC3b * y * z; dY[10][1] = kC3b * x * z;
+                                                  dY[10][2] = kC3b * x * y;
+    Y[11] = -kC3c * y * (4.0f * zz - xx - yy);    dY[11][0] = 2.0f * kC3c * x * y;
+                                                  dY[11][1] = -kC3c * (4.0f * zz - xx - 3.0f * yy);
+                                                  dY[11][2] = -8.0f * kC3c * y * z;
+    Y[12] = kC3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+                                                  dY[12][0] = -6.0f * kC3d * x * z; dY[12][1] = -6.0f * kC3d * y * z;
+                                                  dY[12][2] = kC3d * (6.0f * zz - 3.0f * xx - 3.0f * yy);
+    Y[13] = -kC3c * x * (4.0f * zz - xx - yy);    dY[13][0] = -kC3c * (4.0f * zz - 3.0f * xx - yy);
+                                                  dY[13][1] = 2.0f * kC3c * x * y; dY[13][2] = -8.0f * kC3c * x * z;
+    Y[14] = kC3e * z * (xx - yy);                 dY[14][0] = 2.0f * kC3e * x * z; dY[14][1] = -2.0f * kC3e * y * z;
+                                                  dY[14][2] = kC3e * (xx - yy);
+    Y[15] = -kC3a * x * (xx - 3.0f * yy);         dY[15][0] = -3.0f * kC3a * (xx - yy);
+                                                  dY[15][1] = 6.0f * kC3a * x * y; dY[15][2] = 0;
+}
+
+struct GradsArg {
+    lodge_grads g[LODGE_MAX_LEVELS];
+};
+
+__global__ __launch_bounds__(256) void k_project_bwd(LevelsArg lv, GradsArg ga, int32_t grad_level,
+                                                     const uint32_t* __restrict__ ids, const float* __restrict__ wsel,
+                                                     const uint32_t* __restrict__ count, uint32_t cap,
+                                                     const FrameParams* __restrict__ fp,
+                                                     const float4* __restrict__ proj, const float* __restrict__ g2d)
+{
+    const uint32_t n_act = min(*count, cap);
+    const lodge_camera& cam = fp->cam;
+    const float s2d = fp->s2d;
+    const int compensate = fp->compensate;
+    for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < n_act; a += gridDim.x * blockDim.x) {
+        const float4 r2 = proj[3 * (size_t)a + 2];
+        const uint32_t p0 = __float_as_uint(r2.z), p1 = __float_as_uint(r2.w);
+        if ((p1 & 0xffffu) <= (p0 & 0xffffu)) continue;   // culled: empty rectangle
+        const uint32_t gid = ids[a];
+        int l = 0;
+#pragma unroll
+        for (int j = 1; j < LODGE_MAX_LEVELS; j++)
+            if (j < lv.L && gid >= lv.lv[j].base) l = j;
+        if (grad_level >= 0 && l != grad_level) continue;
+        const LevelDev& L = lv.lv[l];
+        const lodge_grads& G = ga.g[l];
+        const size_t n = L.n;
+        const uint32_t i = gid - L.base;
+        const float* g = g2d + (size_t)a * kG2;
+        const float gu = g[0], gv = g[1], gA = g[2], gB = g[3], gC = g[4], go_eff = g[5];
+        const float grgb[3] = {g[6], g[7], g[8]};
+
+        // ---- forward recomputation (as in the projection kernel)
+        const float mx = L.mean[i], my = L.mean[n + i], mz = L.mean[2 * n + i];
+        const float s[3] = {L.scale[i], L.scale[n + i], L.scale[2 * n + i]};
+        const float qw = L.quat[i], qx = L.quat[n + i], qy = L.quat[2 * n + i], qz = L.quat[3 * n + i];
+        const float op = L.opacity[i], w = wsel[a], var = L.var;
+        const float* Wc = cam.R;
+        const float tx = ((Wc[0] * mx + Wc[1] * my) + Wc[2] * mz) + cam.t[0];
+        const float ty = ((Wc[3] * mx + Wc[4] * my) + Wc[5] * mz) + cam.t[1];
+        const float tz = ((Wc[6] * mx + Wc[7] * my) + Wc[8] * mz) + cam.t[2];
+        const float xx = qx * qx, yy = qy * qy, zz = qz * qz;
+        const float xy = qx * qy, xz = qx * qz, yz = qy * qz;
+        const float wx = qw * qx, wy = qw * qy, wz = qw * qz;
+        const float R[9] = {1.0f - 2.0f * (yy + zz), 2.0f * (xy - wz),        2.0f * (xz + wy),
+                            2.0f * (xy + wz),        1.0f - 2.0f * (xx + zz), 2.0f * (yz - wx),
+                            2.0f * (xz - wy),        2.0f * (yz + wx),        1.0f - 2.0f * (xx + yy)};
+        const float v[3] = {s[0] * s[0] + var, s[1] * s[1] + var, s[2] * s[2] + var};
+        float S[9];
+        for (int p = 0; p < 3; p++)
+            for (int q = p; q < 3; q++) {
+                const float e = ((R[3 * p] * v[0]) * R[3 * q] + (R[3 * p + 1] * v[1]) * R[3 * q + 1])
+                                + (R[3 * p + 2] * v[2]) * R[3 * q + 2];
+                S[3 * p + q] = e;
+                S[3 * q + p] = e;
+            }
+        const float comp3 = sqrtf(((s[0] * s[0] / v[0]) * (s[1] * s[1] / v[1])) * (s[2] * s[2] / v[2]));
+        const float ix = tx / tz, iy = ty / tz;
+        float rx = ix, ry = iy;
+        bool clx = false, cly = false;
+        if (rx < -cam.lim_x) { rx = -cam.lim_x; clx = true; }
+        if (rx > cam.lim_x) { rx = cam.lim_x; clx = true; }
+        if (ry < -cam.lim_y) { ry = -cam.lim_y; cly = true; }
+        if (ry > cam.lim_y) { ry = cam.lim_y; cly = true; }
+        const float J00 = cam.fx / tz, J02 = -((cam.fx * rx) / tz);
+        const float J11 = cam.fy / tz, J12 = -((cam.fy * ry) / tz);
+        float M[6];
+        for (int j = 0; j < 3; j++) {
+            M[j] = J00 * Wc[j] + J02 * Wc[6 + j];
+            M[3 + j] = J11 * Wc[3 + j] + J12 * Wc[6 + j];
+        }
+        float T6[6];
+        for (int r = 0; r < 2; r++)
+            for (int j = 0; j < 3; j++)
+                T6[3 * r + j] = (M[3 * r] * S[j] + M[3 * r + 1] * S[3 + j]) + M[3 * r + 2] * S[6 + j];
+        const float a0 = (T6[0] * M[0] + T6[1] * M[1]) + T6[2] * M[2];
+        const float b = (T6[0] * M[3] + T6[1] * M[4]) + T6[2] * M[5];
+        const float c0 = (T6[3] * M[3] + T6[4] * M[4]) + T6[5] * M[5];
+        const float aa = a0 + s2d, cc = c0 + s2d;
+        const float det0 = a0 * c0 - b * b;
+        const float det = aa * cc - b * b;
+        const float comp2 = compensate ? sqrtf((det0 > 0.0f ? det0 : 0.0f) / det) : 1.0f;
+
+        float dmu[3] = {0.0f, 0.0f, 0.0f};
+
+        // ---- colour: rgb = max(0, sum_k sh_k Y_k(dir) + 1/2), dir = (mu - pos) / |mu - pos|
+        const float d0 = mx - cam.pos[0], d1 = my - cam.pos[1], d2 = mz - cam.pos[2];
+        const float dn = sqrtf((d0 * d0 + d1 * d1) + d2 * d2);
+        const float ux = d0 / dn, uy = d1 / dn, uz = d2 / dn;
+        float Y[kMaxSh], dY[kMaxSh][3];
+        sh_basis_grad(ux, uy, uz, Y, dY);
+        const int nb = (L.sh_degree + 1) * (L.sh_degree + 1);
+        float ddir[3] = {0.0f, 0.0f, 0.0f};
+        for (int ch = 0; ch < 3; ch++) {
+            float acc = 0.0f;
+            for (int k = 0; k < nb; k++) acc = acc + L.sh[((size_t)(k * 3 + ch)) * n + i] * Y[k];
+            if (!(acc + 0.5f > 0.0f) || grgb[ch] == 0.0f) continue;
+            for (int k = 0; k < nb; k++) {
+                const size_t idx = ((size_t)(k * 3 + ch)) * n + i;
+                if (G.sh) G.sh[idx] += grgb[ch] * Y[k];
+                const float c = grgb[ch] * L.sh[idx];
+                ddir[0] += c * dY[k][0];
+                ddir[1] += c * dY[k][1];
+                ddir[2] += c * dY[k][2];
+            }
+        }
+        const float dot = ddir[0] * ux + ddir[1] * uy + ddir[2] * uz;
+        dmu[0] += (ddir[0] - ux * dot) / dn;
+        dmu[1] += (ddir[1] - uy * dot) / dn;
+        dmu[2] += (ddir[2] - uz * dot) / dn;
+
+        // ---- opacity: o_eff = o w comp3 comp2
+        if (G.opacity) G.opacity[i] += go_eff * w * comp3 * comp2;
+        const float dcomp3 = go_eff * op * w * comp2;
+        const float dcomp2 = go_eff * op * w * comp3;
+
+        // ---- conic (A, B, C) = (c, -b, a) / det, a = a0 + s2d, c = c0 + s2d
+        const float det2 = det * det;
+        float ga_ = gA * (-(cc * cc) / det2) + gB * (b * cc / det2) + gC * (-(b * b) / det2);
+        float gc_ = gA * (-(b * b) / det2) + gB * (b * aa / det2) + gC * (-(aa * aa) / det2);
+        float gb_ = gA * (2.0f * b * cc / det2) + gB * (-(aa * cc + b * b) / det2) + gC * (2.0f * aa * b / det2);
+        if (compensate && det0 > 0.0f) {
+            const float ddet0 = dcomp2 / (2.0f * comp2 * det);
+            const float ddet = -dcomp2 * comp2 / (2.0f * det);
+            ga_ += ddet0 * c0 + ddet * cc;
+            gc_ += ddet0 * a0 + ddet * aa;
+            gb_ += -2.0f * b * (ddet0 + ddet);
+        }
+        // ---- Sigma' = M Sigma M^T
+        const float Gp[4] = {ga_, 0.5f * gb_, 0.5f * gb_, gc_};
+        float dS[9];
+        for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++) {
+                float acc = 0.0f;
+                for (int p = 0; p < 2; p++)
+                    for (int q = 0; q < 2; q++) acc += M[3 * p + r] * Gp[2 * p + q] * M[3 * q + c];
+                dS[3 * r + c] = acc;
+            }
+        float dM[6];
+        for (int p = 0; p < 2; p++)
+            for (int c = 0; c < 3; c++) {
+                float acc = 0.0f;
+                for (int q = 0; q < 2; q++)
+                    for (int k = 0; k < 3; k++) acc += 2.0f * Gp[2 * p + q] * M[3 * q + k] * S[3 * k + c];
+                dM[3 * p + c] = acc;
+            }
+        // ---- M = J W
+        float dJ00 = 0.0f, dJ02 = 0.0f, dJ11 = 0.0f, dJ12 = 0.0f;
+        for (int c = 0; c < 3; c++) {
+            dJ00 += dM[c] * Wc[c];
+            dJ02 += dM[c] * Wc[6 + c];
+            dJ11 += dM[3 + c] * Wc[3 + c];
+            dJ12 += dM[3 + c] * Wc[6 + c];
+        }
+        const float tz2 = tz * tz, tz3 = tz2 * tz;
+        float dtx = 0.0f, dty = 0.0f, dtz = 0.0f;
+        dtz += dJ00 * (-cam.fx / tz2) + dJ11 * (-cam.fy / tz2);
+        if (clx) dtz += dJ02 * (cam.fx * rx / tz2);
+        else { dtx += dJ02 * (-cam.fx / tz2); dtz += dJ02 * (2.0f * cam.fx * tx / tz3); }
+        if (cly) dtz += dJ12 * (cam.fy * ry / tz2);
+        else { dty += dJ12 * (-cam.fy / tz2); dtz += dJ12 * (2.0f * cam.fy * ty / tz3); }
+        dtx += gu * cam.fx / tz;
+        dtz += gu * (-cam.fx * tx / tz2);
+        dty += gv * cam.fy / tz;
+        dtz += gv * (-cam.fy * ty / tz2);
+        for (int j = 0; j < 3; j++) dmu[j] += Wc[j] * dtx + Wc[3 + j] * dty + Wc[6 + j] * dtz;
+
+        // ---- Sigma = R diag(v) R^T, v_j = s_j^2 + var, comp3 = sqrt(prod s_j^2 / v_j)
+        float dR[9];
+        float ds[3];
+        for (int j = 0; j < 3; j++) {
+            float acc = 0.0f;
+            for (int p = 0; p < 3; p++)
+                for (int q = 0; q < 3; q++) acc += R[3 * p + j] * dS[3 * p + q] * R[3 * q + j];
+            ds[j] = acc * 2.0f * s[j] + dcomp3 * comp3 * var / (s[j] * v[j]);
+        }
+        for (int p = 0; p < 3; p++)
+            for (int j = 0; j < 3; j++) {
+                float acc = 0.0f;
+                for (int q = 0; q < 3; q++) acc += dS[3 * p + q] * R[3 * q + j];
+                dR[3 * p + j] = 2.0f * acc * v[j];
+            }
+        // ---- R(q), q = (w, x, y, z) as given
+        const float dqw = dR[1] * (-2.0f * qz) + dR[2] * (2.0f * qy) + dR[3] * (2.0f * qz) + dR[5] * (-2.0f * qx) +
+                          dR[6] * (-2.0f * qy) + dR[7] * (2.0f * qx);
+        const float dqx = dR[1] * (2.0f * qy) + dR[2] * (2.0f * qz) + dR[3] * (2.0f * qy) + dR[4] * (-4.0f * qx) +
+                          dR[5] * (-2.0f * qw) + dR[6] * (2.0f * qz) + dR[7] * (2.0f * qw) + dR[8] * (-4.0f * qx);
+        const float dqy = dR[0] * (-4.0f * qy) + dR[1] * (2.0f * qx) + dR[2] * (2.0f * qw) + dR[3] * (2.0f * qx) +
+                          dR[5] * (2.0f * qz) + dR[6] * (-2.0f * qw) + dR[7] * (2.0f * qz) + dR[8] * (-4.0f * qy);
+        const float dqz = dR[0] * (-4.0f * qz) + dR[1] * (-2.0f * qw) + dR[2] * (2.0f * qx) + dR[3] * (2.0f * qw) +
+                          dR[4] * (-4.0f * qz) + dR[5] * (2.0f * qy) + dR[6] * (2.0f * qx) + dR[7] * (2.0f * qy);
+
+        if (G.mean) {
+            G.mean[i] += dmu[0];
+            G.mean[n + i] += dmu[1];
+            G.mean[2 * n + i] += dmu[2];
+        }
+        if (G.scale) {
+            G.scale[i] += ds[0];
+            G.scale[n + i] += ds[1];
+            G.scale[2 * n + i] += ds[2];
+        }
+        if (G.quat) {
+            G.quat[i] += dqw;
+            G.quat[n + i] += dqx;
+            G.quat[2 * n + i] += dqy;
+            G.quat[3 * n + i] += dqz;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_backward(const LevelsArg& lv, const lodge_selection& sel, const Views& v, const float* final_T,
+                           const uint32_t* n_contrib, const float* dL_dimage, int32_t grad_level,
+                           const lodge_grads* grads, hipStream_t st)
+{
+    GradsArg ga{};
+    for (int l = 0; l < lv.L; l++) ga.g[l] = grads[l];
+    uint32_t blocks = std::min<uint32_t>(2048, std::max<uint32_t>(1, (v.max_active * (uint32_t)kG2 + 255) / 256));
+    k_bwd_setup<<<blocks, 256, 0, st>>>(v.g2d, sel.count, sel.cap);
+    k_composite_bwd<<<v.lay.T, 256, 0, st>>>(v.params, v.ranges, v.sorted, v.proj, final_T, n_contrib, dL_dimage,
+                                             v.g2d, v.max_active);
+    blocks = std::min<uint32_t>(4096, std::max<uint32_t>(1, (v.max_active + 255) / 256));
+    k_project_bwd<<<blocks, 256, 0, st>>>(lv, ga, grad_level, sel.ids, sel.w, sel.count, sel.cap, v.params, v.proj,
+                                          v.g2d);
+    return hipGetLastError();
+}
+
+}  // namespace lodge

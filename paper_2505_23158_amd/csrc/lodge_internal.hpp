@@ -1,0 +1,154 @@
+// Internal declarations of the gfx950 renderer: device-side argument
+// structs, the workspace layout and the kernel launchers each translation
+// unit provides.  Not part of the public ABI (see include/lodge.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/lodge.h"
+
+namespace lodge {
+
+constexpr int kTile = 16;           // screen tiles are 16 x 16 pixels
+constexpr int kMaxSh = 16;          // SH coefficients per channel at degree 3
+
+// ---------------------------------------------------------------- arguments
+
+// One level as the kernels see it (passed by value inside LevelsArg).
+struct LevelDev {
+    const float* mean;
+    const float* scale;
+    const float* quat;
+    const float* opacity;
+    const float* sh;
+    uint32_t n;
+    uint32_t base;      // global id of the level's first Gaussian
+    int32_t sh_degree;
+    float var;          // Eq. 3 filter variance
+};
+
+struct LevelsArg {
+    LevelDev lv[LODGE_MAX_LEVELS];
+    int32_t L;
+    uint32_t total;
+    float d[LODGE_MAX_LEVELS];   // d_1 .. d_{L-1}
+};
+
+struct ChunksArg {
+    int32_t K;
+    float band;
+    float c[LODGE_MAX_CHUNKS][3];
+    float r[LODGE_MAX_CHUNKS];
+};
+
+// Frame parameters in device memory: the camera copy plus what the setup
+// kernel derives from it.  Kernels read these instead of kernel arguments so
+// that a captured graph re-reads the camera at every replay.
+struct FrameParams {
+    lodge_camera cam;
+    int32_t mode;
+    int32_t f, o;
+    float t, w_o;
+    float cf[3], co[3];              // centres the selection measures from
+    float lo_f[LODGE_MAX_LEVELS], hi_f[LODGE_MAX_LEVELS];
+    float lo_o[LODGE_MAX_LEVELS], hi_o[LODGE_MAX_LEVELS];
+    float s2d;
+    int32_t compensate;
+    int32_t TX, TY;
+};
+
+// Device counters of one frame (mirrors lodge_frame_info, plus tickets).
+struct FrameInfo {
+    uint32_t n_selected;
+    uint32_t n_front;
+    uint32_t n_visible;
+    unsigned long long n_instances;
+    unsigned long long pairs_evaluated;
+    unsigned long long pairs_blended;
+    uint32_t max_tile_len;
+    uint32_t overflow;
+    int32_t f, o;
+    float t;
+    uint32_t n_large;     // tiles sorted by the large-list kernel
+    uint32_t n_huge;      // tiles sorted by the merge fallback
+    uint32_t sel_ticket;
+    uint32_t scan_ticket;
+    uint32_t pad[2];
+};
+
+enum : uint32_t { kOvfSelect = 1u, kOvfInstances = 2u, kOvfTile = 4u };
+
+// ------------------------------------------------------------ workspace map
+
+constexpr int kSelBlock = 256;
+constexpr int kSelItems = 16;                       // per thread
+constexpr int kSelTile = kSelBlock * kSelItems;     // Gaussians per selection block
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanBlock * kScanItems;
+constexpr int kSortSmall = 2048;                    // per-tile LDS sort, 256 threads
+constexpr int kSortLarge = 16384;                   // per-tile LDS sort, 1024 threads
+constexpr int kProjStride = 12;                     // floats per projected record
+
+struct Layout {
+    size_t params, info, sel_flags, scan_flags, proj, vis, vtiles, diff, ranges, cursor, order, large, sorted, temp,
+        g2d, total;
+    uint32_t sel_tiles, scan_tiles, TX, TY, T;
+};
+
+Layout make_layout(uint32_t n_total, int32_t width, int32_t height, uint32_t max_active, uint64_t max_instances);
+
+// Typed views of a workspace.
+struct Views {
+    FrameParams* params;
+    FrameInfo* info;
+    unsigned long long* sel_flags;
+    unsigned long long* scan_flags;
+    float4* proj;          // [max_active][3]: (u, v, A, B), (C, o, r, g), (b, depth, rect01, rect23)
+    uint32_t* vis;         // visible list (active indices, unordered)
+    uint32_t* vtiles;      // tiles touched -> exclusive instance offsets (in place)
+    int32_t* diff;         // (TY+1) x (TX+1) difference grid of per-tile counts
+    uint2* ranges;         // per tile [start, end)
+    uint32_t* cursor;      // per tile fill position
+    uint32_t* order;       // tiles by decreasing list length
+    uint32_t* large;       // tiles whose list exceeds kSortSmall
+    uint32_t* sorted;      // [max_instances] active indices, tile-major
+    unsigned long long* temp;   // [max_instances] merge scratch for very long lists
+    float* g2d;            // [max_active][12] adjoint of the projected quantities
+    Layout lay;
+    uint32_t max_active;
+    uint64_t max_instances;
+};
+
+Views views_of(const lodge_workspace* ws, uint32_t n_total);
+
+// ----------------------------------------------------------------- launchers
+// Each returns hipGetLastError() after enqueueing on `st`.
+
+hipError_t launch_select_setup(const LevelsArg& lv, const ChunksArg& ch, int32_t mode, const Views& v, hipStream_t st);
+hipError_t launch_select(const LevelsArg& lv, const Views& v, const lodge_selection& sel, hipStream_t st);
+hipError_t launch_render_setup(const lodge_render_opts& o, const Views& v, hipStream_t st);
+hipError_t launch_project(const LevelsArg& lv, const lodge_selection& sel, const Views& v, hipStream_t st);
+hipError_t launch_bin(const Views& v, hipStream_t st);
+hipError_t launch_sort(const Views& v, hipStream_t st);
+hipError_t launch_composite(const Views& v, float* image, float* final_T, uint32_t* n_contrib, hipStream_t st);
+hipError_t launch_backward(const LevelsArg& lv, const lodge_selection& sel, const Views& v, const float* final_T,
+                           const uint32_t* n_contrib, const float* dL_dimage, int32_t grad_level,
+                           const lodge_grads* grads, hipStream_t st);
+hipError_t launch_activate(int64_t n, const float* ls, const float* qr, const float* ol, float* s, float* q, float* o,
+                           hipStream_t st);
+hipError_t launch_activate_backward(int64_t n, const float* qr, const float* s, const float* o, const float* gs,
+                                    const float* gq, const float* go, float* gls, float* gqr, float* gol,
+                                    hipStream_t st);
+
+// ------------------------------------------------------------ device helpers
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Grid sizes that fill the chip (256 CUs) without depending on device counts.
+constexpr int kPersistentBlocks = 2048;
+
+}  // namespace lodge

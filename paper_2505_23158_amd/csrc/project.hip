@@ -1,0 +1,240 @@
+// Projection of the active Gaussians (LODGE Sec. 3 "Preliminaries: 3D
+// Gaussian Splatting": EWA splatting of mean and covariance; Eq. 3: the
+// level's 3-D smoothing filter with its opacity factor; supplementary
+// "Details on training the full representation": the renderer's 2-D
+// screen-space filter; Eq. 4: the chunk weight modulates opacity).
+//
+// One thread per active Gaussian (grid-stride to the device count).  The
+// mean, selection id and weight are read first; Gaussians behind the near
+// plane stop there, so scale, rotation, opacity and the 192-byte SH block
+// are read only for Gaussians in front of the camera (SH only for visible
+// ones).  Visible Gaussians append themselves to an unordered list (one
+// atomic per wave) and add their tile rectangle to a 2-D difference grid,
+// whose prefix sums are the per-tile list lengths.
+//
+// Built with -ffp-contract=off: the rectangle and depth (which decide tile
+// membership and sort keys) are evaluated op for op as the oracle defines
+// them.
+#include "lodge_internal.hpp"
+
+namespace lodge {
+
+namespace {
+
+// Real SH basis to degree 3 with the sign convention of include/lodge.h's
+// renderer: k1 = -c1 y, k2 = c1 z, k3 = -c1 x, k4 = c2a xy, k5 = -c2a yz,
+// k6 = c2b (2z^2 - x^2 - y^2), k7 = -c2a xz, k8 = c2c (x^2 - y^2),
+// k9 = -c3a y(3x^2 - y^2), k10 = c3b xyz, k11 = -c3c y(4z^2 - x^2 - y^2),
+// k12 = c3d z(2z^2 - 3x^2 - 3y^2), k13 = -c3c x(4z^2 - x^2 - y^2),
+// k14 = c3e z(x^2 - y^2), k15 = -c3a x(x^2 - 3y^2).
+constexpr float kC0 = 0.28209479177387814f;   // 1 / (2 sqrt(pi))
+constexpr float kC1 = 0.4886025119029199f;    // sqrt(3 / (4 pi))
+constexpr float kC2a = 1.0925484305920792f;   // sqrt(15 / (4 pi))
+constexpr float kC2b = 0.31539156525252005f;  // sqrt(5 / (16 pi))
+constexpr float kC2c = 0.5462742152960396f;   // sqrt(15 / (16 pi))
+constexpr float kC3a = 0.5900435899266435f;   // sqrt(35 / (32 pi))
+constexpr float kC3b = 2.890611442640554f;    // sqrt(105 / (4 pi))
+constexpr float kC3c = 0.4570457994644658f;   // sqrt(21 / (32 pi))
+constexpr float kC3d = 0.3731763325901154f;   // sqrt(7 / (16 pi))
+constexpr float kC3e = 1.445305721320277f;    // sqrt(105 / (16 pi))
+
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float* Y)
+{
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[0] = kC0;
+    Y[1] = -(kC1 * y);
+    Y[2] = kC1 * z;
+    Y[3] = -(kC1 * x);
+    Y[4] = kC2a * (x * y);
+    Y[5] = -(kC2a * (y * z));
+    Y[6] = kC2b * ((2.0f * zz - xx) - yy);
+    Y[7] = -(kC2a * (x * z));
+    Y[8] = kC2c * (xx - yy);
+    Y[9] = -(kC3a * (y * (3.0f * xx - yy)));
+    Y[10] = kC3b * ((x * y) * z);
+    Y[11] = -(kC3c * (y * ((4.0f * zz - xx) - yy)));
+    Y[12] = kC3d * (z * ((2.0f * zz - 3.0f * xx) - 3.0f * yy));
+    Y[13] = -(kC3c * (x * ((4.0f * zz - xx) - yy)));
+    Y[14] = kC3e * (z * (xx - yy));
+    Y[15] = -(kC3a * (x * (xx - 3.0f * yy)));
+}
+
+__device__ __forceinline__ int level_of(const LevelsArg& lv, uint32_t g)
+{
+    int l = 0;
+#pragma unroll
+    for (int j = 1; j < LODGE_MAX_LEVELS; j++)
+        if (j < lv.L && g >= lv.lv[j].base) l = j;
+    return l;
+}
+
+__global__ __launch_bounds__(256) void k_project(LevelsArg lv, const uint32_t* __restrict__ ids,
+                                                 const float* __restrict__ wsel, const uint32_t* __restrict__ count,
+                                                 uint32_t cap, const FrameParams* __restrict__ fp, FrameInfo* info,
+                                                 float4* __restrict__ proj, uint32_t* __restrict__ vis,
+                                                 uint32_t* __restrict__ vtiles, int32_t* __restrict__ diff)
+{
+    const uint32_t n_act = min(*count, cap);
+    const lodge_camera& cam = fp->cam;
+    const float s2d = fp->s2d;
+    const int compensate = fp->compensate;
+    const int32_t TX = fp->TX, TY = fp->TY;
+    const uint32_t lane = threadIdx.x & 63;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    const uint32_t stride = gridDim.x * blockDim.x;
+
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n_act; base += stride) {
+        const uint32_t a = base + threadIdx.x;
+        bool visible = false, front = false;
+        uint32_t ntiles = 0;
+        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+        int32_t x0 = 0, y0 = 0, x1 = 0, y1 = 0;
+        if (a < n_act) {
+            const uint32_t g = ids[a];
+            const int l = level_of(lv, g);
+            const LevelDev& L = lv.lv[l];
+            const size_t n = L.n;
+            const uint32_t i = g - L.base;
+            const float mx = L.mean[i], my = L.mean[n + i], mz = L.mean[2 * n + i];
+            const float* W = cam.R;
+            const float tx = ((W[0] * mx + W[1] * my) + W[2] * mz) + cam.t[0];
+            const float ty = ((W[3] * mx + W[4] * my) + W[5] * mz) + cam.t[1];
+            const float tz = ((W[6] * mx + W[7] * my) + W[8] * mz) + cam.t[2];
+            if (tz > cam.znear) {
+                front = true;
+                const float s0 = L.scale[i], s1 = L.scale[n + i], s2 = L.scale[2 * n + i];
+                const float qw = L.quat[i], qx = L.quat[n + i], qy = L.quat[2 * n + i], qz = L.quat[3 * n + i];
+                // rotation of the quaternion (w, x, y, z) as given
+                const float xx = qx * qx, yy = qy * qy, zz = qz * qz;
+                const float xy = qx * qy, xz = qx * qz, yz = qy * qz;
+                const float wx = qw * qx, wy = qw * qy, wz = qw * qz;
+                const float R[9] = {1.0f - 2.0f * (yy + zz), 2.0f * (xy - wz),        2.0f * (xz + wy),
+                                    2.0f * (xy + wz),        1.0f - 2.0f * (xx + zz), 2.0f * (yz - wx),
+                                    2.0f * (xz - wy),        2.0f * (yz + wx),        1.0f - 2.0f * (xx + yy)};
+                // Eq. 3: Sigma + var I, and sqrt(|Sigma| / |Sigma + var I|)
+                const float v0 = s0 * s0 + L.var, v1 = s1 * s1 + L.var, v2 = s2 * s2 + L.var;
+                float S[9];
+#pragma unroll
+                for (int p = 0; p < 3; p++)
+#pragma unroll
+                    for (int q = p; q < 3; q++) {
+                        const float e = ((R[3 * p] * v0) * R[3 * q] + (R[3 * p + 1] * v1) * R[3 * q + 1])
+                                        + (R[3 * p + 2] * v2) * R[3 * q + 2];
+                        S[3 * p + q] = e;
+                        S[3 * q + p] = e;
+                    }
+                const float comp3 = sqrtf(((s0 * s0 / v0) * (s1 * s1 / v1)) * (s2 * s2 / v2));
+                // perspective Jacobian at the clamped mean
+                const float ix = tx / tz, iy = ty / tz;
+                const float u = cam.fx * ix + cam.cx;
+                const float v = cam.fy * iy + cam.cy;
+                float rx = ix, ry = iy;
+                if (rx < -cam.lim_x) rx = -cam.lim_x;
+                if (rx > cam.lim_x) rx = cam.lim_x;
+                if (ry < -cam.lim_y) ry = -cam.lim_y;
+                if (ry > cam.lim_y) ry = cam.lim_y;
+                const float J00 = cam.fx / tz, J02 = -((cam.fx * rx) / tz);
+                const float J11 = cam.fy / tz, J12 = -((cam.fy * ry) / tz);
+                float M[6];
+#pragma unroll
+                for (int j = 0; j < 3; j++) {
+                    M[j] = J00 * W[j] + J02 * W[6 + j];
+                    M[3 + j] = J11 * W[3 + j] + J12 * W[6 + j];
+                }
+                float T[6];
+#pragma unroll
+                for (int r = 0; r < 2; r++)
+#pragma unroll
+                    for (int j = 0; j < 3; j++)
+                        T[3 * r + j] = (M[3 * r] * S[j] + M[3 * r + 1] * S[3 + j]) + M[3 * r + 2] * S[6 + j];
+                const float a0 = (T[0] * M[0] + T[1] * M[1]) + T[2] * M[2];
+                const float b = (T[0] * M[3] + T[1] * M[4]) + T[2] * M[5];
+                const float c0 = (T[3] * M[3] + T[4] * M[4]) + T[5] * M[5];
+                // 2-D filter
+                const float aa = a0 + s2d, cc = c0 + s2d;
+                const float det0 = a0 * c0 - b * b;
+                const float det = aa * cc - b * b;
+                if (det > 0.0f) {
+                    const float comp2 = compensate ? sqrtf((det0 > 0.0f ? det0 : 0.0f) / det) : 1.0f;
+                    const float A = cc / det, B = -(b / det), C = aa / det;
+                    const float mid = 0.5f * (aa + cc);
+                    const float disc = mid * mid - det;
+                    const float lam = mid + sqrtf(disc > 0.0f ? disc : 0.0f);
+                    const float rad = ceilf(3.0f * sqrtf(lam));
+                    float fx0 = floorf((u - rad) / 16.0f), fx1 = floorf((u + rad) / 16.0f) + 1.0f;
+                    float fy0 = floorf((v - rad) / 16.0f), fy1 = floorf((v + rad) / 16.0f) + 1.0f;
+                    const float hx = (float)(TX + 1), hy = (float)(TY + 1);
+                    fx0 = fx0 < -1.0f ? -1.0f : (fx0 > hx ? hx : fx0);
+                    fx1 = fx1 < -1.0f ? -1.0f : (fx1 > hx ? hx : fx1);
+                    fy0 = fy0 < -1.0f ? -1.0f : (fy0 > hy ? hy : fy0);
+                    fy1 = fy1 < -1.0f ? -1.0f : (fy1 > hy ? hy : fy1);
+                    x0 = max((int32_t)fx0, 0);
+                    y0 = max((int32_t)fy0, 0);
+                    x1 = min((int32_t)fx1, TX);
+                    y1 = min((int32_t)fy1, TY);
+                    if (x0 < x1 && y0 < y1) {
+                        visible = true;
+                        ntiles = (uint32_t)((x1 - x0) * (y1 - y0));
+                        // view-dependent colour from the direction camera -> mean
+                        const float d0 = mx - cam.pos[0], d1 = my - cam.pos[1], d2 = mz - cam.pos[2];
+                        const float dn = sqrtf((d0 * d0 + d1 * d1) + d2 * d2);
+                        float Y[kMaxSh];
+                        sh_basis(d0 / dn, d1 / dn, d2 / dn, Y);
+                        const int nb = (L.sh_degree + 1) * (L.sh_degree + 1);
+                        float rgb[3];
+#pragma unroll
+                        for (int ch = 0; ch < 3; ch++) {
+                            float acc = 0.0f;
+                            for (int k = 0; k < nb; k++) acc = acc + L.sh[((size_t)(k * 3 + ch)) * n + i] * Y[k];
+                            acc = acc + 0.5f;
+                            rgb[ch] = acc > 0.0f ? acc : 0.0f;
+                        }
+                        const float o_eff = ((L.opacity[i] * wsel[a]) * comp3) * comp2;
+                        r0 = make_float4(u, v, A, B);
+                        r1 = make_float4(C, o_eff, rgb[0], rgb[1]);
+                        r2 = make_float4(rgb[2], tz, __uint_as_float((uint32_t)x0 | ((uint32_t)y0 << 16)),
+                                         __uint_as_float((uint32_t)x1 | ((uint32_t)y1 << 16)));
+                    }
+                }
+            }
+            proj[3 * (size_t)a] = r0;
+            proj[3 * (size_t)a + 1] = r1;
+            proj[3 * (size_t)a + 2] = r2;
+        }
+        const unsigned long long mf = __ballot(front);
+        if (mf != 0ull && lane == (uint32_t)(__ffsll((long long)mf) - 1))
+            atomicAdd(&info->n_front, (uint32_t)__popcll(mf));
+        // unordered compaction of the visible set: one atomic per wave
+        const unsigned long long m = __ballot(visible);
+        if (m != 0ull) {
+            uint32_t wbase = 0;
+            const int leader = __ffsll((long long)m) - 1;
+            if ((int)lane == leader) wbase = atomicAdd(&info->n_visible, (uint32_t)__popcll(m));
+            wbase = __shfl(wbase, leader);
+            if (visible) {
+                const uint32_t pos = wbase + (uint32_t)__popcll(m & lt);
+                vis[pos] = a;
+                vtiles[pos] = ntiles;
+                const int32_t P = TX + 1;
+                atomicAdd(&diff[y0 * P + x0], 1);
+                atomicAdd(&diff[y0 * P + x1], -1);
+                atomicAdd(&diff[y1 * P + x0], -1);
+                atomicAdd(&diff[y1 * P + x1], 1);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_project(const LevelsArg& lv, const lodge_selection& sel, const Views& v, hipStream_t st)
+{
+    uint32_t blocks = (v.max_active + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    if (blocks > kPersistentBlocks * 2) blocks = kPersistentBlocks * 2;
+    k_project<<<blocks, 256, 0, st>>>(lv, sel.ids, sel.w, sel.count, sel.cap, v.params, v.info, v.proj, v.vis,
+                                      v.vtiles, v.diff);
+    return hipGetLastError();
+}
+
+}  // namespace lodge

@@ -1,0 +1,389 @@
+"""ctypes binding of liblodge.so (include/lodge.h), names kept one-to-one.
+
+Argument marshalling only: every step of a frame runs in the HIP kernels of
+liblodge.so.  PyTorch supplies device memory (tensors) and streams.  If the
+library is missing or cannot be loaded this module raises; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblodge.so")
+
+LODGE_OK, LODGE_ERR_INVALID_ARG, LODGE_ERR_CAPACITY, LODGE_ERR_HIP, LODGE_ERR_UNSUPPORTED = range(5)
+SELECT_ALL, SELECT_LOD_CAMERA, SELECT_CHUNKED = 0, 1, 2
+MAX_LEVELS = 8
+MAX_CHUNKS = 128
+TILE = 16
+
+
+class LodgeError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"lodge status {status}: {msg}")
+        self.status = status
+
+
+# --------------------------------------------------------------------------- structs
+
+class lodge_level(C.Structure):
+    _fields_ = [("n", C.c_int64), ("mean", C.c_void_p), ("scale", C.c_void_p), ("quat", C.c_void_p),
+                ("opacity", C.c_void_p), ("sh", C.c_void_p), ("sh_degree", C.c_int32), ("filter3d_var", C.c_float)]
+
+
+class lodge_chunks(C.Structure):
+    _fields_ = [("k", C.c_int32), ("center", C.c_void_p), ("offset", C.c_void_p), ("band", C.c_float)]
+
+
+class lodge_camera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("R", C.c_float * 9), ("t", C.c_float * 3),
+                ("pos", C.c_float * 3), ("znear", C.c_float), ("lim_x", C.c_float), ("lim_y", C.c_float),
+                ("bg", C.c_float * 3)]
+
+
+class lodge_workspace(C.Structure):
+    _fields_ = [("base", C.c_void_p), ("bytes", C.c_size_t), ("width", C.c_int32), ("height", C.c_int32),
+                ("max_active", C.c_uint32), ("max_instances", C.c_uint64)]
+
+
+class lodge_selection(C.Structure):
+    _fields_ = [("ids", C.c_void_p), ("w", C.c_void_p), ("count", C.c_void_p), ("cap", C.c_uint32)]
+
+
+class lodge_render_opts(C.Structure):
+    _fields_ = [("s2d", C.c_float), ("compensate", C.c_int32), ("stage_events", C.c_void_p)]
+
+
+STAGE_EVENTS = 5
+
+
+class lodge_frame_info(C.Structure):
+    _fields_ = [("n_selected", C.c_uint32), ("n_front", C.c_uint32), ("n_visible", C.c_uint32),
+                ("max_tile_len", C.c_uint32), ("n_instances", C.c_uint64), ("pairs_evaluated", C.c_uint64),
+                ("pairs_blended", C.c_uint64), ("overflow", C.c_uint32), ("f", C.c_int32), ("o", C.c_int32),
+                ("t", C.c_float), ("n_long", C.c_uint32), ("n_merge", C.c_uint32)]
+
+
+class lodge_grads(C.Structure):
+    _fields_ = [("mean", C.c_void_p), ("scale", C.c_void_p), ("quat", C.c_void_p), ("opacity", C.c_void_p),
+                ("sh", C.c_void_p)]
+
+
+# --------------------------------------------------------------------------- library
+
+_lib = None
+
+
+def lib():
+    """The loaded liblodge.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        # torch first: liblodge.so then binds to the HIP runtime torch already
+        # loaded (same soname), so streams and memory are shared.
+        import torch  # noqa: F401
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2505_23158_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        st = C.c_int
+        vp = C.c_void_p
+        sig = {
+            "lodge_status_string": (C.c_char_p, [st]),
+            "lodge_last_error": (C.c_char_p, []),
+            "lodge_version": (C.c_char_p, []),
+            "lodge_scene_create": (st, [C.POINTER(lodge_level), C.c_int32, vp, C.POINTER(lodge_chunks),
+                                        C.POINTER(vp)]),
+            "lodge_scene_destroy": (None, [vp]),
+            "lodge_scene_total": (C.c_int64, [vp]),
+            "lodge_workspace_size": (st, [vp, C.c_int32, C.c_int32, C.c_uint32, C.c_uint64, C.POINTER(C.c_size_t)]),
+            "lodge_select": (st, [vp, vp, C.c_int32, C.POINTER(lodge_workspace), C.POINTER(lodge_selection), vp]),
+            "lodge_render": (st, [vp, C.POINTER(lodge_selection), vp, C.POINTER(lodge_render_opts),
+                                  C.POINTER(lodge_workspace), vp, vp, vp, vp]),
+            "lodge_frame_info_read": (st, [C.POINTER(lodge_workspace), C.POINTER(lodge_frame_info), vp]),
+            "lodge_check": (st, [C.POINTER(lodge_workspace), C.POINTER(C.c_uint32), C.POINTER(C.c_uint64), vp]),
+            "lodge_debug_views": (st, [C.POINTER(lodge_workspace), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]),
+            "lodge_render_backward": (st, [vp, C.POINTER(lodge_selection), vp, C.POINTER(lodge_render_opts),
+                                           C.POINTER(lodge_workspace), vp, vp, vp, C.c_int32,
+                                           C.POINTER(lodge_grads), vp]),
+            "lodge_activate": (st, [C.c_int64, vp, vp, vp, vp, vp, vp, vp]),
+            "lodge_activate_backward": (st, [C.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != LODGE_OK:
+        raise LodgeError(status, lib().lodge_last_error().decode())
+
+
+EXPORTED = ["lodge_status_string", "lodge_last_error", "lodge_version", "lodge_scene_create", "lodge_scene_destroy",
+            "lodge_scene_total", "lodge_workspace_size", "lodge_select", "lodge_render", "lodge_frame_info_read",
+            "lodge_check", "lodge_debug_views", "lodge_render_backward", "lodge_activate", "lodge_activate_backward"]
+
+
+# --------------------------------------------------------------------------- helpers
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def make_camera(cam) -> lodge_camera:
+    """lodge_camera from any object with the synth.Camera fields."""
+    c = lodge_camera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    for i, v in enumerate(np.asarray(cam.R, np.float32).ravel()):
+        c.R[i] = float(v)
+    for i in range(3):
+        c.t[i] = float(cam.t[i])
+        c.pos[i] = float(cam.pos[i])
+        c.bg[i] = float(cam.bg[i])
+    c.znear, c.lim_x, c.lim_y = float(cam.znear), float(cam.lim_x), float(cam.lim_y)
+    return c
+
+
+class PinnedCamera:
+    """A lodge_camera in pinned host memory: calls captured into a HIP graph
+    record a copy of it that re-reads the current contents at every replay."""
+
+    def __init__(self):
+        torch = _torch()
+        self.buf = torch.zeros(C.sizeof(lodge_camera), dtype=torch.uint8, pin_memory=True)
+        self.ptr = self.buf.data_ptr()
+
+    def set(self, cam):
+        c = make_camera(cam) if not isinstance(cam, lodge_camera) else cam
+        C.memmove(self.ptr, C.addressof(c), C.sizeof(lodge_camera))
+
+
+# --------------------------------------------------------------------------- objects
+
+class Scene:
+    """A lodge_scene over device tensors (levels stay owned by this object)."""
+
+    def __init__(self, levels: Sequence[dict], d: Sequence[float], chunks=None):
+        torch = _torch()
+        self.levels = []
+        arr = (lodge_level * len(levels))()
+        for i, lv in enumerate(levels):
+            keep = {k: lv[k] for k in ("mean", "scale", "quat", "opacity", "sh")}
+            for k, t in keep.items():
+                if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+                    raise ValueError(f"level {i} {k}: need a contiguous float32 CUDA tensor")
+            n = int(keep["mean"].shape[-1])
+            deg = int(lv.get("sh_degree", 3))
+            nsh = (deg + 1) ** 2
+            shapes = {"mean": (3, n), "scale": (3, n), "quat": (4, n), "opacity": (n,)}
+            for k, shp in shapes.items():
+                if tuple(keep[k].shape) != shp:
+                    raise ValueError(f"level {i} {k}: shape {tuple(keep[k].shape)} != {shp}")
+            if keep["sh"].shape[-1] != n or keep["sh"].numel() < nsh * 3 * n:
+                raise ValueError(f"level {i} sh: need at least [{nsh}][3][{n}]")
+            arr[i].n = n
+            arr[i].mean, arr[i].scale, arr[i].quat = _ptr(keep["mean"]), _ptr(keep["scale"]), _ptr(keep["quat"])
+            arr[i].opacity, arr[i].sh = _ptr(keep["opacity"]), _ptr(keep["sh"])
+            arr[i].sh_degree = deg
+            arr[i].filter3d_var = float(lv.get("filter3d_var", 0.0))
+            self.levels.append(dict(keep, n=n, sh_degree=deg, filter3d_var=arr[i].filter3d_var))
+        self._arr = arr
+        self.d = np.asarray(list(d) if d is not None else [], np.float32)
+        ch = None
+        if chunks is not None:
+            self.centers = np.ascontiguousarray(chunks.centers, np.float32)
+            self.offsets = np.ascontiguousarray(chunks.offsets, np.float32)
+            ch = lodge_chunks(k=len(self.centers), center=self.centers.ctypes.data, offset=self.offsets.ctypes.data,
+                              band=float(chunks.band))
+        h = C.c_void_p()
+        _check(lib().lodge_scene_create(arr, len(levels), self.d.ctypes.data if len(self.d) else None,
+                                        C.byref(ch) if ch is not None else None, C.byref(h)))
+        self.handle = h
+        self.total = int(lib().lodge_scene_total(h))
+
+    @classmethod
+    def from_synth(cls, sc, device="cuda"):
+        torch = _torch()
+        levels = []
+        for lv in sc.levels:
+            nsh = (lv.sh_degree + 1) ** 2
+            levels.append(dict(mean=torch.from_numpy(lv.mean).to(device), scale=torch.from_numpy(lv.scale).to(device),
+                               quat=torch.from_numpy(lv.quat).to(device),
+                               opacity=torch.from_numpy(lv.opacity).to(device),
+                               sh=torch.from_numpy(np.ascontiguousarray(lv.sh[:nsh])).to(device),
+                               sh_degree=lv.sh_degree, filter3d_var=lv.filter3d_var))
+        return cls(levels, sc.d, sc.chunks)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.lodge_scene_destroy(h)
+            self.handle = None
+
+
+class Workspace:
+    """Caller-owned device scratch for one frame in flight (a torch uint8 tensor)."""
+
+    def __init__(self, scene: Scene, width: int, height: int, max_active: int, max_instances: int, device="cuda"):
+        torch = _torch()
+        nb = C.c_size_t()
+        _check(lib().lodge_workspace_size(scene.handle, width, height, max_active, max_instances, C.byref(nb)))
+        self.tensor = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=device)
+        base = self.tensor.data_ptr()
+        self.offset = (-base) % 256
+        self.desc = lodge_workspace(base=base + self.offset, bytes=int(nb.value), width=width, height=height,
+                                    max_active=max_active, max_instances=max_instances)
+        self.width, self.height = width, height
+        self.max_active, self.max_instances = max_active, max_instances
+
+    def view(self, ptr: int, nbytes: int, dtype):
+        torch = _torch()
+        off = ptr - self.tensor.data_ptr()
+        return self.tensor[off:off + nbytes].view(dtype)
+
+
+class Selection:
+    def __init__(self, cap: int, device="cuda"):
+        torch = _torch()
+        self.ids = torch.empty(max(cap, 1), dtype=torch.int32, device=device)
+        self.w = torch.empty(max(cap, 1), dtype=torch.float32, device=device)
+        self.count = torch.zeros(1, dtype=torch.int32, device=device)
+        self.desc = lodge_selection(ids=_ptr(self.ids), w=_ptr(self.w), count=_ptr(self.count), cap=cap)
+        self.cap = cap
+
+
+# --------------------------------------------------------------------------- calls
+
+def _cam_arg(cam):
+    if isinstance(cam, PinnedCamera):
+        return C.c_void_p(cam.ptr), None
+    c = cam if isinstance(cam, lodge_camera) else make_camera(cam)
+    return C.c_void_p(C.addressof(c)), c
+
+
+def lodge_select(scene: Scene, cam, mode: int, ws: Workspace, sel: Selection, stream=None):
+    cp, keep = _cam_arg(cam)
+    _check(lib().lodge_select(scene.handle, cp, mode, C.byref(ws.desc), C.byref(sel.desc), _stream_ptr(stream)))
+
+
+def lodge_render(scene: Scene, sel: Selection, cam, ws: Workspace, image, final_T, n_contrib, s2d: float = 0.3,
+                 compensate: bool = True, stream=None, stage_events=None):
+    """stage_events: None or STAGE_EVENTS torch.cuda.Event objects recorded at the stage boundaries."""
+    cp, keep = _cam_arg(cam)
+    evs = None
+    if stage_events is not None:
+        evs = (C.c_void_p * STAGE_EVENTS)(*[e.cuda_event for e in stage_events])
+    opts = lodge_render_opts(s2d=s2d, compensate=int(compensate), stage_events=C.cast(evs, C.c_void_p) if evs else None)
+    _check(lib().lodge_render(scene.handle, C.byref(sel.desc), cp, C.byref(opts), C.byref(ws.desc), _ptr(image),
+                              _ptr(final_T), _ptr(n_contrib), _stream_ptr(stream)))
+
+
+def lodge_frame_info_read(ws: Workspace, stream=None) -> dict:
+    fi = lodge_frame_info()
+    _check(lib().lodge_frame_info_read(C.byref(ws.desc), C.byref(fi), _stream_ptr(stream)))
+    return {k: getattr(fi, k) for k, _ in lodge_frame_info._fields_}
+
+
+def lodge_check(ws: Workspace, stream=None):
+    na, ni = C.c_uint32(), C.c_uint64()
+    st = lib().lodge_check(C.byref(ws.desc), C.byref(na), C.byref(ni), _stream_ptr(stream))
+    return st, int(na.value), int(ni.value)
+
+
+def lodge_debug_views(ws: Workspace, n_instances: int):
+    """(sorted_ids [M] int32, tile_ranges [T,2] int32, proj [max_active,12] float32) views into ws."""
+    torch = _torch()
+    s, r, p = C.c_void_p(), C.c_void_p(), C.c_void_p()
+    _check(lib().lodge_debug_views(C.byref(ws.desc), C.byref(s), C.byref(r), C.byref(p)))
+    T = ((ws.width + TILE - 1) // TILE) * ((ws.height + TILE - 1) // TILE)
+    sorted_ids = ws.view(s.value, 4 * n_instances, torch.int32)
+    ranges = ws.view(r.value, 8 * T, torch.int32).view(T, 2)
+    proj = ws.view(p.value, 48 * ws.max_active, torch.float32).view(ws.max_active, 12)
+    return sorted_ids, ranges, proj
+
+
+def lodge_render_backward(scene: Scene, sel: Selection, cam, ws: Workspace, final_T, n_contrib, dL_dimage,
+                          grads: Sequence[dict], grad_level: int = -1, s2d: float = 0.3, compensate: bool = True,
+                          stream=None):
+    cp, keep = _cam_arg(cam)
+    opts = lodge_render_opts(s2d=s2d, compensate=int(compensate))
+    arr = (lodge_grads * len(scene.levels))()
+    for i, g in enumerate(grads):
+        for k in ("mean", "scale", "quat", "opacity", "sh"):
+            setattr(arr[i], k, _ptr(g.get(k)))
+    _check(lib().lodge_render_backward(scene.handle, C.byref(sel.desc), cp, C.byref(opts), C.byref(ws.desc),
+                                       _ptr(final_T), _ptr(n_contrib), _ptr(dL_dimage), grad_level, arr,
+                                       _stream_ptr(stream)))
+
+
+def lodge_activate(log_scale, quat_raw, opacity_logit, scale, quat, opacity, stream=None):
+    n = int(opacity_logit.numel())
+    _check(lib().lodge_activate(n, _ptr(log_scale), _ptr(quat_raw), _ptr(opacity_logit), _ptr(scale), _ptr(quat),
+                                _ptr(opacity), _stream_ptr(stream)))
+
+
+def lodge_activate_backward(quat_raw, scale, opacity, g_scale, g_quat, g_opacity, g_log_scale, g_quat_raw,
+                            g_opacity_logit, stream=None):
+    n = int(opacity.numel())
+    _check(lib().lodge_activate_backward(n, _ptr(quat_raw), _ptr(scale), _ptr(opacity), _ptr(g_scale), _ptr(g_quat),
+                                         _ptr(g_opacity), _ptr(g_log_scale), _ptr(g_quat_raw),
+                                         _ptr(g_opacity_logit), _stream_ptr(stream)))
+
+
+# --------------------------------------------------------------------------- one frame
+
+@dataclass
+class Frame:
+    image: object
+    final_T: object
+    n_contrib: object
+
+
+class Renderer:
+    """Convenience owner of a workspace, a selection and output buffers for one image size."""
+
+    def __init__(self, scene: Scene, width: int, height: int, max_active: Optional[int] = None,
+                 max_instances: Optional[int] = None, device="cuda"):
+        torch = _torch()
+        self.scene = scene
+        if max_active is None:
+            max_active = max(1, scene.total)
+        if max_instances is None:
+            max_instances = max(1 << 20, 8 * max_active)
+        self.ws = Workspace(scene, width, height, max_active, min(max_instances, (1 << 32) - 1), device)
+        self.sel = Selection(max_active, device)
+        self.image = torch.empty((3, height, width), dtype=torch.float32, device=device)
+        self.final_T = torch.empty((height, width), dtype=torch.float32, device=device)
+        self.n_contrib = torch.empty((height, width), dtype=torch.int32, device=device)
+        self.width, self.height = width, height
+
+    def frame(self, cam, mode: int, s2d: float = 0.3, compensate: bool = True, stream=None,
+              stage_events=None) -> Frame:
+        lodge_select(self.scene, cam, mode, self.ws, self.sel, stream)
+        lodge_render(self.scene, self.sel, cam, self.ws, self.image, self.final_T, self.n_contrib, s2d, compensate,
+                     stream, stage_events)
+        return Frame(self.image, self.final_T, self.n_contrib)
+
+    def info(self, stream=None) -> dict:
+        return lodge_frame_info_read(self.ws, stream)

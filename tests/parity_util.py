@@ -1,0 +1,115 @@
+"""Helpers shared by the GPU parity tests: run the HIP path through the C ABI
+and compare every intermediate with the oracle on the same seeded inputs."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+import oracle
+
+TILE = 16
+IMG_TOL = 1e-4          # FP32 image: max abs error per channel
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_frame(scene_dev, cam, mode, width=None, height=None, max_active=None, max_instances=None, s2d=0.3,
+              compensate=True, renderer=None):
+    """One select + render on the GPU; returns host copies of everything."""
+    import torch
+    from paper_2505_23158_amd import lodge as L
+    R = renderer or L.Renderer(scene_dev, cam.width, cam.height, max_active=max_active, max_instances=max_instances)
+    R.frame(cam, mode, s2d=s2d, compensate=compensate)
+    torch.cuda.synchronize()
+    info = R.info()
+    n = min(info["n_selected"], R.sel.cap)
+    out = dict(info=info, ids=R.sel.ids[:n].cpu().numpy().astype(np.uint32), w=R.sel.w[:n].cpu().numpy(),
+               image=R.image.cpu().numpy(), final_T=R.final_T.cpu().numpy(),
+               n_contrib=R.n_contrib.cpu().numpy().astype(np.uint32), renderer=R)
+    M = int(info["n_instances"])
+    if M <= R.ws.max_instances:
+        s, r, p = L.lodge_debug_views(R.ws, M)
+        out["sorted"] = s.cpu().numpy().astype(np.uint32)
+        out["ranges"] = r.cpu().numpy().astype(np.uint32)
+        out["proj"] = p[:n].cpu().numpy()
+    return out
+
+
+def rect_of(proj_rows):
+    bits = proj_rows[:, 10:12].copy().view(np.uint32)
+    return np.stack([bits[:, 0] & 0xFFFF, bits[:, 0] >> 16, bits[:, 1] & 0xFFFF, bits[:, 1] >> 16], axis=1)
+
+
+def compare_selection(g, ids, w):
+    assert g["info"]["n_selected"] == len(ids), (g["info"]["n_selected"], len(ids))
+    assert np.array_equal(g["ids"], ids), "selected ids differ"
+    assert np.array_equal(g["w"].view(np.uint32), np.asarray(w, np.float32).view(np.uint32)), "weights differ"
+
+
+def compare_projection(g, proj: oracle.Projection):
+    P = g["proj"]
+    vis_o = proj.tiles > 0
+    rect_g = rect_of(P)
+    vis_g = (rect_g[:, 2] > rect_g[:, 0]) & (rect_g[:, 3] > rect_g[:, 1])
+    assert np.array_equal(vis_g, vis_o), f"visibility differs at {np.flatnonzero(vis_g != vis_o)[:10]}"
+    assert np.array_equal(rect_g[vis_o], proj.rect[vis_o].astype(np.uint32)), "tile rectangles differ"
+    # depth is a sort key: bit-exact
+    assert np.array_equal(P[vis_o, 9].view(np.uint32), proj.depth[vis_o].astype(np.float32).view(np.uint32))
+    got = np.concatenate([P[vis_o, 0:2], P[vis_o, 2:5], P[vis_o, 5:6], P[vis_o, 6:9]], axis=1)
+    exp = np.concatenate([proj.uv[vis_o], proj.conic[vis_o], proj.o_eff[vis_o, None], proj.rgb[vis_o]], axis=1)
+    err = np.abs(got - exp) / np.maximum(1.0, np.abs(exp))
+    assert err.max(initial=0.0) <= 1e-5, f"projected values differ (max rel {err.max()})"
+    return int(vis_o.sum())
+
+
+def same_ranges(gr, orr):
+    """Tile ranges agree: equal lengths everywhere, equal starts where non-empty
+    (an empty tile's start carries no information)."""
+    lg, lo = gr[:, 1] - gr[:, 0], orr[:, 1] - orr[:, 0]
+    ne = lo > 0
+    return np.array_equal(lg, lo) and np.array_equal(gr[ne, 0], orr[ne, 0])
+
+
+def compare_binning(g, binned: oracle.Binned):
+    assert int(g["info"]["n_instances"]) == binned.M
+    assert same_ranges(g["ranges"], binned.ranges), "tile ranges differ"
+    assert np.array_equal(g["sorted"], binned.val), "sorted instance lists differ"
+
+
+def compare_image(O, g, r, cam, tol=IMG_TOL):
+    """Image, final T and n_contrib vs the oracle.  A pixel whose difference
+    exceeds tol is accepted only if the oracle, with one or two of its
+    near-threshold decisions inverted, lands within tol of the GPU value."""
+    img_o, img_g = r["image"], g["image"]
+    diff = np.abs(img_g - img_o).max(axis=0)
+    bad = np.argwhere(diff > tol)
+    flipped = np.zeros(diff.shape, bool)
+    for y, x in bad:
+        ok = O.pixel_accept(r["proj"], r["binned"], cam, int(x), int(y), img_g[:, y, x].astype(np.float32), tol)
+        assert ok, f"pixel ({x},{y}) differs by {diff[y, x]:.3g} with no threshold ambiguity"
+        flipped[y, x] = True
+    H, W = diff.shape
+    assert flipped.sum() <= max(8, 2e-4 * H * W), f"too many threshold flips: {flipped.sum()}"
+    ok = ~flipped
+    assert np.abs(g["final_T"] - r["final_T"])[ok].max(initial=0.0) <= tol
+    mism = (g["n_contrib"] != r["n_contrib"]) & ok
+    # n_contrib may also differ where a near-threshold skip happens after the last blend
+    assert (mism & (r["near"] == 0)).sum() == 0, "n_contrib differs at unambiguous pixels"
+    return int(flipped.sum()), float(diff[ok].max(initial=0.0))
+
+
+def full_parity(O, scene_host, scene_dev, cam, mode, label, **kw):
+    log(f"[parity] {label}: {cam.width}x{cam.height} mode={mode}")
+    g = gpu_frame(scene_dev, cam, mode, **kw)
+    r = O.render(scene_host, cam, mode, s2d=kw.get("s2d", 0.3), compensate=kw.get("compensate", True))
+    compare_selection(g, r["ids"], r["w"])
+    nvis = compare_projection(g, r["proj"])
+    compare_binning(g, r["binned"])
+    flips, maxerr = compare_image(O, g, r, cam)
+    log(f"[parity] {label}: active={len(r['ids'])} visible={nvis} M={r['binned'].M} flips={flips} "
+        f"max_err={maxerr:.2e}")
+    return g, r

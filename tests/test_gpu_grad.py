@@ -1,0 +1,182 @@
+"""The HIP adjoint (lodge_render_backward, lodge_activate_backward, the
+autograd Function) against the FP64 oracle adjoint and central differences
+of the FP64 oracle forward: relative error per tensor <= 1e-3."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import Scene
+
+from parity_util import log
+
+pytestmark = pytest.mark.gpu
+
+PARAMS = ("mean", "scale", "quat", "opacity", "sh")
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_23158_amd import lodge
+    lodge.lib()
+    return lodge
+
+
+def rel_ok(got, ref, tol=1e-3):
+    got, ref = np.asarray(got, np.float64).ravel(), np.asarray(ref, np.float64).ravel()
+    nrm = np.linalg.norm(ref)
+    if nrm == 0:
+        return np.abs(got).max(initial=0.0) == 0, 0.0
+    rel = np.linalg.norm(got - ref) / nrm
+    elem = np.all(np.abs(got - ref) <= tol * (np.abs(ref) + np.sqrt(np.mean(ref ** 2))) + 1e-12)
+    return rel <= tol and elem, rel
+
+
+def as64(sc):
+    out = []
+    for lv in sc.levels:
+        c = synth.Level(mean=lv.mean.astype(np.float64), scale=lv.scale.astype(np.float64),
+                        quat=lv.quat.astype(np.float64), opacity=lv.opacity.astype(np.float64),
+                        sh=lv.sh.astype(np.float64), sh_degree=lv.sh_degree, filter3d_var=lv.filter3d_var)
+        out.append(c)
+    return Scene(levels=out, d=sc.d, chunks=sc.chunks)
+
+
+def gpu_grads(L, sc, cam, mode, dL, grad_level=-1):
+    import torch
+    dev = L.Scene.from_synth(sc)
+    R = L.Renderer(dev, cam.width, cam.height)
+    R.frame(cam, mode)
+    grads = [{k: torch.zeros_like(t) for k, t in lv.items() if k in PARAMS} for lv in dev.levels]
+    L.lodge_render_backward(dev, R.sel, cam, R.ws, R.final_T, R.n_contrib,
+                            torch.from_numpy(dL.astype(np.float32)).cuda(), grads, grad_level=grad_level)
+    torch.cuda.synchronize()
+    return [{k: v.cpu().numpy() for k, v in g.items()} for g in grads], R
+
+
+def masked_dL(O32, sc, cam, mode, seed):
+    """Seeded dL/dimage, zero at pixels where the FP32 oracle records a
+    near-threshold decision (there two correct renderers may take different
+    traces, and so have different gradients)."""
+    r = O32.render(sc, cam, mode)
+    rng = np.random.default_rng(seed)
+    dL = rng.normal(size=(3, cam.height, cam.width))
+    dL[:, r["near"] > 0] = 0.0
+    return dL
+
+
+def check_against_oracle(L, O32, O64, sc, cam, mode, seed, grad_level=-1, label=""):
+    log(f"[grad] {label}: {cam.width}x{cam.height}, {sc.n_total} Gaussians, grad_level={grad_level}")
+    dL = masked_dL(O32, sc, cam, mode, seed)
+    g_gpu, _ = gpu_grads(L, sc, cam, mode, dL, grad_level)
+    _, _, g_ref = O64.render_grad(as64(sc), cam, mode, dL, grad_level=grad_level)
+    for l in range(len(sc.levels)):
+        for k in PARAMS:
+            nsh = (sc.levels[l].sh_degree + 1) ** 2
+            ref = g_ref[l][k][:nsh] if k == "sh" else g_ref[l][k]
+            ok, rel = rel_ok(g_gpu[l][k], ref)
+            log(f"[grad] {label} level {l} {k}: rel {rel:.2e}")
+            assert ok, (label, l, k, rel)
+
+
+@pytest.mark.parametrize("var", [0.0, 0.003])
+def test_check_scene_vs_fp64_adjoint(L, oracle32, oracle64, var):
+    sc = synth.check_scene(n=64, width=32, height=32, filter3d_var=var)
+    check_against_oracle(L, oracle32, oracle64, sc, sc.cameras[0], oracle.ALL, 5, label=f"check-64-var{var}")
+
+
+def test_larger_scene_vs_fp64_adjoint(L, oracle32, oracle64):
+    sc = synth.plain_scene(n=4000, seed=61, width=96, height=80)
+    check_against_oracle(L, oracle32, oracle64, sc, sc.cameras[0], oracle.ALL, 6, label="plain-4000")
+
+
+def test_chunked_two_levels_level_mask(L, oracle32, oracle64):
+    sc = synth.lod_city_scene(counts=(6000, 1500), half_xy=12.0, d=(4.0,), grid=2, spacing=6.0, chunk_z=1.0,
+                              band=2.0, seed=62)
+    cam = synth.look_at((-1.0, -6.0, 1.2), (0.0, 6.0, 0.0), (0, 0, 1), 80, 48)
+    for gl in (-1, 1):
+        check_against_oracle(L, oracle32, oracle64, sc, cam, oracle.CHUNKED, 7, grad_level=gl,
+                             label=f"chunked-gl{gl}")
+
+
+def test_gpu_adjoint_vs_central_differences(L, oracle32, oracle64):
+    """Sampled coordinates: (L(theta + h) - L(theta - h)) / 2h on the FP64
+    oracle forward, skipping coordinates whose perturbation changes the trace."""
+    sc = synth.check_scene(n=64, width=32, height=32, filter3d_var=0.001)
+    cam = sc.cameras[0]
+    dL = masked_dL(oracle32, sc, cam, oracle.ALL, 8)
+    g_gpu, _ = gpu_grads(L, sc, cam, oracle.ALL, dL)
+    s64 = as64(sc)
+    base = oracle64.render(s64, cam, oracle.ALL)
+    sig0 = (base["n_contrib"], base["n_blend"], base["proj"].tiles)
+    rng = np.random.default_rng(9)
+    for k in PARAMS:
+        arr = getattr(s64.levels[0], k).reshape(-1)
+        idx = rng.choice(arr.size, size=min(40, arr.size), replace=False)
+        fd, an = [], []
+        for j in idx:
+            th = arr[j]
+            h = 1e-6 * max(1.0, abs(th))
+            arr[j] = th + h
+            rp = oracle64.render(s64, cam, oracle.ALL)
+            arr[j] = th - h
+            rm = oracle64.render(s64, cam, oracle.ALL)
+            arr[j] = th
+            if any(not np.array_equal(a, b) for r in (rp, rm) for a, b in
+                   zip((r["n_contrib"], r["n_blend"], r["proj"].tiles), sig0)):
+                continue
+            fd.append((np.sum(dL * rp["image"]) - np.sum(dL * rm["image"])) / (2 * h))
+            an.append(g_gpu[0][k].reshape(-1)[j])
+        assert len(fd) >= 15, k
+        fd, an = np.asarray(fd), np.asarray(an)
+        rel = np.linalg.norm(an - fd) / max(np.linalg.norm(fd), 1e-30)
+        log(f"[grad] FD {k}: {len(fd)} coords, rel {rel:.2e}")
+        assert rel <= 1e-3, (k, rel)
+
+
+def test_autograd_raw_parameters_and_view_accumulation(L, oracle32, oracle64):
+    """L1 loss over two views through the autograd Function: gradients w.r.t.
+    log-scale, raw quaternion and opacity logit equal the FP64 oracle's
+    activated-parameter gradients chained through the activation."""
+    import torch
+    from paper_2505_23158_amd.autograd import DiffRenderer
+    sc = synth.check_scene(n=64, width=32, height=32, filter3d_var=0.001)
+    cams = [sc.cameras[0], synth.look_at((0.5, 0.3, -4.0), (0, 0, 0), (0, -1, 0), 32, 32)]
+    dr = DiffRenderer.from_synth(sc, n_slots=2)
+    for p in dr.parameters():
+        p.requires_grad_(True)
+    targets = synth.target_images(2, 32, 32, seed=10)
+    # mask near-threshold pixels out of the loss (see masked_dL)
+    masks = [(oracle32.render(sc, c, oracle.ALL)["near"] == 0).astype(np.float32) for c in cams]
+    loss = 0.0
+    for v, c in enumerate(cams):
+        img = dr.render(c, L.SELECT_ALL, slot=v)
+        m = torch.from_numpy(masks[v]).cuda()
+        loss = loss + ((img - torch.from_numpy(targets[v]).cuda()).abs() * m).sum()
+    loss.backward()
+    raw = sc.levels[0].raw
+    s64 = as64(sc)
+    g_ref = {k: 0.0 for k in PARAMS}
+    for v, c in enumerate(cams):
+        r = oracle64.render(s64, c, oracle.ALL)
+        dL = np.sign(r["image"] - targets[v]) * masks[v][None]
+        _, _, g = oracle64.render_grad(s64, c, oracle.ALL, dL)
+        for k in PARAMS:
+            g_ref[k] = g_ref[k] + g[0][k]
+    # chain through the activation in float64
+    scale = s64.levels[0].scale
+    q = raw["quat"].astype(np.float64)
+    qn = np.linalg.norm(q, axis=0)
+    u = q / qn
+    gq = g_ref["quat"]
+    ref = {"mean": g_ref["mean"], "log_scale": g_ref["scale"] * scale,
+           "quat_raw": (gq - u * np.sum(u * gq, axis=0)) / qn,
+           "opacity_logit": g_ref["opacity"] * s64.levels[0].opacity * (1 - s64.levels[0].opacity),
+           "sh": g_ref["sh"]}
+    for k, t in dr.raw[0].items():
+        ok, rel = rel_ok(t.grad.cpu().numpy(), ref[k])
+        log(f"[grad] autograd {k}: rel {rel:.2e}")
+        assert ok, (k, rel)
