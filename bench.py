@@ -85,6 +85,67 @@ def cpu_baseline(sc, cams, mode_oracle, frames):
             "host_nproc": os.cpu_count()}
 
 
+SERVE_CAPS = {(640, 360): (8_000_000, 8_000_000), (1280, 720): (8_000_000, 16_000_000),
+              (1920, 1080): (8_000_000, 32_000_000)}
+
+
+def serving_section(dev, n=256, rate=120.0):
+    """The served form on the resident scene: Poisson arrivals, mixed resolutions,
+    per-slot graph replay; latency = completion - arrival (no device-to-host copy)."""
+    import synth
+    from paper_2505_23158_amd import lodge as L
+    from paper_2505_23158_amd.serve import Request, serve
+    reqs = synth.serving_requests(n, rate=rate, half_xy=500.0, seed=4)
+    requests = [Request(i, t, cam) for i, (t, cam) in enumerate(reqs)]
+    rep, _ = serve(dev, requests, L.SELECT_CHUNKED, SERVE_CAPS, mem_budget=96 << 30, max_slots_per_class=8,
+                   prewarm=2)
+    s = rep.summary()
+    return {"requests": n, "arrival_rate_per_s": rate, "resolutions": ["640x360", "1280x720", "1920x1080"],
+            "p50_ms": round(s["p50_ms"], 3), "p99_ms": round(s["p99_ms"], 3), "mean_ms": round(s["mean_ms"], 3),
+            "frames_per_s": round(s["frames_per_s"], 2), "makespan_s": round(s["makespan_s"], 3),
+            "peak_in_flight": s["peak_in_flight"], "slots": s["slots"], "retries": s["retries"],
+            "graph_replay": True}
+
+
+def diff_section(n=1_000_000, views=8, width=1280, height=720, steps=3):
+    """Differentiation: L1 loss over 8 views of a 1M-Gaussian level, forward + backward
+    through the autograd Function (activation, select, render, adjoints)."""
+    import torch
+
+    import synth
+    from paper_2505_23158_amd import lodge as L
+    from paper_2505_23158_amd.autograd import DiffRenderer
+    sc = synth.diff_scene(n=n, n_views=views, width=width, height=height)
+    dr = DiffRenderer.from_synth(sc, n_slots=views, max_active=n, max_instances=24_000_000)
+    for p in dr.parameters():
+        p.requires_grad_(True)
+    tgt = torch.from_numpy(synth.target_images(views, width, height)).cuda()
+
+    def step():
+        for p in dr.parameters():
+            p.grad = None
+        loss = 0.0
+        for v, cam in enumerate(sc.cameras):
+            loss = loss + (dr.render(cam, L.SELECT_ALL, slot=v) - tgt[v]).abs().mean()
+        (loss / views).backward()
+        return loss
+
+    step()
+    torch.cuda.synchronize()
+    for R in dr.slots:
+        st, na, ni = L.lodge_check(R.ws)
+        if st != L.LODGE_OK:
+            raise SystemExit(f"differentiation workspace too small: {na} active, {ni} instances")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / steps
+    return {"workload": f"1 level, {n} Gaussians, {views} views {width}x{height}, L1 loss, grads for mean, "
+                        "log-scale, raw quaternion, opacity logit, SH",
+            "ms_per_step": round(ms, 3), "views_per_s": round(views * 1000.0 / ms, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +156,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=1)
     ap.add_argument("--stats-every", type=int, default=10)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-diff", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the timed region, one device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -139,6 +204,9 @@ def main():
     # timed region: K frames back to back on one stream, per-stage events live
     K = args.steps
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(K)]
+    for row in ev:            # torch creates the HIP event at its first record
+        for e in row:
+            e.record()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(K):
@@ -201,6 +269,25 @@ def main():
     roofline = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
                 "frac": d["frac"], "traffic": None}
 
+    if args.calib_copy_mib:
+        src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    serving = None
+    if not args.no_serving and args.workload == "large":
+        log("[bench] serving 256 Poisson requests")
+        serving = serving_section(dev)
+        log(f"[bench] serving {serving}")
+    diff = None
+    if not args.no_diff:
+        log("[bench] differentiation, 8 views")
+        diff = diff_section()
+        log(f"[bench] differentiation {diff}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host")
@@ -220,6 +307,8 @@ def main():
         "per_frame": {k: round(v, 1) for k, v in mean.items()},
         "stages": stages,
         "roofline": roofline,
+        "serving": serving,
+        "differentiation": diff,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

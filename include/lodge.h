@@ -17,9 +17,14 @@
  *    pointers are read during the call only unless stated otherwise.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Calls marked
  *    ASYNC enqueue work on `stream` and return; they never synchronise the
- *    host, never allocate device memory, and may be captured into a HIP
- *    graph when the camera struct they are given lives in pinned host
- *    memory (the capture records a copy of it that is re-read at replay).
+ *    host and never allocate device memory.
+ *  - The camera of a frame lives in its workspace.  Calls that take a
+ *    `const lodge_camera* cam` first store it there (as a kernel argument,
+ *    so the caller's struct may change as soon as the call returns); cam =
+ *    NULL uses the camera stored by the last lodge_set_camera or call on
+ *    that workspace.  To replay a captured HIP graph for new cameras,
+ *    capture lodge_select/lodge_render with cam = NULL and call
+ *    lodge_set_camera on the same stream before each replay.
  *  - Every array of Gaussian parameters is a structure of arrays in FP32:
  *    attribute-major planes of n floats each.
  *  - Data-dependent sizes never return to the host inside a frame: device
@@ -144,6 +149,10 @@ typedef struct {
 lodge_status lodge_workspace_size(const lodge_scene* scene, int32_t width, int32_t height, uint32_t max_active,
                                   uint64_t max_instances, size_t* bytes);
 
+/* ASYNC.  Stores *cam in the workspace for the next frame (cam->width and
+ * cam->height must equal the workspace's). */
+lodge_status lodge_set_camera(const lodge_workspace* ws, const lodge_camera* cam, void* stream);
+
 /* -------------------------------------------------------------- selection */
 
 enum {
@@ -226,12 +235,16 @@ lodge_status lodge_check(const lodge_workspace* ws, uint32_t* needed_active, uin
  * next render on ws), for inspection and tests.  Any pointer may be NULL.
  *   sorted_ids [n_instances]  active index of each instance, tile-major,
  *                             each tile's run in ascending (depth bits, index)
- *   tile_ranges[TX*TY][2]     [start, end) of each tile's run
- *   proj       [max_active][12]  per active index: u, v, conic A, B, C, o_eff,
- *                             r, g, b, depth, tile rect (x0 | y0 << 16, x1 | y1 << 16
- *                             as two uint32 bit patterns); rect (0, 0) = culled */
+ *   tile_ranges[TX*TY][2]     [start, end) of each tile's run (any start when empty)
+ *   proj       [max_active][12]  per visible active index: u, v, conic A, B, C,
+ *                             o_eff, r, g, b, then the compositing aids ex, ey
+ *                             (half-extents of the ellipse where alpha can reach
+ *                             1/255) and thr (the power below which it cannot)
+ *   depth      [max_active]   camera depth (0 when culled)
+ *   rect       [max_active][2] tile rect as x0 | y0 << 16, x1 | y1 << 16
+ *                             (x0 >= x1 or y0 >= y1: culled) */
 lodge_status lodge_debug_views(const lodge_workspace* ws, const uint32_t** sorted_ids, const uint32_t** tile_ranges,
-                               const float** proj);
+                               const float** proj, const float** depth, const uint32_t** rect);
 
 /* ---------------------------------------------------------- differentiation */
 

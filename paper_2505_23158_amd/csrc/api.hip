@@ -36,6 +36,8 @@ lodge_status hip_fail(hipError_t e, const char* where)
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
+uint64_t tiles_of(int32_t w, int32_t h) { return (uint64_t)((w + kTile - 1) / kTile) * (uint64_t)((h + kTile - 1) / kTile); }
+
 lodge_status check_ws(const lodge_scene* s, const lodge_workspace* ws)
 {
     if (!ws || !ws->base) return fail(LODGE_ERR_INVALID_ARG, "workspace is NULL");
@@ -44,6 +46,8 @@ lodge_status check_ws(const lodge_scene* s, const lodge_workspace* ws)
         return fail(LODGE_ERR_INVALID_ARG, "workspace image size out of range");
     if (ws->max_instances >= (1ull << 32)) return fail(LODGE_ERR_INVALID_ARG, "max_instances must be < 2^32");
     if (ws->max_active >= (1u << 31)) return fail(LODGE_ERR_INVALID_ARG, "max_active must be < 2^31");
+    if (tiles_of(ws->width, ws->height) > (uint64_t)kMaxTiles)
+        return fail(LODGE_ERR_UNSUPPORTED, "image has more than 32768 16x16 tiles");
     const Layout L = make_layout(s->levels.total, ws->width, ws->height, ws->max_active, ws->max_instances);
     if (ws->bytes < L.total) return fail(LODGE_ERR_INVALID_ARG, "workspace smaller than lodge_workspace_size()");
     return LODGE_OK;
@@ -51,7 +55,7 @@ lodge_status check_ws(const lodge_scene* s, const lodge_workspace* ws)
 
 lodge_status check_cam(const lodge_camera* c, const lodge_workspace* ws)
 {
-    if (!c) return fail(LODGE_ERR_INVALID_ARG, "camera is NULL");
+    if (!c) return LODGE_OK;   // the camera already set on the workspace
     if (ws && (c->width != ws->width || c->height != ws->height))
         return fail(LODGE_ERR_INVALID_ARG, "camera size differs from the workspace's");
     const float v[] = {c->fx, c->fy, c->cx, c->cy, c->znear, c->lim_x, c->lim_y};
@@ -77,19 +81,23 @@ Layout make_layout(uint32_t n_total, int32_t width, int32_t height, uint32_t max
     L.TX = (uint32_t)(width + kTile - 1) / kTile;
     L.TY = (uint32_t)(height + kTile - 1) / kTile;
     L.T = L.TX * L.TY;
-    L.sel_tiles = std::max<uint32_t>(1, (n_total + kSelTile - 1) / kSelTile);
+    // selection blocks never straddle levels: at most one partial block per level
+    L.sel_tiles = (n_total + kSelTile - 1) / kSelTile + LODGE_MAX_LEVELS;
     L.scan_tiles = std::max<uint32_t>(1, (max_active + kScanTile - 1) / kScanTile);
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o = off; off += al(bytes); return o; };
     L.params = take(sizeof(FrameParams));
     L.info = take(sizeof(FrameInfo));
     L.scan_flags = take(8ull * L.scan_tiles);
+    L.bin_blocks = (uint32_t)std::max<uint64_t>(1, (max_instances + kBinChunk - 1) / kBinChunk);
     L.proj = take(48ull * max_active);
-    L.vis = take(4ull * max_active);
-    L.vtiles = take(4ull * max_active);
-    L.diff = take(4ull * (L.TX + 1) * (L.TY + 1));
+    L.depth = take(4ull * max_active);
+    L.rect = take(8ull * max_active);
+    L.vtiles = take(4ull * max_active + 16);
+    L.inst = take(8ull * max_instances);
+    L.hist = take(4ull * L.T * L.bin_blocks);
+    L.tcount = take(4ull * L.T);
     L.ranges = take(8ull * L.T);
-    L.cursor = take(4ull * L.T);
     L.order = take(4ull * L.T);
     L.large = take(8ull * L.T);
     L.sorted = take(4ull * max_instances);
@@ -110,11 +118,13 @@ Views views_of(const lodge_workspace* ws, uint32_t n_total)
     v.sel_flags = reinterpret_cast<unsigned long long*>(b + v.lay.sel_flags);
     v.scan_flags = reinterpret_cast<unsigned long long*>(b + v.lay.scan_flags);
     v.proj = reinterpret_cast<float4*>(b + v.lay.proj);
-    v.vis = reinterpret_cast<uint32_t*>(b + v.lay.vis);
+    v.depth = reinterpret_cast<float*>(b + v.lay.depth);
+    v.rect = reinterpret_cast<uint2*>(b + v.lay.rect);
     v.vtiles = reinterpret_cast<uint32_t*>(b + v.lay.vtiles);
-    v.diff = reinterpret_cast<int32_t*>(b + v.lay.diff);
+    v.inst = reinterpret_cast<uint2*>(b + v.lay.inst);
+    v.hist = reinterpret_cast<uint32_t*>(b + v.lay.hist);
+    v.tcount = reinterpret_cast<uint32_t*>(b + v.lay.tcount);
     v.ranges = reinterpret_cast<uint2*>(b + v.lay.ranges);
-    v.cursor = reinterpret_cast<uint32_t*>(b + v.lay.cursor);
     v.order = reinterpret_cast<uint32_t*>(b + v.lay.order);
     v.large = reinterpret_cast<uint32_t*>(b + v.lay.large);
     v.sorted = reinterpret_cast<uint32_t*>(b + v.lay.sorted);
@@ -125,15 +135,13 @@ Views views_of(const lodge_workspace* ws, uint32_t n_total)
     return v;
 }
 
-// Clears the render counters, the difference grid and the scan flags, and
+// Clears the render counters and the scan flags, and
 // records the options; one small kernel so a captured graph holds no memset.
 namespace {
-__global__ void k_render_setup(FrameParams* fp, FrameInfo* info, int32_t* diff, uint32_t ndiff,
-                               unsigned long long* flags, uint32_t nflags, float s2d, int32_t compensate, int32_t TX,
-                               int32_t TY)
+__global__ void k_render_setup(FrameParams* fp, FrameInfo* info, unsigned long long* flags, uint32_t nflags,
+                               float s2d, int32_t compensate, int32_t TX, int32_t TY)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
-    for (uint32_t k = i; k < ndiff; k += stride) diff[k] = 0;
     for (uint32_t k = i; k < nflags; k += stride) flags[k] = 0ull;
     if (i == 0) {
         fp->s2d = s2d;
@@ -154,14 +162,28 @@ __global__ void k_render_setup(FrameParams* fp, FrameInfo* info, int32_t* diff, 
 }
 }  // namespace
 
+namespace {
+// The camera travels as a kernel argument: the copy is taken at launch, so
+// the caller's struct can change right after the call returns.
+__global__ void k_set_camera(lodge_camera cam, lodge_camera* dst)
+{
+    if (threadIdx.x == 0) *dst = cam;
+}
+}  // namespace
+
+hipError_t launch_set_camera(const lodge_camera& cam, const Views& v, hipStream_t st)
+{
+    k_set_camera<<<1, 64, 0, st>>>(cam, &v.params->cam);
+    return hipGetLastError();
+}
+
 hipError_t launch_render_setup(const lodge_render_opts& o, const Views& v, hipStream_t st)
 {
-    const uint32_t ndiff = (v.lay.TX + 1) * (v.lay.TY + 1);
-    const uint32_t n = std::max(ndiff, v.lay.scan_tiles);
+    const uint32_t n = v.lay.scan_tiles;
     uint32_t blocks = std::min<uint32_t>(256, (n + 255) / 256);
-    k_render_setup<<<std::max<uint32_t>(blocks, 1), 256, 0, st>>>(v.params, v.info, v.diff, ndiff, v.scan_flags,
-                                                                   v.lay.scan_tiles, o.s2d, o.compensate,
-                                                                   (int32_t)v.lay.TX, (int32_t)v.lay.TY);
+    k_render_setup<<<std::max<uint32_t>(blocks, 1), 256, 0, st>>>(v.params, v.info, v.scan_flags, v.lay.scan_tiles,
+                                                                   o.s2d, o.compensate, (int32_t)v.lay.TX,
+                                                                   (int32_t)v.lay.TY);
     return hipGetLastError();
 }
 
@@ -229,6 +251,13 @@ lodge_status lodge_scene_create(const lodge_level* levels, int32_t L, const floa
     }
     s->levels.L = L;
     s->levels.total = (uint32_t)total;
+    uint32_t blk = 0;
+    for (int l = 0; l < L; l++) {
+        s->levels.first_block[l] = blk;
+        blk += (uint32_t)((levels[l].n + kSelTile - 1) / kSelTile);
+    }
+    for (int l = L; l <= LODGE_MAX_LEVELS; l++) s->levels.first_block[l] = blk;
+    s->levels.sel_blocks = blk;
     if (chunks) {
         if (chunks->k < 1 || chunks->k > LODGE_MAX_CHUNKS || !chunks->center || !chunks->offset) {
             delete s;
@@ -262,8 +291,21 @@ lodge_status lodge_workspace_size(const lodge_scene* scene, int32_t width, int32
         return fail(LODGE_ERR_INVALID_ARG, "image size out of range");
     if (max_instances >= (1ull << 32)) return fail(LODGE_ERR_INVALID_ARG, "max_instances must be < 2^32");
     if (max_active >= (1u << 31)) return fail(LODGE_ERR_INVALID_ARG, "max_active must be < 2^31");
+    if (tiles_of(width, height) > (uint64_t)kMaxTiles)
+        return fail(LODGE_ERR_UNSUPPORTED, "image has more than 32768 16x16 tiles");
     *bytes = make_layout(scene->levels.total, width, height, max_active, max_instances).total;
     return LODGE_OK;
+}
+
+lodge_status lodge_set_camera(const lodge_workspace* ws, const lodge_camera* cam, void* stream)
+{
+    if (!ws || !ws->base) return fail(LODGE_ERR_INVALID_ARG, "workspace is NULL");
+    if (!cam) return fail(LODGE_ERR_INVALID_ARG, "camera is NULL");
+    lodge_status s;
+    if ((s = check_cam(cam, ws)) != LODGE_OK) return s;
+    const Views v = views_of(ws, 0);
+    const hipError_t e = launch_set_camera(*cam, v, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LODGE_OK : hip_fail(e, "lodge_set_camera");
 }
 
 lodge_status lodge_select(const lodge_scene* scene, const lodge_camera* cam, int32_t mode, const lodge_workspace* ws,
@@ -279,8 +321,8 @@ lodge_status lodge_select(const lodge_scene* scene, const lodge_camera* cam, int
         return fail(LODGE_ERR_INVALID_ARG, "chunked selection on a scene without chunks");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Views v = views_of(ws, scene->levels.total);
-    hipError_t e = hipMemcpyAsync(&v.params->cam, cam, sizeof(lodge_camera), hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, "lodge_select: camera upload");
+    hipError_t e = hipSuccess;
+    if (cam && (e = launch_set_camera(*cam, v, st)) != hipSuccess) return hip_fail(e, "lodge_select: camera");
     if ((e = launch_select_setup(scene->levels, scene->chunks, mode, v, st)) != hipSuccess)
         return hip_fail(e, "lodge_select: setup");
     if ((e = launch_select(scene->levels, v, *sel, st)) != hipSuccess) return hip_fail(e, "lodge_select");
@@ -302,8 +344,8 @@ lodge_status lodge_render(const lodge_scene* scene, const lodge_selection* sel, 
     if (!(o.s2d >= 0.0f) || !std::isfinite(o.s2d)) return fail(LODGE_ERR_INVALID_ARG, "s2d must be finite and >= 0");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Views v = views_of(ws, scene->levels.total);
-    hipError_t e = hipMemcpyAsync(&v.params->cam, cam, sizeof(lodge_camera), hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, "lodge_render: camera upload");
+    hipError_t e = hipSuccess;
+    if (cam && (e = launch_set_camera(*cam, v, st)) != hipSuccess) return hip_fail(e, "lodge_render: camera");
     auto mark = [&](int k) -> hipError_t {
         return o.stage_events ? hipEventRecord(static_cast<hipEvent_t>(o.stage_events[k]), st) : hipSuccess;
     };
@@ -311,7 +353,7 @@ lodge_status lodge_render(const lodge_scene* scene, const lodge_selection* sel, 
     if ((e = mark(0)) != hipSuccess) return hip_fail(e, "lodge_render: event");
     if ((e = launch_project(scene->levels, *sel, v, st)) != hipSuccess) return hip_fail(e, "lodge_render: project");
     if ((e = mark(1)) != hipSuccess) return hip_fail(e, "lodge_render: event");
-    if ((e = launch_bin(v, st)) != hipSuccess) return hip_fail(e, "lodge_render: bin");
+    if ((e = launch_bin(v, *sel, st)) != hipSuccess) return hip_fail(e, "lodge_render: bin");
     if ((e = mark(2)) != hipSuccess) return hip_fail(e, "lodge_render: event");
     if ((e = launch_sort(v, st)) != hipSuccess) return hip_fail(e, "lodge_render: sort");
     if ((e = mark(3)) != hipSuccess) return hip_fail(e, "lodge_render: event");
@@ -365,7 +407,7 @@ lodge_status lodge_check(const lodge_workspace* ws, uint32_t* needed_active, uin
 }
 
 lodge_status lodge_debug_views(const lodge_workspace* ws, const uint32_t** sorted_ids, const uint32_t** tile_ranges,
-                               const float** proj)
+                               const float** proj, const float** depth, const uint32_t** rect)
 {
     if (!ws || !ws->base) return fail(LODGE_ERR_INVALID_ARG, "workspace is NULL");
     // every region but the trailing selection flags is independent of the scene size
@@ -373,6 +415,8 @@ lodge_status lodge_debug_views(const lodge_workspace* ws, const uint32_t** sorte
     if (sorted_ids) *sorted_ids = v.sorted;
     if (tile_ranges) *tile_ranges = reinterpret_cast<const uint32_t*>(v.ranges);
     if (proj) *proj = reinterpret_cast<const float*>(v.proj);
+    if (depth) *depth = v.depth;
+    if (rect) *rect = reinterpret_cast<const uint32_t*>(v.rect);
     return LODGE_OK;
 }
 
@@ -393,9 +437,9 @@ lodge_status lodge_render_backward(const lodge_scene* scene, const lodge_selecti
     if (opts) o = *opts;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Views v = views_of(ws, scene->levels.total);
-    // the forward's options and camera are in ws; refresh them in case the caller changed nothing else
-    hipError_t e = hipMemcpyAsync(&v.params->cam, cam, sizeof(lodge_camera), hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, "lodge_render_backward: camera upload");
+    // the forward's camera and options are still in ws; a given camera replaces it
+    hipError_t e = hipSuccess;
+    if (cam && (e = launch_set_camera(*cam, v, st)) != hipSuccess) return hip_fail(e, "lodge_render_backward: camera");
     if ((e = launch_backward(scene->levels, *sel, v, final_T, n_contrib, dL_dimage, grad_level, grads, st)) !=
         hipSuccess)
         return hip_fail(e, "lodge_render_backward");

@@ -198,16 +198,15 @@ __global__ __launch_bounds__(256) void k_project_bwd(LevelsArg lv, GradsArg ga, 
                                                      const uint32_t* __restrict__ ids, const float* __restrict__ wsel,
                                                      const uint32_t* __restrict__ count, uint32_t cap,
                                                      const FrameParams* __restrict__ fp,
-                                                     const float4* __restrict__ proj, const float* __restrict__ g2d)
+                                                     const uint2* __restrict__ rect, const float* __restrict__ g2d)
 {
     const uint32_t n_act = min(*count, cap);
     const lodge_camera& cam = fp->cam;
     const float s2d = fp->s2d;
     const int compensate = fp->compensate;
     for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < n_act; a += gridDim.x * blockDim.x) {
-        const float4 r2 = proj[3 * (size_t)a + 2];
-        const uint32_t p0 = __float_as_uint(r2.z), p1 = __float_as_uint(r2.w);
-        if ((p1 & 0xffffu) <= (p0 & 0xffffu)) continue;   // culled: empty rectangle
+        const uint2 rc = rect[a];
+        if ((rc.y & 0xffffu) <= (rc.x & 0xffffu)) continue;   // culled: empty rectangle
         const uint32_t gid = ids[a];
         int l = 0;
 #pragma unroll
@@ -414,7 +413,7 @@ hipError_t launch_backward(const LevelsArg& lv, const lodge_selection& sel, cons
     k_composite_bwd<<<v.lay.T, 256, 0, st>>>(v.params, v.ranges, v.sorted, v.proj, final_T, n_contrib, dL_dimage,
                                              v.g2d, v.max_active);
     blocks = std::min<uint32_t>(4096, std::max<uint32_t>(1, (v.max_active + 255) / 256));
-    k_project_bwd<<<blocks, 256, 0, st>>>(lv, ga, grad_level, sel.ids, sel.w, sel.count, sel.cap, v.params, v.proj,
+    k_project_bwd<<<blocks, 256, 0, st>>>(lv, ga, grad_level, sel.ids, sel.w, sel.count, sel.cap, v.params, v.rect,
                                           v.g2d);
     return hipGetLastError();
 }

@@ -2,27 +2,32 @@
 // projected Gaussian is assigned to every 16 x 16 tile its rectangle
 // overlaps; each tile's Gaussians are then depth sorted).
 //
-// k_scan_inst   exclusive scan of tiles-touched over the visible list
-//               (single pass, decoupled look-back) -> instance offsets and
-//               the instance count M.
-// k_tiles       one block: 2-D prefix sums of the difference grid give each
-//               tile's list length; a scan gives each tile's [start, end),
-//               the emission cursors, a longest-first processing order for
-//               compositing and the lists of tiles too long for the small
-//               LDS sort.
-// k_emit        load-balanced expansion: each thread takes instances, finds
-//               its Gaussian by binary search over an LDS window of the
-//               offsets, and claims a slot in its tile's run with an atomic.
-//               Slot order inside a run is arbitrary; the per-tile sort
-//               restores the total order (depth bits, active index).
+// A counting sort by tile built without device-scope atomics (which are
+// slow on the die-spanning L2 of this part): block-local LDS histograms,
+// coalesced column passes over a [block][tile] matrix, and LDS ranks.
+//
+//   k_scan_inst   exclusive scan of tiles-touched over the active set
+//                 (single pass, decoupled look-back) -> instance offsets, M.
+//   k_emit_hist   block b takes instances [b C, (b+1) C): finds each one's
+//                 Gaussian by binary search over an LDS window of the
+//                 offsets, writes (tile, index) pairs and its tile histogram
+//                 (packed 16-bit LDS counters) as row b of the matrix.
+//   k_col_sum     per tile: total count over the blocks (16 tiles x 16 row
+//                 groups per block, row reads contiguous across tiles).
+//   k_tile_scan   one block: exclusive scan of the tile totals -> [start,
+//                 end) per tile, a longest-first processing order, the
+//                 queues of tiles too long for the small LDS sort.
+//   k_col_offset  per tile: running offsets down the column -> each block's
+//                 first slot in each tile's run.
+//   k_scatter     block b re-reads its pairs and places each at its block's
+//                 offset plus an LDS rank.  Order inside a run is arbitrary;
+//                 the per-tile sort restores (depth bits, active index).
 #include "lodge_internal.hpp"
 
 namespace lodge {
 
 namespace {
 
-// Decoupled look-back over 64-bit flag words: status in bits 62-63 (1 = block
-// aggregate, 2 = inclusive prefix), value in bits 0-61.
 constexpr unsigned long long kValMask = (1ull << 62) - 1ull;
 
 __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
@@ -31,6 +36,8 @@ __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
     return v;
 }
 
+// Decoupled look-back over 64-bit flag words: status in bits 62-63 (1 = block
+// aggregate, 2 = inclusive prefix), value in bits 0-61.
 __device__ unsigned long long lookback64(unsigned long long* flags, int32_t tile, uint32_t lane)
 {
     unsigned long long prefix = 0;
@@ -55,9 +62,10 @@ __device__ unsigned long long lookback64(unsigned long long* flags, int32_t tile
     return prefix;
 }
 
-// In-place exclusive scan of vtiles[0, n_visible); total -> info->n_instances.
+// In-place exclusive scan of vt[0, n_active); total -> info->n_instances.
 __global__ __launch_bounds__(kScanBlock) void k_scan_inst(FrameInfo* info, unsigned long long* flags,
-                                                          uint32_t* __restrict__ vt, uint64_t max_instances)
+                                                          uint32_t* __restrict__ vt, const uint32_t* __restrict__ count,
+                                                          uint32_t cap, uint64_t max_instances)
 {
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_wave[kScanBlock / 64];
@@ -66,23 +74,28 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_inst(FrameInfo* info, unsig
     if (tid == 0) s_tile = atomicAdd(&info->scan_ticket, 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
-    const uint32_t n = info->n_visible;
+    const uint32_t n = min(*count, cap);
     const uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
     if (tile >= ntiles) {
-        if (tile == 0 && tid == 0) info->n_instances = 0;   // nothing visible
+        if (tile == 0 && tid == 0) info->n_instances = 0;   // nothing selected
         return;
     }
-    // each thread owns kScanItems consecutive items
     const uint32_t first = tile * kScanTile + tid * kScanItems;
     uint32_t x[kScanItems];
     uint32_t sum = 0;
+    if (first + kScanItems <= n) {
+        const uint4* p = reinterpret_cast<const uint4*>(vt + first);
 #pragma unroll
-    for (int k = 0; k < kScanItems; k++) {
-        const uint32_t idx = first + k;
-        x[k] = idx < n ? vt[idx] : 0u;
-        sum += x[k];
+        for (int k = 0; k < kScanItems / 4; k++) {
+            const uint4 q = p[k];
+            x[4 * k] = q.x; x[4 * k + 1] = q.y; x[4 * k + 2] = q.z; x[4 * k + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; k++) x[k] = first + k < n ? vt[first + k] : 0u;
     }
-    // block exclusive scan of the per-thread sums
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) sum += x[k];
     uint32_t inc = sum;
     for (int off = 1; off < 64; off <<= 1) {
         const uint32_t o = __shfl_up(inc, off);
@@ -131,46 +144,183 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_inst(FrameInfo* info, unsig
     }
 }
 
-// Single block: per-tile lengths from the difference grid, ranges, cursors,
-// processing order (longest class first) and the long-list work queues.
+__device__ __forceinline__ uint32_t upper_bound_g(const uint32_t* a, uint32_t n, uint32_t key)
+{
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] <= key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t blocks_of(unsigned long long M)
+{
+    return (uint32_t)((M + kBinChunk - 1) / kBinChunk);
+}
+
+// 16-bit counter t of a packed LDS histogram: add 1, return the old count.
+__device__ __forceinline__ uint32_t hist_inc(uint32_t* h, uint32_t t)
+{
+    const uint32_t sh = (t & 1u) << 4;
+    return (atomicAdd(&h[t >> 1], 1u << sh) >> sh) & 0xffffu;
+}
+
+__device__ __forceinline__ uint32_t hist_get(const uint32_t* h, uint32_t t)
+{
+    return (h[t >> 1] >> ((t & 1u) << 4)) & 0xffffu;
+}
+
+constexpr int kBinThreads = 1024;
+constexpr int kWindow = 16384;   // LDS window of instance offsets (active indices)
+
+__global__ __launch_bounds__(kBinThreads) void k_emit_hist(const FrameParams* fp, const FrameInfo* info,
+                                                           const uint32_t* __restrict__ off,
+                                                           const uint32_t* __restrict__ count, uint32_t cap,
+                                                           const uint2* __restrict__ rect, uint2* __restrict__ inst,
+                                                           uint32_t* __restrict__ hist, uint64_t max_instances)
+{
+    __shared__ uint32_t s_hist[kMaxTiles / 2];
+    __shared__ uint32_t s_off[kWindow];
+    __shared__ uint32_t s_lo, s_cnt;
+    const unsigned long long M = info->n_instances;
+    if (M == 0 || M > max_instances) return;
+    const uint32_t n_act = min(*count, cap);
+    const int32_t TX = fp->TX;
+    const uint32_t T = (uint32_t)(fp->TX * fp->TY);
+    const uint32_t B = blocks_of(M);
+    for (uint32_t b = blockIdx.x; b < B; b += gridDim.x) {
+        const uint32_t j0 = b * kBinChunk;
+        const uint32_t j1 = (uint32_t)min((unsigned long long)j0 + kBinChunk, M);
+        for (uint32_t k = threadIdx.x; k < (T + 1) / 2; k += kBinThreads) s_hist[k] = 0;
+        if (threadIdx.x == 0) {
+            const uint32_t lo = upper_bound_g(off, n_act, j0) - 1;
+            const uint32_t hi = upper_bound_g(off, n_act, j1 - 1) - 1;
+            s_lo = lo;
+            s_cnt = hi - lo + 1;
+        }
+        __syncthreads();
+        const uint32_t lo = s_lo, cnt = s_cnt;
+        const bool in_lds = cnt <= (uint32_t)kWindow;
+        if (in_lds)
+            for (uint32_t k = threadIdx.x; k < cnt; k += kBinThreads) s_off[k] = off[lo + k];
+        __syncthreads();
+        for (uint32_t j = j0 + threadIdx.x; j < j1; j += kBinThreads) {
+            // last active index whose offset is <= j (zero-tile entries share offsets: take the last)
+            uint32_t a;
+            if (in_lds) {
+                uint32_t l = 0, h = cnt;
+                while (l < h) {
+                    const uint32_t mid = (l + h) >> 1;
+                    if (s_off[mid] <= j) l = mid + 1; else h = mid;
+                }
+                a = lo + l - 1;
+            } else {
+                a = upper_bound_g(off, n_act, j) - 1;
+            }
+            const uint32_t k = j - off[a];
+            const uint2 rc = rect[a];
+            const uint32_t p0 = rc.x, p1 = rc.y;
+            const uint32_t x0 = p0 & 0xffffu, y0 = p0 >> 16, wr = (p1 & 0xffffu) - x0;
+            const uint32_t row = k / wr;
+            const uint32_t tile = (y0 + row) * (uint32_t)TX + x0 + (k - row * wr);
+            inst[j] = make_uint2(tile, a);
+            hist_inc(s_hist, tile);
+        }
+        __syncthreads();
+        uint32_t* row_out = hist + (size_t)b * T;
+        for (uint32_t t = threadIdx.x; t < T; t += kBinThreads) row_out[t] = hist_get(s_hist, t);
+        __syncthreads();
+    }
+}
+
+// Column passes over the [B][T] matrix: a block takes 16 tiles x 16 groups
+// of consecutive rows, so row reads are contiguous across the tile lanes and
+// every tile's column is walked by 16 threads at once.
+constexpr int kColTiles = 16, kColGroups = 16;
+
+// tile totals
+__global__ __launch_bounds__(256) void k_col_sum(const FrameParams* fp, const FrameInfo* info,
+                                                 const uint32_t* __restrict__ hist, uint32_t* __restrict__ tcount,
+                                                 uint64_t max_instances)
+{
+    __shared__ uint32_t s_part[kColGroups][kColTiles];
+    const unsigned long long M = info->n_instances;
+    const uint32_t T = (uint32_t)(fp->TX * fp->TY);
+    const uint32_t tl = threadIdx.x % kColTiles, g = threadIdx.x / kColTiles;
+    const uint32_t t = blockIdx.x * kColTiles + tl;
+    uint32_t s = 0;
+    if (t < T && M <= max_instances) {
+        const uint32_t B = blocks_of(M);
+        const uint32_t R = (B + kColGroups - 1) / kColGroups;
+        const uint32_t b0 = g * R, b1 = min(B, b0 + R);
+        for (uint32_t b = b0; b < b1; b++) s += hist[(size_t)b * T + t];
+    }
+    s_part[g][tl] = s;
+    __syncthreads();
+    if (g == 0 && t < T) {
+        uint32_t tot = 0;
+        for (int k = 0; k < kColGroups; k++) tot += s_part[k][tl];
+        tcount[t] = tot;
+    }
+}
+
+// per-(block, tile) first slot: tile start + running count down the column
+__global__ __launch_bounds__(256) void k_col_offset(const FrameParams* fp, const FrameInfo* info,
+                                                    const uint2* __restrict__ ranges, uint32_t* __restrict__ hist,
+                                                    uint64_t max_instances)
+{
+    __shared__ uint32_t s_part[kColGroups][kColTiles];
+    const unsigned long long M = info->n_instances;
+    if (M == 0 || M > max_instances) return;
+    const uint32_t T = (uint32_t)(fp->TX * fp->TY);
+    const uint32_t tl = threadIdx.x % kColTiles, g = threadIdx.x / kColTiles;
+    const uint32_t t = blockIdx.x * kColTiles + tl;
+    const uint32_t B = blocks_of(M);
+    const uint32_t R = (B + kColGroups - 1) / kColGroups;
+    const uint32_t b0 = min(B, g * R), b1 = min(B, b0 + R);
+    uint32_t s = 0;
+    if (t < T)
+        for (uint32_t b = b0; b < b1; b++) s += hist[(size_t)b * T + t];
+    s_part[g][tl] = s;
+    __syncthreads();
+    if (t >= T) return;
+    uint32_t run = ranges[t].x;
+    for (uint32_t k = 0; k < g; k++) run += s_part[k][tl];
+    for (uint32_t b = b0; b < b1; b++) {
+        const size_t i = (size_t)b * T + t;
+        const uint32_t c = hist[i];
+        hist[i] = run;
+        run += c;
+    }
+}
+
+// One block: exclusive scan of the tile totals -> ranges, processing order,
+// long-list queues, longest list.
 constexpr int kTilesThreads = 1024;
 
-__global__ __launch_bounds__(kTilesThreads) void k_tiles(const FrameParams* fp, FrameInfo* info,
-                                                         int32_t* __restrict__ diff, uint2* __restrict__ ranges,
-                                                         uint32_t* __restrict__ cursor, uint32_t* __restrict__ order,
-                                                         uint32_t* __restrict__ large, uint64_t max_instances)
+__global__ __launch_bounds__(kTilesThreads) void k_tile_scan(const FrameParams* fp, FrameInfo* info,
+                                                             const uint32_t* __restrict__ tcount,
+                                                             uint2* __restrict__ ranges, uint32_t* __restrict__ order,
+                                                             uint32_t* __restrict__ large)
 {
     __shared__ uint32_t s_part[kTilesThreads];
     __shared__ uint32_t s_cls[4], s_cls_base[4], s_max, s_nl, s_nh;
-    const int32_t TX = fp->TX, TY = fp->TY, P = TX + 1;
-    const uint32_t T = (uint32_t)(TX * TY);
+    const uint32_t T = (uint32_t)(fp->TX * fp->TY);
     const uint32_t tid = threadIdx.x;
     if (tid < 4) s_cls[tid] = 0;
     if (tid == 0) { s_max = 0; s_nl = 0; s_nh = 0; }
-    // prefix along x within each row, then along y within each column
-    for (int32_t y = tid; y < TY; y += kTilesThreads) {
-        int32_t run = 0;
-        for (int32_t x = 0; x < TX; x++) { run += diff[y * P + x]; diff[y * P + x] = run; }
-    }
-    __syncthreads();
-    for (int32_t x = tid; x < TX; x += kTilesThreads) {
-        int32_t run = 0;
-        for (int32_t y = 0; y < TY; y++) { run += diff[y * P + x]; diff[y * P + x] = run; }
-    }
-    __syncthreads();
-    const bool ovf = info->n_instances > max_instances;
-    // exclusive scan over tiles in row-major order; each thread a contiguous chunk
     const uint32_t per = (T + kTilesThreads - 1) / kTilesThreads;
-    const uint32_t t0 = tid * per, t1 = min(T, t0 + per);
+    const uint32_t t0 = min(T, tid * per), t1 = min(T, t0 + per);
     uint32_t local = 0, lmax = 0;
     for (uint32_t t = t0; t < t1; t++) {
-        const uint32_t c = (uint32_t)diff[(t / TX) * P + (t % TX)];
+        const uint32_t c = tcount[t];
         local += c;
         lmax = max(lmax, c);
     }
     s_part[tid] = local;
-    atomicMax(&s_max, lmax);
     __syncthreads();
+    atomicMax(&s_max, lmax);
     for (int off = 1; off < kTilesThreads; off <<= 1) {
         const uint32_t o = tid >= (uint32_t)off ? s_part[tid - off] : 0u;
         __syncthreads();
@@ -179,9 +329,8 @@ __global__ __launch_bounds__(kTilesThreads) void k_tiles(const FrameParams* fp, 
     }
     uint32_t run = s_part[tid] - local;
     for (uint32_t t = t0; t < t1; t++) {
-        const uint32_t c = ovf ? 0u : (uint32_t)diff[(t / TX) * P + (t % TX)];
+        const uint32_t c = tcount[t];
         ranges[t] = make_uint2(run, run + c);
-        cursor[t] = run;
         const uint32_t cls = c > 1024u ? 0u : (c > 256u ? 1u : (c > 64u ? 2u : 3u));
         atomicAdd(&s_cls[cls], 1u);
         if (c > (uint32_t)kSortLarge) large[T + atomicAdd(&s_nh, 1u)] = t;
@@ -198,76 +347,32 @@ __global__ __launch_bounds__(kTilesThreads) void k_tiles(const FrameParams* fp, 
     }
     __syncthreads();
     for (uint32_t t = t0; t < t1; t++) {
-        const uint32_t c = ranges[t].y - ranges[t].x;
+        const uint32_t c = tcount[t];
         const uint32_t cls = c > 1024u ? 0u : (c > 256u ? 1u : (c > 64u ? 2u : 3u));
         order[s_cls_base[cls] + atomicAdd(&s_cls[cls], 1u)] = t;
     }
 }
 
-constexpr int kEmitThreads = 256;
-constexpr int kEmitItems = 4;
-constexpr int kEmitChunk = kEmitThreads * kEmitItems;
-
-__device__ __forceinline__ uint32_t upper_bound_g(const uint32_t* a, uint32_t n, uint32_t key)
+__global__ __launch_bounds__(kBinThreads) void k_scatter(const FrameParams* fp, const FrameInfo* info,
+                                                         const uint2* __restrict__ inst,
+                                                         const uint32_t* __restrict__ hist,
+                                                         uint32_t* __restrict__ sorted, uint64_t max_instances)
 {
-    uint32_t lo = 0, hi = n;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (a[mid] <= key) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
-__global__ __launch_bounds__(kEmitThreads) void k_emit(const FrameParams* fp, const FrameInfo* info,
-                                                        const uint32_t* __restrict__ off,
-                                                        const uint32_t* __restrict__ vis,
-                                                        const float4* __restrict__ proj,
-                                                        uint32_t* __restrict__ cursor, uint32_t* __restrict__ sorted,
-                                                        uint64_t max_instances)
-{
-    __shared__ uint32_t s_off[kEmitChunk + 1];
-    __shared__ uint32_t s_lo, s_cnt;
-    const uint32_t nvis = info->n_visible;
+    __shared__ uint32_t s_rank[kMaxTiles / 2];
     const unsigned long long M = info->n_instances;
-    if (M > max_instances || nvis == 0) return;
-    const int32_t TX = fp->TX;
-    const uint32_t nchunks = (uint32_t)((M + kEmitChunk - 1) / kEmitChunk);
-    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        const uint32_t j0 = c * kEmitChunk;
-        const uint32_t j1 = (uint32_t)min((unsigned long long)j0 + kEmitChunk, M);   // exclusive
-        if (threadIdx.x == 0) {
-            const uint32_t lo = upper_bound_g(off, nvis, j0) - 1;
-            const uint32_t hi = upper_bound_g(off, nvis, j1 - 1) - 1;
-            s_lo = lo;
-            const uint32_t c = hi - lo + 1;   // <= kEmitChunk: every visible Gaussian has >= 1 instance
-            s_cnt = c <= (uint32_t)kEmitChunk ? c : (uint32_t)kEmitChunk;
-        }
+    if (M == 0 || M > max_instances) return;
+    const uint32_t T = (uint32_t)(fp->TX * fp->TY);
+    const uint32_t B = blocks_of(M);
+    for (uint32_t b = blockIdx.x; b < B; b += gridDim.x) {
+        const uint32_t j0 = b * kBinChunk;
+        const uint32_t j1 = (uint32_t)min((unsigned long long)j0 + kBinChunk, M);
+        for (uint32_t k = threadIdx.x; k < (T + 1) / 2; k += kBinThreads) s_rank[k] = 0;
         __syncthreads();
-        const uint32_t lo = s_lo, cnt = s_cnt;
-        for (uint32_t k = threadIdx.x; k < cnt; k += kEmitThreads) s_off[k] = off[lo + k];
-        __syncthreads();
-#pragma unroll
-        for (int it = 0; it < kEmitItems; it++) {
-            const uint32_t j = j0 + it * kEmitThreads + threadIdx.x;
-            if (j < j1) {
-                // last window entry with s_off <= j
-                uint32_t a_lo = 0, a_hi = cnt;
-                while (a_lo < a_hi) {
-                    const uint32_t mid = (a_lo + a_hi) >> 1;
-                    if (s_off[mid] <= j) a_lo = mid + 1; else a_hi = mid;
-                }
-                const uint32_t vi = lo + a_lo - 1;
-                const uint32_t k = j - s_off[a_lo - 1];
-                const uint32_t a = vis[vi];
-                const float4 r2 = proj[3 * (size_t)a + 2];
-                const uint32_t p0 = __float_as_uint(r2.z), p1 = __float_as_uint(r2.w);
-                const uint32_t x0 = p0 & 0xffffu, y0 = p0 >> 16, x1 = p1 & 0xffffu;
-                const uint32_t wr = x1 - x0;
-                const uint32_t row = k / wr;
-                const uint32_t tile = (y0 + row) * (uint32_t)TX + x0 + (k - row * wr);
-                const uint32_t dst = atomicAdd(&cursor[tile], 1u);
-                if (dst < max_instances) sorted[dst] = a;
-            }
+        const uint32_t* row = hist + (size_t)b * T;
+        for (uint32_t j = j0 + threadIdx.x; j < j1; j += kBinThreads) {
+            const uint2 e = inst[j];
+            const uint32_t slot = row[e.x] + hist_inc(s_rank, e.x);
+            if (slot < max_instances) sorted[slot] = e.y;
         }
         __syncthreads();
     }
@@ -275,16 +380,19 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(const FrameParams* fp, co
 
 }  // namespace
 
-hipError_t launch_bin(const Views& v, hipStream_t st)
+hipError_t launch_bin(const Views& v, const lodge_selection& sel, hipStream_t st)
 {
-    k_scan_inst<<<v.lay.scan_tiles, kScanBlock, 0, st>>>(v.info, v.scan_flags, v.vtiles, v.max_instances);
-    k_tiles<<<1, kTilesThreads, 0, st>>>(v.params, v.info, v.diff, v.ranges, v.cursor, v.order, v.large,
-                                         v.max_instances);
-    uint32_t blocks = (uint32_t)((v.max_instances + kEmitChunk - 1) / kEmitChunk);
-    if (blocks < 1) blocks = 1;
-    if (blocks > (uint32_t)kPersistentBlocks) blocks = kPersistentBlocks;
-    k_emit<<<blocks, kEmitThreads, 0, st>>>(v.params, v.info, v.vtiles, v.vis, v.proj, v.cursor, v.sorted,
-                                            v.max_instances);
+    k_scan_inst<<<v.lay.scan_tiles, kScanBlock, 0, st>>>(v.info, v.scan_flags, v.vtiles, sel.count, sel.cap,
+                                                         v.max_instances);
+    const uint32_t bmax = std::max<uint32_t>(1, (uint32_t)((v.max_instances + kBinChunk - 1) / kBinChunk));
+    const uint32_t grid = std::min<uint32_t>(bmax, 1024);
+    k_emit_hist<<<grid, kBinThreads, 0, st>>>(v.params, v.info, v.vtiles, sel.count, sel.cap, v.rect, v.inst, v.hist,
+                                              v.max_instances);
+    const uint32_t tb = (v.lay.T + kColTiles - 1) / kColTiles;
+    k_col_sum<<<tb, 256, 0, st>>>(v.params, v.info, v.hist, v.tcount, v.max_instances);
+    k_tile_scan<<<1, kTilesThreads, 0, st>>>(v.params, v.info, v.tcount, v.ranges, v.order, v.large);
+    k_col_offset<<<tb, 256, 0, st>>>(v.params, v.info, v.ranges, v.hist, v.max_instances);
+    k_scatter<<<grid, kBinThreads, 0, st>>>(v.params, v.info, v.inst, v.hist, v.sorted, v.max_instances);
     return hipGetLastError();
 }
 

@@ -35,6 +35,8 @@ struct LevelsArg {
     int32_t L;
     uint32_t total;
     float d[LODGE_MAX_LEVELS];   // d_1 .. d_{L-1}
+    uint32_t first_block[LODGE_MAX_LEVELS + 1];   // selection blocks: level l owns [first_block[l], first_block[l+1])
+    uint32_t sel_blocks;
 };
 
 struct ChunksArg {
@@ -92,11 +94,13 @@ constexpr int kScanTile = kScanBlock * kScanItems;
 constexpr int kSortSmall = 2048;                    // per-tile LDS sort, 256 threads
 constexpr int kSortLarge = 16384;                   // per-tile LDS sort, 1024 threads
 constexpr int kProjStride = 12;                     // floats per projected record
+constexpr int kBinChunk = 8192;                     // instances per binning block
+constexpr int kMaxTiles = 32768;                    // 16-bit-packed LDS tile histograms (e.g. 3840 x 2160)
 
 struct Layout {
-    size_t params, info, sel_flags, scan_flags, proj, vis, vtiles, diff, ranges, cursor, order, large, sorted, temp,
-        g2d, total;
-    uint32_t sel_tiles, scan_tiles, TX, TY, T;
+    size_t params, info, sel_flags, scan_flags, proj, depth, rect, vtiles, inst, hist, tcount, ranges, order, large,
+        sorted, temp, g2d, total;
+    uint32_t sel_tiles, scan_tiles, TX, TY, T, bin_blocks;
 };
 
 Layout make_layout(uint32_t n_total, int32_t width, int32_t height, uint32_t max_active, uint64_t max_instances);
@@ -107,12 +111,14 @@ struct Views {
     FrameInfo* info;
     unsigned long long* sel_flags;
     unsigned long long* scan_flags;
-    float4* proj;          // [max_active][3]: (u, v, A, B), (C, o, r, g), (b, depth, rect01, rect23)
-    uint32_t* vis;         // visible list (active indices, unordered)
-    uint32_t* vtiles;      // tiles touched -> exclusive instance offsets (in place)
-    int32_t* diff;         // (TY+1) x (TX+1) difference grid of per-tile counts
+    float4* proj;          // [max_active][3]: (u, v, A, B), (C, o, r, g), (b, ex, ey, thr); visible only
+    float* depth;          // [max_active] camera depth (sort key), 0 when culled
+    uint2* rect;           // [max_active] tile rect (x0 | y0 << 16, x1 | y1 << 16), empty when culled
+    uint32_t* vtiles;      // tiles touched per active index -> exclusive instance offsets (in place)
+    uint2* inst;           // [max_instances] (tile, active index) in emission order
+    uint32_t* hist;        // [bin blocks][T] per-block tile counts -> per-block first slots
+    uint32_t* tcount;      // per tile list length
     uint2* ranges;         // per tile [start, end)
-    uint32_t* cursor;      // per tile fill position
     uint32_t* order;       // tiles by decreasing list length
     uint32_t* large;       // tiles whose list exceeds kSortSmall
     uint32_t* sorted;      // [max_instances] active indices, tile-major
@@ -128,11 +134,12 @@ Views views_of(const lodge_workspace* ws, uint32_t n_total);
 // ----------------------------------------------------------------- launchers
 // Each returns hipGetLastError() after enqueueing on `st`.
 
+hipError_t launch_set_camera(const lodge_camera& cam, const Views& v, hipStream_t st);
 hipError_t launch_select_setup(const LevelsArg& lv, const ChunksArg& ch, int32_t mode, const Views& v, hipStream_t st);
 hipError_t launch_select(const LevelsArg& lv, const Views& v, const lodge_selection& sel, hipStream_t st);
 hipError_t launch_render_setup(const lodge_render_opts& o, const Views& v, hipStream_t st);
 hipError_t launch_project(const LevelsArg& lv, const lodge_selection& sel, const Views& v, hipStream_t st);
-hipError_t launch_bin(const Views& v, hipStream_t st);
+hipError_t launch_bin(const Views& v, const lodge_selection& sel, hipStream_t st);
 hipError_t launch_sort(const Views& v, hipStream_t st);
 hipError_t launch_composite(const Views& v, float* image, float* final_T, uint32_t* n_contrib, hipStream_t st);
 hipError_t launch_backward(const LevelsArg& lv, const lodge_selection& sel, const Views& v, const float* final_T,

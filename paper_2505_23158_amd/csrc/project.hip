@@ -8,9 +8,11 @@
 // mean, selection id and weight are read first; Gaussians behind the near
 // plane stop there, so scale, rotation, opacity and the 192-byte SH block
 // are read only for Gaussians in front of the camera (SH only for visible
-// ones).  Visible Gaussians append themselves to an unordered list (one
-// atomic per wave) and add their tile rectangle to a 2-D difference grid,
-// whose prefix sums are the per-tile list lengths.
+// ones).  Each active Gaussian writes its depth, tile rectangle and tile
+// count (0 when culled); visible ones also write a 48-byte compositing
+// record (centre, conic, opacity, colour, the power below which alpha
+// cannot reach 1/255, and the half-extents of the ellipse where it can).
+// The front/visible counters are reduced per block and added once.
 //
 // Built with -ffp-contract=off: the rectangle and depth (which decide tile
 // membership and sort keys) are evaluated op for op as the oracle defines
@@ -71,23 +73,24 @@ __device__ __forceinline__ int level_of(const LevelsArg& lv, uint32_t g)
 __global__ __launch_bounds__(256) void k_project(LevelsArg lv, const uint32_t* __restrict__ ids,
                                                  const float* __restrict__ wsel, const uint32_t* __restrict__ count,
                                                  uint32_t cap, const FrameParams* __restrict__ fp, FrameInfo* info,
-                                                 float4* __restrict__ proj, uint32_t* __restrict__ vis,
-                                                 uint32_t* __restrict__ vtiles, int32_t* __restrict__ diff)
+                                                 float4* __restrict__ proj, float* __restrict__ depth,
+                                                 uint2* __restrict__ rect, uint32_t* __restrict__ vtiles)
 {
+    __shared__ uint32_t s_cnt[2][4];
     const uint32_t n_act = min(*count, cap);
     const lodge_camera& cam = fp->cam;
     const float s2d = fp->s2d;
     const int compensate = fp->compensate;
     const int32_t TX = fp->TX, TY = fp->TY;
-    const uint32_t lane = threadIdx.x & 63;
-    const unsigned long long lt = (1ull << lane) - 1ull;
     const uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t n_front = 0, n_vis = 0;
 
     for (uint32_t base = blockIdx.x * blockDim.x; base < n_act; base += stride) {
         const uint32_t a = base + threadIdx.x;
         bool visible = false, front = false;
         uint32_t ntiles = 0;
         float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+        float dep = 0.0f;
         int32_t x0 = 0, y0 = 0, x1 = 0, y1 = 0;
         if (a < n_act) {
             const uint32_t g = ids[a];
@@ -190,38 +193,45 @@ __global__ __launch_bounds__(256) void k_project(LevelsArg lv, const uint32_t* _
                             rgb[ch] = acc > 0.0f ? acc : 0.0f;
                         }
                         const float o_eff = ((L.opacity[i] * wsel[a]) * comp3) * comp2;
+                        // compositing aids: below power thr alpha cannot reach 1/255 (margin 1e-3);
+                        // (ex, ey) half-extents of the ellipse where it can: d^T conic d <= -2 thr
+                        const float thr = o_eff > 0.0f ? -logf(255.0f * o_eff) - 1e-3f : INFINITY;
+                        const float rho = -2.0f * thr;
+                        const float ex = rho > 0.0f ? sqrtf(rho * aa) : -1.0f;
+                        const float ey = rho > 0.0f ? sqrtf(rho * cc) : -1.0f;
                         r0 = make_float4(u, v, A, B);
                         r1 = make_float4(C, o_eff, rgb[0], rgb[1]);
-                        r2 = make_float4(rgb[2], tz, __uint_as_float((uint32_t)x0 | ((uint32_t)y0 << 16)),
-                                         __uint_as_float((uint32_t)x1 | ((uint32_t)y1 << 16)));
+                        r2 = make_float4(rgb[2], ex, ey, thr);
+                        dep = tz;
                     }
                 }
             }
-            proj[3 * (size_t)a] = r0;
-            proj[3 * (size_t)a + 1] = r1;
-            proj[3 * (size_t)a + 2] = r2;
-        }
-        const unsigned long long mf = __ballot(front);
-        if (mf != 0ull && lane == (uint32_t)(__ffsll((long long)mf) - 1))
-            atomicAdd(&info->n_front, (uint32_t)__popcll(mf));
-        // unordered compaction of the visible set: one atomic per wave
-        const unsigned long long m = __ballot(visible);
-        if (m != 0ull) {
-            uint32_t wbase = 0;
-            const int leader = __ffsll((long long)m) - 1;
-            if ((int)lane == leader) wbase = atomicAdd(&info->n_visible, (uint32_t)__popcll(m));
-            wbase = __shfl(wbase, leader);
             if (visible) {
-                const uint32_t pos = wbase + (uint32_t)__popcll(m & lt);
-                vis[pos] = a;
-                vtiles[pos] = ntiles;
-                const int32_t P = TX + 1;
-                atomicAdd(&diff[y0 * P + x0], 1);
-                atomicAdd(&diff[y0 * P + x1], -1);
-                atomicAdd(&diff[y1 * P + x0], -1);
-                atomicAdd(&diff[y1 * P + x1], 1);
+                proj[3 * (size_t)a] = r0;
+                proj[3 * (size_t)a + 1] = r1;
+                proj[3 * (size_t)a + 2] = r2;
             }
+            depth[a] = dep;
+            // culled: the canonical empty rect (the clamped bounds may be -1 and must not be packed)
+            rect[a] = visible ? make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16))
+                              : make_uint2(0u, 0u);
+            vtiles[a] = ntiles;
+            n_front += front ? 1u : 0u;
+            n_vis += visible ? 1u : 0u;
         }
+    }
+    // counters: wave sums, block sum, one atomic per block
+    for (int off = 32; off > 0; off >>= 1) {
+        n_front += __shfl_xor(n_front, off);
+        n_vis += __shfl_xor(n_vis, off);
+    }
+    if ((threadIdx.x & 63) == 0) { s_cnt[0][threadIdx.x >> 6] = n_front; s_cnt[1][threadIdx.x >> 6] = n_vis; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t f = s_cnt[0][0] + s_cnt[0][1] + s_cnt[0][2] + s_cnt[0][3];
+        const uint32_t v = s_cnt[1][0] + s_cnt[1][1] + s_cnt[1][2] + s_cnt[1][3];
+        if (f) atomicAdd(&info->n_front, f);
+        if (v) atomicAdd(&info->n_visible, v);
     }
 }
 
@@ -231,9 +241,9 @@ hipError_t launch_project(const LevelsArg& lv, const lodge_selection& sel, const
 {
     uint32_t blocks = (v.max_active + 255) / 256;
     if (blocks < 1) blocks = 1;
-    if (blocks > kPersistentBlocks * 2) blocks = kPersistentBlocks * 2;
-    k_project<<<blocks, 256, 0, st>>>(lv, sel.ids, sel.w, sel.count, sel.cap, v.params, v.info, v.proj, v.vis,
-                                      v.vtiles, v.diff);
+    if (blocks > kPersistentBlocks) blocks = kPersistentBlocks;
+    k_project<<<blocks, 256, 0, st>>>(lv, sel.ids, sel.w, sel.count, sel.cap, v.params, v.info, v.proj, v.depth,
+                                      v.rect, v.vtiles);
     return hipGetLastError();
 }
 

@@ -3,13 +3,15 @@
 // two-chunk opacity weights of Eq. 4).
 //
 // k_select_setup  one wave finds the two nearest chunk centres and t, and
-//                 turns the switch distances into squared FP32 bounds;
-//                 the other blocks clear the look-back flags.
-// k_select        one pass over every Gaussian of every level: coalesced
-//                 loads of the three mean planes, membership on squared
-//                 FP32 distances, wave ballots + an LDS scan for the block
-//                 offsets, and a decoupled look-back across blocks so the
-//                 output stays in ascending global id without a second pass.
+//                 turns the switch distances into squared FP32 bounds
+//                 (k_zero64 clears the look-back flags before it).
+// k_select        one pass over every Gaussian of every level (each block
+//                 inside one level, so its parameters and bounds are
+//                 uniform): coalesced loads of the three mean planes,
+//                 membership on squared FP32 distances, wave ballots + an
+//                 LDS scan for the block offsets, and a decoupled look-back
+//                 across blocks so the output stays in ascending global id
+//                 without a second pass.
 //
 // Bit-exactness: this file is built with -ffp-contract=off, so each
 // +, -, *, / and sqrt below is one IEEE-rounded FP32 operation, evaluated
@@ -163,34 +165,47 @@ __global__ __launch_bounds__(kSelBlock) void k_select(LevelsArg lv, const FrameP
     const uint32_t tile = s_tile;
     if (tile >= ntiles) return;
 
+    // every block lies inside one level: level parameters and bounds are block-uniform
+    int l = 0;
+#pragma unroll
+    for (int j = 1; j < LODGE_MAX_LEVELS; j++)
+        if (j < lv.L && tile >= lv.first_block[j]) l = j;
+    const LevelDev& L = lv.lv[l];
+    const uint32_t n = L.n;
+    const uint32_t i0 = (tile - lv.first_block[l]) * (uint32_t)kSelTile;
     const int32_t mode = fp->mode;
+    const bool all = mode == LODGE_SELECT_ALL;
     const bool two = (mode == LODGE_SELECT_CHUNKED) && (fp->o >= 0);
     const float cf[3] = {fp->cf[0], fp->cf[1], fp->cf[2]};
     const float co[3] = {fp->co[0], fp->co[1], fp->co[2]};
-    const uint32_t total = lv.total;
-    const uint32_t base = tile * (uint32_t)kSelTile;
+    const float lof = fp->lo_f[l], hif = fp->hi_f[l], loo = fp->lo_o[l], hio = fp->hi_o[l];
 
+    // all loads first (48 in flight per thread), then the tests
+    float mx[kSelItems], my[kSelItems], mz[kSelItems];
+#pragma unroll
+    for (int r = 0; r < kSelItems; r++) {
+        const uint32_t i = i0 + (uint32_t)r * kSelBlock + tid;
+        mx[r] = my[r] = mz[r] = 0.0f;
+        if (i < n && !all) {
+            mx[r] = L.mean[i];
+            my[r] = L.mean[(size_t)n + i];
+            mz[r] = L.mean[2 * (size_t)n + i];
+        }
+    }
     uint32_t bits = 0;   // 2 bits per item: in_f, in_o
 #pragma unroll
     for (int r = 0; r < kSelItems; r++) {
-        const uint32_t g = base + (uint32_t)r * kSelBlock + tid;
+        const uint32_t i = i0 + (uint32_t)r * kSelBlock + tid;
         uint32_t s = 0;
-        if (g < total) {
-            int l = 0;
-#pragma unroll
-            for (int j = 1; j < LODGE_MAX_LEVELS; j++)
-                if (j < lv.L && g >= lv.lv[j].base) l = j;
-            if (mode == LODGE_SELECT_ALL) {
+        if (i < n) {
+            if (all) {
                 s = 1;
             } else {
-                const LevelDev& L = lv.lv[l];
-                const uint32_t i = g - L.base;
-                const float mx = L.mean[i], my = L.mean[(size_t)L.n + i], mz = L.mean[2 * (size_t)L.n + i];
-                const float df = dist2(mx, my, mz, cf);
-                if (fp->lo_f[l] <= df && df < fp->hi_f[l]) s |= 1u;
+                const float df = dist2(mx[r], my[r], mz[r], cf);
+                if (lof <= df && df < hif) s |= 1u;
                 if (two) {
-                    const float dq = dist2(mx, my, mz, co);
-                    if (fp->lo_o[l] <= dq && dq < fp->hi_o[l]) s |= 2u;
+                    const float dq = dist2(mx[r], my[r], mz[r], co);
+                    if (loo <= dq && dq < hio) s |= 2u;
                 }
             }
         }
@@ -242,7 +257,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select(LevelsArg lv, const FrameP
         if (s != 0u) {
             const uint32_t pos = excl + s_cnt[r * 4 + wave] + (uint32_t)__popcll(m & lt);
             if (pos < cap) {
-                ids[pos] = base + (uint32_t)r * kSelBlock + tid;
+                ids[pos] = L.base + i0 + (uint32_t)r * kSelBlock + tid;
                 w[pos] = (s == 3u) ? 1.0f : (s == 1u ? t : w_o);
             }
         }
@@ -253,7 +268,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select(LevelsArg lv, const FrameP
 
 hipError_t launch_select_setup(const LevelsArg& lv, const ChunksArg& ch, int32_t mode, const Views& v, hipStream_t st)
 {
-    const uint32_t n = v.lay.sel_tiles;
+    const uint32_t n = std::max<uint32_t>(lv.sel_blocks, 1);   // an empty scene still runs one block (count 0)
     uint32_t blocks = (n + 255) / 256;
     if (blocks < 1) blocks = 1;
     if (blocks > 1024) blocks = 1024;
@@ -264,7 +279,7 @@ hipError_t launch_select_setup(const LevelsArg& lv, const ChunksArg& ch, int32_t
 
 hipError_t launch_select(const LevelsArg& lv, const Views& v, const lodge_selection& sel, hipStream_t st)
 {
-    const uint32_t ntiles = v.lay.sel_tiles;
+    const uint32_t ntiles = std::max<uint32_t>(lv.sel_blocks, 1);
     k_select<<<ntiles, kSelBlock, 0, st>>>(lv, v.params, v.info, v.sel_flags, ntiles, sel.ids, sel.w, sel.cap,
                                            sel.count);
     return hipGetLastError();

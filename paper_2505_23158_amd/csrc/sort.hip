@@ -21,11 +21,10 @@ namespace {
 
 // Indices come from the emission pass; one outside [0, cap) would be a
 // binning bug, so it sorts last instead of being dereferenced.
-__device__ __forceinline__ unsigned long long key_of(const float4* __restrict__ proj, uint32_t a, uint32_t cap)
+__device__ __forceinline__ unsigned long long key_of(const float* __restrict__ depth, uint32_t a, uint32_t cap)
 {
     if (a >= cap) return ~0ull;
-    const float depth = proj[3 * (size_t)a + 2].y;
-    return ((unsigned long long)__float_as_uint(depth) << 32) | a;
+    return ((unsigned long long)__float_as_uint(depth[a]) << 32) | a;
 }
 
 __device__ __forceinline__ uint32_t next_pow2(uint32_t n)
@@ -54,7 +53,7 @@ __device__ __forceinline__ void bitonic_lds(unsigned long long* s, uint32_t P)
 }
 
 template <int NT, int CAP>
-__device__ __forceinline__ void sort_run(unsigned long long* s, const float4* __restrict__ proj,
+__device__ __forceinline__ void sort_run(unsigned long long* s, const float* __restrict__ proj,
                                          uint32_t* __restrict__ run, uint32_t n, uint32_t cap)
 {
     const uint32_t P = next_pow2(n);
@@ -66,7 +65,7 @@ __device__ __forceinline__ void sort_run(unsigned long long* s, const float4* __
 }
 
 __global__ __launch_bounds__(256) void k_sort_small(const FrameParams* fp, const uint2* __restrict__ ranges,
-                                                    const float4* __restrict__ proj, uint32_t* __restrict__ sorted,
+                                                    const float* __restrict__ proj, uint32_t* __restrict__ sorted,
                                                     uint32_t cap)
 {
     __shared__ unsigned long long s[kSortSmall];
@@ -75,13 +74,28 @@ __global__ __launch_bounds__(256) void k_sort_small(const FrameParams* fp, const
         const uint2 r = ranges[t];
         const uint32_t n = r.y - r.x;
         if (n <= 1 || n > (uint32_t)kSortSmall) continue;
-        sort_run<256, kSortSmall>(s, proj, sorted + r.x, n, cap);
+        uint32_t* run = sorted + r.x;
+        if (n <= 256) {
+            // rank sort: keys are unique, so each key's rank is the number of smaller keys
+            const uint32_t i = threadIdx.x;
+            unsigned long long mine = ~0ull;
+            if (i < n) s[i] = mine = key_of(proj, run[i], cap);
+            __syncthreads();
+            uint32_t rank = 0;
+            if (i < n)
+                for (uint32_t j = 0; j < n; j++) rank += s[j] < mine ? 1u : 0u;
+            __syncthreads();
+            if (i < n) run[rank] = mine == ~0ull ? 0xffffffffu : (uint32_t)mine;
+            __syncthreads();
+        } else {
+            sort_run<256, kSortSmall>(s, proj, run, n, cap);
+        }
     }
 }
 
 __global__ __launch_bounds__(1024) void k_sort_large(const FrameInfo* info, const uint2* __restrict__ ranges,
                                                      const uint32_t* __restrict__ large,
-                                                     const float4* __restrict__ proj, uint32_t* __restrict__ sorted,
+                                                     const float* __restrict__ proj, uint32_t* __restrict__ sorted,
                                                      uint32_t cap)
 {
     __shared__ unsigned long long s[kSortLarge];
@@ -94,7 +108,7 @@ __global__ __launch_bounds__(1024) void k_sort_large(const FrameInfo* info, cons
 
 // position of key x among the sorted run b[0, n): number of keys < x
 __device__ __forceinline__ uint32_t rank_in(const uint32_t* __restrict__ b, uint32_t n, unsigned long long x,
-                                            const float4* __restrict__ proj, uint32_t cap)
+                                            const float* __restrict__ proj, uint32_t cap)
 {
     uint32_t lo = 0, hi = n;
     while (lo < hi) {
@@ -106,7 +120,7 @@ __device__ __forceinline__ uint32_t rank_in(const uint32_t* __restrict__ b, uint
 
 __global__ __launch_bounds__(1024) void k_sort_huge(const FrameParams* fp, const FrameInfo* info,
                                                     const uint2* __restrict__ ranges, const uint32_t* __restrict__ large,
-                                                    const float4* __restrict__ proj, uint32_t* __restrict__ sorted,
+                                                    const float* __restrict__ proj, uint32_t* __restrict__ sorted,
                                                     uint32_t* __restrict__ scratch, uint32_t cap)
 {
     __shared__ unsigned long long s[kSortLarge];
@@ -145,9 +159,9 @@ __global__ __launch_bounds__(1024) void k_sort_huge(const FrameParams* fp, const
 
 hipError_t launch_sort(const Views& v, hipStream_t st)
 {
-    k_sort_small<<<v.lay.T, 256, 0, st>>>(v.params, v.ranges, v.proj, v.sorted, v.max_active);
-    k_sort_large<<<256, 1024, 0, st>>>(v.info, v.ranges, v.large, v.proj, v.sorted, v.max_active);
-    k_sort_huge<<<64, 1024, 0, st>>>(v.params, v.info, v.ranges, v.large, v.proj, v.sorted,
+    k_sort_small<<<v.lay.T, 256, 0, st>>>(v.params, v.ranges, v.depth, v.sorted, v.max_active);
+    k_sort_large<<<256, 1024, 0, st>>>(v.info, v.ranges, v.large, v.depth, v.sorted, v.max_active);
+    k_sort_huge<<<64, 1024, 0, st>>>(v.params, v.info, v.ranges, v.large, v.depth, v.sorted,
                                      reinterpret_cast<uint32_t*>(v.temp), v.max_active);
     return hipGetLastError();
 }

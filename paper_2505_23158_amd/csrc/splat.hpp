@@ -3,10 +3,11 @@
 //
 // A staged splat is three LDS words: geo = (u, v, -A/2, -B),
 // col = (-C/2, o_eff, skip threshold, r), gb = (g, b), where (A, B, C) is the
-// conic and the skip threshold is ln(1 / (255 o_eff)) - 1e-3 (+inf when
-// o_eff <= 0): a power below it cannot give alpha >= 1/255, so exp is not
-// evaluated for it.  Explicit fmaf keeps the arithmetic identical wherever
-// this is inlined (the files are built without FMA contraction).
+// conic and the skip threshold, from the projection, is ln(1 / (255 o_eff))
+// - 1e-3 (+inf when o_eff <= 0): a power below it cannot give alpha >= 1/255,
+// so exp is not evaluated for it.  Explicit fmaf keeps the arithmetic
+// identical wherever this is inlined (the files are built without FMA
+// contraction).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,12 +23,10 @@ __device__ __forceinline__ void stage_splat(const float4* __restrict__ proj, uin
 {
     const float4 r0 = proj[3 * (size_t)a];
     const float4 r1 = proj[3 * (size_t)a + 1];
-    const float b = proj[3 * (size_t)a + 2].x;
-    const float o = r1.y;
-    const float thr = o > 0.0f ? -__logf(255.0f * o) - 1e-3f : INFINITY;
+    const float4 r2 = proj[3 * (size_t)a + 2];
     geo = make_float4(r0.x, r0.y, -0.5f * r0.z, -r0.w);
-    col = make_float4(-0.5f * r1.x, o, thr, r1.z);
-    gb = make_float2(r1.w, b);
+    col = make_float4(-0.5f * r1.x, r1.y, r2.w, r1.z);
+    gb = make_float2(r1.w, r2.x);
 }
 
 __device__ __forceinline__ float splat_power(const float4& geo, const float4& col, float px, float py, float& dx,

@@ -102,12 +102,14 @@ def lib():
             "lodge_scene_destroy": (None, [vp]),
             "lodge_scene_total": (C.c_int64, [vp]),
             "lodge_workspace_size": (st, [vp, C.c_int32, C.c_int32, C.c_uint32, C.c_uint64, C.POINTER(C.c_size_t)]),
+            "lodge_set_camera": (st, [C.POINTER(lodge_workspace), vp, vp]),
             "lodge_select": (st, [vp, vp, C.c_int32, C.POINTER(lodge_workspace), C.POINTER(lodge_selection), vp]),
             "lodge_render": (st, [vp, C.POINTER(lodge_selection), vp, C.POINTER(lodge_render_opts),
                                   C.POINTER(lodge_workspace), vp, vp, vp, vp]),
             "lodge_frame_info_read": (st, [C.POINTER(lodge_workspace), C.POINTER(lodge_frame_info), vp]),
             "lodge_check": (st, [C.POINTER(lodge_workspace), C.POINTER(C.c_uint32), C.POINTER(C.c_uint64), vp]),
-            "lodge_debug_views": (st, [C.POINTER(lodge_workspace), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]),
+            "lodge_debug_views": (st, [C.POINTER(lodge_workspace), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                                       C.POINTER(vp), C.POINTER(vp)]),
             "lodge_render_backward": (st, [vp, C.POINTER(lodge_selection), vp, C.POINTER(lodge_render_opts),
                                            C.POINTER(lodge_workspace), vp, vp, vp, C.c_int32,
                                            C.POINTER(lodge_grads), vp]),
@@ -128,7 +130,7 @@ def _check(status: int):
 
 
 EXPORTED = ["lodge_status_string", "lodge_last_error", "lodge_version", "lodge_scene_create", "lodge_scene_destroy",
-            "lodge_scene_total", "lodge_workspace_size", "lodge_select", "lodge_render", "lodge_frame_info_read",
+            "lodge_scene_total", "lodge_workspace_size", "lodge_set_camera", "lodge_select", "lodge_render", "lodge_frame_info_read",
             "lodge_check", "lodge_debug_views", "lodge_render_backward", "lodge_activate", "lodge_activate_backward"]
 
 
@@ -163,20 +165,6 @@ def make_camera(cam) -> lodge_camera:
         c.bg[i] = float(cam.bg[i])
     c.znear, c.lim_x, c.lim_y = float(cam.znear), float(cam.lim_x), float(cam.lim_y)
     return c
-
-
-class PinnedCamera:
-    """A lodge_camera in pinned host memory: calls captured into a HIP graph
-    record a copy of it that re-reads the current contents at every replay."""
-
-    def __init__(self):
-        torch = _torch()
-        self.buf = torch.zeros(C.sizeof(lodge_camera), dtype=torch.uint8, pin_memory=True)
-        self.ptr = self.buf.data_ptr()
-
-    def set(self, cam):
-        c = make_camera(cam) if not isinstance(cam, lodge_camera) else cam
-        C.memmove(self.ptr, C.addressof(c), C.sizeof(lodge_camera))
 
 
 # --------------------------------------------------------------------------- objects
@@ -276,10 +264,16 @@ class Selection:
 # --------------------------------------------------------------------------- calls
 
 def _cam_arg(cam):
-    if isinstance(cam, PinnedCamera):
-        return C.c_void_p(cam.ptr), None
+    """(pointer, keep-alive) for a camera argument; None = the camera stored on the workspace."""
+    if cam is None:
+        return None, None
     c = cam if isinstance(cam, lodge_camera) else make_camera(cam)
     return C.c_void_p(C.addressof(c)), c
+
+
+def lodge_set_camera(ws: "Workspace", cam, stream=None):
+    cp, keep = _cam_arg(cam)
+    _check(lib().lodge_set_camera(C.byref(ws.desc), cp, _stream_ptr(stream)))
 
 
 def lodge_select(scene: Scene, cam, mode: int, ws: Workspace, sel: Selection, stream=None):
@@ -312,15 +306,18 @@ def lodge_check(ws: Workspace, stream=None):
 
 
 def lodge_debug_views(ws: Workspace, n_instances: int):
-    """(sorted_ids [M] int32, tile_ranges [T,2] int32, proj [max_active,12] float32) views into ws."""
+    """Views into ws: sorted_ids [M] int32, tile_ranges [T, 2] int32, proj [max_active, 12] float32
+    (u, v, A, B, C, o, r, g, b, ex, ey, thr), depth [max_active] float32, rect [max_active, 2] int32."""
     torch = _torch()
-    s, r, p = C.c_void_p(), C.c_void_p(), C.c_void_p()
-    _check(lib().lodge_debug_views(C.byref(ws.desc), C.byref(s), C.byref(r), C.byref(p)))
+    s, r, p, d, rc = C.c_void_p(), C.c_void_p(), C.c_void_p(), C.c_void_p(), C.c_void_p()
+    _check(lib().lodge_debug_views(C.byref(ws.desc), C.byref(s), C.byref(r), C.byref(p), C.byref(d), C.byref(rc)))
     T = ((ws.width + TILE - 1) // TILE) * ((ws.height + TILE - 1) // TILE)
     sorted_ids = ws.view(s.value, 4 * n_instances, torch.int32)
     ranges = ws.view(r.value, 8 * T, torch.int32).view(T, 2)
     proj = ws.view(p.value, 48 * ws.max_active, torch.float32).view(ws.max_active, 12)
-    return sorted_ids, ranges, proj
+    depth = ws.view(d.value, 4 * ws.max_active, torch.float32)
+    rect = ws.view(rc.value, 8 * ws.max_active, torch.int32).view(ws.max_active, 2)
+    return sorted_ids, ranges, proj, depth, rect
 
 
 def lodge_render_backward(scene: Scene, sel: Selection, cam, ws: Workspace, final_T, n_contrib, dL_dimage,

@@ -1,13 +1,14 @@
 """Continuous-batching render server over one resident LOD scene.
 
 Requests (camera + resolution) arrive over time.  Each resolution class owns
-render slots; a slot is a workspace, a selection, output buffers, a pinned
-camera record, a HIP stream and a captured HIP graph of one frame
-(lodge_select + lodge_render).  The scheduler admits a waiting request as
-soon as a slot of its class is free, or creates a new slot when the memory
-budget allows; it writes the camera into the slot's pinned record and
-replays the slot's graph on the slot's stream, so requests of different
-resolutions that arrive while others are on the GPU run concurrently.
+render slots; a slot is a workspace, a selection, output buffers, a HIP
+stream and a captured HIP graph of one frame (lodge_select + lodge_render
+with the camera taken from the workspace).  The scheduler admits a waiting
+request as soon as a slot of its class is free, or creates a new slot when
+the memory budget allows; it stores the request's camera in the slot's
+workspace (lodge_set_camera) and replays the slot's graph on the slot's
+stream, so requests of different resolutions that arrive while others are on
+the GPU run concurrently.
 Completion is detected by polling the slot's event; latency is completion
 minus arrival (the device-to-host copy of the image is not included, as in
 the paper's timing protocol).  A frame whose capacities overflowed is
@@ -233,9 +234,8 @@ class GpuBackend:
         torch, L = self.torch, self.L
         w, h = res
         R = L.Renderer(self.scene, w, h, max_active=caps[0], max_instances=caps[1])
-        cam = L.PinnedCamera()
         stream = torch.cuda.Stream()
-        return R, cam, stream
+        return R, stream
 
     def prewarm(self, res, k: int):
         """Creates k slots of a class ahead of the run (returned to the scheduler's free lists)."""
@@ -243,37 +243,34 @@ class GpuBackend:
 
     def new_slot(self, res):
         torch, L = self.torch, self.L
-        R, cam, stream = self._make(res, self.caps[res])
-        # any camera of the right size to capture with; replays re-read the pinned record
+        R, stream = self._make(res, self.caps[res])
         graph = None
         if self.use_graphs:
-            # any valid camera of this size: replays re-read the pinned record
+            # any valid camera of this size; the graph reads whatever camera is set before a replay
             c = L.lodge_camera(width=res[0], height=res[1], fx=float(res[0]), fy=float(res[0]), cx=res[0] / 2.0,
                                cy=res[1] / 2.0, znear=0.2, lim_x=1.0, lim_y=1.0)
             c.R[0] = c.R[4] = c.R[8] = 1.0
-            cam.set(c)
             with torch.cuda.stream(stream):
-                R.frame(cam, self.mode)          # warm-up outside the capture
+                R.frame(c, self.mode)            # warm-up outside the capture
             stream.synchronize()
             graph = torch.cuda.CUDAGraph()
             with torch.cuda.graph(graph, stream=stream):
-                R.frame(cam, self.mode)
+                R.frame(None, self.mode)
         done = torch.cuda.Event()
         sid = len(self.slots)
-        self.slots.append({"res": res, "R": R, "cam": cam, "stream": stream, "graph": graph, "done": done,
-                           "req": None})
+        self.slots.append({"res": res, "R": R, "stream": stream, "graph": graph, "done": done, "req": None})
         return sid
 
     def launch(self, sid, req):
         torch = self.torch
         s = self.slots[sid]
-        s["cam"].set(req.cam)
         s["req"] = req
         with torch.cuda.stream(s["stream"]):
             if s["graph"] is not None:
+                self.L.lodge_set_camera(s["R"].ws, req.cam, s["stream"])
                 s["graph"].replay()
             else:
-                s["R"].frame(s["cam"], self.mode)
+                s["R"].frame(req.cam, self.mode)
             s["done"].record()
 
     def poll(self, sid):
@@ -288,10 +285,9 @@ class GpuBackend:
             # grow to what the frame needed and render it again outside the graph
             res = s["res"]
             caps = (max(na, self.caps[res][0]), max(int(ni * 1.25), self.caps[res][1]))
-            R, cam, stream = self._make(res, caps)
-            cam.set(s["req"].cam)
+            R, stream = self._make(res, caps)
             with self.torch.cuda.stream(stream):
-                R.frame(cam, self.mode)
+                R.frame(s["req"].cam, self.mode)
             stream.synchronize()
             t = time.perf_counter()
             retried = True

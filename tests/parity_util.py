@@ -32,15 +32,16 @@ def gpu_frame(scene_dev, cam, mode, width=None, height=None, max_active=None, ma
                n_contrib=R.n_contrib.cpu().numpy().astype(np.uint32), renderer=R)
     M = int(info["n_instances"])
     if M <= R.ws.max_instances:
-        s, r, p = L.lodge_debug_views(R.ws, M)
+        s, r, p, d, rc = L.lodge_debug_views(R.ws, M)
         out["sorted"] = s.cpu().numpy().astype(np.uint32)
         out["ranges"] = r.cpu().numpy().astype(np.uint32)
         out["proj"] = p[:n].cpu().numpy()
+        out["depth"] = d[:n].cpu().numpy()
+        out["rect"] = rc[:n].cpu().numpy().view(np.uint32)
     return out
 
 
-def rect_of(proj_rows):
-    bits = proj_rows[:, 10:12].copy().view(np.uint32)
+def rect_of(bits):
     return np.stack([bits[:, 0] & 0xFFFF, bits[:, 0] >> 16, bits[:, 1] & 0xFFFF, bits[:, 1] >> 16], axis=1)
 
 
@@ -53,12 +54,12 @@ def compare_selection(g, ids, w):
 def compare_projection(g, proj: oracle.Projection):
     P = g["proj"]
     vis_o = proj.tiles > 0
-    rect_g = rect_of(P)
+    rect_g = rect_of(g["rect"])
     vis_g = (rect_g[:, 2] > rect_g[:, 0]) & (rect_g[:, 3] > rect_g[:, 1])
     assert np.array_equal(vis_g, vis_o), f"visibility differs at {np.flatnonzero(vis_g != vis_o)[:10]}"
     assert np.array_equal(rect_g[vis_o], proj.rect[vis_o].astype(np.uint32)), "tile rectangles differ"
     # depth is a sort key: bit-exact
-    assert np.array_equal(P[vis_o, 9].view(np.uint32), proj.depth[vis_o].astype(np.float32).view(np.uint32))
+    assert np.array_equal(g["depth"][vis_o].view(np.uint32), proj.depth[vis_o].astype(np.float32).view(np.uint32))
     got = np.concatenate([P[vis_o, 0:2], P[vis_o, 2:5], P[vis_o, 5:6], P[vis_o, 6:9]], axis=1)
     exp = np.concatenate([proj.uv[vis_o], proj.conic[vis_o], proj.o_eff[vis_o, None], proj.rgb[vis_o]], axis=1)
     err = np.abs(got - exp) / np.maximum(1.0, np.abs(exp))
