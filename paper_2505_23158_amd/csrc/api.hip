@@ -83,12 +83,12 @@ Layout make_layout(uint32_t n_total, int32_t width, int32_t height, uint32_t max
     L.T = L.TX * L.TY;
     // selection blocks never straddle levels: at most one partial block per level
     L.sel_tiles = (n_total + kSelTile - 1) / kSelTile + LODGE_MAX_LEVELS;
-    L.scan_tiles = std::max<uint32_t>(1, (max_active + kScanTile - 1) / kScanTile);
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o = off; off += al(bytes); return o; };
     L.params = take(sizeof(FrameParams));
     L.info = take(sizeof(FrameInfo));
-    L.scan_flags = take(8ull * L.scan_tiles);
+    L.wstats = take(16ull * 4 * L.T);
+    L.chunk_sum = take(4ull * ((max_active + kProjChunk - 1) / kProjChunk + 1));
     L.bin_blocks = (uint32_t)std::max<uint64_t>(1, (max_instances + kBinChunk - 1) / kBinChunk);
     L.proj = take(48ull * max_active);
     L.depth = take(4ull * max_active);
@@ -103,7 +103,10 @@ Layout make_layout(uint32_t n_total, int32_t width, int32_t height, uint32_t max
     L.sorted = take(4ull * max_instances);
     L.temp = take(8ull * max_instances);
     L.g2d = take(48ull * max_active);
-    L.sel_flags = take(8ull * L.sel_tiles);   // last: the only region whose size depends on the scene
+    // last: the only regions whose size depends on the scene
+    L.sel_cnt = take(4ull * L.sel_tiles);
+    L.sel_off = take(4ull * L.sel_tiles);
+    L.sel_bits = take(4ull * kSelBlock * L.sel_tiles);
     L.total = off;
     return L;
 }
@@ -115,8 +118,11 @@ Views views_of(const lodge_workspace* ws, uint32_t n_total)
     char* b = static_cast<char*>(ws->base);
     v.params = reinterpret_cast<FrameParams*>(b + v.lay.params);
     v.info = reinterpret_cast<FrameInfo*>(b + v.lay.info);
-    v.sel_flags = reinterpret_cast<unsigned long long*>(b + v.lay.sel_flags);
-    v.scan_flags = reinterpret_cast<unsigned long long*>(b + v.lay.scan_flags);
+    v.wstats = reinterpret_cast<uint4*>(b + v.lay.wstats);
+    v.sel_cnt = reinterpret_cast<uint32_t*>(b + v.lay.sel_cnt);
+    v.sel_off = reinterpret_cast<uint32_t*>(b + v.lay.sel_off);
+    v.sel_bits = reinterpret_cast<uint32_t*>(b + v.lay.sel_bits);
+    v.chunk_sum = reinterpret_cast<uint32_t*>(b + v.lay.chunk_sum);
     v.proj = reinterpret_cast<float4*>(b + v.lay.proj);
     v.depth = reinterpret_cast<float*>(b + v.lay.depth);
     v.rect = reinterpret_cast<uint2*>(b + v.lay.rect);
@@ -135,14 +141,12 @@ Views views_of(const lodge_workspace* ws, uint32_t n_total)
     return v;
 }
 
-// Clears the render counters and the scan flags, and
-// records the options; one small kernel so a captured graph holds no memset.
+// Clears the render counters and records the options; a small kernel so a
+// captured graph holds no memset.
 namespace {
-__global__ void k_render_setup(FrameParams* fp, FrameInfo* info, unsigned long long* flags, uint32_t nflags,
-                               float s2d, int32_t compensate, int32_t TX, int32_t TY)
+__global__ void k_render_setup(FrameParams* fp, FrameInfo* info, float s2d, int32_t compensate, int32_t TX, int32_t TY)
 {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
-    for (uint32_t k = i; k < nflags; k += stride) flags[k] = 0ull;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) {
         fp->s2d = s2d;
         fp->compensate = compensate;
@@ -151,13 +155,10 @@ __global__ void k_render_setup(FrameParams* fp, FrameInfo* info, unsigned long l
         info->n_front = 0;
         info->n_visible = 0;
         info->n_instances = 0;
-        info->pairs_evaluated = 0;
-        info->pairs_blended = 0;
         info->max_tile_len = 0;
         info->overflow &= kOvfSelect;
         info->n_large = 0;
         info->n_huge = 0;
-        info->scan_ticket = 0;
     }
 }
 }  // namespace
@@ -179,11 +180,7 @@ hipError_t launch_set_camera(const lodge_camera& cam, const Views& v, hipStream_
 
 hipError_t launch_render_setup(const lodge_render_opts& o, const Views& v, hipStream_t st)
 {
-    const uint32_t n = v.lay.scan_tiles;
-    uint32_t blocks = std::min<uint32_t>(256, (n + 255) / 256);
-    k_render_setup<<<std::max<uint32_t>(blocks, 1), 256, 0, st>>>(v.params, v.info, v.scan_flags, v.lay.scan_tiles,
-                                                                   o.s2d, o.compensate, (int32_t)v.lay.TX,
-                                                                   (int32_t)v.lay.TY);
+    k_render_setup<<<1, 64, 0, st>>>(v.params, v.info, o.s2d, o.compensate, (int32_t)v.lay.TX, (int32_t)v.lay.TY);
     return hipGetLastError();
 }
 
@@ -363,17 +360,34 @@ lodge_status lodge_render(const lodge_scene* scene, const lodge_selection* sel, 
     return LODGE_OK;
 }
 
-lodge_status lodge_frame_info_read(const lodge_workspace* ws, lodge_frame_info* out, void* stream)
+namespace {
+
+// Synchronises the stream and copies the frame's info block; with_pairs also
+// sums the compositor's per-(tile, quadrant) pair counters.
+lodge_status read_info(const lodge_workspace* ws, lodge_frame_info* out, void* stream, bool with_pairs)
 {
     if (!ws || !ws->base || !out) return fail(LODGE_ERR_INVALID_ARG, "workspace or out is NULL");
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "lodge_frame_info_read: sync");
+    // the leading regions of the layout do not depend on the scene
+    const Layout lay = make_layout(0, ws->width, ws->height, ws->max_active, ws->max_instances);
+    const char* base = static_cast<const char*>(ws->base);
     FrameInfo fi;
-    // the info block sits right after the params block
-    const size_t off = al(sizeof(FrameParams));
-    e = hipMemcpy(&fi, static_cast<const char*>(ws->base) + off, sizeof(fi), hipMemcpyDeviceToHost);
+    e = hipMemcpy(&fi, base + lay.info, sizeof(fi), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "lodge_frame_info_read: copy");
+    if (with_pairs) {
+        std::vector<uint4> ws4(4ull * lay.T);
+        e = hipMemcpy(ws4.data(), base + lay.wstats, ws4.size() * sizeof(uint4), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "lodge_frame_info_read: copy counters");
+        unsigned long long ev = 0, bl = 0;
+        for (const uint4& q : ws4) {
+            ev += (unsigned long long)q.x | ((unsigned long long)q.y << 32);
+            bl += q.z;
+        }
+        fi.pairs_evaluated = ev;
+        fi.pairs_blended = bl;
+    }
     out->n_selected = fi.n_selected;
     out->n_front = fi.n_front;
     out->n_visible = fi.n_visible;
@@ -390,10 +404,17 @@ lodge_status lodge_frame_info_read(const lodge_workspace* ws, lodge_frame_info* 
     return LODGE_OK;
 }
 
+}  // namespace
+
+lodge_status lodge_frame_info_read(const lodge_workspace* ws, lodge_frame_info* out, void* stream)
+{
+    return read_info(ws, out, stream, true);
+}
+
 lodge_status lodge_check(const lodge_workspace* ws, uint32_t* needed_active, uint64_t* needed_instances, void* stream)
 {
     lodge_frame_info fi;
-    lodge_status s = lodge_frame_info_read(ws, &fi, stream);
+    lodge_status s = read_info(ws, &fi, stream, false);
     if (s != LODGE_OK) return s;
     if (needed_active) *needed_active = fi.n_selected;
     if (needed_instances) *needed_instances = fi.n_instances;

@@ -6,8 +6,10 @@
 // slow on the die-spanning L2 of this part): block-local LDS histograms,
 // coalesced column passes over a [block][tile] matrix, and LDS ranks.
 //
-//   k_scan_inst   exclusive scan of tiles-touched over the active set
-//                 (single pass, decoupled look-back) -> instance offsets, M.
+//   k_chunk_scan  one block: exclusive scan of the per-chunk tile totals the
+//                 projection wrote -> chunk offsets and the instance count M.
+//   k_inst_off    per chunk (one wave): scan of the tile counts + chunk
+//                 offset -> exclusive instance offsets of every active.
 //   k_emit_hist   block b takes instances [b C, (b+1) C): finds each one's
 //                 Gaussian by binary search over an LDS window of the
 //                 offsets, writes (tile, index) pairs and its tile histogram
@@ -28,119 +30,66 @@ namespace lodge {
 
 namespace {
 
-constexpr unsigned long long kValMask = (1ull << 62) - 1ull;
+// One block: exclusive scan of the per-chunk tile totals written by the
+// projection (one per 64 actives) -> chunk offsets and M.  Each thread
+// takes a contiguous run of chunks; the run totals are scanned in LDS.
+constexpr int kChunkScanThreads = 1024;
 
-__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
+__global__ __launch_bounds__(kChunkScanThreads) void k_chunk_scan(FrameInfo* info, uint32_t* __restrict__ csum,
+                                                                 const uint32_t* __restrict__ count, uint32_t cap,
+                                                                 uint64_t max_instances)
 {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
-// Decoupled look-back over 64-bit flag words: status in bits 62-63 (1 = block
-// aggregate, 2 = inclusive prefix), value in bits 0-61.
-__device__ unsigned long long lookback64(unsigned long long* flags, int32_t tile, uint32_t lane)
-{
-    unsigned long long prefix = 0;
-    int32_t pred = tile - 1;
-    while (true) {
-        const int32_t idx = pred - (int32_t)lane;
-        unsigned long long v = 2ull << 62;
-        if (idx >= 0) v = __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t st = (uint32_t)(v >> 62);
-        if (__ballot(st == 0u) != 0ull) continue;          // a predecessor has not published yet
-        const unsigned long long inc = __ballot(st == 2u);
-        unsigned long long val = v & kValMask;
-        if (inc != 0ull) {
-            const int first = __ffsll((long long)inc) - 1;
-            if ((int)lane > first) val = 0;
-            prefix += wave_sum64(val);
-            break;
-        }
-        prefix += wave_sum64(val);
-        pred -= 64;
-    }
-    return prefix;
-}
-
-// In-place exclusive scan of vt[0, n_active); total -> info->n_instances.
-__global__ __launch_bounds__(kScanBlock) void k_scan_inst(FrameInfo* info, unsigned long long* flags,
-                                                          uint32_t* __restrict__ vt, const uint32_t* __restrict__ count,
-                                                          uint32_t cap, uint64_t max_instances)
-{
-    __shared__ uint32_t s_tile;
-    __shared__ uint32_t s_wave[kScanBlock / 64];
-    __shared__ unsigned long long s_excl;
-    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    if (tid == 0) s_tile = atomicAdd(&info->scan_ticket, 1u);
-    __syncthreads();
-    const uint32_t tile = s_tile;
+    __shared__ unsigned long long s_part[kChunkScanThreads];
     const uint32_t n = min(*count, cap);
-    const uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
-    if (tile >= ntiles) {
-        if (tile == 0 && tid == 0) info->n_instances = 0;   // nothing selected
-        return;
-    }
-    const uint32_t first = tile * kScanTile + tid * kScanItems;
-    uint32_t x[kScanItems];
-    uint32_t sum = 0;
-    if (first + kScanItems <= n) {
-        const uint4* p = reinterpret_cast<const uint4*>(vt + first);
-#pragma unroll
-        for (int k = 0; k < kScanItems / 4; k++) {
-            const uint4 q = p[k];
-            x[4 * k] = q.x; x[4 * k + 1] = q.y; x[4 * k + 2] = q.z; x[4 * k + 3] = q.w;
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < kScanItems; k++) x[k] = first + k < n ? vt[first + k] : 0u;
-    }
-#pragma unroll
-    for (int k = 0; k < kScanItems; k++) sum += x[k];
-    uint32_t inc = sum;
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t o = __shfl_up(inc, off);
-        if ((int)lane >= off) inc += o;
-    }
-    if (lane == 63) s_wave[wave] = inc;
+    const uint32_t nc = (n + kProjChunk - 1) / kProjChunk;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t per = (nc + kChunkScanThreads - 1) / kChunkScanThreads;
+    const uint32_t c0 = min(nc, tid * per), c1 = min(nc, c0 + per);
+    unsigned long long local = 0;
+    for (uint32_t c = c0; c < c1; c++) local += csum[c];
+    s_part[tid] = local;
     __syncthreads();
-    uint32_t wave_excl = 0, block_total = 0;
-#pragma unroll
-    for (int wv = 0; wv < kScanBlock / 64; wv++) {
-        const uint32_t s = s_wave[wv];
-        if (wv < (int)wave) wave_excl += s;
-        block_total += s;
+    for (int off = 1; off < kChunkScanThreads; off <<= 1) {
+        const unsigned long long o = tid >= (uint32_t)off ? s_part[tid - off] : 0ull;
+        __syncthreads();
+        s_part[tid] += o;
+        __syncthreads();
     }
-    if (wave == 0) {
-        unsigned long long prefix = 0;
-        if (tile == 0) {
-            if (lane == 0)
-                __hip_atomic_store(&flags[0], (2ull << 62) | block_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            if (lane == 0)
-                __hip_atomic_store(&flags[tile], (1ull << 62) | block_total, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            prefix = lookback64(flags, (int32_t)tile, lane);
-            if (lane == 0)
-                __hip_atomic_store(&flags[tile], (2ull << 62) | (prefix + block_total), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (lane == 0) {
-            s_excl = prefix;
-            if (tile == ntiles - 1) {
-                const unsigned long long M = prefix + block_total;
-                info->n_instances = M;
-                if (M > max_instances) atomicOr(&info->overflow, kOvfInstances);
-            }
-        }
+    unsigned long long run = s_part[tid] - local;
+    for (uint32_t c = c0; c < c1; c++) {
+        const uint32_t v = csum[c];
+        csum[c] = (uint32_t)run;    // offsets only matter when M fits the instance capacity (< 2^32)
+        run += v;
     }
-    __syncthreads();
-    // offsets only matter when M fits the instance capacity (< 2^32)
-    uint32_t run = (uint32_t)s_excl + wave_excl + (inc - sum);
-#pragma unroll
-    for (int k = 0; k < kScanItems; k++) {
-        const uint32_t idx = first + k;
-        if (idx < n) vt[idx] = run;
-        run += x[k];
+    if (tid == kChunkScanThreads - 1) {
+        const unsigned long long M = s_part[tid];
+        info->n_instances = M;
+        if (M > max_instances) atomicOr(&info->overflow, kOvfInstances);
+    }
+}
+
+// Per chunk of kProjChunk (= 64) actives, one wave: inclusive wave scan of
+// their tile counts plus the chunk offset -> exclusive instance offsets, in place.
+__global__ __launch_bounds__(256) void k_inst_off(const FrameInfo* info, uint32_t* __restrict__ vt,
+                                                  const uint32_t* __restrict__ coff,
+                                                  const uint32_t* __restrict__ count, uint32_t cap,
+                                                  uint64_t max_instances)
+{
+    static_assert(kProjChunk == 64, "one wave per chunk");
+    if (info->n_instances > max_instances) return;
+    const uint32_t n = min(*count, cap);
+    const uint32_t nc = (n + kProjChunk - 1) / kProjChunk;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    for (uint32_t c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < nc; c += waves) {
+        const uint32_t a = c * kProjChunk + lane;
+        const uint32_t x = a < n ? vt[a] : 0u;
+        uint32_t inc = x;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off);
+            if ((int)lane >= off) inc += o;
+        }
+        if (a < n) vt[a] = coff[c] + inc - x;
     }
 }
 
@@ -382,8 +331,9 @@ __global__ __launch_bounds__(kBinThreads) void k_scatter(const FrameParams* fp, 
 
 hipError_t launch_bin(const Views& v, const lodge_selection& sel, hipStream_t st)
 {
-    k_scan_inst<<<v.lay.scan_tiles, kScanBlock, 0, st>>>(v.info, v.scan_flags, v.vtiles, sel.count, sel.cap,
-                                                         v.max_instances);
+    k_chunk_scan<<<1, kChunkScanThreads, 0, st>>>(v.info, v.chunk_sum, sel.count, sel.cap, v.max_instances);
+    const uint32_t cg = std::max<uint32_t>(1, std::min<uint32_t>(4096, (v.max_active + 255) / 256));
+    k_inst_off<<<cg, 256, 0, st>>>(v.info, v.vtiles, v.chunk_sum, sel.count, sel.cap, v.max_instances);
     const uint32_t bmax = std::max<uint32_t>(1, (uint32_t)((v.max_instances + kBinChunk - 1) / kBinChunk));
     const uint32_t grid = std::min<uint32_t>(bmax, 1024);
     k_emit_hist<<<grid, kBinThreads, 0, st>>>(v.params, v.info, v.vtiles, sel.count, sel.cap, v.rect, v.inst, v.hist,

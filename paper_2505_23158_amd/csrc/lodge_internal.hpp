@@ -68,7 +68,7 @@ struct FrameInfo {
     uint32_t n_front;
     uint32_t n_visible;
     unsigned long long n_instances;
-    unsigned long long pairs_evaluated;
+    unsigned long long pairs_evaluated;   // filled on the host from the per-wave counters
     unsigned long long pairs_blended;
     uint32_t max_tile_len;
     uint32_t overflow;
@@ -76,9 +76,7 @@ struct FrameInfo {
     float t;
     uint32_t n_large;     // tiles sorted by the large-list kernel
     uint32_t n_huge;      // tiles sorted by the merge fallback
-    uint32_t sel_ticket;
-    uint32_t scan_ticket;
-    uint32_t pad[2];
+    uint32_t pad[4];
 };
 
 enum : uint32_t { kOvfSelect = 1u, kOvfInstances = 2u, kOvfTile = 4u };
@@ -88,19 +86,17 @@ enum : uint32_t { kOvfSelect = 1u, kOvfInstances = 2u, kOvfTile = 4u };
 constexpr int kSelBlock = 256;
 constexpr int kSelItems = 16;                       // per thread
 constexpr int kSelTile = kSelBlock * kSelItems;     // Gaussians per selection block
-constexpr int kScanBlock = 256;
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kScanBlock * kScanItems;
 constexpr int kSortSmall = 2048;                    // per-tile LDS sort, 256 threads
 constexpr int kSortLarge = 16384;                   // per-tile LDS sort, 1024 threads
 constexpr int kProjStride = 12;                     // floats per projected record
 constexpr int kBinChunk = 8192;                     // instances per binning block
+constexpr int kProjChunk = 64;                      // actives per projection chunk: one wave (instance-scan granule)
 constexpr int kMaxTiles = 32768;                    // 16-bit-packed LDS tile histograms (e.g. 3840 x 2160)
 
 struct Layout {
-    size_t params, info, sel_flags, scan_flags, proj, depth, rect, vtiles, inst, hist, tcount, ranges, order, large,
+    size_t params, info, wstats, sel_cnt, sel_off, sel_bits, chunk_sum, proj, depth, rect, vtiles, inst, hist, tcount, ranges, order, large,
         sorted, temp, g2d, total;
-    uint32_t sel_tiles, scan_tiles, TX, TY, T, bin_blocks;
+    uint32_t sel_tiles, TX, TY, T, bin_blocks;
 };
 
 Layout make_layout(uint32_t n_total, int32_t width, int32_t height, uint32_t max_active, uint64_t max_instances);
@@ -109,8 +105,11 @@ Layout make_layout(uint32_t n_total, int32_t width, int32_t height, uint32_t max
 struct Views {
     FrameParams* params;
     FrameInfo* info;
-    unsigned long long* sel_flags;
-    unsigned long long* scan_flags;
+    uint4* wstats;         // per (tile, quadrant): pairs evaluated (lo, hi), pairs blended
+    uint32_t* sel_cnt;     // per selection tile: member count
+    uint32_t* sel_off;     // per selection tile: exclusive offset of its members
+    uint32_t* sel_bits;    // [selection tiles][kSelBlock] two membership bits per item
+    uint32_t* chunk_sum;   // per projection chunk: tile total -> exclusive instance offset
     float4* proj;          // [max_active][3]: (u, v, A, B), (C, o, r, g), (b, ex, ey, thr); visible only
     float* depth;          // [max_active] camera depth (sort key), 0 when culled
     uint2* rect;           // [max_active] tile rect (x0 | y0 << 16, x1 | y1 << 16), empty when culled

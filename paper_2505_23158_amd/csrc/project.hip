@@ -12,7 +12,9 @@
 // count (0 when culled); visible ones also write a 48-byte compositing
 // record (centre, conic, opacity, colour, the power below which alpha
 // cannot reach 1/255, and the half-extents of the ellipse where it can).
-// The front/visible counters are reduced per block and added once.
+// Each wave also writes the tile total of its 64 consecutive actives (the
+// first level of the instance-offset scan).  The front/visible counters are
+// reduced per block and added once.
 //
 // Built with -ffp-contract=off: the rectangle and depth (which decide tile
 // membership and sort keys) are evaluated op for op as the oracle defines
@@ -61,20 +63,23 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, float* Y)
     Y[15] = -(kC3a * (x * (xx - 3.0f * yy)));
 }
 
-__device__ __forceinline__ int level_of(const LevelsArg& lv, uint32_t g)
+// The level of global id g, with its fields picked out of the (uniform)
+// kernel argument by selects, so every later load has its base in registers.
+__device__ __forceinline__ LevelDev level_of(const LevelsArg& lv, uint32_t g)
 {
-    int l = 0;
+    LevelDev o = lv.lv[0];
 #pragma unroll
     for (int j = 1; j < LODGE_MAX_LEVELS; j++)
-        if (j < lv.L && g >= lv.lv[j].base) l = j;
-    return l;
+        if (j < lv.L && g >= lv.lv[j].base) o = lv.lv[j];
+    return o;
 }
 
 __global__ __launch_bounds__(256) void k_project(LevelsArg lv, const uint32_t* __restrict__ ids,
                                                  const float* __restrict__ wsel, const uint32_t* __restrict__ count,
                                                  uint32_t cap, const FrameParams* __restrict__ fp, FrameInfo* info,
                                                  float4* __restrict__ proj, float* __restrict__ depth,
-                                                 uint2* __restrict__ rect, uint32_t* __restrict__ vtiles)
+                                                 uint2* __restrict__ rect, uint32_t* __restrict__ vtiles,
+                                                 uint32_t* __restrict__ chunk_sum)
 {
     __shared__ uint32_t s_cnt[2][4];
     const uint32_t n_act = min(*count, cap);
@@ -82,9 +87,9 @@ __global__ __launch_bounds__(256) void k_project(LevelsArg lv, const uint32_t* _
     const float s2d = fp->s2d;
     const int compensate = fp->compensate;
     const int32_t TX = fp->TX, TY = fp->TY;
-    const uint32_t stride = gridDim.x * blockDim.x;
     uint32_t n_front = 0, n_vis = 0;
 
+    const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t base = blockIdx.x * blockDim.x; base < n_act; base += stride) {
         const uint32_t a = base + threadIdx.x;
         bool visible = false, front = false;
@@ -94,8 +99,7 @@ __global__ __launch_bounds__(256) void k_project(LevelsArg lv, const uint32_t* _
         int32_t x0 = 0, y0 = 0, x1 = 0, y1 = 0;
         if (a < n_act) {
             const uint32_t g = ids[a];
-            const int l = level_of(lv, g);
-            const LevelDev& L = lv.lv[l];
+            const LevelDev L = level_of(lv, g);
             const size_t n = L.n;
             const uint32_t i = g - L.base;
             const float mx = L.mean[i], my = L.mean[n + i], mz = L.mean[2 * n + i];
@@ -183,12 +187,22 @@ __global__ __launch_bounds__(256) void k_project(LevelsArg lv, const uint32_t* _
                         const float dn = sqrtf((d0 * d0 + d1 * d1) + d2 * d2);
                         float Y[kMaxSh];
                         sh_basis(d0 / dn, d1 / dn, d2 / dn, Y);
+                        // all (d+1)^2 x 3 coefficients are loaded before the first use; planes past
+                        // the level's degree are clamped in bounds and contribute an exact zero
                         const int nb = (L.sh_degree + 1) * (L.sh_degree + 1);
+                        const float* __restrict__ sh = L.sh + i;
+                        float coef[kMaxSh][3];
+#pragma unroll
+                        for (int k = 0; k < kMaxSh; k++)
+#pragma unroll
+                            for (int ch = 0; ch < 3; ch++)
+                                coef[k][ch] = sh[(size_t)((k < nb ? k : nb - 1) * 3 + ch) * n];
                         float rgb[3];
 #pragma unroll
                         for (int ch = 0; ch < 3; ch++) {
                             float acc = 0.0f;
-                            for (int k = 0; k < nb; k++) acc = acc + L.sh[((size_t)(k * 3 + ch)) * n + i] * Y[k];
+#pragma unroll
+                            for (int k = 0; k < kMaxSh; k++) acc = acc + (k < nb ? coef[k][ch] : 0.0f) * Y[k];
                             acc = acc + 0.5f;
                             rgb[ch] = acc > 0.0f ? acc : 0.0f;
                         }
@@ -219,6 +233,11 @@ __global__ __launch_bounds__(256) void k_project(LevelsArg lv, const uint32_t* _
             n_front += front ? 1u : 0u;
             n_vis += visible ? 1u : 0u;
         }
+        // each wave's 64 consecutive actives form one chunk of the instance scan
+        uint32_t csum = ntiles;
+        for (int off = 32; off > 0; off >>= 1) csum += __shfl_xor(csum, off);
+        const uint32_t first = a - (threadIdx.x & 63u);
+        if ((threadIdx.x & 63u) == 0 && first < n_act) chunk_sum[first / kProjChunk] = csum;
     }
     // counters: wave sums, block sum, one atomic per block
     for (int off = 32; off > 0; off >>= 1) {
@@ -243,7 +262,7 @@ hipError_t launch_project(const LevelsArg& lv, const lodge_selection& sel, const
     if (blocks < 1) blocks = 1;
     if (blocks > kPersistentBlocks) blocks = kPersistentBlocks;
     k_project<<<blocks, 256, 0, st>>>(lv, sel.ids, sel.w, sel.count, sel.cap, v.params, v.info, v.proj, v.depth,
-                                      v.rect, v.vtiles);
+                                      v.rect, v.vtiles, v.chunk_sum);
     return hipGetLastError();
 }
 

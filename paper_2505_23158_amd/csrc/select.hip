@@ -3,15 +3,17 @@
 // two-chunk opacity weights of Eq. 4).
 //
 // k_select_setup  one wave finds the two nearest chunk centres and t, and
-//                 turns the switch distances into squared FP32 bounds
-//                 (k_zero64 clears the look-back flags before it).
+//                 turns the switch distances into squared FP32 bounds.
 // k_select        one pass over every Gaussian of every level (each block
 //                 inside one level, so its parameters and bounds are
 //                 uniform): coalesced loads of the three mean planes,
-//                 membership on squared FP32 distances, wave ballots + an
-//                 LDS scan for the block offsets, and a decoupled look-back
-//                 across blocks so the output stays in ascending global id
-//                 without a second pass.
+//                 membership on squared FP32 distances, two bits per item
+//                 packed per thread, and the tile's member count.
+// k_select_scan   one block: exclusive scan of the tile counts.
+// k_select_emit   tiles with members only: re-derives the in-tile order
+//                 from the packed bits (ballots + an LDS scan) and writes
+//                 ids (ascending global id) and weights.  The positions
+//                 are read once; no block waits on another.
 //
 // Bit-exactness: this file is built with -ffp-contract=off, so each
 // +, -, *, / and sqrt below is one IEEE-rounded FP32 operation, evaluated
@@ -42,11 +44,6 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     return v;
-}
-
-__global__ void k_zero64(unsigned long long* p, uint32_t n)
-{
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0ull;
 }
 
 // One wave.  (The chunk table is a by-value kernel argument indexed with
@@ -120,52 +117,23 @@ __global__ __launch_bounds__(64) void k_select_setup(ChunksArg ch, LevelsArg lv,
     }
     info->n_selected = 0;
     info->overflow = 0;
-    info->sel_ticket = 0;
     info->f = f;
     info->o = o;
     info->t = t;
 }
 
-// Decoupled look-back by one wave: returns the exclusive prefix of `tile`.
-// Flag word = status << 32 | value; status 1 = block aggregate, 2 = inclusive.
-__device__ uint32_t lookback(unsigned long long* flags, int32_t tile, uint32_t lane)
+// Pass 1, one block per selection tile of kSelTile Gaussians (every tile
+// inside one level, so level parameters and bounds are block-uniform).
+// Thread tid holds items i0 + r * kSelBlock + tid, r < kSelItems, and packs
+// their membership (in_f, in_o) as two bits per item into one word.  The
+// tile's count is always written; the words only when it is non-zero.
+__global__ __launch_bounds__(kSelBlock) void k_select(LevelsArg lv, const FrameParams* fp, uint32_t ntiles,
+                                                      uint32_t* __restrict__ cnt, uint32_t* __restrict__ bits_out)
 {
-    uint32_t prefix = 0;
-    int32_t pred = tile - 1;
-    while (true) {
-        const int32_t idx = pred - (int32_t)lane;
-        unsigned long long v = 2ull << 32;
-        if (idx >= 0) v = __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t st = (uint32_t)(v >> 32);
-        if (__ballot(st == 0u) != 0ull) continue;          // a predecessor has not published yet
-        const unsigned long long inc = __ballot(st == 2u);
-        uint32_t val = (uint32_t)v;
-        if (inc != 0ull) {
-            const int first = __ffsll((long long)inc) - 1;
-            if ((int)lane > first) val = 0;
-            prefix += wave_sum(val);
-            break;
-        }
-        prefix += wave_sum(val);
-        pred -= 64;
-    }
-    return prefix;
-}
-
-__global__ __launch_bounds__(kSelBlock) void k_select(LevelsArg lv, const FrameParams* fp, FrameInfo* info,
-                                                      unsigned long long* flags, uint32_t ntiles, uint32_t* ids,
-                                                      float* w, uint32_t cap, uint32_t* count_out)
-{
-    __shared__ uint32_t s_tile;
-    __shared__ uint32_t s_cnt[kSelItems * 4];
-    __shared__ uint32_t s_excl;
+    __shared__ uint32_t s_wave[kSelBlock / 64];
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    if (tid == 0) s_tile = atomicAdd(&info->sel_ticket, 1u);
-    __syncthreads();
-    const uint32_t tile = s_tile;
+    const uint32_t tile = blockIdx.x;
     if (tile >= ntiles) return;
-
-    // every block lies inside one level: level parameters and bounds are block-uniform
     int l = 0;
 #pragma unroll
     for (int j = 1; j < LODGE_MAX_LEVELS; j++)
@@ -180,19 +148,25 @@ __global__ __launch_bounds__(kSelBlock) void k_select(LevelsArg lv, const FrameP
     const float co[3] = {fp->co[0], fp->co[1], fp->co[2]};
     const float lof = fp->lo_f[l], hif = fp->hi_f[l], loo = fp->lo_o[l], hio = fp->hi_o[l];
 
-    // all loads first (48 in flight per thread), then the tests
+    // all loads first, then the tests: block-uniform plane bases, 32-bit lane
+    // offsets, indices clamped into the level so no load sits in a branch
     float mx[kSelItems], my[kSelItems], mz[kSelItems];
+    if (!all && n > 0) {
+        const float* __restrict__ px = L.mean;
+        const float* __restrict__ py = L.mean + n;
+        const float* __restrict__ pz = L.mean + 2 * (size_t)n;
 #pragma unroll
-    for (int r = 0; r < kSelItems; r++) {
-        const uint32_t i = i0 + (uint32_t)r * kSelBlock + tid;
-        mx[r] = my[r] = mz[r] = 0.0f;
-        if (i < n && !all) {
-            mx[r] = L.mean[i];
-            my[r] = L.mean[(size_t)n + i];
-            mz[r] = L.mean[2 * (size_t)n + i];
+        for (int r = 0; r < kSelItems; r++) {
+            const uint32_t i = min(i0 + (uint32_t)r * kSelBlock + tid, n - 1);
+            mx[r] = px[i];
+            my[r] = py[i];
+            mz[r] = pz[i];
         }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kSelItems; r++) mx[r] = my[r] = mz[r] = 0.0f;
     }
-    uint32_t bits = 0;   // 2 bits per item: in_f, in_o
+    uint32_t bits = 0, mine = 0;
 #pragma unroll
     for (int r = 0; r < kSelItems; r++) {
         const uint32_t i = i0 + (uint32_t)r * kSelBlock + tid;
@@ -210,44 +184,89 @@ __global__ __launch_bounds__(kSelBlock) void k_select(LevelsArg lv, const FrameP
             }
         }
         bits |= s << (2 * r);
-        const unsigned long long m = __ballot(s != 0u);
+        mine += s != 0u ? 1u : 0u;
+    }
+    const uint32_t wsum = wave_sum(mine);
+    if (lane == 0) s_wave[wave] = wsum;
+    __syncthreads();
+    uint32_t total = 0;
+#pragma unroll
+    for (int k = 0; k < kSelBlock / 64; k++) total += s_wave[k];
+    if (tid == 0) cnt[tile] = total;
+    if (total != 0u) bits_out[(size_t)tile * kSelBlock + tid] = bits;
+}
+
+// One block: exclusive scan of the tile counts -> tile offsets, the active
+// count and the capacity flag.  Each thread takes a contiguous run of tiles.
+constexpr int kSelScanThreads = 1024;
+
+__global__ __launch_bounds__(kSelScanThreads) void k_select_scan(FrameInfo* info, const uint32_t* __restrict__ cnt,
+                                                                 uint32_t* __restrict__ off, uint32_t ntiles,
+                                                                 uint32_t cap, uint32_t* count_out)
+{
+    __shared__ uint32_t s_part[kSelScanThreads];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t per = (ntiles + kSelScanThreads - 1) / kSelScanThreads;
+    const uint32_t c0 = min(ntiles, tid * per), c1 = min(ntiles, c0 + per);
+    uint32_t local = 0;
+    for (uint32_t c = c0; c < c1; c++) local += cnt[c];
+    s_part[tid] = local;
+    __syncthreads();
+    for (int o = 1; o < kSelScanThreads; o <<= 1) {
+        const uint32_t v = tid >= (uint32_t)o ? s_part[tid - o] : 0u;
+        __syncthreads();
+        s_part[tid] += v;
+        __syncthreads();
+    }
+    uint32_t run = s_part[tid] - local;   // totals stay below 2^32: at most n_total Gaussians
+    for (uint32_t c = c0; c < c1; c++) {
+        off[c] = run;
+        run += cnt[c];
+    }
+    if (tid == kSelScanThreads - 1) {
+        const uint32_t n = s_part[tid];
+        *count_out = n;
+        info->n_selected = n;
+        if (n > cap) atomicOr(&info->overflow, kOvfSelect);
+    }
+}
+
+// Pass 2, one block per tile with a non-zero count: the membership words
+// give each (item round, wave) count by ballots; an LDS scan in the item
+// order (round, wave, lane) places every member at its ascending-id slot.
+__global__ __launch_bounds__(kSelBlock) void k_select_emit(LevelsArg lv, const FrameParams* fp, uint32_t ntiles,
+                                                           const uint32_t* __restrict__ cnt,
+                                                           const uint32_t* __restrict__ off,
+                                                           const uint32_t* __restrict__ bits_in, uint32_t* ids,
+                                                           float* w, uint32_t cap)
+{
+    __shared__ uint32_t s_cnt[kSelItems * 4];
+    const uint32_t tile = blockIdx.x;
+    if (tile >= ntiles || cnt[tile] == 0u) return;
+    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    int l = 0;
+#pragma unroll
+    for (int j = 1; j < LODGE_MAX_LEVELS; j++)
+        if (j < lv.L && tile >= lv.first_block[j]) l = j;
+    const uint32_t gbase = lv.lv[l].base + (tile - lv.first_block[l]) * (uint32_t)kSelTile;
+    const uint32_t bits = bits_in[(size_t)tile * kSelBlock + tid];
+#pragma unroll
+    for (int r = 0; r < kSelItems; r++) {
+        const unsigned long long m = __ballot(((bits >> (2 * r)) & 3u) != 0u);
         if (lane == 0) s_cnt[r * 4 + wave] = (uint32_t)__popcll(m);
     }
     __syncthreads();
     if (wave == 0) {
-        const uint32_t v = s_cnt[lane];
+        const uint32_t v = lane < (uint32_t)(kSelItems * 4) ? s_cnt[lane] : 0u;
         uint32_t inc = v;
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t o = __shfl_up(inc, off);
-            if ((int)lane >= off) inc += o;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(inc, o);
+            if ((int)lane >= o) inc += u;
         }
-        const uint32_t block_total = __shfl(inc, 63);
-        s_cnt[lane] = inc - v;
-        uint32_t prefix = 0;
-        if (tile == 0) {
-            if (lane == 0)
-                __hip_atomic_store(&flags[0], (2ull << 32) | block_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            if (lane == 0)
-                __hip_atomic_store(&flags[tile], (1ull << 32) | block_total, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            prefix = lookback(flags, (int32_t)tile, lane);
-            if (lane == 0)
-                __hip_atomic_store(&flags[tile], (2ull << 32) | (prefix + block_total), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (lane == 0) {
-            s_excl = prefix;
-            if (tile == ntiles - 1) {
-                const uint32_t n = prefix + block_total;
-                *count_out = n;
-                info->n_selected = n;
-                if (n > cap) atomicOr(&info->overflow, kOvfSelect);
-            }
-        }
+        if (lane < (uint32_t)(kSelItems * 4)) s_cnt[lane] = inc - v;
     }
     __syncthreads();
-    const uint32_t excl = s_excl;
+    const uint32_t excl = off[tile];
     const float t = fp->t, w_o = fp->w_o;
     const unsigned long long lt = (1ull << lane) - 1ull;
 #pragma unroll
@@ -257,7 +276,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select(LevelsArg lv, const FrameP
         if (s != 0u) {
             const uint32_t pos = excl + s_cnt[r * 4 + wave] + (uint32_t)__popcll(m & lt);
             if (pos < cap) {
-                ids[pos] = L.base + i0 + (uint32_t)r * kSelBlock + tid;
+                ids[pos] = gbase + (uint32_t)r * kSelBlock + tid;
                 w[pos] = (s == 3u) ? 1.0f : (s == 1u ? t : w_o);
             }
         }
@@ -268,20 +287,17 @@ __global__ __launch_bounds__(kSelBlock) void k_select(LevelsArg lv, const FrameP
 
 hipError_t launch_select_setup(const LevelsArg& lv, const ChunksArg& ch, int32_t mode, const Views& v, hipStream_t st)
 {
-    const uint32_t n = std::max<uint32_t>(lv.sel_blocks, 1);   // an empty scene still runs one block (count 0)
-    uint32_t blocks = (n + 255) / 256;
-    if (blocks < 1) blocks = 1;
-    if (blocks > 1024) blocks = 1024;
-    k_zero64<<<blocks, 256, 0, st>>>(v.sel_flags, n);
     k_select_setup<<<1, 64, 0, st>>>(ch, lv, mode, v.params, v.info);
     return hipGetLastError();
 }
 
 hipError_t launch_select(const LevelsArg& lv, const Views& v, const lodge_selection& sel, hipStream_t st)
 {
-    const uint32_t ntiles = std::max<uint32_t>(lv.sel_blocks, 1);
-    k_select<<<ntiles, kSelBlock, 0, st>>>(lv, v.params, v.info, v.sel_flags, ntiles, sel.ids, sel.w, sel.cap,
-                                           sel.count);
+    const uint32_t ntiles = std::max<uint32_t>(lv.sel_blocks, 1);   // an empty scene still runs (count 0)
+    k_select<<<ntiles, kSelBlock, 0, st>>>(lv, v.params, ntiles, v.sel_cnt, v.sel_bits);
+    k_select_scan<<<1, kSelScanThreads, 0, st>>>(v.info, v.sel_cnt, v.sel_off, ntiles, sel.cap, sel.count);
+    k_select_emit<<<ntiles, kSelBlock, 0, st>>>(lv, v.params, ntiles, v.sel_cnt, v.sel_off, v.sel_bits, sel.ids,
+                                                sel.w, sel.cap);
     return hipGetLastError();
 }
 
