@@ -31,11 +31,12 @@ HBM_PEAK_GBS = 8000.0
 # VALU: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 lane-ops/s (each FMA one op);
 # the published 157.3 TFLOP/s FP32 counts an FMA as 2 flops and packed FP32 as 2 lanes.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# composite work per evaluated pair: dx, dy, quadratic form (6), skip test, exp (4 VALU
-# slots: quarter-rate transcendental), o*G, min, alpha test = 16; per blended pair: 1-alpha,
-# T*(1-alpha), stop test, alpha*T, 3 colour FMAs = 7.
-OPS_PER_EVAL = 16
-OPS_PER_BLEND = 7
+# compositing work: every (pixel, splat) pair whose alpha reaches 1/255 before the pixel stops (the blended pairs
+# plus the one that stops a pixel) must be evaluated in full by any exact compositor: dx, dy, quadratic form (7),
+# threshold test, exp (1 + 4 slots: quarter-rate transcendental, with its log2(e) scale), o*G, min, alpha test,
+# 1-alpha, T(1-alpha), stop test, alpha*T, 3 colour FMAs = 25 lane-ops.  Pairs a bounding test can reject are not
+# counted: the compositor culls them per sub-quadrant, so they are not work the method has to do.
+OPS_PER_SIGNIFICANT_PAIR = 25
 CSRC = os.path.join(ROOT, "paper_2505_23158_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_lod4_1080p.txt")
 
@@ -229,7 +230,8 @@ def main():
             raise SystemExit(f"capacity exceeded at frame {k}: active {na}, instances {ni}")
         stats.append(R.info())
     mean = {k: float(np.mean([s[k] for s in stats])) for k in
-            ("n_selected", "n_front", "n_visible", "n_instances", "pairs_evaluated", "pairs_blended", "max_tile_len")}
+            ("n_selected", "n_front", "n_visible", "n_instances", "pairs_evaluated", "pairs_blended", "pixels_stopped",
+             "max_tile_len")}
     log(f"[bench] per-frame means over {len(stats)} frames: " + ", ".join(f"{k}={v:.4g}" for k, v in mean.items()))
 
     # warm-up
@@ -237,26 +239,32 @@ def main():
         R.frame(cams[k % len(cams)], mode)
     torch.cuda.synchronize()
 
-    # timed region: K frames back to back on one stream, per-stage events live
+    def timed(select):
+        """K frames back to back on one stream, per-stage events recorded live."""
+        K = args.steps
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(K)]
+        for row in ev:            # torch creates the HIP event at its first record
+            for e in row:
+                e.record()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(K):
+            e = ev[k]
+            e[0].record()
+            select(cams[k % len(cams)])
+            L.lodge_render(dev, R.sel, cams[k % len(cams)], R.ws, R.image, R.final_T, R.n_contrib,
+                           stage_events=e[1:6])
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        stage_ms = {n: float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(K)]))
+                    for i, n in enumerate(stage_names)}
+        frame_ms_events = float(np.mean([ev[k][0].elapsed_time(ev[k][5]) for k in range(K)]))
+        return elapsed, stage_ms, frame_ms_events
+
+    # timed region: per-frame selection from the Gaussians' means (every frame re-derives the active set)
     K = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(K)]
-    for row in ev:            # torch creates the HIP event at its first record
-        for e in row:
-            e.record()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(K):
-        e = ev[k]
-        e[0].record()
-        L.lodge_select(dev, cams[k % len(cams)], mode, R.ws, R.sel)
-        L.lodge_render(dev, R.sel, cams[k % len(cams)], R.ws, R.image, R.final_T, R.n_contrib,
-                       stage_events=e[1:6])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
     stage_names = ["select", "project", "bin", "sort", "composite"]
-    stage_ms = {n: float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(K)]))
-                for i, n in enumerate(stage_names)}
-    frame_ms_events = float(np.mean([ev[k][0].elapsed_time(ev[k][5]) for k in range(K)]))
+    elapsed, stage_ms, frame_ms_events = timed(lambda cam: L.lodge_select(dev, cam, mode, R.ws, R.sel))
     fps = K / elapsed
     log(f"[bench] {K} frames in {elapsed:.3f} s -> {fps:.1f} frames/s; stage ms " +
         ", ".join(f"{k}={v:.3f}" for k, v in stage_ms.items()))
@@ -275,12 +283,29 @@ def main():
         per.append(statistics.median(ts))
     paper_fps = 1000.0 / float(np.mean(per)) if per else None
 
+    # the paper's storage form: per-chunk active sets stored once, a frame reads the two chunks' sets
+    chunk_sets = None
+    if mode == L.SELECT_CHUNKED:
+        sets = L.ChunkSets(dev)
+        for k in range(args.warmup):
+            R.frame(cams[k % len(cams)], mode, sets=sets)
+        torch.cuda.synchronize()
+        el2, st2, fm2 = timed(lambda cam: L.lodge_select_chunk_sets(dev, sets, cam, R.ws, R.sel))
+        sets_bytes = 0.25 * sc.n_total + 8.0 * mean["n_selected"]   # two 16-bit words per 16 Gaussians + ids, w
+        chunk_sets = {"frames_per_s": round(K / el2, 2), "ms_per_step": round(1000.0 * el2 / K, 4),
+                      "frame_ms_events": round(fm2, 4), "stage_ms": {k: round(v, 4) for k, v in st2.items()},
+                      "select_bytes": sets_bytes, "sets_bytes_resident": sets.bytes,
+                      "select_achieved_GBs": round(sets_bytes / (st2["select"] * 1e-3) / 1e9, 2)}
+        log(f"[bench] chunk sets: {chunk_sets}")
+        del sets
+
     # roofline terms (algorithmic bytes / ops per launch, divided by live event durations)
     N = sc.n_total
     sel_bytes = 12.0 * N + 8.0 * mean["n_selected"]
-    proj_bytes = (20.0 * mean["n_selected"] + 32.0 * mean["n_front"] + 192.0 * mean["n_visible"]
-                  + 48.0 * mean["n_visible"] + 8.0 * mean["n_visible"])
-    comp_ops = OPS_PER_EVAL * mean["pairs_evaluated"] + OPS_PER_BLEND * mean["pairs_blended"]
+    # per active: id + mean read, depth + rect + tile count written; per Gaussian in front: scale, rotation,
+    # opacity; per visible: weight + 48 SH coefficients read, 48-byte compositing record written
+    proj_bytes = 32.0 * mean["n_selected"] + 32.0 * mean["n_front"] + 244.0 * mean["n_visible"]
+    comp_ops = OPS_PER_SIGNIFICANT_PAIR * (mean["pairs_blended"] + mean["pixels_stopped"])
     stages = {
         "select": {"ms": stage_ms["select"], "bound": "hbm", "bytes": sel_bytes,
                    "achieved": sel_bytes / (stage_ms["select"] * 1e-3) / 1e9, "unit": "GB/s", "peak": HBM_PEAK_GBS},
@@ -348,6 +373,7 @@ def main():
         "roofline": roofline,
         "serving": serving,
         "differentiation": diff,
+        "chunk_sets": chunk_sets,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

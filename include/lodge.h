@@ -122,7 +122,9 @@ typedef struct lodge_scene lodge_scene;
  * and d_L = infinity implicitly; d may be NULL when L = 1).  chunks may be
  * NULL (then only LODGE_SELECT_ALL and LODGE_SELECT_LOD_CAMERA work).
  * Validates: n >= 0, sum of n < 2^32, d strictly increasing and > 0,
- * sh_degree in 0..3, non-NULL planes when n > 0, filter3d_var >= 0.
+ * sh_degree in 0..3, non-NULL planes when n > 0, filter3d_var >= 0;
+ * LODGE_ERR_UNSUPPORTED for a level of 2^30 or more Gaussians (its planes
+ * are addressed with 32-bit byte offsets).
  * Allocates host memory only.  *out is NULL on failure. */
 lodge_status lodge_scene_create(const lodge_level* levels, int32_t L, const float* d,
                                 const lodge_chunks* chunks, lodge_scene** out);
@@ -183,6 +185,28 @@ typedef struct {
 lodge_status lodge_select(const lodge_scene* scene, const lodge_camera* cam, int32_t mode,
                           const lodge_workspace* ws, lodge_selection* sel, void* stream);
 
+/* Precomputed per-chunk active sets (Sec. 3 "Reducing memory with
+ * chunk-based rendering": each chunk stores the Gaussians Eq. 2 selects at
+ * its centre with the offset thresholds d_l + r_k; a frame loads the union
+ * of the two nearest chunks' sets).  One bit per Gaussian per chunk, in the
+ * selection's tile order: K x ceil-per-level(n_l / 4096) x 256 x 2 bytes
+ * (3.3 MB per chunk at 26.55M Gaussians).  The buffer is device memory owned
+ * by the caller, 4-byte aligned; it stays valid while the scene's level
+ * planes and chunk table are unchanged.  LODGE_ERR_INVALID_ARG for a scene
+ * without chunks. */
+lodge_status lodge_chunk_sets_size(const lodge_scene* scene, size_t* bytes);
+
+/* ASYNC.  Fills the chunk sets (every chunk's membership of every Gaussian,
+ * evaluated with the same FP32 operations as lodge_select). */
+lodge_status lodge_chunk_sets_build(const lodge_scene* scene, void* sets, size_t bytes, void* stream);
+
+/* ASYNC.  The same result as lodge_select(..., LODGE_SELECT_CHUNKED, ...)
+ * (ids, weights, count, bit for bit), read from the two chunks' stored sets
+ * instead of the Gaussians' means: 2 bits of input per Gaussian instead of
+ * 12 bytes. */
+lodge_status lodge_select_chunk_sets(const lodge_scene* scene, const void* sets, const lodge_camera* cam,
+                                     const lodge_workspace* ws, lodge_selection* sel, void* stream);
+
 /* -------------------------------------------------------------- rendering */
 
 typedef struct {
@@ -219,8 +243,9 @@ typedef struct {
     uint32_t overflow;       /* bit 0 selection cap, bit 1 instance cap */
     int32_t f, o;            /* chunk pair (-1 when unused) */
     float t;                 /* Eq. 4 weight of the nearest chunk */
-    uint32_t n_long;         /* tiles whose list took the 16384-entry LDS sort */
+    uint32_t n_long;         /* tiles whose list took a 1024-thread LDS sort (2048 < length <= 16384) */
     uint32_t n_merge;        /* tiles whose list took the chunked merge sort */
+    uint64_t pixels_stopped; /* pixels that stopped before the end of their list (T (1 - alpha) < 1e-4) */
 } lodge_frame_info;
 
 /* Synchronises `stream`, then copies the counters of the last frame on ws. */

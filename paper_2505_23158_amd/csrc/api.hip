@@ -90,6 +90,7 @@ Layout make_layout(uint32_t n_total, int32_t width, int32_t height, uint32_t max
     L.wstats = take(16ull * 4 * L.T);
     L.chunk_sum = take(4ull * ((max_active + kProjChunk - 1) / kProjChunk + 1));
     L.bin_blocks = (uint32_t)std::max<uint64_t>(1, (max_instances + kBinChunk - 1) / kBinChunk);
+    L.bstart = take(4ull * (L.bin_blocks + 1));
     L.proj = take(48ull * max_active);
     L.depth = take(4ull * max_active);
     L.rect = take(8ull * max_active);
@@ -99,7 +100,7 @@ Layout make_layout(uint32_t n_total, int32_t width, int32_t height, uint32_t max
     L.tcount = take(4ull * L.T);
     L.ranges = take(8ull * L.T);
     L.order = take(4ull * L.T);
-    L.large = take(8ull * L.T);
+    L.large = take(12ull * L.T);
     L.sorted = take(4ull * max_instances);
     L.temp = take(8ull * max_instances);
     L.g2d = take(48ull * max_active);
@@ -127,6 +128,7 @@ Views views_of(const lodge_workspace* ws, uint32_t n_total)
     v.depth = reinterpret_cast<float*>(b + v.lay.depth);
     v.rect = reinterpret_cast<uint2*>(b + v.lay.rect);
     v.vtiles = reinterpret_cast<uint32_t*>(b + v.lay.vtiles);
+    v.bstart = reinterpret_cast<uint32_t*>(b + v.lay.bstart);
     v.inst = reinterpret_cast<uint2*>(b + v.lay.inst);
     v.hist = reinterpret_cast<uint32_t*>(b + v.lay.hist);
     v.tcount = reinterpret_cast<uint32_t*>(b + v.lay.tcount);
@@ -144,10 +146,12 @@ Views views_of(const lodge_workspace* ws, uint32_t n_total)
 // Clears the render counters and records the options; a small kernel so a
 // captured graph holds no memset.
 namespace {
-__global__ void k_render_setup(FrameParams* fp, FrameInfo* info, float s2d, int32_t compensate, int32_t TX, int32_t TY)
+__global__ void k_render_setup(FrameParams* fp, FrameInfo* info, lodge_camera cam, int32_t has_cam, float s2d,
+                               int32_t compensate, int32_t TX, int32_t TY)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) {
+        if (has_cam) store_camera(&fp->cam, cam);
         fp->s2d = s2d;
         fp->compensate = compensate;
         fp->TX = TX;
@@ -159,6 +163,7 @@ __global__ void k_render_setup(FrameParams* fp, FrameInfo* info, float s2d, int3
         info->overflow &= kOvfSelect;
         info->n_large = 0;
         info->n_huge = 0;
+        info->n_mid = 0;
     }
 }
 }  // namespace
@@ -168,7 +173,7 @@ namespace {
 // the caller's struct can change right after the call returns.
 __global__ void k_set_camera(lodge_camera cam, lodge_camera* dst)
 {
-    if (threadIdx.x == 0) *dst = cam;
+    if (threadIdx.x == 0) store_camera(dst, cam);
 }
 }  // namespace
 
@@ -178,9 +183,12 @@ hipError_t launch_set_camera(const lodge_camera& cam, const Views& v, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_render_setup(const lodge_render_opts& o, const Views& v, hipStream_t st)
+hipError_t launch_render_setup(const lodge_render_opts& o, const lodge_camera* cam, const Views& v, hipStream_t st)
 {
-    k_render_setup<<<1, 64, 0, st>>>(v.params, v.info, o.s2d, o.compensate, (int32_t)v.lay.TX, (int32_t)v.lay.TY);
+    lodge_camera c{};
+    if (cam) c = *cam;
+    k_render_setup<<<1, 64, 0, st>>>(v.params, v.info, c, cam ? 1 : 0, o.s2d, o.compensate, (int32_t)v.lay.TX,
+                                     (int32_t)v.lay.TY);
     return hipGetLastError();
 }
 
@@ -219,6 +227,11 @@ lodge_status lodge_scene_create(const lodge_level* levels, int32_t L, const floa
     for (int l = 0; l < L; l++) {
         const lodge_level& v = levels[l];
         if (v.n < 0) { delete s; return fail(LODGE_ERR_INVALID_ARG, "negative level size"); }
+        if (v.n >= (int64_t)1 << 30) {
+            delete s;
+            return fail(LODGE_ERR_UNSUPPORTED, "a level holds 2^30 or more Gaussians (planes are addressed with 32-bit "
+                                               "byte offsets)");
+        }
         if (v.sh_degree < 0 || v.sh_degree > 3) { delete s; return fail(LODGE_ERR_INVALID_ARG, "sh_degree must be 0..3"); }
         if (!(v.filter3d_var >= 0.0f) || !std::isfinite(v.filter3d_var)) {
             delete s;
@@ -263,9 +276,9 @@ lodge_status lodge_scene_create(const lodge_level* levels, int32_t L, const floa
         s->chunks.K = chunks->k;
         s->chunks.band = chunks->band;
         for (int k = 0; k < chunks->k; k++) {
-            for (int j = 0; j < 3; j++) s->chunks.c[k][j] = chunks->center[3 * k + j];
-            s->chunks.r[k] = chunks->offset[k];
-            if (!std::isfinite(s->chunks.r[k]) || s->chunks.r[k] < 0.0f) {
+            s->chunks.c[k] = make_float4(chunks->center[3 * k], chunks->center[3 * k + 1], chunks->center[3 * k + 2],
+                                         chunks->offset[k]);
+            if (!std::isfinite(s->chunks.c[k].w) || s->chunks.c[k].w < 0.0f) {
                 delete s;
                 return fail(LODGE_ERR_INVALID_ARG, "chunk offsets must be finite and >= 0");
             }
@@ -319,10 +332,51 @@ lodge_status lodge_select(const lodge_scene* scene, const lodge_camera* cam, int
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Views v = views_of(ws, scene->levels.total);
     hipError_t e = hipSuccess;
-    if (cam && (e = launch_set_camera(*cam, v, st)) != hipSuccess) return hip_fail(e, "lodge_select: camera");
-    if ((e = launch_select_setup(scene->levels, scene->chunks, mode, v, st)) != hipSuccess)
+    if ((e = launch_select_setup(scene->levels, scene->chunks, mode, cam, v, st)) != hipSuccess)
         return hip_fail(e, "lodge_select: setup");
     if ((e = launch_select(scene->levels, v, *sel, st)) != hipSuccess) return hip_fail(e, "lodge_select");
+    return LODGE_OK;
+}
+
+lodge_status lodge_chunk_sets_size(const lodge_scene* scene, size_t* bytes)
+{
+    if (!scene || !bytes) return fail(LODGE_ERR_INVALID_ARG, "scene or bytes is NULL");
+    if (!scene->has_chunks) return fail(LODGE_ERR_INVALID_ARG, "the scene has no chunks");
+    *bytes = (size_t)scene->chunks.K * std::max<uint32_t>(scene->levels.sel_blocks, 1) * kSelBlock * sizeof(uint16_t);
+    return LODGE_OK;
+}
+
+lodge_status lodge_chunk_sets_build(const lodge_scene* scene, void* sets, size_t bytes, void* stream)
+{
+    size_t need = 0;
+    lodge_status s = lodge_chunk_sets_size(scene, &need);
+    if (s != LODGE_OK) return s;
+    if (!sets || bytes < need) return fail(LODGE_ERR_INVALID_ARG, "chunk-set buffer is NULL or too small");
+    if (reinterpret_cast<uintptr_t>(sets) % 4) return fail(LODGE_ERR_INVALID_ARG, "chunk-set buffer must be 4-byte aligned");
+    const hipError_t e = launch_sets_build(scene->levels, scene->chunks, static_cast<uint16_t*>(sets),
+                                           static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LODGE_OK : hip_fail(e, "lodge_chunk_sets_build");
+}
+
+lodge_status lodge_select_chunk_sets(const lodge_scene* scene, const void* sets, const lodge_camera* cam,
+                                     const lodge_workspace* ws, lodge_selection* sel, void* stream)
+{
+    if (!scene) return fail(LODGE_ERR_INVALID_ARG, "scene is NULL");
+    if (!scene->has_chunks) return fail(LODGE_ERR_INVALID_ARG, "the scene has no chunks");
+    if (!sets) return fail(LODGE_ERR_INVALID_ARG, "chunk sets are NULL");
+    lodge_status s;
+    if ((s = check_ws(scene, ws)) != LODGE_OK) return s;
+    if ((s = check_cam(cam, nullptr)) != LODGE_OK) return s;
+    if ((s = check_sel(sel, ws)) != LODGE_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Views v = views_of(ws, scene->levels.total);
+    hipError_t e = hipSuccess;
+    if ((e = launch_select_setup(scene->levels, scene->chunks, LODGE_SELECT_CHUNKED, cam, v, st)) != hipSuccess)
+        return hip_fail(e, "lodge_select_chunk_sets: setup");
+    if ((e = launch_sets_mark(scene->levels, v, static_cast<const uint16_t*>(sets), st)) != hipSuccess)
+        return hip_fail(e, "lodge_select_chunk_sets: mark");
+    if ((e = launch_select_finish(scene->levels, v, *sel, st)) != hipSuccess)
+        return hip_fail(e, "lodge_select_chunk_sets");
     return LODGE_OK;
 }
 
@@ -342,11 +396,10 @@ lodge_status lodge_render(const lodge_scene* scene, const lodge_selection* sel, 
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Views v = views_of(ws, scene->levels.total);
     hipError_t e = hipSuccess;
-    if (cam && (e = launch_set_camera(*cam, v, st)) != hipSuccess) return hip_fail(e, "lodge_render: camera");
     auto mark = [&](int k) -> hipError_t {
         return o.stage_events ? hipEventRecord(static_cast<hipEvent_t>(o.stage_events[k]), st) : hipSuccess;
     };
-    if ((e = launch_render_setup(o, v, st)) != hipSuccess) return hip_fail(e, "lodge_render: setup");
+    if ((e = launch_render_setup(o, cam, v, st)) != hipSuccess) return hip_fail(e, "lodge_render: setup");
     if ((e = mark(0)) != hipSuccess) return hip_fail(e, "lodge_render: event");
     if ((e = launch_project(scene->levels, *sel, v, st)) != hipSuccess) return hip_fail(e, "lodge_render: project");
     if ((e = mark(1)) != hipSuccess) return hip_fail(e, "lodge_render: event");
@@ -380,13 +433,17 @@ lodge_status read_info(const lodge_workspace* ws, lodge_frame_info* out, void* s
         std::vector<uint4> ws4(4ull * lay.T);
         e = hipMemcpy(ws4.data(), base + lay.wstats, ws4.size() * sizeof(uint4), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "lodge_frame_info_read: copy counters");
-        unsigned long long ev = 0, bl = 0;
+        unsigned long long ev = 0, bl = 0, st = 0;
         for (const uint4& q : ws4) {
             ev += (unsigned long long)q.x | ((unsigned long long)q.y << 32);
             bl += q.z;
+            st += q.w;
         }
         fi.pairs_evaluated = ev;
         fi.pairs_blended = bl;
+        out->pixels_stopped = st;
+    } else {
+        out->pixels_stopped = 0;
     }
     out->n_selected = fi.n_selected;
     out->n_front = fi.n_front;

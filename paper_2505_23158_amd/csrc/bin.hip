@@ -9,10 +9,14 @@
 //   k_chunk_scan  one block: exclusive scan of the per-chunk tile totals the
 //                 projection wrote -> chunk offsets and the instance count M.
 //   k_inst_off    per chunk (one wave): scan of the tile counts + chunk
-//                 offset -> exclusive instance offsets of every active.
-//   k_emit_hist   block b takes instances [b C, (b+1) C): finds each one's
-//                 Gaussian by binary search over an LDS window of the
-//                 offsets, writes (tile, index) pairs and its tile histogram
+//                 offset -> exclusive instance offsets of every active, and
+//                 for each binning block the active its first instance
+//                 belongs to.
+//   k_emit_hist   block b takes instances [b C, (b+1) C), i.e. the actives
+//                 between the first actives of blocks b and b + 1 (from
+//                 k_inst_off): one thread per active expands its part of
+//                 those instances, the whole block the parts longer than 32;
+//                 it writes (tile, index) pairs and its tile histogram
 //                 (packed 16-bit LDS counters) as row b of the matrix.
 //   k_col_sum     per tile: total count over the blocks (16 tiles x 16 row
 //                 groups per block, row reads contiguous across tiles).
@@ -31,40 +35,73 @@ namespace lodge {
 namespace {
 
 // One block: exclusive scan of the per-chunk tile totals written by the
-// projection (one per 64 actives) -> chunk offsets and M.  Each thread
-// takes a contiguous run of chunks; the run totals are scanned in LDS.
+// projection (one per 64 actives) -> chunk offsets and M.  The totals are
+// read as coalesced uint4 runs, kChunkScanGroup tiles of 4 x 1024 at a time,
+// all loads issued before the first tile is scanned; each tile is one block
+// scan (wave scans + wave totals in LDS) on top of the running carry.
 constexpr int kChunkScanThreads = 1024;
+constexpr int kChunkScanTile = 4 * kChunkScanThreads;
+constexpr int kChunkScanGroup = 8;
 
 __global__ __launch_bounds__(kChunkScanThreads) void k_chunk_scan(FrameInfo* info, uint32_t* __restrict__ csum,
                                                                  const uint32_t* __restrict__ count, uint32_t cap,
                                                                  uint64_t max_instances)
 {
-    __shared__ unsigned long long s_part[kChunkScanThreads];
+    __shared__ uint32_t s_w[kChunkScanThreads / 64];
     const uint32_t n = min(*count, cap);
     const uint32_t nc = (n + kProjChunk - 1) / kProjChunk;
-    const uint32_t tid = threadIdx.x;
-    const uint32_t per = (nc + kChunkScanThreads - 1) / kChunkScanThreads;
-    const uint32_t c0 = min(nc, tid * per), c1 = min(nc, c0 + per);
-    unsigned long long local = 0;
-    for (uint32_t c = c0; c < c1; c++) local += csum[c];
-    s_part[tid] = local;
-    __syncthreads();
-    for (int off = 1; off < kChunkScanThreads; off <<= 1) {
-        const unsigned long long o = tid >= (uint32_t)off ? s_part[tid - off] : 0ull;
-        __syncthreads();
-        s_part[tid] += o;
-        __syncthreads();
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    unsigned long long carry = 0;
+    for (uint32_t g0 = 0; g0 < nc; g0 += kChunkScanTile * kChunkScanGroup) {
+        uint4 v[kChunkScanGroup];
+#pragma unroll
+        for (int t = 0; t < kChunkScanGroup; t++) {
+            const uint32_t c = g0 + t * kChunkScanTile + 4 * tid;
+            if (c + 3 < nc) {
+                v[t] = *reinterpret_cast<const uint4*>(csum + c);
+            } else {
+                v[t].x = c < nc ? csum[c] : 0u;
+                v[t].y = c + 1 < nc ? csum[c + 1] : 0u;
+                v[t].z = c + 2 < nc ? csum[c + 2] : 0u;
+                v[t].w = 0u;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < kChunkScanGroup; t++) {
+            const uint32_t c = g0 + t * kChunkScanTile + 4 * tid;
+            if (g0 + t * kChunkScanTile >= nc) break;   // block-uniform
+            const uint32_t own = (v[t].x + v[t].y) + (v[t].z + v[t].w);
+            uint32_t inc = own;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t u = __shfl_up(inc, o);
+                if ((int)lane >= o) inc += u;
+            }
+            if (lane == 63) s_w[wave] = inc;
+            __syncthreads();
+            uint32_t before = 0, total = 0;
+#pragma unroll
+            for (int w = 0; w < kChunkScanThreads / 64; w++) {
+                const uint32_t x = s_w[w];
+                before += (uint32_t)w < wave ? x : 0u;
+                total += x;
+            }
+            // offsets only matter when M fits the instance capacity (< 2^32)
+            const uint32_t e0 = (uint32_t)carry + before + inc - own;
+            const uint4 o4 = make_uint4(e0, e0 + v[t].x, e0 + v[t].x + v[t].y, e0 + v[t].x + v[t].y + v[t].z);
+            if (c + 3 < nc) {
+                *reinterpret_cast<uint4*>(csum + c) = o4;
+            } else {
+                if (c < nc) csum[c] = o4.x;
+                if (c + 1 < nc) csum[c + 1] = o4.y;
+                if (c + 2 < nc) csum[c + 2] = o4.z;
+            }
+            carry += total;
+            __syncthreads();   // s_w is rewritten by the next tile
+        }
     }
-    unsigned long long run = s_part[tid] - local;
-    for (uint32_t c = c0; c < c1; c++) {
-        const uint32_t v = csum[c];
-        csum[c] = (uint32_t)run;    // offsets only matter when M fits the instance capacity (< 2^32)
-        run += v;
-    }
-    if (tid == kChunkScanThreads - 1) {
-        const unsigned long long M = s_part[tid];
-        info->n_instances = M;
-        if (M > max_instances) atomicOr(&info->overflow, kOvfInstances);
+    if (tid == 0) {
+        info->n_instances = carry;
+        if (carry > max_instances) atomicOr(&info->overflow, kOvfInstances);
     }
 }
 
@@ -73,7 +110,7 @@ __global__ __launch_bounds__(kChunkScanThreads) void k_chunk_scan(FrameInfo* inf
 __global__ __launch_bounds__(256) void k_inst_off(const FrameInfo* info, uint32_t* __restrict__ vt,
                                                   const uint32_t* __restrict__ coff,
                                                   const uint32_t* __restrict__ count, uint32_t cap,
-                                                  uint64_t max_instances)
+                                                  uint32_t* __restrict__ bstart, uint64_t max_instances)
 {
     static_assert(kProjChunk == 64, "one wave per chunk");
     if (info->n_instances > max_instances) return;
@@ -89,18 +126,13 @@ __global__ __launch_bounds__(256) void k_inst_off(const FrameInfo* info, uint32_
             const uint32_t o = __shfl_up(inc, off);
             if ((int)lane >= off) inc += o;
         }
-        if (a < n) vt[a] = coff[c] + inc - x;
+        const uint32_t o = coff[c] + inc - x;
+        if (a < n) vt[a] = o;
+        // the binning block starting at instance b kBinChunk is owned by the
+        // active whose run [o, o + x) holds that instance
+        for (uint32_t b = (o + kBinChunk - 1) / kBinChunk; x > 0 && (unsigned long long)b * kBinChunk < o + x; b++)
+            bstart[b] = a;
     }
-}
-
-__device__ __forceinline__ uint32_t upper_bound_g(const uint32_t* a, uint32_t n, uint32_t key)
-{
-    uint32_t lo = 0, hi = n;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (a[mid] <= key) lo = mid + 1; else hi = mid;
-    }
-    return lo;
 }
 
 __device__ __forceinline__ uint32_t blocks_of(unsigned long long M)
@@ -121,17 +153,27 @@ __device__ __forceinline__ uint32_t hist_get(const uint32_t* h, uint32_t t)
 }
 
 constexpr int kBinThreads = 1024;
-constexpr int kWindow = 16384;   // LDS window of instance offsets (active indices)
+constexpr uint32_t kBigSplat = 32;   // actives with more instances in a block are expanded by the whole block
+constexpr int kBigQueue = 1024;
+
+// (tile, active) of instance k of an active whose rect starts at (x0, y0) and
+// is wr tiles wide: row-major over the rect.
+__device__ __forceinline__ uint32_t tile_of(uint32_t k, uint32_t x0, uint32_t y0, uint32_t wr, int32_t TX)
+{
+    const uint32_t row = k / wr;
+    return (y0 + row) * (uint32_t)TX + x0 + (k - row * wr);
+}
 
 __global__ __launch_bounds__(kBinThreads) void k_emit_hist(const FrameParams* fp, const FrameInfo* info,
                                                            const uint32_t* __restrict__ off,
+                                                           const uint32_t* __restrict__ bstart,
                                                            const uint32_t* __restrict__ count, uint32_t cap,
                                                            const uint2* __restrict__ rect, uint2* __restrict__ inst,
                                                            uint32_t* __restrict__ hist, uint64_t max_instances)
 {
     __shared__ uint32_t s_hist[kMaxTiles / 2];
-    __shared__ uint32_t s_off[kWindow];
-    __shared__ uint32_t s_lo, s_cnt;
+    __shared__ uint32_t s_big[kBigQueue];
+    __shared__ uint32_t s_nbig;
     const unsigned long long M = info->n_instances;
     if (M == 0 || M > max_instances) return;
     const uint32_t n_act = min(*count, cap);
@@ -142,39 +184,44 @@ __global__ __launch_bounds__(kBinThreads) void k_emit_hist(const FrameParams* fp
         const uint32_t j0 = b * kBinChunk;
         const uint32_t j1 = (uint32_t)min((unsigned long long)j0 + kBinChunk, M);
         for (uint32_t k = threadIdx.x; k < (T + 1) / 2; k += kBinThreads) s_hist[k] = 0;
-        if (threadIdx.x == 0) {
-            const uint32_t lo = upper_bound_g(off, n_act, j0) - 1;
-            const uint32_t hi = upper_bound_g(off, n_act, j1 - 1) - 1;
-            s_lo = lo;
-            s_cnt = hi - lo + 1;
+        if (threadIdx.x == 0) s_nbig = 0;
+        // actives [lo, hi] hold the block's instances (hi may be one past the last)
+        const uint32_t lo = bstart[b];
+        const uint32_t hi = b + 1 < B ? bstart[b + 1] : n_act - 1;
+        __syncthreads();
+        // each thread expands its actives' instances that fall in [j0, j1); an
+        // active with many of them goes to the block-wide queue instead
+        for (uint32_t a = lo + threadIdx.x; a <= hi; a += kBinThreads) {
+            const uint32_t o = off[a];
+            const uint32_t o1 = a + 1 < n_act ? off[a + 1] : (uint32_t)M;
+            const uint32_t k0 = (o < j0 ? j0 : o) - o, k1 = (o1 > j1 ? j1 : o1) - o;
+            if (o1 <= o || k0 >= k1) continue;
+            if (k1 - k0 > kBigSplat) {
+                const uint32_t q = atomicAdd(&s_nbig, 1u);
+                if (q < (uint32_t)kBigQueue) { s_big[q] = a; continue; }
+            }
+            const uint2 rc = rect[a];
+            const uint32_t x0 = rc.x & 0xffffu, y0 = rc.x >> 16, wr = (rc.y & 0xffffu) - x0;
+            for (uint32_t k = k0; k < k1; k++) {
+                const uint32_t tile = tile_of(k, x0, y0, wr, TX);
+                inst[o + k] = make_uint2(tile, a);
+                hist_inc(s_hist, tile);
+            }
         }
         __syncthreads();
-        const uint32_t lo = s_lo, cnt = s_cnt;
-        const bool in_lds = cnt <= (uint32_t)kWindow;
-        if (in_lds)
-            for (uint32_t k = threadIdx.x; k < cnt; k += kBinThreads) s_off[k] = off[lo + k];
-        __syncthreads();
-        for (uint32_t j = j0 + threadIdx.x; j < j1; j += kBinThreads) {
-            // last active index whose offset is <= j (zero-tile entries share offsets: take the last)
-            uint32_t a;
-            if (in_lds) {
-                uint32_t l = 0, h = cnt;
-                while (l < h) {
-                    const uint32_t mid = (l + h) >> 1;
-                    if (s_off[mid] <= j) l = mid + 1; else h = mid;
-                }
-                a = lo + l - 1;
-            } else {
-                a = upper_bound_g(off, n_act, j) - 1;
-            }
-            const uint32_t k = j - off[a];
+        const uint32_t nbig = min(s_nbig, (uint32_t)kBigQueue);
+        for (uint32_t q = 0; q < nbig; q++) {
+            const uint32_t a = s_big[q];
+            const uint32_t o = off[a];
+            const uint32_t o1 = a + 1 < n_act ? off[a + 1] : (uint32_t)M;
+            const uint32_t k0 = (o < j0 ? j0 : o) - o, k1 = (o1 > j1 ? j1 : o1) - o;
             const uint2 rc = rect[a];
-            const uint32_t p0 = rc.x, p1 = rc.y;
-            const uint32_t x0 = p0 & 0xffffu, y0 = p0 >> 16, wr = (p1 & 0xffffu) - x0;
-            const uint32_t row = k / wr;
-            const uint32_t tile = (y0 + row) * (uint32_t)TX + x0 + (k - row * wr);
-            inst[j] = make_uint2(tile, a);
-            hist_inc(s_hist, tile);
+            const uint32_t x0 = rc.x & 0xffffu, y0 = rc.x >> 16, wr = (rc.y & 0xffffu) - x0;
+            for (uint32_t k = k0 + threadIdx.x; k < k1; k += kBinThreads) {
+                const uint32_t tile = tile_of(k, x0, y0, wr, TX);
+                inst[o + k] = make_uint2(tile, a);
+                hist_inc(s_hist, tile);
+            }
         }
         __syncthreads();
         uint32_t* row_out = hist + (size_t)b * T;
@@ -248,57 +295,111 @@ __global__ __launch_bounds__(256) void k_col_offset(const FrameParams* fp, const
 // long-list queues, longest list.
 constexpr int kTilesThreads = 1024;
 
+// Sort queue of a tile list, as one unit in a packed count: large (2048,
+// 16384] in bits 0-20, huge above in bits 21-41, mid (256, 2048] in 42-62.
+constexpr unsigned long long kQMask = (1ull << 21) - 1;
+__device__ __forceinline__ unsigned long long queue_unit(uint32_t c)
+{
+    return c > (uint32_t)kSortLarge ? 1ull << 21
+         : c > (uint32_t)kSortSmall ? 1ull : c > (uint32_t)kSortWave ? 1ull << 42 : 0ull;
+}
+
+// Length class of a tile list in the compositing order (longest first).
+__device__ __forceinline__ uint32_t length_class(uint32_t c)
+{
+    return c > 1024u ? 0u : (c > 256u ? 1u : (c > 64u ? 2u : 3u));
+}
+
+// Inclusive scan over the block of a 64-bit value (wave scans, wave totals in
+// LDS); returns the exclusive prefix and the block total.
+template <int NT>
+__device__ __forceinline__ unsigned long long block_scan64(unsigned long long v, unsigned long long* s_w,
+                                                           unsigned long long& total)
+{
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    unsigned long long inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long u = __shfl_up(inc, o);
+        if ((int)lane >= o) inc += u;
+    }
+    if (lane == 63) s_w[wave] = inc;
+    __syncthreads();
+    unsigned long long before = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; w++) {
+        const unsigned long long x = s_w[w];
+        before += (uint32_t)w < wave ? x : 0ull;
+        total += x;
+    }
+    __syncthreads();
+    return before + inc - v;
+}
+
+// One block over all tiles, each thread a contiguous run of them:
+// exclusive scan of the list lengths -> [start, end) per tile;
+// the compositing order (four length classes, longest first, tile order
+// inside a class) and the queues of lists too long for the per-tile LDS
+// sort, all placed by scans of packed per-thread counts (no atomics).
 __global__ __launch_bounds__(kTilesThreads) void k_tile_scan(const FrameParams* fp, FrameInfo* info,
                                                              const uint32_t* __restrict__ tcount,
                                                              uint2* __restrict__ ranges, uint32_t* __restrict__ order,
                                                              uint32_t* __restrict__ large)
 {
-    __shared__ uint32_t s_part[kTilesThreads];
-    __shared__ uint32_t s_cls[4], s_cls_base[4], s_max, s_nl, s_nh;
+    __shared__ unsigned long long s_w[3][kTilesThreads / 64];
+    __shared__ uint32_t s_max[kTilesThreads / 64];
     const uint32_t T = (uint32_t)(fp->TX * fp->TY);
-    const uint32_t tid = threadIdx.x;
-    if (tid < 4) s_cls[tid] = 0;
-    if (tid == 0) { s_max = 0; s_nl = 0; s_nh = 0; }
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t per = (T + kTilesThreads - 1) / kTilesThreads;
     const uint32_t t0 = min(T, tid * per), t1 = min(T, t0 + per);
-    uint32_t local = 0, lmax = 0;
+    // cls: four 16-bit class counts; big: three 21-bit queue counts (large, huge, mid)
+    unsigned long long sum = 0, cls = 0, big = 0;
+    uint32_t lmax = 0;
+#pragma unroll 8
     for (uint32_t t = t0; t < t1; t++) {
         const uint32_t c = tcount[t];
-        local += c;
+        sum += c;
         lmax = max(lmax, c);
+        cls += 1ull << (16 * length_class(c));
+        big += queue_unit(c);
     }
-    s_part[tid] = local;
-    __syncthreads();
-    atomicMax(&s_max, lmax);
-    for (int off = 1; off < kTilesThreads; off <<= 1) {
-        const uint32_t o = tid >= (uint32_t)off ? s_part[tid - off] : 0u;
-        __syncthreads();
-        s_part[tid] += o;
-        __syncthreads();
-    }
-    uint32_t run = s_part[tid] - local;
-    for (uint32_t t = t0; t < t1; t++) {
-        const uint32_t c = tcount[t];
-        ranges[t] = make_uint2(run, run + c);
-        const uint32_t cls = c > 1024u ? 0u : (c > 256u ? 1u : (c > 64u ? 2u : 3u));
-        atomicAdd(&s_cls[cls], 1u);
-        if (c > (uint32_t)kSortLarge) large[T + atomicAdd(&s_nh, 1u)] = t;
-        else if (c > (uint32_t)kSortSmall) large[atomicAdd(&s_nl, 1u)] = t;
-        run += c;
-    }
-    __syncthreads();
-    if (tid == 0) {
+    for (int o = 32; o > 0; o >>= 1) lmax = max(lmax, (uint32_t)__shfl_xor(lmax, o));
+    if (lane == 0) s_max[wave] = lmax;
+    unsigned long long sum_tot, cls_tot, big_tot;
+    unsigned long long run = block_scan64<kTilesThreads>(sum, s_w[0], sum_tot);
+    unsigned long long cpos = block_scan64<kTilesThreads>(cls, s_w[1], cls_tot);
+    unsigned long long bpos = block_scan64<kTilesThreads>(big, s_w[2], big_tot);
+    uint32_t base[4];
+    {
         uint32_t b = 0;
-        for (int k = 0; k < 4; k++) { s_cls_base[k] = b; b += s_cls[k]; s_cls[k] = 0; }
-        info->max_tile_len = s_max;
-        info->n_large = s_nl;
-        info->n_huge = s_nh;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            base[k] = b;
+            b += (uint32_t)(cls_tot >> (16 * k)) & 0xffffu;
+        }
     }
-    __syncthreads();
+    uint32_t nl = (uint32_t)(bpos & kQMask), nh = (uint32_t)((bpos >> 21) & kQMask),
+             nm = (uint32_t)((bpos >> 42) & kQMask);
+#pragma unroll 8
     for (uint32_t t = t0; t < t1; t++) {
-        const uint32_t c = tcount[t];
-        const uint32_t cls = c > 1024u ? 0u : (c > 256u ? 1u : (c > 64u ? 2u : 3u));
-        order[s_cls_base[cls] + atomicAdd(&s_cls[cls], 1u)] = t;
+        const uint32_t c = tcount[t];   // second read: the first pass left it in cache
+        // offsets only matter when the total fits the instance capacity (< 2^32)
+        ranges[t] = make_uint2((uint32_t)run, (uint32_t)(run + c));
+        run += c;
+        const uint32_t q = length_class(c);
+        order[base[q] + ((uint32_t)(cpos >> (16 * q)) & 0xffffu)] = t;
+        cpos += 1ull << (16 * q);
+        if (c > (uint32_t)kSortLarge) large[T + nh++] = t;
+        else if (c > (uint32_t)kSortSmall) large[nl++] = t;
+        else if (c > (uint32_t)kSortWave) large[2 * T + nm++] = t;
+    }
+    if (tid == 0) {
+        uint32_t m = 0;
+        for (int w = 0; w < kTilesThreads / 64; w++) m = max(m, s_max[w]);
+        info->max_tile_len = m;
+        info->n_large = (uint32_t)(big_tot & kQMask);
+        info->n_huge = (uint32_t)((big_tot >> 21) & kQMask);
+        info->n_mid = (uint32_t)((big_tot >> 42) & kQMask);
     }
 }
 
@@ -333,11 +434,11 @@ hipError_t launch_bin(const Views& v, const lodge_selection& sel, hipStream_t st
 {
     k_chunk_scan<<<1, kChunkScanThreads, 0, st>>>(v.info, v.chunk_sum, sel.count, sel.cap, v.max_instances);
     const uint32_t cg = std::max<uint32_t>(1, std::min<uint32_t>(4096, (v.max_active + 255) / 256));
-    k_inst_off<<<cg, 256, 0, st>>>(v.info, v.vtiles, v.chunk_sum, sel.count, sel.cap, v.max_instances);
+    k_inst_off<<<cg, 256, 0, st>>>(v.info, v.vtiles, v.chunk_sum, sel.count, sel.cap, v.bstart, v.max_instances);
     const uint32_t bmax = std::max<uint32_t>(1, (uint32_t)((v.max_instances + kBinChunk - 1) / kBinChunk));
     const uint32_t grid = std::min<uint32_t>(bmax, 1024);
-    k_emit_hist<<<grid, kBinThreads, 0, st>>>(v.params, v.info, v.vtiles, sel.count, sel.cap, v.rect, v.inst, v.hist,
-                                              v.max_instances);
+    k_emit_hist<<<grid, kBinThreads, 0, st>>>(v.params, v.info, v.vtiles, v.bstart, sel.count, sel.cap, v.rect,
+                                              v.inst, v.hist, v.max_instances);
     const uint32_t tb = (v.lay.T + kColTiles - 1) / kColTiles;
     k_col_sum<<<tb, 256, 0, st>>>(v.params, v.info, v.hist, v.tcount, v.max_instances);
     k_tile_scan<<<1, kTilesThreads, 0, st>>>(v.params, v.info, v.tcount, v.ranges, v.order, v.large);

@@ -2,24 +2,29 @@
 // alpha = o G(p), G = exp(-1/2 (p - mu')^T Sigma'^-1 (p - mu'))).
 //
 // Each 16 x 16 tile is split into four 8 x 8 quadrants and every quadrant is
-// one wave, one pixel per lane, working on its own: the waves of a block
-// share no data and never wait for each other, so a quadrant that reaches
-// full opacity stops at once.  Blocks take tiles longest-list first.
+// one wave that works on its own: the waves of a block share no data and
+// never wait for each other, so a quadrant that reaches full opacity stops
+// at once.  Blocks take tiles longest-list first.  Inside a wave, each group
+// of 16 lanes is a 4 x 4 sub-quadrant with a list of its own.
 //
-// A wave walks its tile's sorted run in batches of 64.  Each lane gathers
-// one splat's record and tests whether its alpha can reach 1/255 anywhere
-// in the quadrant: a bounding-box test on the ellipse where it can
-// (half-extents ex, ey from the projection), then the exact minimum of the
-// conic quadratic form over the box of the quadrant's pixel centres.  A
-// ballot compacts the survivors, in list order, into the wave's LDS slice;
-// the wave then walks them.  Per (pixel, splat): power = -1/2 (A dx^2 +
-// C dy^2) - B dx dy; skip if power > 0 or below the splat's threshold
-// ln(1/(255 o)) - 1e-3 (alpha < 1/255 there, so exp is not needed);
-// alpha = min(0.99, o exp(power)); skip if alpha < 1/255; stop (without
-// blending) once T (1 - alpha) < 1e-4; else C += rgb alpha T,
-// T *= 1 - alpha.  A splat dropped for a quadrant changes no decision: the
-// test keeps every splat that any pixel of the quadrant would not skip,
-// with a margin above the rounding of both computations.
+// A wave walks its tile's sorted run in batches of 64, the gathers of the
+// next batch in flight while the current one is composited.  Each lane
+// takes one splat of the batch, stores its record in the wave's LDS slice
+// and tests where its alpha can reach 1/255: against the quadrant, a
+// bounding-box test on that ellipse (half-extents ex, ey from the
+// projection) and then the exact minimum of the conic quadratic form over
+// the quadrant's box of pixel centres; against each sub-quadrant, the
+// bounding box.  Ballots compact the survivors, in list order, into one
+// slot list per sub-quadrant; the wave then runs as many steps as the
+// longest of the four lists, each lane following its own, predicated, with
+// the next entry read one step ahead.  Per (pixel, splat): power = -1/2
+// (A dx^2 + C dy^2) - B dx dy; skip if power > 0 or below the splat's
+// threshold ln(1/(255 o)) - 1e-3 (alpha < 1/255 there); alpha = min(0.99,
+// o exp(power)); skip if alpha < 1/255; stop (without blending) once
+// T (1 - alpha) < 1e-4; else C += rgb alpha T, T *= 1 - alpha.  A splat
+// dropped for a sub-quadrant changes no decision: the tests keep every
+// splat that any of its pixels would not skip, with a margin above the
+// rounding of both computations.
 //
 // Per-wave pair counters go to one slot each (no atomics); the host sums
 // them when the frame info is read.
@@ -30,45 +35,70 @@ namespace lodge {
 
 namespace {
 
-// Can the splat's alpha reach 1/255 at some point of the box [bx0, bx1] x
-// [by0, by1]?  r0 = (u, v, A, B), r1 = (C, ...), r2 = (.., ex, ey, thr) as
-// written by the projection; alpha >= 1/255 needs q(d) = A dx^2 + 2B dx dy
-// + C dy^2 <= rho = -2 thr.
-__device__ __forceinline__ bool reaches_box(const float4& r0, const float4& r1, const float4& r2, float bx0,
-                                            float bx1, float by0, float by1)
+// Per-splat terms of the box test, shared by the four sub-quadrants.
+struct BoxTest {
+    float u, v, mx, my;   // centre and bounding half-extents (with margin)
+    float A, B, C;        // conic
+    float nba, nbc;       // edge minimisers: x = -B y / A, y = -B x / C
+    float lim;            // accept if the minimum of the form is <= lim
+    bool any;             // alpha can reach 1/255 somewhere
+};
+
+// r0 = (u, v, A, B), r1 = (C, ...), r2 = (.., ex, ey, thr) as written by the
+// projection; alpha >= 1/255 needs q(d) = A dx^2 + 2B dx dy + C dy^2 <= -2 thr.
+__device__ __forceinline__ BoxTest box_test(const float4& r0, const float4& r1, const float4& r2)
 {
+    BoxTest b;
     const float ex = r2.y, ey = r2.z;
-    if (!(ex >= 0.0f)) return false;   // alpha below 1/255 everywhere (or a non-finite record)
-    const float u = r0.x, v = r0.y;
-    const float mx = ex + 1e-3f * ex + 0.01f, my = ey + 1e-3f * ey + 0.01f;
-    if (u + mx < bx0 || u - mx > bx1 || v + my < by0 || v - my > by1) return false;
-    const float du0 = bx0 - u, du1 = bx1 - u, dv0 = by0 - v, dv1 = by1 - v;
+    b.any = ex >= 0.0f;   // false: alpha below 1/255 everywhere (or a non-finite record)
+    b.u = r0.x;
+    b.v = r0.y;
+    b.mx = ex + 1e-3f * ex + 0.01f;
+    b.my = ey + 1e-3f * ey + 0.01f;
+    b.A = r0.z;
+    b.B = r0.w;
+    b.C = r1.x;
+    // an approximate reciprocal moves an edge minimiser by an ulp, which
+    // changes the form only to second order: far inside the margin below
+    b.nba = -b.B * __builtin_amdgcn_rcpf(b.A);
+    b.nbc = -b.B * __builtin_amdgcn_rcpf(b.C);
+    // rounding of the minimum and of the per-pixel power both grow with the
+    // conditioning of the form; lam bounds the largest covariance eigenvalue
+    // (approximate reciprocals: their ulp errors are far inside these margins)
+    const float rho = -2.0f * r2.w;
+    const float lam = (ex * ex + ey * ey) * __builtin_amdgcn_rcpf(rho);
+    const float gamma = 1.001e-5f * (1.0f + lam);
+    b.lim = gamma < 0.5f ? (rho + 1e-3f * rho) * __builtin_amdgcn_rcpf(1.0f - gamma) : INFINITY;
+    return b;
+}
+
+// Does the bounding box of the splat's alpha >= 1/255 ellipse meet [bx0, bx1] x [by0, by1]?
+__device__ __forceinline__ bool box_overlaps(const BoxTest& b, float bx0, float bx1, float by0, float by1)
+{
+    return !(b.u + b.mx < bx0 || b.u - b.mx > bx1 || b.v + b.my < by0 || b.v - b.my > by1);
+}
+
+// Can the splat reach alpha >= 1/255 at a point of [bx0, bx1] x [by0, by1]?
+__device__ __forceinline__ bool reaches(const BoxTest& b, float bx0, float bx1, float by0, float by1)
+{
+    if (!b.any || !box_overlaps(b, bx0, bx1, by0, by1)) return false;
+    const float du0 = bx0 - b.u, du1 = bx1 - b.u, dv0 = by0 - b.v, dv1 = by1 - b.v;
     if (du0 <= 0.0f && du1 >= 0.0f && dv0 <= 0.0f && dv1 >= 0.0f) return true;   // centre inside
     // the convex form is smallest on the boundary: minimise along each edge
-    // (an approximate reciprocal moves the edge minimiser by an ulp, which
-    // changes the form only to second order: far inside the margin below)
-    const float A = r0.z, B = r0.w, C = r1.x;
-    const float rho = -2.0f * r2.w;
-    const float nba = -B * __builtin_amdgcn_rcpf(A), nbc = -B * __builtin_amdgcn_rcpf(C);
     float qmin = INFINITY;
 #pragma unroll
     for (int e = 0; e < 2; e++) {
         const float x = e ? du1 : du0;
-        const float y = fminf(fmaxf(nbc * x, dv0), dv1);
-        qmin = fminf(qmin, (A * x) * x + (2.0f * B * x) * y + (C * y) * y);
+        const float y = fminf(fmaxf(b.nbc * x, dv0), dv1);
+        qmin = fminf(qmin, (b.A * x) * x + (2.0f * b.B * x) * y + (b.C * y) * y);
     }
 #pragma unroll
     for (int e = 0; e < 2; e++) {
         const float y = e ? dv1 : dv0;
-        const float x = fminf(fmaxf(nba * y, du0), du1);
-        qmin = fminf(qmin, (A * x) * x + (2.0f * B * x) * y + (C * y) * y);
+        const float x = fminf(fmaxf(b.nba * y, du0), du1);
+        qmin = fminf(qmin, (b.A * x) * x + (2.0f * b.B * x) * y + (b.C * y) * y);
     }
-    // rounding of this minimum and of the per-pixel power both grow with the
-    // conditioning of the form; lam bounds the largest covariance eigenvalue
-    const float lam = (ex * ex + ey * ey) / rho;
-    const float gamma = 1e-5f * (1.0f + lam);
-    if (!(gamma < 0.5f)) return true;
-    return qmin * (1.0f - gamma) <= rho + 1e-3f * rho;
+    return qmin <= b.lim;
 }
 
 __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict__ fp,
@@ -79,77 +109,118 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
                                                    float* __restrict__ final_T, uint32_t* __restrict__ n_contrib,
                                                    uint4* __restrict__ wstats, uint32_t cap)
 {
-    __shared__ float4 s_a[4][64];   // per wave: u, v, -A/2, -B
-    __shared__ float4 s_b[4][64];   // -C/2, o, threshold, r
-    __shared__ float4 s_c[4][64];   // g, b, list position + 1 (bits), -
+    // per wave, by batch slot: [0] u, v, -A/2, -B; [1] -C/2, o, threshold, r; [2] g, b, -, -
+    __shared__ float4 s_rec[4][3][64];
+    __shared__ uint8_t s_idx[4][4][64];   // per wave and sub-quadrant: batch slots in list order
 
     const int32_t W = fp->cam.width, H = fp->cam.height, TX = fp->TX;
     const uint32_t tile = order[blockIdx.x];
     const uint32_t tx = tile % (uint32_t)TX, ty = tile / (uint32_t)TX;
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t sub = lane >> 4;
     const uint32_t qx0 = tx * kTile + (wave & 1u) * 8u, qy0 = ty * kTile + (wave >> 1) * 8u;
-    const uint32_t x = qx0 + (lane & 7u), y = qy0 + (lane >> 3);
+    const uint32_t x = qx0 + (sub & 1u) * 4u + (lane & 3u), y = qy0 + (sub >> 1) * 4u + ((lane >> 2) & 3u);
     const bool inside = (int32_t)x < W && (int32_t)y < H;
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
-    const float bx0 = (float)qx0 + 0.5f, bx1 = bx0 + 7.0f, by0 = (float)qy0 + 0.5f, by1 = by0 + 7.0f;
+    const float bx0 = (float)qx0 + 0.5f, by0 = (float)qy0 + 0.5f;
     const uint2 rg = ranges[tile];
     const uint32_t len = rg.y - rg.x;
     const unsigned long long lt = (1ull << lane) - 1ull;
-    float4* const sa = s_a[wave];
-    float4* const sb = s_b[wave];
-    float4* const sc = s_c[wave];
+    float4* const sa = s_rec[wave][0];
+    float4* const sb = s_rec[wave][1];
+    float4* const sc = s_rec[wave][2];
+    uint8_t* const sidx = s_idx[wave][sub];
 
     float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
     uint32_t last = 0, nblend = 0, neval = len;
     bool done = !inside;
 
+    // software pipeline: records of batch b in r*, of batch b + 1 in flight,
+    // the list index of batch b + 2 in flight
+    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+    if (lane < len) {
+        uint32_t a = sorted[rg.x + lane];
+        a = a < cap ? a : 0u;   // an index outside the active set would be a binning bug
+        r0 = proj[3 * (size_t)a];
+        r1 = proj[3 * (size_t)a + 1];
+        r2 = proj[3 * (size_t)a + 2];
+    }
+    uint32_t a_next = 64 + lane < len ? sorted[rg.x + 64 + lane] : 0u;
+
     for (uint32_t b0 = 0; b0 < len; b0 += 64) {
         if (__ballot(!done) == 0ull) break;
         const uint32_t k = b0 + lane;
-        bool hit = false;
-        float4 r0, r1, r2;
-        if (k < len) {
-            uint32_t a = sorted[rg.x + k];
-            a = a < cap ? a : 0u;   // an index outside the active set would be a binning bug
+        const bool cur = k < len;
+        const float4 q0 = r0, q1 = r1, q2 = r2;
+        if (b0 + 64 + lane < len) {
+            const uint32_t a = a_next < cap ? a_next : 0u;
             r0 = proj[3 * (size_t)a];
             r1 = proj[3 * (size_t)a + 1];
             r2 = proj[3 * (size_t)a + 2];
-            hit = reaches_box(r0, r1, r2, bx0, bx1, by0, by1);
         }
-        const unsigned long long m = __ballot(hit);
-        if (hit) {
-            const uint32_t pos = (uint32_t)__popcll(m & lt);
-            sa[pos] = make_float4(r0.x, r0.y, -0.5f * r0.z, -r0.w);
-            sb[pos] = make_float4(-0.5f * r1.x, r1.y, r2.w, r1.z);
-            sc[pos] = make_float4(r1.w, r2.x, __uint_as_float(k + 1u), 0.0f);
+        a_next = b0 + 128 + lane < len ? sorted[rg.x + b0 + 128 + lane] : 0u;
+
+        bool hit[4] = {false, false, false, false};
+        if (cur) {
+            sa[lane] = make_float4(q0.x, q0.y, -0.5f * q0.z, -q0.w);
+            sb[lane] = make_float4(-0.5f * q1.x, q1.y, q2.w, q1.z);
+            sc[lane] = make_float4(q1.w, q2.x, 0.0f, 0.0f);
+            const BoxTest bt = box_test(q0, q1, q2);
+            // exact test for the quadrant, bounding boxes for its sub-quadrants
+            if (reaches(bt, bx0, bx0 + 7.0f, by0, by0 + 7.0f)) {
+#pragma unroll
+                for (int g = 0; g < 4; g++) {
+                    const float sx0 = bx0 + (float)((g & 1) * 4), sy0 = by0 + (float)((g >> 1) * 4);
+                    hit[g] = box_overlaps(bt, sx0, sx0 + 3.0f, sy0, sy0 + 3.0f);
+                }
+            }
+        }
+        uint32_t n_mine = 0, n_max = 0;
+#pragma unroll
+        for (int g = 0; g < 4; g++) {
+            const unsigned long long m = __ballot(hit[g]);
+            if (hit[g]) s_idx[wave][g][__popcll(m & lt)] = (uint8_t)lane;
+            const uint32_t c = (uint32_t)__popcll(m);
+            n_mine = (uint32_t)g == sub ? c : n_mine;
+            n_max = c > n_max ? c : n_max;
         }
         // the wave's own LDS slice: order its writes before its reads
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const uint32_t n = (uint32_t)__popcll(m);
-        if (!done) {
-            for (uint32_t j = 0; j < n; j++) {
-                const float4 g = sa[j];
-                const float4 c = sb[j];
-                float dx, dy, G;
-                bool clamped;
-                const float alpha = splat_alpha(g, c, px, py, dx, dy, G, clamped);
-                if (alpha < 0.0f) continue;
+        // walk the lane's sub-quadrant list, predicated rather than branched, with
+        // the next entry's slot and records read one step ahead
+        if (__ballot(!done && n_mine > 0) != 0ull) {
+            uint32_t e = sidx[0] & 63u;
+            uint32_t e_next = sidx[n_max > 1 ? 1 : 0] & 63u;
+            float4 g = sa[e], c = sb[e];
+            for (uint32_t j = 0; j < n_max; j++) {
+                const bool act = !done && j < n_mine;
+                if (__ballot(act) == 0ull) break;
+                const float4 gn = sa[e_next], cn = sb[e_next];
+                const uint32_t e_after = sidx[j + 2 < n_max ? j + 2 : 0] & 63u;
+                float alpha;
+                const bool keep = splat_keep(g, c, px, py, alpha) && act;
                 const float Tn = T * (1.0f - alpha);
-                if (Tn < kTStop) {
+                const bool stop = keep && Tn < kTStop;
+                if (stop) {
                     done = true;
-                    neval = __float_as_uint(sc[j].z);
-                    break;
+                    neval = b0 + e + 1u;
                 }
-                const float4 e = sc[j];
-                const float wgt = alpha * T;
-                cr = __builtin_fmaf(c.w, wgt, cr);
-                cg = __builtin_fmaf(e.x, wgt, cg);
-                cb = __builtin_fmaf(e.y, wgt, cb);
-                T = Tn;
-                last = __float_as_uint(e.z);
-                nblend++;
+                if (keep && !stop) {
+                    const float4 f = sc[e];
+                    const float wgt = alpha * T;
+                    cr = __builtin_fmaf(c.w, wgt, cr);
+                    cg = __builtin_fmaf(f.x, wgt, cg);
+                    cb = __builtin_fmaf(f.y, wgt, cb);
+                    T = Tn;
+                    last = b0 + e + 1u;
+                    nblend++;
+                }
+                e = e_next;
+                e_next = e_after;
+                g = gn;
+                c = cn;
             }
         }
         // every lane is past its reads before the next batch overwrites the slice
@@ -171,11 +242,12 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
     // per-wave counters, one slot per (tile, quadrant)
     unsigned long long ev = neval;
     uint32_t bl = nblend;
+    const uint32_t stopped = (uint32_t)__popcll(__ballot(inside && done));
     for (int off = 32; off > 0; off >>= 1) {
         ev += __shfl_xor(ev, off);
         bl += __shfl_xor(bl, off);
     }
-    if (lane == 0) wstats[4 * tile + wave] = make_uint4((uint32_t)ev, (uint32_t)(ev >> 32), bl, 0u);
+    if (lane == 0) wstats[4 * tile + wave] = make_uint4((uint32_t)ev, (uint32_t)(ev >> 32), bl, stopped);
 }
 
 }  // namespace

@@ -42,8 +42,7 @@ struct LevelsArg {
 struct ChunksArg {
     int32_t K;
     float band;
-    float c[LODGE_MAX_CHUNKS][3];
-    float r[LODGE_MAX_CHUNKS];
+    float4 c[LODGE_MAX_CHUNKS];   // centre (x, y, z), offset r
 };
 
 // Frame parameters in device memory: the camera copy plus what the setup
@@ -76,25 +75,51 @@ struct FrameInfo {
     float t;
     uint32_t n_large;     // tiles sorted by the large-list kernel
     uint32_t n_huge;      // tiles sorted by the merge fallback
-    uint32_t pad[4];
+    uint32_t n_mid;       // tiles sorted by the mid-length kernel
+    uint32_t pad[3];
 };
 
 enum : uint32_t { kOvfSelect = 1u, kOvfInstances = 2u, kOvfTile = 4u };
+
+// Field-by-field store of a camera held in kernel arguments (a struct
+// assignment would stage the argument through private memory).
+__device__ __forceinline__ void store_camera(lodge_camera* __restrict__ d, const lodge_camera& c)
+{
+    d->width = c.width;
+    d->height = c.height;
+    d->fx = c.fx;
+    d->fy = c.fy;
+    d->cx = c.cx;
+    d->cy = c.cy;
+#pragma unroll
+    for (int k = 0; k < 9; k++) d->R[k] = c.R[k];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        d->t[k] = c.t[k];
+        d->pos[k] = c.pos[k];
+        d->bg[k] = c.bg[k];
+    }
+    d->znear = c.znear;
+    d->lim_x = c.lim_x;
+    d->lim_y = c.lim_y;
+}
 
 // ------------------------------------------------------------ workspace map
 
 constexpr int kSelBlock = 256;
 constexpr int kSelItems = 16;                       // per thread
 constexpr int kSelTile = kSelBlock * kSelItems;     // Gaussians per selection block
+constexpr int kSortWave = 256;                      // per-tile register sort, one wave
 constexpr int kSortSmall = 2048;                    // per-tile LDS sort, 256 threads
-constexpr int kSortLarge = 16384;                   // per-tile LDS sort, 1024 threads
+constexpr int kSortMid = 4096;                      // per-tile LDS sort, 1024 threads, 32 KB
+constexpr int kSortLarge = 16384;                   // per-tile LDS sort, 1024 threads, 128 KB
 constexpr int kProjStride = 12;                     // floats per projected record
 constexpr int kBinChunk = 8192;                     // instances per binning block
 constexpr int kProjChunk = 64;                      // actives per projection chunk: one wave (instance-scan granule)
 constexpr int kMaxTiles = 32768;                    // 16-bit-packed LDS tile histograms (e.g. 3840 x 2160)
 
 struct Layout {
-    size_t params, info, wstats, sel_cnt, sel_off, sel_bits, chunk_sum, proj, depth, rect, vtiles, inst, hist, tcount, ranges, order, large,
+    size_t params, info, wstats, bstart, sel_cnt, sel_off, sel_bits, chunk_sum, proj, depth, rect, vtiles, inst, hist, tcount, ranges, order, large,
         sorted, temp, g2d, total;
     uint32_t sel_tiles, TX, TY, T, bin_blocks;
 };
@@ -105,7 +130,7 @@ Layout make_layout(uint32_t n_total, int32_t width, int32_t height, uint32_t max
 struct Views {
     FrameParams* params;
     FrameInfo* info;
-    uint4* wstats;         // per (tile, quadrant): pairs evaluated (lo, hi), pairs blended
+    uint4* wstats;         // per (tile, quadrant): pairs evaluated (lo, hi), pairs blended, pixels stopped
     uint32_t* sel_cnt;     // per selection tile: member count
     uint32_t* sel_off;     // per selection tile: exclusive offset of its members
     uint32_t* sel_bits;    // [selection tiles][kSelBlock] two membership bits per item
@@ -114,12 +139,13 @@ struct Views {
     float* depth;          // [max_active] camera depth (sort key), 0 when culled
     uint2* rect;           // [max_active] tile rect (x0 | y0 << 16, x1 | y1 << 16), empty when culled
     uint32_t* vtiles;      // tiles touched per active index -> exclusive instance offsets (in place)
+    uint32_t* bstart;      // per binning block: the active holding its first instance
     uint2* inst;           // [max_instances] (tile, active index) in emission order
     uint32_t* hist;        // [bin blocks][T] per-block tile counts -> per-block first slots
     uint32_t* tcount;      // per tile list length
     uint2* ranges;         // per tile [start, end)
     uint32_t* order;       // tiles by decreasing list length
-    uint32_t* large;       // tiles whose list exceeds kSortSmall
+    uint32_t* large;       // queues: [0, T) lists in (2048, 16384], [T, 2T) longer, [2T, 3T) in (256, 2048]
     uint32_t* sorted;      // [max_instances] active indices, tile-major
     unsigned long long* temp;   // [max_instances] merge scratch for very long lists
     float* g2d;            // [max_active][12] adjoint of the projected quantities
@@ -134,9 +160,14 @@ Views views_of(const lodge_workspace* ws, uint32_t n_total);
 // Each returns hipGetLastError() after enqueueing on `st`.
 
 hipError_t launch_set_camera(const lodge_camera& cam, const Views& v, hipStream_t st);
-hipError_t launch_select_setup(const LevelsArg& lv, const ChunksArg& ch, int32_t mode, const Views& v, hipStream_t st);
+hipError_t launch_select_setup(const LevelsArg& lv, const ChunksArg& ch, int32_t mode, const lodge_camera* cam,
+                              const Views& v, hipStream_t st);
 hipError_t launch_select(const LevelsArg& lv, const Views& v, const lodge_selection& sel, hipStream_t st);
-hipError_t launch_render_setup(const lodge_render_opts& o, const Views& v, hipStream_t st);
+// scan + emit of the selection from the per-tile counts and packed bits already in the workspace
+hipError_t launch_select_finish(const LevelsArg& lv, const Views& v, const lodge_selection& sel, hipStream_t st);
+hipError_t launch_sets_build(const LevelsArg& lv, const ChunksArg& ch, uint16_t* sets, hipStream_t st);
+hipError_t launch_sets_mark(const LevelsArg& lv, const Views& v, const uint16_t* sets, hipStream_t st);
+hipError_t launch_render_setup(const lodge_render_opts& o, const lodge_camera* cam, const Views& v, hipStream_t st);
 hipError_t launch_project(const LevelsArg& lv, const lodge_selection& sel, const Views& v, hipStream_t st);
 hipError_t launch_bin(const Views& v, const lodge_selection& sel, hipStream_t st);
 hipError_t launch_sort(const Views& v, hipStream_t st);

@@ -4,17 +4,18 @@
 // "Details on training the full representation": the renderer's 2-D
 // screen-space filter; Eq. 4: the chunk weight modulates opacity).
 //
-// One thread per active Gaussian (grid-stride to the device count).  The
-// mean, selection id and weight are read first; Gaussians behind the near
-// plane stop there, so scale, rotation, opacity and the 192-byte SH block
-// are read only for Gaussians in front of the camera (SH only for visible
-// ones).  Each active Gaussian writes its depth, tile rectangle and tile
-// count (0 when culled); visible ones also write a 48-byte compositing
-// record (centre, conic, opacity, colour, the power below which alpha
-// cannot reach 1/255, and the half-extents of the ellipse where it can).
-// Each wave also writes the tile total of its 64 consecutive actives (the
-// first level of the instance-offset scan).  The front/visible counters are
-// reduced per block and added once.
+// Each wave takes chunks of 64 consecutive actives (grid-stride over the
+// chunks), one per lane.  Geometry first: the mean, selection id and weight
+// are read; Gaussians behind the near plane stop there, the others read
+// scale, rotation and opacity.  Each active writes its depth, tile rectangle
+// and tile count (0 when culled), and each chunk writes its tile total (the
+// first level of the instance-offset scan).  A visible Gaussian writes its
+// compositing record (centre, conic, opacity, the power below which alpha
+// cannot reach 1/255, the half-extents of the ellipse where it can) and
+// joins the wave's LDS queue with its view direction.  Colour is evaluated
+// from the queue 64 at a time, so the 48 SH loads and the basis run with
+// every lane busy rather than on the few visible lanes of each chunk.
+// The front/visible counters are reduced per block and added once.
 //
 // Built with -ffp-contract=off: the rectangle and depth (which decide tile
 // membership and sort keys) are evaluated op for op as the oracle defines
@@ -63,18 +64,85 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, float* Y)
     Y[15] = -(kC3a * (x * (xx - 3.0f * yy)));
 }
 
-// The level of global id g, with its fields picked out of the (uniform)
-// kernel argument by selects, so every later load has its base in registers.
-__device__ __forceinline__ LevelDev level_of(const LevelsArg& lv, uint32_t g)
+// A pointer every active lane holds the same value of, moved to scalar registers.
+__device__ __forceinline__ const float* uniform_ptr(const float* p)
 {
-    LevelDev o = lv.lv[0];
-#pragma unroll
-    for (int j = 1; j < LODGE_MAX_LEVELS; j++)
-        if (j < lv.L && g >= lv.lv[j].base) o = lv.lv[j];
-    return o;
+    const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<const float*>(((unsigned long long)hi << 32) | lo);
 }
 
-__global__ __launch_bounds__(256) void k_project(LevelsArg lv, const uint32_t* __restrict__ ids,
+// Element at byte offset off of a plane: scalar base + 32-bit lane offset.
+typedef const __attribute__((address_space(1))) char gchar;
+typedef const __attribute__((address_space(1))) float gfloat;
+__device__ __forceinline__ float ld(const float* plane, uint32_t off)
+{
+    return *(gfloat*)((gchar*)plane + off);
+}
+
+__device__ __forceinline__ int level_index(const LevelsArg& lv, uint32_t g)
+{
+    int l = 0;
+#pragma unroll
+    for (int j = 1; j < LODGE_MAX_LEVELS; j++)
+        if (j < lv.L && g >= lv.lv[j].base) l = j;
+    return l;
+}
+
+constexpr int kQueue = 128;   // per-wave colour queue: < 64 left over + one chunk of 64
+
+// Colour of up to 64 queued Gaussians, one per lane (lanes >= cnt idle):
+// degree-3 real SH at the view direction, + 0.5, clamped at 0; written into
+// the record's colour fields.
+__device__ __forceinline__ void colour_batch(const LevelsArg& lv, const uint32_t* qa, const uint32_t* qg,
+                                             const float (*qd)[kQueue], uint32_t cnt, float4* __restrict__ proj)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const bool mine = lane < cnt;
+    const uint32_t a = mine ? qa[lane] : 0u;
+    const uint32_t g = mine ? qg[lane] : 0u;
+    const float dx = mine ? qd[0][lane] : 0.0f, dy = mine ? qd[1][lane] : 0.0f, dz = mine ? qd[2][lane] : 0.0f;
+    const int lvl = level_index(lv, g);
+    bool todo = mine;
+    while (true) {
+        const unsigned long long pend = __ballot(todo);
+        if (pend == 0ull) break;
+        const int l0 = __builtin_amdgcn_readlane(lvl, __ffsll((long long)pend) - 1);
+        if (todo && lvl == l0) {
+            todo = false;
+            const LevelDev& Lv = lv.lv[l0];
+            const float* __restrict__ shp = uniform_ptr(Lv.sh);
+            const size_t n = __builtin_amdgcn_readfirstlane(Lv.n);
+            const int sh_degree = __builtin_amdgcn_readfirstlane(Lv.sh_degree);
+            const uint32_t off = (g - __builtin_amdgcn_readfirstlane(Lv.base)) * 4u;
+            // all (d+1)^2 x 3 coefficients are loaded before the first use; planes past
+            // the level's degree are clamped in bounds and contribute an exact zero
+            const int nb = (sh_degree + 1) * (sh_degree + 1);
+            float coef[kMaxSh][3];
+#pragma unroll
+            for (int k = 0; k < kMaxSh; k++)
+#pragma unroll
+                for (int ch = 0; ch < 3; ch++) coef[k][ch] = ld(shp + (size_t)((k < nb ? k : nb - 1) * 3 + ch) * n, off);
+            float Y[kMaxSh];
+            sh_basis(dx, dy, dz, Y);
+            float rgb[3];
+#pragma unroll
+            for (int ch = 0; ch < 3; ch++) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int k = 0; k < kMaxSh; k++) acc = acc + (k < nb ? coef[k][ch] : 0.0f) * Y[k];
+                acc = acc + 0.5f;
+                rgb[ch] = acc > 0.0f ? acc : 0.0f;
+            }
+            float* r = reinterpret_cast<float*>(proj + 3 * (size_t)a);
+            *reinterpret_cast<float2*>(r + 6) = make_float2(rgb[0], rgb[1]);
+            r[8] = rgb[2];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_project(LevelsArg lv, const uint32_t* __restrict__ ids,
                                                  const float* __restrict__ wsel, const uint32_t* __restrict__ count,
                                                  uint32_t cap, const FrameParams* __restrict__ fp, FrameInfo* info,
                                                  float4* __restrict__ proj, float* __restrict__ depth,
@@ -82,35 +150,60 @@ __global__ __launch_bounds__(256) void k_project(LevelsArg lv, const uint32_t* _
                                                  uint32_t* __restrict__ chunk_sum)
 {
     __shared__ uint32_t s_cnt[2][4];
+    __shared__ uint32_t s_qa[4][kQueue], s_qg[4][kQueue];
+    __shared__ float s_qd[4][3][kQueue];
     const uint32_t n_act = min(*count, cap);
     const lodge_camera& cam = fp->cam;
     const float s2d = fp->s2d;
     const int compensate = fp->compensate;
     const int32_t TX = fp->TX, TY = fp->TY;
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    uint32_t* const qa = s_qa[wave];
+    uint32_t* const qg = s_qg[wave];
+    float (*const qd)[kQueue] = s_qd[wave];
     uint32_t n_front = 0, n_vis = 0;
+    uint32_t qn = 0;   // wave-uniform queue length
 
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < n_act; base += stride) {
-        const uint32_t a = base + threadIdx.x;
+    const uint32_t nchunks = (n_act + kProjChunk - 1) / kProjChunk;
+    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    for (uint32_t c = blockIdx.x * (blockDim.x >> 6) + wave; c < nchunks; c += waves) {
+        const uint32_t a = c * kProjChunk + lane;
         bool visible = false, front = false;
         uint32_t ntiles = 0;
         float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
-        float dep = 0.0f;
+        float dep = 0.0f, d0n = 0.0f, d1n = 0.0f, d2n = 0.0f;
         int32_t x0 = 0, y0 = 0, x1 = 0, y1 = 0;
-        if (a < n_act) {
-            const uint32_t g = ids[a];
-            const LevelDev L = level_of(lv, g);
-            const size_t n = L.n;
-            const uint32_t i = g - L.base;
-            const float mx = L.mean[i], my = L.mean[n + i], mz = L.mean[2 * n + i];
+        const uint32_t g = a < n_act ? ids[a] : 0u;
+        const int lvl = level_index(lv, g);
+        bool todo = a < n_act;
+        // one pass per level present in the wave (almost always one): the
+        // level's fields are then wave-uniform and live in scalar registers
+        while (true) {
+          const unsigned long long pend = __ballot(todo);
+          if (pend == 0ull) break;
+          const int l0 = __builtin_amdgcn_readlane(lvl, __ffsll((long long)pend) - 1);
+          if (todo && lvl == l0) {
+            todo = false;
+            const LevelDev& Lv = lv.lv[l0];
+            const float* __restrict__ mean = uniform_ptr(Lv.mean);
+            const float* __restrict__ scale = uniform_ptr(Lv.scale);
+            const float* __restrict__ quat = uniform_ptr(Lv.quat);
+            const float* __restrict__ opac = uniform_ptr(Lv.opacity);
+            const size_t n = __builtin_amdgcn_readfirstlane(Lv.n);
+            const float var = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(Lv.var)));
+            // byte offset inside a plane (levels hold fewer than 2^30 Gaussians)
+            const uint32_t off = (g - __builtin_amdgcn_readfirstlane(Lv.base)) * 4u;
+            const float mx = ld(mean, off), my = ld(mean + n, off), mz = ld(mean + 2 * n, off);
             const float* W = cam.R;
             const float tx = ((W[0] * mx + W[1] * my) + W[2] * mz) + cam.t[0];
             const float ty = ((W[3] * mx + W[4] * my) + W[5] * mz) + cam.t[1];
             const float tz = ((W[6] * mx + W[7] * my) + W[8] * mz) + cam.t[2];
             if (tz > cam.znear) {
                 front = true;
-                const float s0 = L.scale[i], s1 = L.scale[n + i], s2 = L.scale[2 * n + i];
-                const float qw = L.quat[i], qx = L.quat[n + i], qy = L.quat[2 * n + i], qz = L.quat[3 * n + i];
+                const float s0 = ld(scale, off), s1 = ld(scale + n, off), s2 = ld(scale + 2 * n, off);
+                const float qw = ld(quat, off), qx = ld(quat + n, off), qy = ld(quat + 2 * n, off),
+                            qz = ld(quat + 3 * n, off);
                 // rotation of the quaternion (w, x, y, z) as given
                 const float xx = qx * qx, yy = qy * qy, zz = qz * qz;
                 const float xy = qx * qy, xz = qx * qz, yz = qy * qz;
@@ -119,7 +212,7 @@ __global__ __launch_bounds__(256) void k_project(LevelsArg lv, const uint32_t* _
                                     2.0f * (xy + wz),        1.0f - 2.0f * (xx + zz), 2.0f * (yz - wx),
                                     2.0f * (xz - wy),        2.0f * (yz + wx),        1.0f - 2.0f * (xx + yy)};
                 // Eq. 3: Sigma + var I, and sqrt(|Sigma| / |Sigma + var I|)
-                const float v0 = s0 * s0 + L.var, v1 = s1 * s1 + L.var, v2 = s2 * s2 + L.var;
+                const float v0 = s0 * s0 + var, v1 = s1 * s1 + var, v2 = s2 * s2 + var;
                 float S[9];
 #pragma unroll
                 for (int p = 0; p < 3; p++)
@@ -182,31 +275,13 @@ __global__ __launch_bounds__(256) void k_project(LevelsArg lv, const uint32_t* _
                     if (x0 < x1 && y0 < y1) {
                         visible = true;
                         ntiles = (uint32_t)((x1 - x0) * (y1 - y0));
-                        // view-dependent colour from the direction camera -> mean
+                        // view direction camera -> mean, for the colour pass
                         const float d0 = mx - cam.pos[0], d1 = my - cam.pos[1], d2 = mz - cam.pos[2];
                         const float dn = sqrtf((d0 * d0 + d1 * d1) + d2 * d2);
-                        float Y[kMaxSh];
-                        sh_basis(d0 / dn, d1 / dn, d2 / dn, Y);
-                        // all (d+1)^2 x 3 coefficients are loaded before the first use; planes past
-                        // the level's degree are clamped in bounds and contribute an exact zero
-                        const int nb = (L.sh_degree + 1) * (L.sh_degree + 1);
-                        const float* __restrict__ sh = L.sh + i;
-                        float coef[kMaxSh][3];
-#pragma unroll
-                        for (int k = 0; k < kMaxSh; k++)
-#pragma unroll
-                            for (int ch = 0; ch < 3; ch++)
-                                coef[k][ch] = sh[(size_t)((k < nb ? k : nb - 1) * 3 + ch) * n];
-                        float rgb[3];
-#pragma unroll
-                        for (int ch = 0; ch < 3; ch++) {
-                            float acc = 0.0f;
-#pragma unroll
-                            for (int k = 0; k < kMaxSh; k++) acc = acc + (k < nb ? coef[k][ch] : 0.0f) * Y[k];
-                            acc = acc + 0.5f;
-                            rgb[ch] = acc > 0.0f ? acc : 0.0f;
-                        }
-                        const float o_eff = ((L.opacity[i] * wsel[a]) * comp3) * comp2;
+                        d0n = d0 / dn;
+                        d1n = d1 / dn;
+                        d2n = d2 / dn;
+                        const float o_eff = ((ld(opac, off) * wsel[a]) * comp3) * comp2;
                         // compositing aids: below power thr alpha cannot reach 1/255 (margin 1e-3);
                         // (ex, ey) half-extents of the ellipse where it can: d^T conic d <= -2 thr
                         const float thr = o_eff > 0.0f ? -logf(255.0f * o_eff) - 1e-3f : INFINITY;
@@ -214,12 +289,15 @@ __global__ __launch_bounds__(256) void k_project(LevelsArg lv, const uint32_t* _
                         const float ex = rho > 0.0f ? sqrtf(rho * aa) : -1.0f;
                         const float ey = rho > 0.0f ? sqrtf(rho * cc) : -1.0f;
                         r0 = make_float4(u, v, A, B);
-                        r1 = make_float4(C, o_eff, rgb[0], rgb[1]);
-                        r2 = make_float4(rgb[2], ex, ey, thr);
+                        r1 = make_float4(C, o_eff, 0.0f, 0.0f);
+                        r2 = make_float4(0.0f, ex, ey, thr);
                         dep = tz;
                     }
                 }
             }
+          }
+        }
+        if (a < n_act) {
             if (visible) {
                 proj[3 * (size_t)a] = r0;
                 proj[3 * (size_t)a + 1] = r1;
@@ -233,18 +311,60 @@ __global__ __launch_bounds__(256) void k_project(LevelsArg lv, const uint32_t* _
             n_front += front ? 1u : 0u;
             n_vis += visible ? 1u : 0u;
         }
-        // each wave's 64 consecutive actives form one chunk of the instance scan
+        // the chunk's tile total: first level of the instance scan
         uint32_t csum = ntiles;
-        for (int off = 32; off > 0; off >>= 1) csum += __shfl_xor(csum, off);
-        const uint32_t first = a - (threadIdx.x & 63u);
-        if ((threadIdx.x & 63u) == 0 && first < n_act) chunk_sum[first / kProjChunk] = csum;
+        for (int o = 32; o > 0; o >>= 1) csum += __shfl_xor(csum, o);
+        if (lane == 0) chunk_sum[c] = csum;
+        // queue the visible ones for colour
+        const unsigned long long m = __ballot(visible);
+        if (visible) {
+            const uint32_t p = qn + (uint32_t)__popcll(m & lt);
+            qa[p] = a;
+            qg[p] = g;
+            qd[0][p] = d0n;
+            qd[1][p] = d1n;
+            qd[2][p] = d2n;
+        }
+        qn += (uint32_t)__popcll(m);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (qn >= 64) {
+            colour_batch(lv, qa, qg, qd, 64, proj);
+            // move the left-over entries to the front of the queue
+            const uint32_t rem = qn - 64;
+            uint32_t ta = 0, tg = 0;
+            float t0 = 0.0f, t1 = 0.0f, t2 = 0.0f;
+            if (lane < rem) {
+                ta = qa[64 + lane];
+                tg = qg[64 + lane];
+                t0 = qd[0][64 + lane];
+                t1 = qd[1][64 + lane];
+                t2 = qd[2][64 + lane];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (lane < rem) {
+                qa[lane] = ta;
+                qg[lane] = tg;
+                qd[0][lane] = t0;
+                qd[1][lane] = t1;
+                qd[2][lane] = t2;
+            }
+            qn = rem;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
     }
+    if (qn > 0) colour_batch(lv, qa, qg, qd, qn, proj);
     // counters: wave sums, block sum, one atomic per block
-    for (int off = 32; off > 0; off >>= 1) {
-        n_front += __shfl_xor(n_front, off);
-        n_vis += __shfl_xor(n_vis, off);
+    for (int o = 32; o > 0; o >>= 1) {
+        n_front += __shfl_xor(n_front, o);
+        n_vis += __shfl_xor(n_vis, o);
     }
-    if ((threadIdx.x & 63) == 0) { s_cnt[0][threadIdx.x >> 6] = n_front; s_cnt[1][threadIdx.x >> 6] = n_vis; }
+    if (lane == 0) { s_cnt[0][wave] = n_front; s_cnt[1][wave] = n_vis; }
     __syncthreads();
     if (threadIdx.x == 0) {
         const uint32_t f = s_cnt[0][0] + s_cnt[0][1] + s_cnt[0][2] + s_cnt[0][3];
@@ -258,9 +378,23 @@ __global__ __launch_bounds__(256) void k_project(LevelsArg lv, const uint32_t* _
 
 hipError_t launch_project(const LevelsArg& lv, const lodge_selection& sel, const Views& v, hipStream_t st)
 {
+    // persistent waves: exactly as many blocks as the device holds at once, so
+    // every wave's queue spans many chunks and no second partial round is left
+    static thread_local int dev_cached = -1;
+    static thread_local uint32_t resident = 0;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev != dev_cached) {
+        int per_cu = 0, cus = 0;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_project, 256, 0)) != hipSuccess) return e;
+        if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+        resident = (uint32_t)std::max(1, per_cu * cus);
+        dev_cached = dev;
+    }
     uint32_t blocks = (v.max_active + 255) / 256;
     if (blocks < 1) blocks = 1;
-    if (blocks > kPersistentBlocks) blocks = kPersistentBlocks;
+    if (blocks > resident) blocks = resident;
     k_project<<<blocks, 256, 0, st>>>(lv, sel.ids, sel.w, sel.count, sel.cap, v.params, v.info, v.proj, v.depth,
                                       v.rect, v.vtiles, v.chunk_sum);
     return hipGetLastError();

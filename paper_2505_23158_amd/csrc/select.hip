@@ -24,9 +24,9 @@ namespace lodge {
 
 namespace {
 
-__device__ __forceinline__ float dist2(float px, float py, float pz, const float* q)
+__device__ __forceinline__ float dist2(float px, float py, float pz, float qx, float qy, float qz)
 {
-    const float dx = px - q[0], dy = py - q[1], dz = pz - q[2];
+    const float dx = px - qx, dy = py - qy, dz = pz - qz;
     return (dx * dx + dy * dy) + dz * dz;
 }
 
@@ -46,21 +46,23 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
     return v;
 }
 
-// One wave.  (The chunk table is a by-value kernel argument indexed with
-// lane-dependent subscripts, which the compiler stages through private
-// memory; keeping this kernel to 64 lanes keeps that copy negligible.)
-__global__ __launch_bounds__(64) void k_select_setup(ChunksArg ch, LevelsArg lv, int32_t mode, FrameParams* fp,
-                                                     FrameInfo* info)
+// One wave.  With a camera argument (has_cam) the kernel also stores it into
+// the frame parameters, which saves a launch.
+__global__ __launch_bounds__(64) void k_select_setup(ChunksArg ch, LevelsArg lv, int32_t mode, lodge_camera cam,
+                                                     int32_t has_cam, FrameParams* fp, FrameInfo* info)
 {
     const int lane = threadIdx.x;
-    const float px = fp->cam.pos[0], py = fp->cam.pos[1], pz = fp->cam.pos[2];
+    const float px = has_cam ? cam.pos[0] : fp->cam.pos[0];
+    const float py = has_cam ? cam.pos[1] : fp->cam.pos[1];
+    const float pz = has_cam ? cam.pos[2] : fp->cam.pos[2];
     int f = -1, o = -1;
     float t = 1.0f;
     if (mode == LODGE_SELECT_CHUNKED) {
         float d = INFINITY;
         int k = 0x7fffffff;
         for (int c = lane; c < ch.K; c += 64) {
-            const float dc = dist2(px, py, pz, ch.c[c]);
+            const float4 m = ch.c[c];
+            const float dc = dist2(px, py, pz, m.x, m.y, m.z);
             if (dc < d || (dc == d && c < k)) { d = dc; k = c; }
         }
         wave_argmin(d, k);
@@ -70,14 +72,16 @@ __global__ __launch_bounds__(64) void k_select_setup(ChunksArg ch, LevelsArg lv,
             int k2 = 0x7fffffff;
             for (int c = lane; c < ch.K; c += 64) {
                 if (c == f) continue;
-                const float dc = dist2(px, py, pz, ch.c[c]);
+                const float4 m = ch.c[c];
+                const float dc = dist2(px, py, pz, m.x, m.y, m.z);
                 if (dc < d2 || (dc == d2 && c < k2)) { d2 = dc; k2 = c; }
             }
             wave_argmin(d2, k2);
             o = k2;
             // Eq. 4: t_bar = ((c - m_o) . (m_f - m_o)) / |m_f - m_o|^2
-            const float g0 = ch.c[f][0] - ch.c[o][0], g1 = ch.c[f][1] - ch.c[o][1], g2 = ch.c[f][2] - ch.c[o][2];
-            const float e0 = px - ch.c[o][0], e1 = py - ch.c[o][1], e2 = pz - ch.c[o][2];
+            const float4 mf = ch.c[f], mo = ch.c[o];
+            const float g0 = mf.x - mo.x, g1 = mf.y - mo.y, g2 = mf.z - mo.z;
+            const float e0 = px - mo.x, e1 = py - mo.y, e2 = pz - mo.z;
             const float num = (e0 * g0 + e1 * g1) + e2 * g2;
             const float den = (g0 * g0 + g1 * g1) + g2 * g2;
             float tb = num / den;
@@ -87,24 +91,30 @@ __global__ __launch_bounds__(64) void k_select_setup(ChunksArg ch, LevelsArg lv,
         }
     }
     if (lane != 0) return;
+    if (has_cam) store_camera(&fp->cam, cam);
     fp->mode = mode;
     fp->f = f;
     fp->o = o;
     fp->t = t;
     fp->w_o = 1.0f - t;
-    const float zero3[3] = {0.0f, 0.0f, 0.0f};
-    const float* cf = zero3;
-    const float* co = zero3;
+    float cf[3] = {0.0f, 0.0f, 0.0f}, co[3] = {0.0f, 0.0f, 0.0f};
     float rf = 0.0f, ro = 0.0f;
-    if (mode == LODGE_SELECT_LOD_CAMERA) cf = fp->cam.pos;
+    if (mode == LODGE_SELECT_LOD_CAMERA) { cf[0] = px; cf[1] = py; cf[2] = pz; }
     if (mode == LODGE_SELECT_CHUNKED) {
-        cf = ch.c[f];
-        rf = ch.r[f];
-        if (o >= 0) { co = ch.c[o]; ro = ch.r[o]; }
+        const float4 mf = ch.c[f];
+        cf[0] = mf.x; cf[1] = mf.y; cf[2] = mf.z;
+        rf = mf.w;
+        if (o >= 0) {
+            const float4 mo = ch.c[o];
+            co[0] = mo.x; co[1] = mo.y; co[2] = mo.z;
+            ro = mo.w;
+        }
     }
     for (int j = 0; j < 3; j++) { fp->cf[j] = cf[j]; fp->co[j] = co[j]; }
     // squared bounds: lo(0) = 0, lo(l) = (d_l + r)^2, hi(l) = lo(l+1), hi(L-1) = inf
-    for (int l = 0; l < lv.L; l++) {
+#pragma unroll
+    for (int l = 0; l < LODGE_MAX_LEVELS; l++) {
+        if (l >= lv.L) break;
         float s;
         s = (l == 0) ? 0.0f : lv.d[l - 1] + rf;
         fp->lo_f[l] = (l == 0) ? 0.0f : s * s;
@@ -175,10 +185,10 @@ __global__ __launch_bounds__(kSelBlock) void k_select(LevelsArg lv, const FrameP
             if (all) {
                 s = 1;
             } else {
-                const float df = dist2(mx[r], my[r], mz[r], cf);
+                const float df = dist2(mx[r], my[r], mz[r], cf[0], cf[1], cf[2]);
                 if (lof <= df && df < hif) s |= 1u;
                 if (two) {
-                    const float dq = dist2(mx[r], my[r], mz[r], co);
+                    const float dq = dist2(mx[r], my[r], mz[r], co[0], co[1], co[2]);
                     if (loo <= dq && dq < hio) s |= 2u;
                 }
             }
@@ -285,9 +295,12 @@ __global__ __launch_bounds__(kSelBlock) void k_select_emit(LevelsArg lv, const F
 
 }  // namespace
 
-hipError_t launch_select_setup(const LevelsArg& lv, const ChunksArg& ch, int32_t mode, const Views& v, hipStream_t st)
+hipError_t launch_select_setup(const LevelsArg& lv, const ChunksArg& ch, int32_t mode, const lodge_camera* cam,
+                              const Views& v, hipStream_t st)
 {
-    k_select_setup<<<1, 64, 0, st>>>(ch, lv, mode, v.params, v.info);
+    lodge_camera c{};
+    if (cam) c = *cam;
+    k_select_setup<<<1, 64, 0, st>>>(ch, lv, mode, c, cam ? 1 : 0, v.params, v.info);
     return hipGetLastError();
 }
 
@@ -295,6 +308,12 @@ hipError_t launch_select(const LevelsArg& lv, const Views& v, const lodge_select
 {
     const uint32_t ntiles = std::max<uint32_t>(lv.sel_blocks, 1);   // an empty scene still runs (count 0)
     k_select<<<ntiles, kSelBlock, 0, st>>>(lv, v.params, ntiles, v.sel_cnt, v.sel_bits);
+    return launch_select_finish(lv, v, sel, st);
+}
+
+hipError_t launch_select_finish(const LevelsArg& lv, const Views& v, const lodge_selection& sel, hipStream_t st)
+{
+    const uint32_t ntiles = std::max<uint32_t>(lv.sel_blocks, 1);
     k_select_scan<<<1, kSelScanThreads, 0, st>>>(v.info, v.sel_cnt, v.sel_off, ntiles, sel.cap, sel.count);
     k_select_emit<<<ntiles, kSelBlock, 0, st>>>(lv, v.params, ntiles, v.sel_cnt, v.sel_off, v.sel_bits, sel.ids,
                                                 sel.w, sel.cap);

@@ -6,10 +6,18 @@
 // so the bit pattern orders like the value, and the index makes the order
 // total (ties in depth are broken by active index, i.e. by global id).
 //
-//   k_sort_small  one 256-thread block per tile, runs <= 2048: bitonic
-//                 network on 64-bit keys in LDS (16 KB).
-//   k_sort_large  1024-thread blocks over the queue of runs in (2048, 16384]:
-//                 the same network in 128 KB of LDS (gfx950 allows 160 KB).
+// Runs up to 4096 keys are sorted by a bitonic network held in registers:
+// each thread keeps E consecutive keys; stages whose partner is in the same
+// thread compare registers, stages whose partner is in another lane of the
+// wave exchange keys with lane shuffles, and only stages whose partner is in
+// another wave go through LDS (double-buffered, one barrier per stage).
+//
+//   k_sort_wave   runs <= 256, one wave each (four per block), 1-4 keys per
+//                 lane: no LDS, no barrier.
+//   k_sort_mid    queued runs in (256, 2048], 256 threads x 8 keys.
+//   k_sort_big    queued runs in (2048, 4096], 1024 threads x 4 keys.
+//   k_sort_large  queued runs in (4096, 16384]: the bitonic network in 128 KB
+//                 of LDS, 1024 threads (gfx950 allows 160 KB).
 //   k_sort_huge   runs > 16384: 16384-key chunks sorted in LDS, then merge
 //                 passes in global memory where each key finds its output
 //                 slot by binary search in the sibling run.
@@ -64,45 +72,145 @@ __device__ __forceinline__ void sort_run(unsigned long long* s, const float* __r
     __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_sort_small(const FrameParams* fp, const uint2* __restrict__ ranges,
-                                                    const float* __restrict__ proj, uint32_t* __restrict__ sorted,
-                                                    uint32_t cap)
+__device__ __forceinline__ unsigned long long keep(unsigned long long a, unsigned long long b, bool keep_min)
 {
-    __shared__ unsigned long long s[kSortSmall];
-    const uint32_t T = (uint32_t)(fp->TX * fp->TY);
-    for (uint32_t t = blockIdx.x; t < T; t += gridDim.x) {
-        const uint2 r = ranges[t];
-        const uint32_t n = r.y - r.x;
-        if (n <= 1 || n > (uint32_t)kSortSmall) continue;
-        uint32_t* run = sorted + r.x;
-        if (n <= 256) {
-            // rank sort: keys are unique, so each key's rank is the number of smaller keys
-            const uint32_t i = threadIdx.x;
-            unsigned long long mine = ~0ull;
-            if (i < n) s[i] = mine = key_of(proj, run[i], cap);
-            __syncthreads();
-            uint32_t rank = 0;
-            if (i < n)
-                for (uint32_t j = 0; j < n; j++) rank += s[j] < mine ? 1u : 0u;
-            __syncthreads();
-            if (i < n) run[rank] = mine == ~0ull ? 0xffffffffu : (uint32_t)mine;
-            __syncthreads();
-        } else {
-            sort_run<256, kSortSmall>(s, proj, run, n, cap);
+    const bool lt = a < b;
+    return keep_min ? (lt ? a : b) : (lt ? b : a);
+}
+
+// Ascending bitonic sort of the NT x E keys of the block (thread t holds
+// positions t E ... t E + E - 1).  lds: 2 NT E keys when NT E > 64 E (a
+// partner in another wave), unused otherwise.
+template <int NT, int E, int LOG2P>
+__device__ __forceinline__ void bitonic_regs(unsigned long long (&x)[E], unsigned long long* lds)
+{
+    static_assert((NT * E) == (1 << LOG2P), "NT x E must be 2^LOG2P");
+    constexpr int P = NT * E;
+    const uint32_t t = threadIdx.x % NT;   // several NT = 64 groups (waves) may share a block
+    int buf = 0;
+#pragma unroll
+    for (int lk = 1; lk <= LOG2P; lk++) {
+        const uint32_t k = 1u << lk;
+#pragma unroll
+        for (int lj = lk - 1; lj >= 0; lj--) {
+            const uint32_t j = 1u << lj;
+            if (j >= 64u * E) {
+                // partner in another wave: exchange through LDS
+                unsigned long long* s = lds + buf * P;
+#pragma unroll
+                for (int e = 0; e < E; e++) s[t * E + e] = x[e];
+                __syncthreads();
+#pragma unroll
+                for (int e = 0; e < E; e++) {
+                    const uint32_t i = t * E + e;
+                    const unsigned long long y = s[i ^ j];
+                    x[e] = keep(x[e], y, ((i & j) == 0) == ((i & k) == 0));
+                }
+                buf ^= 1;
+            } else if (j >= (uint32_t)E) {
+                // partner in lane t ^ (j / E) of this wave
+#pragma unroll
+                for (int e = 0; e < E; e++) {
+                    const uint32_t i = t * E + e;
+                    const unsigned long long y = __shfl_xor(x[e], (int)(j / E));
+                    x[e] = keep(x[e], y, ((i & j) == 0) == ((i & k) == 0));
+                }
+            } else {
+                // partner in this thread
+#pragma unroll
+                for (int e = 0; e < E; e++) {
+                    if ((e & (int)j) != 0) continue;
+                    const uint32_t i = t * E + e;
+                    const unsigned long long a = x[e], b = x[e ^ j];
+                    const bool up = (i & k) == 0;
+                    x[e] = keep(a, b, up);
+                    x[e ^ j] = keep(a, b, !up);
+                }
+            }
         }
     }
 }
 
+template <int NT, int E, int LOG2P>
+__device__ __forceinline__ void sort_run_regs(unsigned long long* lds, const float* __restrict__ depth,
+                                              uint32_t* __restrict__ run, uint32_t n, uint32_t cap)
+{
+    unsigned long long x[E];
+    const uint32_t t = threadIdx.x % NT;
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+        const uint32_t i = t * E + e;
+        x[e] = i < n ? key_of(depth, run[i], cap) : ~0ull;
+    }
+    bitonic_regs<NT, E, LOG2P>(x, lds);
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+        const uint32_t i = t * E + e;
+        if (i < n) run[i] = x[e] == ~0ull ? 0xffffffffu : (uint32_t)x[e];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sort_wave(const FrameParams* fp, const uint2* __restrict__ ranges,
+                                                   const float* __restrict__ depth, uint32_t* __restrict__ sorted,
+                                                   uint32_t cap)
+{
+    const uint32_t T = (uint32_t)(fp->TX * fp->TY);
+    const uint32_t t = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= T) return;
+    const uint2 r = ranges[t];
+    const uint32_t n = r.y - r.x;
+    if (n <= 1 || n > (uint32_t)kSortWave) return;
+    uint32_t* run = sorted + r.x;
+    // the lane index is threadIdx.x % 64 inside sort_run_regs<64, ...>
+    if (n <= 64) sort_run_regs<64, 1, 6>(nullptr, depth, run, n, cap);
+    else if (n <= 128) sort_run_regs<64, 2, 7>(nullptr, depth, run, n, cap);
+    else sort_run_regs<64, 4, 8>(nullptr, depth, run, n, cap);
+}
+
+__global__ __launch_bounds__(256) void k_sort_mid(const FrameInfo* info, const uint2* __restrict__ ranges,
+                                                  const uint32_t* __restrict__ mid, const float* __restrict__ depth,
+                                                  uint32_t* __restrict__ sorted, uint32_t cap)
+{
+    __shared__ unsigned long long s[2 * kSortSmall];
+    const uint32_t nm = info->n_mid;
+    for (uint32_t q = blockIdx.x; q < nm; q += gridDim.x) {
+        const uint2 r = ranges[mid[q]];
+        sort_run_regs<256, kSortSmall / 256, 11>(s, depth, sorted + r.x, r.y - r.x, cap);
+        __syncthreads();   // LDS is reused by the next run
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_sort_big(const FrameInfo* info, const uint2* __restrict__ ranges,
+                                                  const uint32_t* __restrict__ large, const float* __restrict__ depth,
+                                                  uint32_t* __restrict__ sorted, uint32_t cap)
+{
+    __shared__ unsigned long long s[2 * kSortMid];
+    const uint32_t nl = info->n_large;
+    for (uint32_t q = blockIdx.x; q < nl; q += gridDim.x) {
+        const uint2 r = ranges[large[q]];
+        const uint32_t n = r.y - r.x;
+        if (n > (uint32_t)kSortMid) continue;
+        sort_run_regs<1024, kSortMid / 1024, 12>(s, depth, sorted + r.x, n, cap);
+        __syncthreads();
+    }
+}
+
+// Runs in (kSortSmall, kSortLarge], in two length bands: each instantiation
+// takes the queued runs in (LO, CAP] and allocates only the LDS that CAP
+// needs, so that more blocks fit a CU.
+template <int LO, int CAP>
 __global__ __launch_bounds__(1024) void k_sort_large(const FrameInfo* info, const uint2* __restrict__ ranges,
                                                      const uint32_t* __restrict__ large,
                                                      const float* __restrict__ proj, uint32_t* __restrict__ sorted,
                                                      uint32_t cap)
 {
-    __shared__ unsigned long long s[kSortLarge];
+    __shared__ unsigned long long s[CAP];
     const uint32_t nl = info->n_large;
     for (uint32_t q = blockIdx.x; q < nl; q += gridDim.x) {
         const uint2 r = ranges[large[q]];
-        sort_run<1024, kSortLarge>(s, proj, sorted + r.x, r.y - r.x, cap);
+        const uint32_t n = r.y - r.x;
+        if (n <= (uint32_t)LO || n > (uint32_t)CAP) continue;
+        sort_run<1024, CAP>(s, proj, sorted + r.x, n, cap);
     }
 }
 
@@ -159,8 +267,11 @@ __global__ __launch_bounds__(1024) void k_sort_huge(const FrameParams* fp, const
 
 hipError_t launch_sort(const Views& v, hipStream_t st)
 {
-    k_sort_small<<<v.lay.T, 256, 0, st>>>(v.params, v.ranges, v.depth, v.sorted, v.max_active);
-    k_sort_large<<<256, 1024, 0, st>>>(v.info, v.ranges, v.large, v.depth, v.sorted, v.max_active);
+    k_sort_wave<<<(v.lay.T + 3) / 4, 256, 0, st>>>(v.params, v.ranges, v.depth, v.sorted, v.max_active);
+    k_sort_mid<<<1024, 256, 0, st>>>(v.info, v.ranges, v.large + 2 * v.lay.T, v.depth, v.sorted, v.max_active);
+    k_sort_big<<<512, 1024, 0, st>>>(v.info, v.ranges, v.large, v.depth, v.sorted, v.max_active);
+    k_sort_large<kSortMid, kSortLarge><<<256, 1024, 0, st>>>(v.info, v.ranges, v.large, v.depth, v.sorted,
+                                                              v.max_active);
     k_sort_huge<<<64, 1024, 0, st>>>(v.params, v.info, v.ranges, v.large, v.depth, v.sorted,
                                      reinterpret_cast<uint32_t*>(v.temp), v.max_active);
     return hipGetLastError();

@@ -52,4 +52,15 @@ __device__ __forceinline__ float splat_alpha(const float4& geo, const float4& co
     return alpha < kAlphaMin ? -1.0f : alpha;
 }
 
+// The same decision as splat_alpha without branches: alpha (clamped at
+// kAlphaMax) and whether the pair counts; exp is evaluated either way.
+__device__ __forceinline__ bool splat_keep(const float4& geo, const float4& col, float px, float py, float& alpha)
+{
+    float dx, dy;
+    const float power = splat_power(geo, col, px, py, dx, dy);
+    const float og = col.y * __expf(power);
+    alpha = og > kAlphaMax ? kAlphaMax : og;
+    return !(power > 0.0f || power < col.z) && !(alpha < kAlphaMin);
+}
+
 }  // namespace lodge

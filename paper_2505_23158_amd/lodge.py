@@ -68,7 +68,8 @@ class lodge_frame_info(C.Structure):
     _fields_ = [("n_selected", C.c_uint32), ("n_front", C.c_uint32), ("n_visible", C.c_uint32),
                 ("max_tile_len", C.c_uint32), ("n_instances", C.c_uint64), ("pairs_evaluated", C.c_uint64),
                 ("pairs_blended", C.c_uint64), ("overflow", C.c_uint32), ("f", C.c_int32), ("o", C.c_int32),
-                ("t", C.c_float), ("n_long", C.c_uint32), ("n_merge", C.c_uint32)]
+                ("t", C.c_float), ("n_long", C.c_uint32), ("n_merge", C.c_uint32),
+                ("pixels_stopped", C.c_uint64)]
 
 
 class lodge_grads(C.Structure):
@@ -104,6 +105,10 @@ def lib():
             "lodge_workspace_size": (st, [vp, C.c_int32, C.c_int32, C.c_uint32, C.c_uint64, C.POINTER(C.c_size_t)]),
             "lodge_set_camera": (st, [C.POINTER(lodge_workspace), vp, vp]),
             "lodge_select": (st, [vp, vp, C.c_int32, C.POINTER(lodge_workspace), C.POINTER(lodge_selection), vp]),
+            "lodge_chunk_sets_size": (st, [vp, C.POINTER(C.c_size_t)]),
+            "lodge_chunk_sets_build": (st, [vp, vp, C.c_size_t, vp]),
+            "lodge_select_chunk_sets": (st, [vp, vp, vp, C.POINTER(lodge_workspace), C.POINTER(lodge_selection),
+                                             vp]),
             "lodge_render": (st, [vp, C.POINTER(lodge_selection), vp, C.POINTER(lodge_render_opts),
                                   C.POINTER(lodge_workspace), vp, vp, vp, vp]),
             "lodge_frame_info_read": (st, [C.POINTER(lodge_workspace), C.POINTER(lodge_frame_info), vp]),
@@ -130,7 +135,8 @@ def _check(status: int):
 
 
 EXPORTED = ["lodge_status_string", "lodge_last_error", "lodge_version", "lodge_scene_create", "lodge_scene_destroy",
-            "lodge_scene_total", "lodge_workspace_size", "lodge_set_camera", "lodge_select", "lodge_render", "lodge_frame_info_read",
+            "lodge_scene_total", "lodge_workspace_size", "lodge_set_camera", "lodge_select", "lodge_chunk_sets_size",
+            "lodge_chunk_sets_build", "lodge_select_chunk_sets", "lodge_render", "lodge_frame_info_read",
             "lodge_check", "lodge_debug_views", "lodge_render_backward", "lodge_activate", "lodge_activate_backward"]
 
 
@@ -281,6 +287,26 @@ def lodge_select(scene: Scene, cam, mode: int, ws: Workspace, sel: Selection, st
     _check(lib().lodge_select(scene.handle, cp, mode, C.byref(ws.desc), C.byref(sel.desc), _stream_ptr(stream)))
 
 
+class ChunkSets:
+    """Device buffer of a scene's precomputed per-chunk active sets (lodge_chunk_sets_build)."""
+
+    def __init__(self, scene: Scene, stream=None, device="cuda"):
+        torch = _torch()
+        nb = C.c_size_t()
+        _check(lib().lodge_chunk_sets_size(scene.handle, C.byref(nb)))
+        self.bytes = int(nb.value)
+        self.buf = torch.empty(max(4, self.bytes), dtype=torch.uint8, device=device)
+        self.scene = scene
+        _check(lib().lodge_chunk_sets_build(scene.handle, _ptr(self.buf), C.c_size_t(self.bytes),
+                                            _stream_ptr(stream)))
+
+
+def lodge_select_chunk_sets(scene: Scene, sets: ChunkSets, cam, ws: Workspace, sel: Selection, stream=None):
+    cp, keep = _cam_arg(cam)
+    _check(lib().lodge_select_chunk_sets(scene.handle, _ptr(sets.buf), cp, C.byref(ws.desc), C.byref(sel.desc),
+                                         _stream_ptr(stream)))
+
+
 def lodge_render(scene: Scene, sel: Selection, cam, ws: Workspace, image, final_T, n_contrib, s2d: float = 0.3,
                  compensate: bool = True, stream=None, stage_events=None):
     """stage_events: None or STAGE_EVENTS torch.cuda.Event objects recorded at the stage boundaries."""
@@ -376,8 +402,14 @@ class Renderer:
         self.width, self.height = width, height
 
     def frame(self, cam, mode: int, s2d: float = 0.3, compensate: bool = True, stream=None,
-              stage_events=None) -> Frame:
-        lodge_select(self.scene, cam, mode, self.ws, self.sel, stream)
+              stage_events=None, sets: Optional["ChunkSets"] = None) -> Frame:
+        """One select + render; with sets (chunked mode only) the selection reads the stored chunk sets."""
+        if sets is not None:
+            if mode != SELECT_CHUNKED:
+                raise ValueError("chunk sets serve the chunked selection only")
+            lodge_select_chunk_sets(self.scene, sets, cam, self.ws, self.sel, stream)
+        else:
+            lodge_select(self.scene, cam, mode, self.ws, self.sel, stream)
         lodge_render(self.scene, self.sel, cam, self.ws, self.image, self.final_T, self.n_contrib, s2d, compensate,
                      stream, stage_events)
         return Frame(self.image, self.final_T, self.n_contrib)

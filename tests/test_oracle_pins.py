@@ -531,3 +531,30 @@ def test_sh_colour_uses_direction_from_camera_to_gaussian(oracle64):
     cam_back = synth.look_at((0.0, 0.0, 10.0), (0.0, 0.0, 0.0), (0, -1, 0), 64, 64)
     p2 = oracle64.render(one_level_scene(lv), cam_back, oracle.ALL)["proj"]
     assert np.allclose(p2.rgb[0], 0.5 - c1 * float(np.float32(k)), atol=1e-6)
+
+
+def test_chunked_selection_is_union_of_stored_chunk_sets(oracle32):
+    """Per-chunk storage (Sec. 3 "chunk-based rendering"): the set chunk k keeps
+    is the selection about its centre alone; a frame's chunked selection is the
+    union of the two nearest chunks' sets, weighted 1 / t / 1 - t by membership
+    (Eq. 4).  Checked for several camera positions on a 4 x 4 chunk grid."""
+    sc = synth.lod_city_scene(counts=(20000, 5000, 1250), half_xy=40.0, d=(6.0, 18.0), grid=4, spacing=20.0,
+                              chunk_z=1.7, band=5.0, seed=21)
+    K = len(sc.chunks.centers)
+    stored = []
+    for k in range(K):
+        only_k = Scene(levels=sc.levels, d=sc.d,
+                       chunks=Chunks(centers=sc.chunks.centers[k:k + 1], offsets=sc.chunks.offsets[k:k + 1]))
+        ids_k, w_k, (f1, o1, t1) = oracle32.select(only_k, oracle.CHUNKED, np.zeros(3, np.float32))
+        assert (f1, o1, t1) == (0, -1, 1.0) and np.all(w_k == 1.0)
+        stored.append(set(ids_k.tolist()))
+    rng = np.random.default_rng(22)
+    for _ in range(6):
+        pos = np.array([rng.uniform(-40, 40), rng.uniform(-40, 40), 1.7], np.float32)
+        ids, w, (f, o, t) = oracle32.select(sc, oracle.CHUNKED, pos)
+        union = sorted(stored[f] | stored[o])
+        assert ids.tolist() == union
+        t32 = np.float32(t)
+        expect = [1.0 if (g in stored[f] and g in stored[o]) else (t32 if g in stored[f] else np.float32(1) - t32)
+                  for g in union]
+        assert np.array_equal(w, np.asarray(expect, np.float32))
