@@ -3,16 +3,19 @@
 // optimization steps": only the parameters of G_l are updated).
 //
 // k_bwd_setup      zero the per-active 2-D gradient records.
-// k_composite_bwd  one 256-thread block per tile, one pixel per thread,
+// k_composite_bwd  one wave per 8 x 8 quadrant of a tile (four per block,
+//                  never waiting for each other), one pixel per lane,
 //                  walking the tile's sorted run back to front from the
-//                  largest n_contrib of the tile.  The transmittance before
-//                  entry k is recovered from the stored final T by division,
+//                  largest n_contrib of the quadrant, in batches of 64 whose
+//                  entries are culled for the quadrant exactly as the
+//                  compositor culls them.  The transmittance before entry k
+//                  is recovered from the stored final T by division,
 //                  T_k = T_{k+1} / (1 - alpha_k), rather than stored per pair.
 //                  With S_k the colour behind entry k (plus T_final * bg):
 //                    dC/dc_k = alpha_k T_k,  dC/dalpha_k = c_k T_k - S_k / (1 - alpha_k).
-//                  Per entry the 256 pixels' gradients are summed with wave
-//                  reductions (only in waves where some pixel contributed)
-//                  and one atomic add per wave.
+//                  Per entry the quadrant's gradients are summed with a wave
+//                  reduction (only where some pixel contributed) and one
+//                  atomic add per wave.
 // k_project_bwd    one thread per visible active Gaussian: the chain rule from
 //                  (u, v, conic, o_eff, rgb) back through the 2-D filter, the
 //                  EWA covariance, the camera and the Eq. 3 filter to the
@@ -25,7 +28,6 @@ namespace lodge {
 
 namespace {
 
-constexpr int kBatch = 256;
 constexpr int kG2 = 12;   // floats per 2-D gradient record: u, v, A, B, C, o, r, g, b (+3 pad)
 
 __global__ void k_bwd_setup(float* __restrict__ g2d, const uint32_t* __restrict__ count, uint32_t cap)
@@ -42,6 +44,7 @@ __device__ __forceinline__ float wave_sum(float v)
 
 __global__ __launch_bounds__(256) void k_composite_bwd(const FrameParams* __restrict__ fp,
                                                        const uint2* __restrict__ ranges,
+                                                       const uint32_t* __restrict__ order,
                                                        const uint32_t* __restrict__ sorted,
                                                        const float4* __restrict__ proj,
                                                        const float* __restrict__ final_T,
@@ -49,20 +52,24 @@ __global__ __launch_bounds__(256) void k_composite_bwd(const FrameParams* __rest
                                                        const float* __restrict__ dL, float* __restrict__ g2d,
                                                        uint32_t cap)
 {
-    __shared__ float4 s_geo[kBatch];
-    __shared__ float4 s_col[kBatch];
-    __shared__ float2 s_gb[kBatch];
-    __shared__ uint32_t s_a[kBatch];
-    __shared__ uint32_t s_max;
+    __shared__ float4 s_rec[4][3][64];     // per wave, by batch slot: geo, col, (g, b, -, -)
+    __shared__ uint32_t s_a[4][64];        // active index of each slot
+    __shared__ uint8_t s_idx[4][64];       // slots that reach the quadrant, in list order
 
     const int32_t W = fp->cam.width, H = fp->cam.height, TX = fp->TX;
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = order[blockIdx.x];
     const uint32_t tx = tile % (uint32_t)TX, ty = tile / (uint32_t)TX;
-    const uint32_t x = tx * kTile + (threadIdx.x & 15), y = ty * kTile + (threadIdx.x >> 4);
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t qx0 = tx * kTile + (wave & 1u) * 8u, qy0 = ty * kTile + (wave >> 1) * 8u;
+    const uint32_t x = qx0 + (lane & 7u), y = qy0 + (lane >> 3);
     const bool inside = (int32_t)x < W && (int32_t)y < H;
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+    const float bx0 = (float)qx0 + 0.5f, by0 = (float)qy0 + 0.5f;
     const uint2 rg = ranges[tile];
-    const uint32_t lane = threadIdx.x & 63;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    float4* const sa = s_rec[wave][0];
+    float4* const sb = s_rec[wave][1];
+    float4* const sc = s_rec[wave][2];
 
     const size_t HW = (size_t)W * H, p = (size_t)y * W + x;
     uint32_t last = 0;
@@ -77,29 +84,39 @@ __global__ __launch_bounds__(256) void k_composite_bwd(const FrameParams* __rest
     const float* bg = fp->cam.bg;
     float S0 = T * bg[0], S1 = T * bg[1], S2 = T * bg[2];   // colour behind the current entry
 
-    if (threadIdx.x == 0) s_max = 0;
-    __syncthreads();
-    atomicMax(&s_max, last);
-    __syncthreads();
-    const uint32_t end = min(s_max, rg.y - rg.x);
+    // the quadrant's entries that any pixel blended lie in [0, end)
+    uint32_t end = last;
+    for (int off = 32; off > 0; off >>= 1) end = max(end, (uint32_t)__shfl_xor(end, off));
+    end = min(__builtin_amdgcn_readfirstlane(end), rg.y - rg.x);
 
-    for (uint32_t e = end; e > 0;) {
-        const uint32_t b0 = e > (uint32_t)kBatch ? e - kBatch : 0u;
-        const uint32_t nb = e - b0;
-        if (threadIdx.x < nb) {
-            uint32_t a = sorted[rg.x + b0 + threadIdx.x];
-            a = a < cap ? a : 0u;
-            s_a[threadIdx.x] = a;
-            stage_splat(proj, a, s_geo[threadIdx.x], s_col[threadIdx.x], s_gb[threadIdx.x]);
+    for (uint32_t b0 = end > 0 ? ((end - 1) / 64) * 64 : 0; end > 0;) {
+        // stage the batch [b0, b0 + 64) and keep the slots that reach the quadrant
+        const uint32_t k = b0 + lane;
+        bool hit = false;
+        if (k < end) {
+            uint32_t a = sorted[rg.x + k];
+            a = a < cap ? a : 0u;   // an index outside the active set would be a binning bug
+            const float4 r0 = proj[3 * (size_t)a], r1 = proj[3 * (size_t)a + 1], r2 = proj[3 * (size_t)a + 2];
+            sa[lane] = make_float4(r0.x, r0.y, -0.5f * r0.z, -r0.w);
+            sb[lane] = make_float4(-0.5f * r1.x, r1.y, r2.w, r1.z);
+            sc[lane] = make_float4(r1.w, r2.x, 0.0f, 0.0f);
+            s_a[wave][lane] = a;
+            hit = reaches(box_test(r0, r1, r2), bx0, bx0 + 7.0f, by0, by0 + 7.0f);
         }
-        __syncthreads();
-        for (int j = (int)nb - 1; j >= 0; j--) {
-            const uint32_t k = b0 + (uint32_t)j;
+        const unsigned long long m = __ballot(hit);
+        if (hit) s_idx[wave][__popcll(m & lt)] = (uint8_t)lane;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // back to front over the kept slots
+        for (int jj = (int)__popcll(m) - 1; jj >= 0; jj--) {
+            const uint32_t e = s_idx[wave][jj];
+            const uint32_t kk = b0 + e;
             float g[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
             bool contrib = false;
-            if (k < last) {
-                const float4 geo = s_geo[j];
-                const float4 col = s_col[j];
+            if (kk < last) {
+                const float4 geo = sa[e];
+                const float4 col = sb[e];
                 float dx, dy, G;
                 bool clamped = false;
                 const float alpha = splat_alpha(geo, col, px, py, dx, dy, G, clamped);
@@ -107,7 +124,7 @@ __global__ __launch_bounds__(256) void k_composite_bwd(const FrameParams* __rest
                     contrib = true;
                     const float om = 1.0f - alpha;
                     T = T / om;                       // transmittance before this entry
-                    const float2 gb = s_gb[j];
+                    const float4 gb = sc[e];
                     const float c0 = col.w, c1 = gb.x, c2 = gb.y;
                     const float wgt = alpha * T;
                     g[6] = wgt * dC0;
@@ -133,7 +150,7 @@ __global__ __launch_bounds__(256) void k_composite_bwd(const FrameParams* __rest
                 }
             }
             if (__ballot(contrib) != 0ull) {
-                float* dst = g2d + (size_t)s_a[j] * kG2;
+                float* dst = g2d + (size_t)s_a[wave][e] * kG2;
 #pragma unroll
                 for (int q = 0; q < 9; q++) {
                     const float sum = wave_sum(g[q]);
@@ -141,8 +158,11 @@ __global__ __launch_bounds__(256) void k_composite_bwd(const FrameParams* __rest
                 }
             }
         }
-        __syncthreads();
-        e = b0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (b0 == 0) break;
+        b0 -= 64;
     }
 }
 
@@ -410,8 +430,8 @@ hipError_t launch_backward(const LevelsArg& lv, const lodge_selection& sel, cons
     for (int l = 0; l < lv.L; l++) ga.g[l] = grads[l];
     uint32_t blocks = std::min<uint32_t>(2048, std::max<uint32_t>(1, (v.max_active * (uint32_t)kG2 + 255) / 256));
     k_bwd_setup<<<blocks, 256, 0, st>>>(v.g2d, sel.count, sel.cap);
-    k_composite_bwd<<<v.lay.T, 256, 0, st>>>(v.params, v.ranges, v.sorted, v.proj, final_T, n_contrib, dL_dimage,
-                                             v.g2d, v.max_active);
+    k_composite_bwd<<<v.lay.T, 256, 0, st>>>(v.params, v.ranges, v.order, v.sorted, v.proj, final_T, n_contrib,
+                                             dL_dimage, v.g2d, v.max_active);
     blocks = std::min<uint32_t>(4096, std::max<uint32_t>(1, (v.max_active + 255) / 256));
     k_project_bwd<<<blocks, 256, 0, st>>>(lv, ga, grad_level, sel.ids, sel.w, sel.count, sel.cap, v.params, v.rect,
                                           v.g2d);

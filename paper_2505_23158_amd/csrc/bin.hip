@@ -12,12 +12,12 @@
 //                 offset -> exclusive instance offsets of every active, and
 //                 for each binning block the active its first instance
 //                 belongs to.
-//   k_emit_hist   block b takes instances [b C, (b+1) C), i.e. the actives
-//                 between the first actives of blocks b and b + 1 (from
-//                 k_inst_off): one thread per active expands its part of
-//                 those instances, the whole block the parts longer than 32;
-//                 it writes (tile, index) pairs and its tile histogram
-//                 (packed 16-bit LDS counters) as row b of the matrix.
+//   k_emit_hist   block b takes instances [b C, (b+1) C): finds each one's
+//                 Gaussian by binary search over an LDS window of the
+//                 offsets (the window's ends come from k_inst_off; it gets
+//                 the 160 KB of LDS the tile histogram leaves), writes
+//                 (tile, index) pairs and its tile histogram (packed 16-bit
+//                 LDS counters) as row b of the matrix.
 //   k_col_sum     per tile: total count over the blocks (16 tiles x 16 row
 //                 groups per block, row reads contiguous across tiles).
 //   k_tile_scan   one block: exclusive scan of the tile totals -> [start,
@@ -153,15 +153,17 @@ __device__ __forceinline__ uint32_t hist_get(const uint32_t* h, uint32_t t)
 }
 
 constexpr int kBinThreads = 1024;
-constexpr uint32_t kBigSplat = 32;   // actives with more instances in a block are expanded by the whole block
-constexpr int kBigQueue = 1024;
+constexpr int kEmitLdsWords = 40960;   // 160 KB: the tile histogram, then as long an offset window as fits
 
-// (tile, active) of instance k of an active whose rect starts at (x0, y0) and
-// is wr tiles wide: row-major over the rect.
-__device__ __forceinline__ uint32_t tile_of(uint32_t k, uint32_t x0, uint32_t y0, uint32_t wr, int32_t TX)
+// last index i in [0, n) with a[i] <= key (a ascending, a[0] <= key)
+__device__ __forceinline__ uint32_t last_le(const uint32_t* a, uint32_t n, uint32_t key)
 {
-    const uint32_t row = k / wr;
-    return (y0 + row) * (uint32_t)TX + x0 + (k - row * wr);
+    uint32_t l = 0, h = n;
+    while (l < h) {
+        const uint32_t mid = (l + h) >> 1;
+        if (a[mid] <= key) l = mid + 1; else h = mid;
+    }
+    return l - 1;
 }
 
 __global__ __launch_bounds__(kBinThreads) void k_emit_hist(const FrameParams* fp, const FrameInfo* info,
@@ -171,57 +173,60 @@ __global__ __launch_bounds__(kBinThreads) void k_emit_hist(const FrameParams* fp
                                                            const uint2* __restrict__ rect, uint2* __restrict__ inst,
                                                            uint32_t* __restrict__ hist, uint64_t max_instances)
 {
-    __shared__ uint32_t s_hist[kMaxTiles / 2];
-    __shared__ uint32_t s_big[kBigQueue];
-    __shared__ uint32_t s_nbig;
+    constexpr int kPer = kBinChunk / kBinThreads;   // instances per thread, processed together
+    __shared__ uint32_t s_lds[kEmitLdsWords];
     const unsigned long long M = info->n_instances;
     if (M == 0 || M > max_instances) return;
     const uint32_t n_act = min(*count, cap);
     const int32_t TX = fp->TX;
     const uint32_t T = (uint32_t)(fp->TX * fp->TY);
     const uint32_t B = blocks_of(M);
+    // packed 16-bit tile counters first (T <= kMaxTiles), the offset window after them
+    uint32_t* const s_hist = s_lds;
+    uint32_t* const s_off = s_lds + (T + 1) / 2;
+    const uint32_t window = kEmitLdsWords - (T + 1) / 2;
     for (uint32_t b = blockIdx.x; b < B; b += gridDim.x) {
         const uint32_t j0 = b * kBinChunk;
         const uint32_t j1 = (uint32_t)min((unsigned long long)j0 + kBinChunk, M);
         for (uint32_t k = threadIdx.x; k < (T + 1) / 2; k += kBinThreads) s_hist[k] = 0;
-        if (threadIdx.x == 0) s_nbig = 0;
         // actives [lo, hi] hold the block's instances (hi may be one past the last)
         const uint32_t lo = bstart[b];
         const uint32_t hi = b + 1 < B ? bstart[b + 1] : n_act - 1;
+        const uint32_t cnt = hi - lo + 1;
+        const bool in_lds = cnt <= window;
+        if (in_lds)
+            for (uint32_t k = threadIdx.x; k < cnt; k += kBinThreads) s_off[k] = off[lo + k];
         __syncthreads();
-        // each thread expands its actives' instances that fall in [j0, j1); an
-        // active with many of them goes to the block-wide queue instead
-        for (uint32_t a = lo + threadIdx.x; a <= hi; a += kBinThreads) {
-            const uint32_t o = off[a];
-            const uint32_t o1 = a + 1 < n_act ? off[a + 1] : (uint32_t)M;
-            const uint32_t k0 = (o < j0 ? j0 : o) - o, k1 = (o1 > j1 ? j1 : o1) - o;
-            if (o1 <= o || k0 >= k1) continue;
-            if (k1 - k0 > kBigSplat) {
-                const uint32_t q = atomicAdd(&s_nbig, 1u);
-                if (q < (uint32_t)kBigQueue) { s_big[q] = a; continue; }
-            }
-            const uint2 rc = rect[a];
-            const uint32_t x0 = rc.x & 0xffffu, y0 = rc.x >> 16, wr = (rc.y & 0xffffu) - x0;
-            for (uint32_t k = k0; k < k1; k++) {
-                const uint32_t tile = tile_of(k, x0, y0, wr, TX);
-                inst[o + k] = make_uint2(tile, a);
-                hist_inc(s_hist, tile);
+        // each instance's active: the last whose offset is <= it (zero-tile actives share offsets)
+        uint32_t a[kPer], kk[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; q++) {
+            const uint32_t j = j0 + threadIdx.x + q * kBinThreads;
+            a[q] = lo;
+            kk[q] = 0;
+            if (j < j1) {
+                if (in_lds) {
+                    const uint32_t l = last_le(s_off, cnt, j);
+                    a[q] = lo + l;
+                    kk[q] = j - s_off[l];
+                } else {
+                    a[q] = lo + last_le(off + lo, cnt, j);
+                    kk[q] = j - off[a[q]];
+                }
             }
         }
-        __syncthreads();
-        const uint32_t nbig = min(s_nbig, (uint32_t)kBigQueue);
-        for (uint32_t q = 0; q < nbig; q++) {
-            const uint32_t a = s_big[q];
-            const uint32_t o = off[a];
-            const uint32_t o1 = a + 1 < n_act ? off[a + 1] : (uint32_t)M;
-            const uint32_t k0 = (o < j0 ? j0 : o) - o, k1 = (o1 > j1 ? j1 : o1) - o;
-            const uint2 rc = rect[a];
-            const uint32_t x0 = rc.x & 0xffffu, y0 = rc.x >> 16, wr = (rc.y & 0xffffu) - x0;
-            for (uint32_t k = k0 + threadIdx.x; k < k1; k += kBinThreads) {
-                const uint32_t tile = tile_of(k, x0, y0, wr, TX);
-                inst[o + k] = make_uint2(tile, a);
-                hist_inc(s_hist, tile);
-            }
+        uint2 rc[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; q++) rc[q] = rect[a[q]];
+#pragma unroll
+        for (int q = 0; q < kPer; q++) {
+            const uint32_t j = j0 + threadIdx.x + q * kBinThreads;
+            if (j >= j1) continue;
+            const uint32_t x0 = rc[q].x & 0xffffu, y0 = rc[q].x >> 16, wr = (rc[q].y & 0xffffu) - x0;
+            const uint32_t row = kk[q] / wr;
+            const uint32_t tile = (y0 + row) * (uint32_t)TX + x0 + (kk[q] - row * wr);
+            inst[j] = make_uint2(tile, a[q]);
+            hist_inc(s_hist, tile);
         }
         __syncthreads();
         uint32_t* row_out = hist + (size_t)b * T;
@@ -310,30 +315,37 @@ __device__ __forceinline__ uint32_t length_class(uint32_t c)
     return c > 1024u ? 0u : (c > 256u ? 1u : (c > 64u ? 2u : 3u));
 }
 
-// Inclusive scan over the block of a 64-bit value (wave scans, wave totals in
-// LDS); returns the exclusive prefix and the block total.
+// Exclusive scan over the block of three 64-bit values at once (wave scans,
+// wave totals in LDS, two barriers); returns the prefixes and the totals.
 template <int NT>
-__device__ __forceinline__ unsigned long long block_scan64(unsigned long long v, unsigned long long* s_w,
-                                                           unsigned long long& total)
+__device__ __forceinline__ void block_scan3(unsigned long long (&v)[3], unsigned long long (*s_w)[NT / 64],
+                                            unsigned long long (&total)[3])
 {
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    unsigned long long inc = v;
+    unsigned long long inc[3] = {v[0], v[1], v[2]};
     for (int o = 1; o < 64; o <<= 1) {
-        const unsigned long long u = __shfl_up(inc, o);
-        if ((int)lane >= o) inc += u;
-    }
-    if (lane == 63) s_w[wave] = inc;
-    __syncthreads();
-    unsigned long long before = 0;
-    total = 0;
 #pragma unroll
-    for (int w = 0; w < NT / 64; w++) {
-        const unsigned long long x = s_w[w];
-        before += (uint32_t)w < wave ? x : 0ull;
-        total += x;
+        for (int c = 0; c < 3; c++) {
+            const unsigned long long u = __shfl_up(inc[c], o);
+            if ((int)lane >= o) inc[c] += u;
+        }
+    }
+    if (lane == 63)
+        for (int c = 0; c < 3; c++) s_w[c][wave] = inc[c];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        unsigned long long before = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; w++) {
+            const unsigned long long x = s_w[c][w];
+            before += (uint32_t)w < wave ? x : 0ull;
+            tot += x;
+        }
+        total[c] = tot;
+        v[c] = before + inc[c] - v[c];
     }
     __syncthreads();
-    return before + inc - v;
 }
 
 // One block over all tiles, each thread a contiguous run of them:
@@ -365,10 +377,10 @@ __global__ __launch_bounds__(kTilesThreads) void k_tile_scan(const FrameParams* 
     }
     for (int o = 32; o > 0; o >>= 1) lmax = max(lmax, (uint32_t)__shfl_xor(lmax, o));
     if (lane == 0) s_max[wave] = lmax;
-    unsigned long long sum_tot, cls_tot, big_tot;
-    unsigned long long run = block_scan64<kTilesThreads>(sum, s_w[0], sum_tot);
-    unsigned long long cpos = block_scan64<kTilesThreads>(cls, s_w[1], cls_tot);
-    unsigned long long bpos = block_scan64<kTilesThreads>(big, s_w[2], big_tot);
+    unsigned long long sc[3] = {sum, cls, big}, tot[3];
+    block_scan3<kTilesThreads>(sc, s_w, tot);
+    unsigned long long run = sc[0], cpos = sc[1];
+    const unsigned long long bpos = sc[2], cls_tot = tot[1], big_tot = tot[2];
     uint32_t base[4];
     {
         uint32_t b = 0;

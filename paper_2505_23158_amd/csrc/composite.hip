@@ -15,9 +15,10 @@
 // projection) and then the exact minimum of the conic quadratic form over
 // the quadrant's box of pixel centres; against each sub-quadrant, the
 // bounding box.  Ballots compact the survivors, in list order, into one
-// slot list per sub-quadrant; the wave then runs as many steps as the
-// longest of the four lists, each lane following its own, predicated, with
-// the next entry read one step ahead.  Per (pixel, splat): power = -1/2
+// slot list per sub-quadrant, the shorter ones padded with a slot every
+// pixel skips; the wave then runs as many steps as the longest list, each
+// lane following its own, predicated, with the next entry read one step
+// ahead.  Per (pixel, splat): power = -1/2
 // (A dx^2 + C dy^2) - B dx dy; skip if power > 0 or below the splat's
 // threshold ln(1/(255 o)) - 1e-3 (alpha < 1/255 there); alpha = min(0.99,
 // o exp(power)); skip if alpha < 1/255; stop (without blending) once
@@ -35,72 +36,6 @@ namespace lodge {
 
 namespace {
 
-// Per-splat terms of the box test, shared by the four sub-quadrants.
-struct BoxTest {
-    float u, v, mx, my;   // centre and bounding half-extents (with margin)
-    float A, B, C;        // conic
-    float nba, nbc;       // edge minimisers: x = -B y / A, y = -B x / C
-    float lim;            // accept if the minimum of the form is <= lim
-    bool any;             // alpha can reach 1/255 somewhere
-};
-
-// r0 = (u, v, A, B), r1 = (C, ...), r2 = (.., ex, ey, thr) as written by the
-// projection; alpha >= 1/255 needs q(d) = A dx^2 + 2B dx dy + C dy^2 <= -2 thr.
-__device__ __forceinline__ BoxTest box_test(const float4& r0, const float4& r1, const float4& r2)
-{
-    BoxTest b;
-    const float ex = r2.y, ey = r2.z;
-    b.any = ex >= 0.0f;   // false: alpha below 1/255 everywhere (or a non-finite record)
-    b.u = r0.x;
-    b.v = r0.y;
-    b.mx = ex + 1e-3f * ex + 0.01f;
-    b.my = ey + 1e-3f * ey + 0.01f;
-    b.A = r0.z;
-    b.B = r0.w;
-    b.C = r1.x;
-    // an approximate reciprocal moves an edge minimiser by an ulp, which
-    // changes the form only to second order: far inside the margin below
-    b.nba = -b.B * __builtin_amdgcn_rcpf(b.A);
-    b.nbc = -b.B * __builtin_amdgcn_rcpf(b.C);
-    // rounding of the minimum and of the per-pixel power both grow with the
-    // conditioning of the form; lam bounds the largest covariance eigenvalue
-    // (approximate reciprocals: their ulp errors are far inside these margins)
-    const float rho = -2.0f * r2.w;
-    const float lam = (ex * ex + ey * ey) * __builtin_amdgcn_rcpf(rho);
-    const float gamma = 1.001e-5f * (1.0f + lam);
-    b.lim = gamma < 0.5f ? (rho + 1e-3f * rho) * __builtin_amdgcn_rcpf(1.0f - gamma) : INFINITY;
-    return b;
-}
-
-// Does the bounding box of the splat's alpha >= 1/255 ellipse meet [bx0, bx1] x [by0, by1]?
-__device__ __forceinline__ bool box_overlaps(const BoxTest& b, float bx0, float bx1, float by0, float by1)
-{
-    return !(b.u + b.mx < bx0 || b.u - b.mx > bx1 || b.v + b.my < by0 || b.v - b.my > by1);
-}
-
-// Can the splat reach alpha >= 1/255 at a point of [bx0, bx1] x [by0, by1]?
-__device__ __forceinline__ bool reaches(const BoxTest& b, float bx0, float bx1, float by0, float by1)
-{
-    if (!b.any || !box_overlaps(b, bx0, bx1, by0, by1)) return false;
-    const float du0 = bx0 - b.u, du1 = bx1 - b.u, dv0 = by0 - b.v, dv1 = by1 - b.v;
-    if (du0 <= 0.0f && du1 >= 0.0f && dv0 <= 0.0f && dv1 >= 0.0f) return true;   // centre inside
-    // the convex form is smallest on the boundary: minimise along each edge
-    float qmin = INFINITY;
-#pragma unroll
-    for (int e = 0; e < 2; e++) {
-        const float x = e ? du1 : du0;
-        const float y = fminf(fmaxf(b.nbc * x, dv0), dv1);
-        qmin = fminf(qmin, (b.A * x) * x + (2.0f * b.B * x) * y + (b.C * y) * y);
-    }
-#pragma unroll
-    for (int e = 0; e < 2; e++) {
-        const float y = e ? dv1 : dv0;
-        const float x = fminf(fmaxf(b.nba * y, du0), du1);
-        qmin = fminf(qmin, (b.A * x) * x + (2.0f * b.B * x) * y + (b.C * y) * y);
-    }
-    return qmin <= b.lim;
-}
-
 __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict__ fp,
                                                    const uint2* __restrict__ ranges,
                                                    const uint32_t* __restrict__ order,
@@ -109,8 +44,10 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
                                                    float* __restrict__ final_T, uint32_t* __restrict__ n_contrib,
                                                    uint4* __restrict__ wstats, uint32_t cap)
 {
-    // per wave, by batch slot: [0] u, v, -A/2, -B; [1] -C/2, o, threshold, r; [2] g, b, -, -
-    __shared__ float4 s_rec[4][3][64];
+    // per wave, by batch slot: [0] u, v, -A/2, -B; [1] -C/2, o, threshold, r; [2] g, b, -, -.
+    // Slot 64 is a sentinel every pixel skips (threshold +inf): it pads the
+    // shorter sub-quadrant lists to the longest one.
+    __shared__ float4 s_rec[4][3][65];
     __shared__ uint8_t s_idx[4][4][64];   // per wave and sub-quadrant: batch slots in list order
 
     const int32_t W = fp->cam.width, H = fp->cam.height, TX = fp->TX;
@@ -130,6 +67,11 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
     float4* const sb = s_rec[wave][1];
     float4* const sc = s_rec[wave][2];
     uint8_t* const sidx = s_idx[wave][sub];
+
+    if (lane == 0) {
+        sa[64] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        sb[64] = make_float4(0.0f, 0.0f, INFINITY, 0.0f);
+    }
 
     float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
     uint32_t last = 0, nblend = 0, neval = len;
@@ -175,32 +117,35 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
                 }
             }
         }
-        uint32_t n_mine = 0, n_max = 0;
+        uint32_t cnt[4], n_max = 0;
 #pragma unroll
         for (int g = 0; g < 4; g++) {
             const unsigned long long m = __ballot(hit[g]);
             if (hit[g]) s_idx[wave][g][__popcll(m & lt)] = (uint8_t)lane;
-            const uint32_t c = (uint32_t)__popcll(m);
-            n_mine = (uint32_t)g == sub ? c : n_mine;
-            n_max = c > n_max ? c : n_max;
+            cnt[g] = (uint32_t)__popcll(m);
+            n_max = cnt[g] > n_max ? cnt[g] : n_max;
         }
+        // pad every sub-quadrant list to the longest with the sentinel slot
+#pragma unroll
+        for (int g = 0; g < 4; g++)
+            if (lane >= cnt[g] && lane < n_max) s_idx[wave][g][lane] = 64;
         // the wave's own LDS slice: order its writes before its reads
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         // walk the lane's sub-quadrant list, predicated rather than branched, with
-        // the next entry's slot and records read one step ahead
-        if (__ballot(!done && n_mine > 0) != 0ull) {
-            uint32_t e = sidx[0] & 63u;
-            uint32_t e_next = sidx[n_max > 1 ? 1 : 0] & 63u;
+        // the next entry's slot and records read one step ahead (every slot
+        // read below was written for this batch: a list position < n_max)
+        if (n_max > 0 && __ballot(!done) != 0ull) {
+            uint32_t e = sidx[0];
+            uint32_t e_next = sidx[n_max > 1 ? 1 : 0];
             float4 g = sa[e], c = sb[e];
             for (uint32_t j = 0; j < n_max; j++) {
-                const bool act = !done && j < n_mine;
-                if (__ballot(act) == 0ull) break;
+                if (__ballot(!done) == 0ull) break;
                 const float4 gn = sa[e_next], cn = sb[e_next];
-                const uint32_t e_after = sidx[j + 2 < n_max ? j + 2 : 0] & 63u;
+                const uint32_t e_after = sidx[j + 2 < n_max ? j + 2 : 0];
                 float alpha;
-                const bool keep = splat_keep(g, c, px, py, alpha) && act;
+                const bool keep = splat_keep(g, c, px, py, alpha) && !done;
                 const float Tn = T * (1.0f - alpha);
                 const bool stop = keep && Tn < kTStop;
                 if (stop) {

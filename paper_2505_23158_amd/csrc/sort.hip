@@ -16,7 +16,8 @@
 //                 lane: no LDS, no barrier.
 //   k_sort_mid    queued runs in (256, 2048], 256 threads x 8 keys.
 //   k_sort_big    queued runs in (2048, 4096], 1024 threads x 4 keys.
-//   k_sort_large  queued runs in (4096, 16384]: the bitonic network in 128 KB
+//   k_sort_big8   queued runs in (4096, 8192], 1024 threads x 8 keys.
+//   k_sort_large  queued runs in (8192, 16384]: the bitonic network in 128 KB
 //                 of LDS, 1024 threads (gfx950 allows 160 KB).
 //   k_sort_huge   runs > 16384: 16384-key chunks sorted in LDS, then merge
 //                 passes in global memory where each key finds its output
@@ -72,10 +73,52 @@ __device__ __forceinline__ void sort_run(unsigned long long* s, const float* __r
     __syncthreads();
 }
 
-__device__ __forceinline__ unsigned long long keep(unsigned long long a, unsigned long long b, bool keep_min)
+// 32-bit value of lane (lane ^ D) of the wave.  Distances 1 and 2 are quad
+// permutes and 4 and 8 two row shifts plus a select (DPP: register-speed, no
+// LDS round trip); 16 swizzles within 32 lanes; 32 goes through bpermute.
+template <int D>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v)
 {
-    const bool lt = a < b;
-    return keep_min ? (lt ? a : b) : (lt ? b : a);
+    if constexpr (D == 1) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    } else if constexpr (D == 2) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    } else if constexpr (D == 4 || D == 8) {
+        // row_shl:D reads lane + D, row_shr:D reads lane - D (both stay inside the 16-lane row here)
+        const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x100 + D, 0xF, 0xF, false);
+        const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x110 + D, 0xF, 0xF, false);
+        return (__lane_id() & D) ? dn : up;
+    } else if constexpr (D == 16) {
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);   // bit mode: xor 16 within 32 lanes
+    } else {
+        return (uint32_t)__shfl_xor((int)v, D);
+    }
+}
+
+template <int D>
+__device__ __forceinline__ unsigned long long xor_lane64(unsigned long long v)
+{
+    const uint32_t lo = xor_lane<D>((uint32_t)v), hi = xor_lane<D>((uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long xor_lane64_dyn(unsigned long long v, uint32_t d)
+{
+    switch (d) {
+        case 1: return xor_lane64<1>(v);
+        case 2: return xor_lane64<2>(v);
+        case 4: return xor_lane64<4>(v);
+        case 8: return xor_lane64<8>(v);
+        case 16: return xor_lane64<16>(v);
+        default: return xor_lane64<32>(v);
+    }
+}
+
+// Compare-exchange seen from one side: the key this position keeps, given
+// its own key x and its partner's y (keys are unique, so ties never matter).
+__device__ __forceinline__ unsigned long long keep(unsigned long long x, unsigned long long y, bool keep_min)
+{
+    return ((y < x) == keep_min) ? y : x;
 }
 
 // Ascending bitonic sort of the NT x E keys of the block (thread t holds
@@ -100,20 +143,24 @@ __device__ __forceinline__ void bitonic_regs(unsigned long long (&x)[E], unsigne
 #pragma unroll
                 for (int e = 0; e < E; e++) s[t * E + e] = x[e];
                 __syncthreads();
+                unsigned long long y[E];
+#pragma unroll
+                for (int e = 0; e < E; e++) y[e] = s[(t * E + e) ^ j];
 #pragma unroll
                 for (int e = 0; e < E; e++) {
                     const uint32_t i = t * E + e;
-                    const unsigned long long y = s[i ^ j];
-                    x[e] = keep(x[e], y, ((i & j) == 0) == ((i & k) == 0));
+                    x[e] = keep(x[e], y[e], ((i & j) == 0) == ((i & k) == 0));
                 }
                 buf ^= 1;
             } else if (j >= (uint32_t)E) {
-                // partner in lane t ^ (j / E) of this wave
+                // partner in lane t ^ (j / E) of this wave: all exchanges issued, then compared
+                unsigned long long y[E];
+#pragma unroll
+                for (int e = 0; e < E; e++) y[e] = xor_lane64_dyn(x[e], j / E);
 #pragma unroll
                 for (int e = 0; e < E; e++) {
                     const uint32_t i = t * E + e;
-                    const unsigned long long y = __shfl_xor(x[e], (int)(j / E));
-                    x[e] = keep(x[e], y, ((i & j) == 0) == ((i & k) == 0));
+                    x[e] = keep(x[e], y[e], ((i & j) == 0) == ((i & k) == 0));
                 }
             } else {
                 // partner in this thread
@@ -124,7 +171,7 @@ __device__ __forceinline__ void bitonic_regs(unsigned long long (&x)[E], unsigne
                     const unsigned long long a = x[e], b = x[e ^ j];
                     const bool up = (i & k) == 0;
                     x[e] = keep(a, b, up);
-                    x[e ^ j] = keep(a, b, !up);
+                    x[e ^ j] = keep(b, a, !up);
                 }
             }
         }
@@ -191,6 +238,24 @@ __global__ __launch_bounds__(1024) void k_sort_big(const FrameInfo* info, const 
         const uint32_t n = r.y - r.x;
         if (n > (uint32_t)kSortMid) continue;
         sort_run_regs<1024, kSortMid / 1024, 12>(s, depth, sorted + r.x, n, cap);
+        __syncthreads();
+    }
+}
+
+// Queued runs in (4096, 8192]: 1024 threads x 8 keys in registers, 128 KB
+// of LDS for the double-buffered cross-wave stages.
+__global__ __launch_bounds__(1024) void k_sort_big8(const FrameInfo* info, const uint2* __restrict__ ranges,
+                                                    const uint32_t* __restrict__ large,
+                                                    const float* __restrict__ depth, uint32_t* __restrict__ sorted,
+                                                    uint32_t cap)
+{
+    __shared__ unsigned long long s[2 * 2 * kSortMid];
+    const uint32_t nl = info->n_large;
+    for (uint32_t q = blockIdx.x; q < nl; q += gridDim.x) {
+        const uint2 r = ranges[large[q]];
+        const uint32_t n = r.y - r.x;
+        if (n <= (uint32_t)kSortMid || n > 2u * kSortMid) continue;
+        sort_run_regs<1024, 2 * kSortMid / 1024, 13>(s, depth, sorted + r.x, n, cap);
         __syncthreads();
     }
 }
@@ -270,8 +335,9 @@ hipError_t launch_sort(const Views& v, hipStream_t st)
     k_sort_wave<<<(v.lay.T + 3) / 4, 256, 0, st>>>(v.params, v.ranges, v.depth, v.sorted, v.max_active);
     k_sort_mid<<<1024, 256, 0, st>>>(v.info, v.ranges, v.large + 2 * v.lay.T, v.depth, v.sorted, v.max_active);
     k_sort_big<<<512, 1024, 0, st>>>(v.info, v.ranges, v.large, v.depth, v.sorted, v.max_active);
-    k_sort_large<kSortMid, kSortLarge><<<256, 1024, 0, st>>>(v.info, v.ranges, v.large, v.depth, v.sorted,
-                                                              v.max_active);
+    k_sort_big8<<<256, 1024, 0, st>>>(v.info, v.ranges, v.large, v.depth, v.sorted, v.max_active);
+    k_sort_large<2 * kSortMid, kSortLarge><<<256, 1024, 0, st>>>(v.info, v.ranges, v.large, v.depth, v.sorted,
+                                                                  v.max_active);
     k_sort_huge<<<64, 1024, 0, st>>>(v.params, v.info, v.ranges, v.large, v.depth, v.sorted,
                                      reinterpret_cast<uint32_t*>(v.temp), v.max_active);
     return hipGetLastError();

@@ -63,4 +63,72 @@ __device__ __forceinline__ bool splat_keep(const float4& geo, const float4& col,
     return !(power > 0.0f || power < col.z) && !(alpha < kAlphaMin);
 }
 
+// Culling of a splat against a box of pixel centres, shared by the
+// compositor and its adjoint: a splat rejected for a box is one that no
+// pixel of the box would keep.  Per-splat terms of the test:
+struct BoxTest {
+    float u, v, mx, my;   // centre and bounding half-extents (with margin)
+    float A, B, C;        // conic
+    float nba, nbc;       // edge minimisers: x = -B y / A, y = -B x / C
+    float lim;            // accept if the minimum of the form is <= lim
+    bool any;             // alpha can reach 1/255 somewhere
+};
+
+// r0 = (u, v, A, B), r1 = (C, ...), r2 = (.., ex, ey, thr) as written by the
+// projection; alpha >= 1/255 needs q(d) = A dx^2 + 2B dx dy + C dy^2 <= -2 thr.
+__device__ __forceinline__ BoxTest box_test(const float4& r0, const float4& r1, const float4& r2)
+{
+    BoxTest b;
+    const float ex = r2.y, ey = r2.z;
+    b.any = ex >= 0.0f;   // false: alpha below 1/255 everywhere (or a non-finite record)
+    b.u = r0.x;
+    b.v = r0.y;
+    b.mx = ex + 1e-3f * ex + 0.01f;
+    b.my = ey + 1e-3f * ey + 0.01f;
+    b.A = r0.z;
+    b.B = r0.w;
+    b.C = r1.x;
+    // an approximate reciprocal moves an edge minimiser by an ulp, which
+    // changes the form only to second order: far inside the margin below
+    b.nba = -b.B * __builtin_amdgcn_rcpf(b.A);
+    b.nbc = -b.B * __builtin_amdgcn_rcpf(b.C);
+    // rounding of the minimum and of the per-pixel power both grow with the
+    // conditioning of the form; lam bounds the largest covariance eigenvalue
+    // (approximate reciprocals: their ulp errors are far inside these margins)
+    const float rho = -2.0f * r2.w;
+    const float lam = (ex * ex + ey * ey) * __builtin_amdgcn_rcpf(rho);
+    const float gamma = 1.001e-5f * (1.0f + lam);
+    b.lim = gamma < 0.5f ? (rho + 1e-3f * rho) * __builtin_amdgcn_rcpf(1.0f - gamma) : INFINITY;
+    return b;
+}
+
+// Does the bounding box of the splat's alpha >= 1/255 ellipse meet [bx0, bx1] x [by0, by1]?
+__device__ __forceinline__ bool box_overlaps(const BoxTest& b, float bx0, float bx1, float by0, float by1)
+{
+    return !(b.u + b.mx < bx0 || b.u - b.mx > bx1 || b.v + b.my < by0 || b.v - b.my > by1);
+}
+
+// Can the splat reach alpha >= 1/255 at a point of [bx0, bx1] x [by0, by1]?
+__device__ __forceinline__ bool reaches(const BoxTest& b, float bx0, float bx1, float by0, float by1)
+{
+    if (!b.any || !box_overlaps(b, bx0, bx1, by0, by1)) return false;
+    const float du0 = bx0 - b.u, du1 = bx1 - b.u, dv0 = by0 - b.v, dv1 = by1 - b.v;
+    if (du0 <= 0.0f && du1 >= 0.0f && dv0 <= 0.0f && dv1 >= 0.0f) return true;   // centre inside
+    // the convex form is smallest on the boundary: minimise along each edge
+    float qmin = INFINITY;
+#pragma unroll
+    for (int e = 0; e < 2; e++) {
+        const float x = e ? du1 : du0;
+        const float y = fminf(fmaxf(b.nbc * x, dv0), dv1);
+        qmin = fminf(qmin, (b.A * x) * x + (2.0f * b.B * x) * y + (b.C * y) * y);
+    }
+#pragma unroll
+    for (int e = 0; e < 2; e++) {
+        const float y = e ? dv1 : dv0;
+        const float x = fminf(fmaxf(b.nba * y, du0), du1);
+        qmin = fminf(qmin, (b.A * x) * x + (2.0f * b.B * x) * y + (b.C * y) * y);
+    }
+    return qmin <= b.lim;
+}
+
 }  // namespace lodge

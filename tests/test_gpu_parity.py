@@ -80,10 +80,11 @@ def test_nothing_selected_or_visible(L, oracle32):
     assert g["info"]["n_visible"] == 0 and np.all(g["final_T"] == 1.0)
 
 
-@pytest.mark.parametrize("n", [3000, 9000, 40000])
+@pytest.mark.parametrize("n", [200, 1500, 3000, 6000, 9000, 40000])
 def test_long_tile_lists(L, oracle32, n):
-    """Many small Gaussians in front of one tile: per-tile runs beyond the
-    2048-entry and 16384-entry LDS sorts (the merge fallback)."""
+    """Many small Gaussians in front of one tile: per-tile runs in every sort
+    band (one wave up to 256, 2048, 4096, 8192, 16384, and the merge fallback
+    beyond)."""
     lv = synth.gaussians(n, (45, n), synth._cube(0.05), -6.0, 0.3, morton=False)
     lv.mean[2] += 10.0
     sc = Scene(levels=[lv], d=[])
