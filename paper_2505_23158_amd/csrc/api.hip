@@ -89,12 +89,15 @@ Layout make_layout(uint32_t n_total, int32_t width, int32_t height, uint32_t max
     L.info = take(sizeof(FrameInfo));
     L.wstats = take(16ull * 4 * L.T);
     L.chunk_sum = take(4ull * ((max_active + kProjChunk - 1) / kProjChunk + 1));
+    L.chunk_vis = take(4ull * ((max_active + kProjChunk - 1) / kProjChunk + 1));
     L.bin_blocks = (uint32_t)std::max<uint64_t>(1, (max_instances + kBinChunk - 1) / kBinChunk);
     L.bstart = take(4ull * (L.bin_blocks + 1));
     L.proj = take(48ull * max_active);
     L.depth = take(4ull * max_active);
     L.rect = take(8ull * max_active);
     L.vtiles = take(4ull * max_active + 16);
+    L.vis_off = take(4ull * max_active + 16);
+    L.vis_id = take(4ull * max_active + 16);
     L.inst = take(8ull * max_instances);
     L.hist = take(4ull * L.T * L.bin_blocks);
     L.tcount = take(4ull * L.T);
@@ -124,10 +127,13 @@ Views views_of(const lodge_workspace* ws, uint32_t n_total)
     v.sel_off = reinterpret_cast<uint32_t*>(b + v.lay.sel_off);
     v.sel_bits = reinterpret_cast<uint32_t*>(b + v.lay.sel_bits);
     v.chunk_sum = reinterpret_cast<uint32_t*>(b + v.lay.chunk_sum);
+    v.chunk_vis = reinterpret_cast<uint32_t*>(b + v.lay.chunk_vis);
     v.proj = reinterpret_cast<float4*>(b + v.lay.proj);
     v.depth = reinterpret_cast<float*>(b + v.lay.depth);
     v.rect = reinterpret_cast<uint2*>(b + v.lay.rect);
     v.vtiles = reinterpret_cast<uint32_t*>(b + v.lay.vtiles);
+    v.vis_off = reinterpret_cast<uint32_t*>(b + v.lay.vis_off);
+    v.vis_id = reinterpret_cast<uint32_t*>(b + v.lay.vis_id);
     v.bstart = reinterpret_cast<uint32_t*>(b + v.lay.bstart);
     v.inst = reinterpret_cast<uint2*>(b + v.lay.inst);
     v.hist = reinterpret_cast<uint32_t*>(b + v.lay.hist);
@@ -164,6 +170,8 @@ __global__ void k_render_setup(FrameParams* fp, FrameInfo* info, lodge_camera ca
         info->n_large = 0;
         info->n_huge = 0;
         info->n_mid = 0;
+        info->n_binned = 0;
+        info->sort_next = 0;
     }
 }
 }  // namespace

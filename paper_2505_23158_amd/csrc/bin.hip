@@ -6,18 +6,20 @@
 // slow on the die-spanning L2 of this part): block-local LDS histograms,
 // coalesced column passes over a [block][tile] matrix, and LDS ranks.
 //
-//   k_chunk_scan  one block: exclusive scan of the per-chunk tile totals the
-//                 projection wrote -> chunk offsets and the instance count M.
+//   k_chunk_scan  one block: exclusive scans of the per-chunk totals the
+//                 projection wrote (tiles; actives with a tile) -> chunk
+//                 offsets, the instance count M and the binned count.
 //   k_inst_off    per chunk (one wave): scan of the tile counts + chunk
-//                 offset -> exclusive instance offsets of every active, and
-//                 for each binning block the active its first instance
-//                 belongs to.
+//                 offset -> exclusive instance offsets; the actives with a
+//                 tile are compacted in index order as (first instance,
+//                 index), and each binning block gets the compacted slot its
+//                 first instance belongs to.
 //   k_emit_hist   block b takes instances [b C, (b+1) C): finds each one's
 //                 Gaussian by binary search over an LDS window of the
-//                 offsets (the window's ends come from k_inst_off; it gets
-//                 the 160 KB of LDS the tile histogram leaves), writes
-//                 (tile, index) pairs and its tile histogram (packed 16-bit
-//                 LDS counters) as row b of the matrix.
+//                 compacted offsets (at most C + 1 of them, since every
+//                 compacted active has an instance), writes (tile, index)
+//                 pairs and its tile histogram (packed 16-bit LDS counters)
+//                 as row b of the matrix.
 //   k_col_sum     per tile: total count over the blocks (16 tiles x 16 row
 //                 groups per block, row reads contiguous across tiles).
 //   k_tile_scan   one block: exclusive scan of the tile totals -> [start,
@@ -34,82 +36,108 @@ namespace lodge {
 
 namespace {
 
-// One block: exclusive scan of the per-chunk tile totals written by the
-// projection (one per 64 actives) -> chunk offsets and M.  The totals are
+// One block: exclusive scans of the two per-chunk totals the projection
+// wrote (one chunk per 64 actives): tiles -> chunk instance offsets and M;
+// actives with a tile -> chunk offsets of their compaction.  The totals are
 // read as coalesced uint4 runs, kChunkScanGroup tiles of 4 x 1024 at a time,
 // all loads issued before the first tile is scanned; each tile is one block
-// scan (wave scans + wave totals in LDS) on top of the running carry.
+// scan of both totals (wave scans + wave totals in LDS) on top of the carries.
 constexpr int kChunkScanThreads = 1024;
 constexpr int kChunkScanTile = 4 * kChunkScanThreads;
 constexpr int kChunkScanGroup = 8;
 
+__device__ __forceinline__ uint4 load4(const uint32_t* __restrict__ p, uint32_t c, uint32_t nc)
+{
+    if (c + 3 < nc) return *reinterpret_cast<const uint4*>(p + c);
+    return make_uint4(c < nc ? p[c] : 0u, c + 1 < nc ? p[c + 1] : 0u, c + 2 < nc ? p[c + 2] : 0u, 0u);
+}
+
+__device__ __forceinline__ void store4(uint32_t* __restrict__ p, uint32_t c, uint32_t nc, uint4 v)
+{
+    if (c + 3 < nc) {
+        *reinterpret_cast<uint4*>(p + c) = v;
+    } else {
+        if (c < nc) p[c] = v.x;
+        if (c + 1 < nc) p[c + 1] = v.y;
+        if (c + 2 < nc) p[c + 2] = v.z;
+    }
+}
+
+__device__ __forceinline__ uint4 excl4(uint32_t e0, uint4 v)
+{
+    return make_uint4(e0, e0 + v.x, e0 + v.x + v.y, e0 + v.x + v.y + v.z);
+}
+
 __global__ __launch_bounds__(kChunkScanThreads) void k_chunk_scan(FrameInfo* info, uint32_t* __restrict__ csum,
+                                                                 uint32_t* __restrict__ cvis,
                                                                  const uint32_t* __restrict__ count, uint32_t cap,
                                                                  uint64_t max_instances)
 {
-    __shared__ uint32_t s_w[kChunkScanThreads / 64];
+    __shared__ uint32_t s_w[2][kChunkScanThreads / 64];
     const uint32_t n = min(*count, cap);
     const uint32_t nc = (n + kProjChunk - 1) / kProjChunk;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     unsigned long long carry = 0;
+    uint32_t vcarry = 0;
     for (uint32_t g0 = 0; g0 < nc; g0 += kChunkScanTile * kChunkScanGroup) {
-        uint4 v[kChunkScanGroup];
+        uint4 v[kChunkScanGroup], w[kChunkScanGroup];
 #pragma unroll
         for (int t = 0; t < kChunkScanGroup; t++) {
             const uint32_t c = g0 + t * kChunkScanTile + 4 * tid;
-            if (c + 3 < nc) {
-                v[t] = *reinterpret_cast<const uint4*>(csum + c);
-            } else {
-                v[t].x = c < nc ? csum[c] : 0u;
-                v[t].y = c + 1 < nc ? csum[c + 1] : 0u;
-                v[t].z = c + 2 < nc ? csum[c + 2] : 0u;
-                v[t].w = 0u;
-            }
+            v[t] = load4(csum, c, nc);
+            w[t] = load4(cvis, c, nc);
         }
 #pragma unroll
         for (int t = 0; t < kChunkScanGroup; t++) {
             const uint32_t c = g0 + t * kChunkScanTile + 4 * tid;
             if (g0 + t * kChunkScanTile >= nc) break;   // block-uniform
             const uint32_t own = (v[t].x + v[t].y) + (v[t].z + v[t].w);
-            uint32_t inc = own;
+            const uint32_t vown = (w[t].x + w[t].y) + (w[t].z + w[t].w);
+            uint32_t inc = own, vinc = vown;
             for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t u = __shfl_up(inc, o);
-                if ((int)lane >= o) inc += u;
+                const uint32_t u = __shfl_up(inc, o), vu = __shfl_up(vinc, o);
+                if ((int)lane >= o) {
+                    inc += u;
+                    vinc += vu;
+                }
             }
-            if (lane == 63) s_w[wave] = inc;
+            if (lane == 63) {
+                s_w[0][wave] = inc;
+                s_w[1][wave] = vinc;
+            }
             __syncthreads();
-            uint32_t before = 0, total = 0;
+            uint32_t before = 0, total = 0, vbefore = 0, vtotal = 0;
 #pragma unroll
-            for (int w = 0; w < kChunkScanThreads / 64; w++) {
-                const uint32_t x = s_w[w];
-                before += (uint32_t)w < wave ? x : 0u;
+            for (int k = 0; k < kChunkScanThreads / 64; k++) {
+                const uint32_t x = s_w[0][k], y = s_w[1][k];
+                before += (uint32_t)k < wave ? x : 0u;
                 total += x;
+                vbefore += (uint32_t)k < wave ? y : 0u;
+                vtotal += y;
             }
             // offsets only matter when M fits the instance capacity (< 2^32)
-            const uint32_t e0 = (uint32_t)carry + before + inc - own;
-            const uint4 o4 = make_uint4(e0, e0 + v[t].x, e0 + v[t].x + v[t].y, e0 + v[t].x + v[t].y + v[t].z);
-            if (c + 3 < nc) {
-                *reinterpret_cast<uint4*>(csum + c) = o4;
-            } else {
-                if (c < nc) csum[c] = o4.x;
-                if (c + 1 < nc) csum[c + 1] = o4.y;
-                if (c + 2 < nc) csum[c + 2] = o4.z;
-            }
+            store4(csum, c, nc, excl4((uint32_t)carry + before + inc - own, v[t]));
+            store4(cvis, c, nc, excl4(vcarry + vbefore + vinc - vown, w[t]));
             carry += total;
+            vcarry += vtotal;
             __syncthreads();   // s_w is rewritten by the next tile
         }
     }
     if (tid == 0) {
         info->n_instances = carry;
+        info->n_binned = vcarry;
         if (carry > max_instances) atomicOr(&info->overflow, kOvfInstances);
     }
 }
 
 // Per chunk of kProjChunk (= 64) actives, one wave: inclusive wave scan of
-// their tile counts plus the chunk offset -> exclusive instance offsets, in place.
-__global__ __launch_bounds__(256) void k_inst_off(const FrameInfo* info, uint32_t* __restrict__ vt,
+// their tile counts plus the chunk offset -> exclusive instance offsets; the
+// actives with a tile are compacted, in index order, into (vis_off, vis_id).
+__global__ __launch_bounds__(256) void k_inst_off(const FrameInfo* info, const uint32_t* __restrict__ vt,
                                                   const uint32_t* __restrict__ coff,
+                                                  const uint32_t* __restrict__ cvis,
                                                   const uint32_t* __restrict__ count, uint32_t cap,
+                                                  uint32_t* __restrict__ vis_off, uint32_t* __restrict__ vis_id,
                                                   uint32_t* __restrict__ bstart, uint64_t max_instances)
 {
     static_assert(kProjChunk == 64, "one wave per chunk");
@@ -117,6 +145,7 @@ __global__ __launch_bounds__(256) void k_inst_off(const FrameInfo* info, uint32_
     const uint32_t n = min(*count, cap);
     const uint32_t nc = (n + kProjChunk - 1) / kProjChunk;
     const uint32_t lane = threadIdx.x & 63;
+    const unsigned long long lt = (1ull << lane) - 1ull;
     const uint32_t waves = gridDim.x * (blockDim.x >> 6);
     for (uint32_t c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < nc; c += waves) {
         const uint32_t a = c * kProjChunk + lane;
@@ -127,11 +156,16 @@ __global__ __launch_bounds__(256) void k_inst_off(const FrameInfo* info, uint32_
             if ((int)lane >= off) inc += o;
         }
         const uint32_t o = coff[c] + inc - x;
-        if (a < n) vt[a] = o;
-        // the binning block starting at instance b kBinChunk is owned by the
-        // active whose run [o, o + x) holds that instance
-        for (uint32_t b = (o + kBinChunk - 1) / kBinChunk; x > 0 && (unsigned long long)b * kBinChunk < o + x; b++)
-            bstart[b] = a;
+        const unsigned long long m = __ballot(x > 0u);
+        if (x > 0u) {
+            const uint32_t s = cvis[c] + (uint32_t)__popcll(m & lt);
+            vis_off[s] = o;
+            vis_id[s] = a;
+            // the binning block starting at instance b kBinChunk is owned by
+            // the active whose run [o, o + x) holds that instance
+            for (uint32_t b = (o + kBinChunk - 1) / kBinChunk; (unsigned long long)b * kBinChunk < o + x; b++)
+                bstart[b] = s;
+        }
     }
 }
 
@@ -153,7 +187,8 @@ __device__ __forceinline__ uint32_t hist_get(const uint32_t* h, uint32_t t)
 }
 
 constexpr int kBinThreads = 1024;
-constexpr int kEmitLdsWords = 40960;   // 160 KB: the tile histogram, then as long an offset window as fits
+// the tile histogram (16-bit counters), then the offset and id windows
+constexpr int kEmitLdsWords = kMaxTiles / 2 + 2 * (kBinChunk + 1);
 
 // last index i in [0, n) with a[i] <= key (a ascending, a[0] <= key)
 __device__ __forceinline__ uint32_t last_le(const uint32_t* a, uint32_t n, uint32_t key)
@@ -167,52 +202,51 @@ __device__ __forceinline__ uint32_t last_le(const uint32_t* a, uint32_t n, uint3
 }
 
 __global__ __launch_bounds__(kBinThreads) void k_emit_hist(const FrameParams* fp, const FrameInfo* info,
-                                                           const uint32_t* __restrict__ off,
+                                                           const uint32_t* __restrict__ vis_off,
+                                                           const uint32_t* __restrict__ vis_id,
                                                            const uint32_t* __restrict__ bstart,
-                                                           const uint32_t* __restrict__ count, uint32_t cap,
                                                            const uint2* __restrict__ rect, uint2* __restrict__ inst,
                                                            uint32_t* __restrict__ hist, uint64_t max_instances)
 {
     constexpr int kPer = kBinChunk / kBinThreads;   // instances per thread, processed together
+    // every compacted active holds at least one instance, so a block's
+    // instances belong to at most kBinChunk + 1 of them
+    constexpr uint32_t kWindow = kBinChunk + 1;
     __shared__ uint32_t s_lds[kEmitLdsWords];
     const unsigned long long M = info->n_instances;
     if (M == 0 || M > max_instances) return;
-    const uint32_t n_act = min(*count, cap);
+    const uint32_t n_bin = info->n_binned;
     const int32_t TX = fp->TX;
     const uint32_t T = (uint32_t)(fp->TX * fp->TY);
     const uint32_t B = blocks_of(M);
-    // packed 16-bit tile counters first (T <= kMaxTiles), the offset window after them
+    // packed 16-bit tile counters first (T <= kMaxTiles), then the windows
     uint32_t* const s_hist = s_lds;
     uint32_t* const s_off = s_lds + (T + 1) / 2;
-    const uint32_t window = kEmitLdsWords - (T + 1) / 2;
+    uint32_t* const s_id = s_off + kWindow;
     for (uint32_t b = blockIdx.x; b < B; b += gridDim.x) {
         const uint32_t j0 = b * kBinChunk;
         const uint32_t j1 = (uint32_t)min((unsigned long long)j0 + kBinChunk, M);
         for (uint32_t k = threadIdx.x; k < (T + 1) / 2; k += kBinThreads) s_hist[k] = 0;
-        // actives [lo, hi] hold the block's instances (hi may be one past the last)
+        // compacted actives [lo, hi] hold the block's instances (hi may be one past the last)
         const uint32_t lo = bstart[b];
-        const uint32_t hi = b + 1 < B ? bstart[b + 1] : n_act - 1;
-        const uint32_t cnt = hi - lo + 1;
-        const bool in_lds = cnt <= window;
-        if (in_lds)
-            for (uint32_t k = threadIdx.x; k < cnt; k += kBinThreads) s_off[k] = off[lo + k];
+        const uint32_t hi = b + 1 < B ? bstart[b + 1] : n_bin - 1;
+        const uint32_t cnt = min(hi - lo + 1, kWindow);
+        for (uint32_t k = threadIdx.x; k < cnt; k += kBinThreads) {
+            s_off[k] = vis_off[lo + k];
+            s_id[k] = vis_id[lo + k];
+        }
         __syncthreads();
-        // each instance's active: the last whose offset is <= it (zero-tile actives share offsets)
+        // each instance's active: the last whose first instance is <= it
         uint32_t a[kPer], kk[kPer];
 #pragma unroll
         for (int q = 0; q < kPer; q++) {
             const uint32_t j = j0 + threadIdx.x + q * kBinThreads;
-            a[q] = lo;
+            a[q] = 0;
             kk[q] = 0;
             if (j < j1) {
-                if (in_lds) {
-                    const uint32_t l = last_le(s_off, cnt, j);
-                    a[q] = lo + l;
-                    kk[q] = j - s_off[l];
-                } else {
-                    a[q] = lo + last_le(off + lo, cnt, j);
-                    kk[q] = j - off[a[q]];
-                }
+                const uint32_t l = last_le(s_off, cnt, j);
+                a[q] = s_id[l];
+                kk[q] = j - s_off[l];
             }
         }
         uint2 rc[kPer];
@@ -444,13 +478,15 @@ __global__ __launch_bounds__(kBinThreads) void k_scatter(const FrameParams* fp, 
 
 hipError_t launch_bin(const Views& v, const lodge_selection& sel, hipStream_t st)
 {
-    k_chunk_scan<<<1, kChunkScanThreads, 0, st>>>(v.info, v.chunk_sum, sel.count, sel.cap, v.max_instances);
+    k_chunk_scan<<<1, kChunkScanThreads, 0, st>>>(v.info, v.chunk_sum, v.chunk_vis, sel.count, sel.cap,
+                                                  v.max_instances);
     const uint32_t cg = std::max<uint32_t>(1, std::min<uint32_t>(4096, (v.max_active + 255) / 256));
-    k_inst_off<<<cg, 256, 0, st>>>(v.info, v.vtiles, v.chunk_sum, sel.count, sel.cap, v.bstart, v.max_instances);
+    k_inst_off<<<cg, 256, 0, st>>>(v.info, v.vtiles, v.chunk_sum, v.chunk_vis, sel.count, sel.cap, v.vis_off,
+                                   v.vis_id, v.bstart, v.max_instances);
     const uint32_t bmax = std::max<uint32_t>(1, (uint32_t)((v.max_instances + kBinChunk - 1) / kBinChunk));
     const uint32_t grid = std::min<uint32_t>(bmax, 1024);
-    k_emit_hist<<<grid, kBinThreads, 0, st>>>(v.params, v.info, v.vtiles, v.bstart, sel.count, sel.cap, v.rect,
-                                              v.inst, v.hist, v.max_instances);
+    k_emit_hist<<<grid, kBinThreads, 0, st>>>(v.params, v.info, v.vis_off, v.vis_id, v.bstart, v.rect, v.inst,
+                                              v.hist, v.max_instances);
     const uint32_t tb = (v.lay.T + kColTiles - 1) / kColTiles;
     k_col_sum<<<tb, 256, 0, st>>>(v.params, v.info, v.hist, v.tcount, v.max_instances);
     k_tile_scan<<<1, kTilesThreads, 0, st>>>(v.params, v.info, v.tcount, v.ranges, v.order, v.large);

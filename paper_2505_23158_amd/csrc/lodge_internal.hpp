@@ -76,7 +76,9 @@ struct FrameInfo {
     uint32_t n_large;     // tiles sorted by the large-list kernel
     uint32_t n_huge;      // tiles sorted by the merge fallback
     uint32_t n_mid;       // tiles sorted by the mid-length kernel
-    uint32_t pad[3];
+    uint32_t n_binned;    // actives with at least one tile
+    uint32_t sort_next;   // next work item of the per-tile sort
+    uint32_t pad;
 };
 
 enum : uint32_t { kOvfSelect = 1u, kOvfInstances = 2u, kOvfTile = 4u };
@@ -119,8 +121,8 @@ constexpr int kProjChunk = 64;                      // actives per projection ch
 constexpr int kMaxTiles = 32768;                    // 16-bit-packed LDS tile histograms (e.g. 3840 x 2160)
 
 struct Layout {
-    size_t params, info, wstats, bstart, sel_cnt, sel_off, sel_bits, chunk_sum, proj, depth, rect, vtiles, inst, hist, tcount, ranges, order, large,
-        sorted, temp, g2d, total;
+    size_t params, info, wstats, bstart, sel_cnt, sel_off, sel_bits, chunk_sum, chunk_vis, proj, depth, rect, vtiles, vis_off,
+        vis_id, inst, hist, tcount, ranges, order, large, sorted, temp, g2d, total;
     uint32_t sel_tiles, TX, TY, T, bin_blocks;
 };
 
@@ -135,11 +137,14 @@ struct Views {
     uint32_t* sel_off;     // per selection tile: exclusive offset of its members
     uint32_t* sel_bits;    // [selection tiles][kSelBlock] two membership bits per item
     uint32_t* chunk_sum;   // per projection chunk: tile total -> exclusive instance offset
+    uint32_t* chunk_vis;   // per projection chunk: actives with >= 1 tile -> exclusive offset among them
     float4* proj;          // [max_active][3]: (u, v, A, B), (C, o, r, g), (b, ex, ey, thr); visible only
     float* depth;          // [max_active] camera depth (sort key), 0 when culled
     uint2* rect;           // [max_active] tile rect (x0 | y0 << 16, x1 | y1 << 16), empty when culled
-    uint32_t* vtiles;      // tiles touched per active index -> exclusive instance offsets (in place)
-    uint32_t* bstart;      // per binning block: the active holding its first instance
+    uint32_t* vtiles;      // tiles touched per active index
+    uint32_t* vis_off;     // per active with >= 1 tile, in index order: its first instance
+    uint32_t* vis_id;      // ... and its active index
+    uint32_t* bstart;      // per binning block: the vis_off slot holding its first instance
     uint2* inst;           // [max_instances] (tile, active index) in emission order
     uint32_t* hist;        // [bin blocks][T] per-block tile counts -> per-block first slots
     uint32_t* tcount;      // per tile list length

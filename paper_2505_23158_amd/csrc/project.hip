@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                                                  uint32_t cap, const FrameParams* __restrict__ fp, FrameInfo* info,
                                                  float4* __restrict__ proj, float* __restrict__ depth,
                                                  uint2* __restrict__ rect, uint32_t* __restrict__ vtiles,
-                                                 uint32_t* __restrict__ chunk_sum)
+                                                 uint32_t* __restrict__ chunk_sum, uint32_t* __restrict__ chunk_vis)
 {
     __shared__ uint32_t s_cnt[2][4];
     __shared__ uint32_t s_qa[4][kQueue], s_qg[4][kQueue];
@@ -311,10 +311,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             n_front += front ? 1u : 0u;
             n_vis += visible ? 1u : 0u;
         }
-        // the chunk's tile total: first level of the instance scan
+        // the chunk's tile total and its actives with a tile: first level
+        // of the instance scan and of their compaction
         uint32_t csum = ntiles;
         for (int o = 32; o > 0; o >>= 1) csum += __shfl_xor(csum, o);
-        if (lane == 0) chunk_sum[c] = csum;
+        const uint32_t cvis = (uint32_t)__popcll(__ballot(ntiles > 0u));
+        if (lane == 0) {
+            chunk_sum[c] = csum;
+            chunk_vis[c] = cvis;
+        }
         // queue the visible ones for colour
         const unsigned long long m = __ballot(visible);
         if (visible) {
@@ -396,7 +401,7 @@ hipError_t launch_project(const LevelsArg& lv, const lodge_selection& sel, const
     if (blocks < 1) blocks = 1;
     if (blocks > resident) blocks = resident;
     k_project<<<blocks, 256, 0, st>>>(lv, sel.ids, sel.w, sel.count, sel.cap, v.params, v.info, v.proj, v.depth,
-                                      v.rect, v.vtiles, v.chunk_sum);
+                                      v.rect, v.vtiles, v.chunk_sum, v.chunk_vis);
     return hipGetLastError();
 }
 

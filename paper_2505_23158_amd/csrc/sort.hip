@@ -6,27 +6,28 @@
 // so the bit pattern orders like the value, and the index makes the order
 // total (ties in depth are broken by active index, i.e. by global id).
 //
-// Runs up to 4096 keys are sorted by a bitonic network held in registers:
+// Runs up to 8192 keys are sorted by a bitonic network held in registers:
 // each thread keeps E consecutive keys; stages whose partner is in the same
 // thread compare registers, stages whose partner is in another lane of the
-// wave exchange keys with lane shuffles, and only stages whose partner is in
-// another wave go through LDS (double-buffered, one barrier per stage).
-//
-//   k_sort_wave   runs <= 256, one wave each (four per block), 1-4 keys per
-//                 lane: no LDS, no barrier.
-//   k_sort_mid    queued runs in (256, 2048], 256 threads x 8 keys.
-//   k_sort_big    queued runs in (2048, 4096], 1024 threads x 4 keys.
-//   k_sort_big8   queued runs in (4096, 8192], 1024 threads x 8 keys.
-//   k_sort_large  queued runs in (8192, 16384]: the bitonic network in 128 KB
-//                 of LDS, 1024 threads (gfx950 allows 160 KB).
-//   k_sort_huge   runs > 16384: 16384-key chunks sorted in LDS, then merge
-//                 passes in global memory where each key finds its output
-//                 slot by binary search in the sibling run.
+// wave exchange keys with lane shuffles (DPP where the distance allows), and
+// only stages whose partner is in another wave go through LDS
+// (double-buffered, one barrier per stage).  One launch, k_sort, sorts every
+// run, by length band:
+//   <= 256         one wave, 1-4 keys per lane: no LDS, no barrier;
+//   (256, 2048]    256 threads x 8 keys (four runs per block, in step);
+//   (2048, 4096]   1024 threads x 4 keys;
+//   (4096, 8192]   1024 threads x 8 keys;
+//   (8192, 16384]  the bitonic network in 128 KB of LDS;
+//   > 16384        16384-key chunks sorted in LDS, then merge passes in
+//                  global memory where each key finds its output slot by
+//                  binary search in the sibling run.
 #include "lodge_internal.hpp"
 
 namespace lodge {
 
 namespace {
+
+constexpr int kSortThreads = 1024;
 
 // Indices come from the emission pass; one outside [0, cap) would be a
 // binning bug, so it sorts last instead of being dereferenced.
@@ -197,88 +198,6 @@ __device__ __forceinline__ void sort_run_regs(unsigned long long* lds, const flo
     }
 }
 
-__global__ __launch_bounds__(256) void k_sort_wave(const FrameParams* fp, const uint2* __restrict__ ranges,
-                                                   const float* __restrict__ depth, uint32_t* __restrict__ sorted,
-                                                   uint32_t cap)
-{
-    const uint32_t T = (uint32_t)(fp->TX * fp->TY);
-    const uint32_t t = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (t >= T) return;
-    const uint2 r = ranges[t];
-    const uint32_t n = r.y - r.x;
-    if (n <= 1 || n > (uint32_t)kSortWave) return;
-    uint32_t* run = sorted + r.x;
-    // the lane index is threadIdx.x % 64 inside sort_run_regs<64, ...>
-    if (n <= 64) sort_run_regs<64, 1, 6>(nullptr, depth, run, n, cap);
-    else if (n <= 128) sort_run_regs<64, 2, 7>(nullptr, depth, run, n, cap);
-    else sort_run_regs<64, 4, 8>(nullptr, depth, run, n, cap);
-}
-
-__global__ __launch_bounds__(256) void k_sort_mid(const FrameInfo* info, const uint2* __restrict__ ranges,
-                                                  const uint32_t* __restrict__ mid, const float* __restrict__ depth,
-                                                  uint32_t* __restrict__ sorted, uint32_t cap)
-{
-    __shared__ unsigned long long s[2 * kSortSmall];
-    const uint32_t nm = info->n_mid;
-    for (uint32_t q = blockIdx.x; q < nm; q += gridDim.x) {
-        const uint2 r = ranges[mid[q]];
-        sort_run_regs<256, kSortSmall / 256, 11>(s, depth, sorted + r.x, r.y - r.x, cap);
-        __syncthreads();   // LDS is reused by the next run
-    }
-}
-
-__global__ __launch_bounds__(1024) void k_sort_big(const FrameInfo* info, const uint2* __restrict__ ranges,
-                                                  const uint32_t* __restrict__ large, const float* __restrict__ depth,
-                                                  uint32_t* __restrict__ sorted, uint32_t cap)
-{
-    __shared__ unsigned long long s[2 * kSortMid];
-    const uint32_t nl = info->n_large;
-    for (uint32_t q = blockIdx.x; q < nl; q += gridDim.x) {
-        const uint2 r = ranges[large[q]];
-        const uint32_t n = r.y - r.x;
-        if (n > (uint32_t)kSortMid) continue;
-        sort_run_regs<1024, kSortMid / 1024, 12>(s, depth, sorted + r.x, n, cap);
-        __syncthreads();
-    }
-}
-
-// Queued runs in (4096, 8192]: 1024 threads x 8 keys in registers, 128 KB
-// of LDS for the double-buffered cross-wave stages.
-__global__ __launch_bounds__(1024) void k_sort_big8(const FrameInfo* info, const uint2* __restrict__ ranges,
-                                                    const uint32_t* __restrict__ large,
-                                                    const float* __restrict__ depth, uint32_t* __restrict__ sorted,
-                                                    uint32_t cap)
-{
-    __shared__ unsigned long long s[2 * 2 * kSortMid];
-    const uint32_t nl = info->n_large;
-    for (uint32_t q = blockIdx.x; q < nl; q += gridDim.x) {
-        const uint2 r = ranges[large[q]];
-        const uint32_t n = r.y - r.x;
-        if (n <= (uint32_t)kSortMid || n > 2u * kSortMid) continue;
-        sort_run_regs<1024, 2 * kSortMid / 1024, 13>(s, depth, sorted + r.x, n, cap);
-        __syncthreads();
-    }
-}
-
-// Runs in (kSortSmall, kSortLarge], in two length bands: each instantiation
-// takes the queued runs in (LO, CAP] and allocates only the LDS that CAP
-// needs, so that more blocks fit a CU.
-template <int LO, int CAP>
-__global__ __launch_bounds__(1024) void k_sort_large(const FrameInfo* info, const uint2* __restrict__ ranges,
-                                                     const uint32_t* __restrict__ large,
-                                                     const float* __restrict__ proj, uint32_t* __restrict__ sorted,
-                                                     uint32_t cap)
-{
-    __shared__ unsigned long long s[CAP];
-    const uint32_t nl = info->n_large;
-    for (uint32_t q = blockIdx.x; q < nl; q += gridDim.x) {
-        const uint2 r = ranges[large[q]];
-        const uint32_t n = r.y - r.x;
-        if (n <= (uint32_t)LO || n > (uint32_t)CAP) continue;
-        sort_run<1024, CAP>(s, proj, sorted + r.x, n, cap);
-    }
-}
-
 // position of key x among the sorted run b[0, n): number of keys < x
 __device__ __forceinline__ uint32_t rank_in(const uint32_t* __restrict__ b, uint32_t n, unsigned long long x,
                                             const float* __restrict__ proj, uint32_t cap)
@@ -291,40 +210,89 @@ __device__ __forceinline__ uint32_t rank_in(const uint32_t* __restrict__ b, uint
     return lo;
 }
 
-__global__ __launch_bounds__(1024) void k_sort_huge(const FrameParams* fp, const FrameInfo* info,
-                                                    const uint2* __restrict__ ranges, const uint32_t* __restrict__ large,
-                                                    const float* __restrict__ proj, uint32_t* __restrict__ sorted,
-                                                    uint32_t* __restrict__ scratch, uint32_t cap)
+// A run longer than kSortLarge: kSortLarge-key chunks sorted in LDS, then
+// merge passes in global memory (ping-pong with scratch) where each key
+// finds its output slot by binary search in the sibling run.
+__device__ __forceinline__ void sort_huge_run(unsigned long long* s, const float* __restrict__ proj,
+                                              uint32_t* __restrict__ run, uint32_t* __restrict__ tmp, uint32_t n,
+                                              uint32_t cap)
+{
+    uint32_t* src = run;
+    uint32_t* dst = tmp;
+    for (uint32_t c0 = 0; c0 < n; c0 += kSortLarge)
+        sort_run<kSortThreads, kSortLarge>(s, proj, src + c0, min((uint32_t)kSortLarge, n - c0), cap);
+    // merge passes: run pairs [i, i + w) and [i + w, i + 2w)
+    for (uint32_t w = kSortLarge; w < n; w <<= 1) {
+        for (uint32_t k = threadIdx.x; k < n; k += kSortThreads) {
+            const uint32_t pair = k / (2 * w) * (2 * w);
+            const uint32_t mid = min(pair + w, n), end = min(pair + 2 * w, n);
+            const unsigned long long x = key_of(proj, src[k], cap);
+            uint32_t out;
+            if (k < mid) out = pair + (k - pair) + rank_in(src + mid, end - mid, x, proj, cap);
+            else out = pair + (k - mid) + rank_in(src + pair, mid - pair, x, proj, cap);
+            out = out < n ? out : n - 1;
+            dst[out] = src[k];
+        }
+        __syncthreads();
+        uint32_t* t = src; src = dst; dst = t;
+    }
+    if (src != run)
+        for (uint32_t k = threadIdx.x; k < n; k += kSortThreads) run[k] = src[k];
+    __syncthreads();
+}
+
+// All runs in one launch.  Work items, longest first, are handed out by a
+// counter (one atomic per item, not per key):
+//   [0, n_large)   one queued run in (2048, 16384]: in registers, 1024 x 4
+//                  or 1024 x 8 keys, else the LDS network;
+//   n_huge items   one run > 16384;
+//   n_mid / 4      four queued runs in (256, 2048], one per 256 threads
+//                  (2048-key networks in step: the block barriers match);
+//   T / 16         sixteen tiles, one per wave, sorted if 1 < n <= 256.
+// Every block leaves once the items run out.
+__global__ __launch_bounds__(kSortThreads) void k_sort(const FrameParams* __restrict__ fp, FrameInfo* info,
+                                                       const uint2* __restrict__ ranges,
+                                                       const uint32_t* __restrict__ queues,
+                                                       const float* __restrict__ depth, uint32_t* __restrict__ sorted,
+                                                       uint32_t* __restrict__ scratch, uint32_t cap)
 {
     __shared__ unsigned long long s[kSortLarge];
+    __shared__ uint32_t s_item;
     const uint32_t T = (uint32_t)(fp->TX * fp->TY);
-    const uint32_t nh = info->n_huge;
-    for (uint32_t q = blockIdx.x; q < nh; q += gridDim.x) {
-        const uint2 r = ranges[large[T + q]];
-        const uint32_t n = r.y - r.x;
-        uint32_t* src = sorted + r.x;
-        uint32_t* dst = scratch + r.x;
-        // sorted chunks in place
-        for (uint32_t c0 = 0; c0 < n; c0 += kSortLarge)
-            sort_run<1024, kSortLarge>(s, proj, src + c0, min((uint32_t)kSortLarge, n - c0), cap);
-        // merge passes: run pairs [i, i + w) and [i + w, i + 2w)
-        for (uint32_t w = kSortLarge; w < n; w <<= 1) {
-            for (uint32_t k = threadIdx.x; k < n; k += 1024) {
-                const uint32_t pair = k / (2 * w) * (2 * w);
-                const uint32_t mid = min(pair + w, n), end = min(pair + 2 * w, n);
-                const unsigned long long x = key_of(proj, src[k], cap);
-                uint32_t out;
-                if (k < mid) out = pair + (k - pair) + rank_in(src + mid, end - mid, x, proj, cap);
-                else out = pair + (k - mid) + rank_in(src + pair, mid - pair, x, proj, cap);
-                out = out < n ? out : n - 1;
-                dst[out] = src[k];
-            }
-            __syncthreads();
-            uint32_t* tmp = src; src = dst; dst = tmp;
-        }
-        if (src != sorted + r.x)
-            for (uint32_t k = threadIdx.x; k < n; k += 1024) sorted[r.x + k] = src[k];
+    const uint32_t nl = info->n_large, nh = info->n_huge, nm = info->n_mid;
+    const uint32_t i_huge = nl, i_mid = i_huge + nh, i_wave = i_mid + (nm + 3) / 4, n_items = i_wave + (T + 15) / 16;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(&info->sort_next, 1u);
         __syncthreads();
+        const uint32_t i = s_item;
+        __syncthreads();
+        if (i >= n_items) break;
+        if (i < i_huge) {
+            const uint2 r = ranges[queues[i]];
+            const uint32_t n = r.y - r.x;
+            if (n <= (uint32_t)kSortMid) sort_run_regs<kSortThreads, kSortMid / kSortThreads, 12>(s, depth, sorted + r.x, n, cap);
+            else if (n <= 2u * kSortMid)
+                sort_run_regs<kSortThreads, 2 * kSortMid / kSortThreads, 13>(s, depth, sorted + r.x, n, cap);
+            else sort_run<kSortThreads, kSortLarge>(s, depth, sorted + r.x, n, cap);
+        } else if (i < i_mid) {
+            const uint2 r = ranges[queues[T + (i - i_huge)]];
+            sort_huge_run(s, depth, sorted + r.x, scratch + r.x, r.y - r.x, cap);
+        } else if (i < i_wave) {
+            const uint32_t g = threadIdx.x / 256, q = 4 * (i - i_mid) + g;
+            uint2 r = make_uint2(0u, 0u);   // an empty run still steps through the network
+            if (q < nm) r = ranges[queues[2 * T + q]];
+            sort_run_regs<256, kSortSmall / 256, 11>(s + g * 2 * kSortSmall, depth, sorted + r.x, r.y - r.x, cap);
+        } else {
+            const uint32_t t = 16 * (i - i_wave) + threadIdx.x / 64;
+            const uint2 r = t < T ? ranges[t] : make_uint2(0u, 0u);
+            const uint32_t n = r.y - r.x;
+            uint32_t* run = sorted + r.x;
+            // the lane index is threadIdx.x % 64 inside sort_run_regs<64, ...>
+            if (n > 1 && n <= 64) sort_run_regs<64, 1, 6>(nullptr, depth, run, n, cap);
+            else if (n > 64 && n <= 128) sort_run_regs<64, 2, 7>(nullptr, depth, run, n, cap);
+            else if (n > 128 && n <= (uint32_t)kSortWave) sort_run_regs<64, 4, 8>(nullptr, depth, run, n, cap);
+        }
+        __syncthreads();   // LDS is reused by the next item
     }
 }
 
@@ -332,14 +300,17 @@ __global__ __launch_bounds__(1024) void k_sort_huge(const FrameParams* fp, const
 
 hipError_t launch_sort(const Views& v, hipStream_t st)
 {
-    k_sort_wave<<<(v.lay.T + 3) / 4, 256, 0, st>>>(v.params, v.ranges, v.depth, v.sorted, v.max_active);
-    k_sort_mid<<<1024, 256, 0, st>>>(v.info, v.ranges, v.large + 2 * v.lay.T, v.depth, v.sorted, v.max_active);
-    k_sort_big<<<512, 1024, 0, st>>>(v.info, v.ranges, v.large, v.depth, v.sorted, v.max_active);
-    k_sort_big8<<<256, 1024, 0, st>>>(v.info, v.ranges, v.large, v.depth, v.sorted, v.max_active);
-    k_sort_large<2 * kSortMid, kSortLarge><<<256, 1024, 0, st>>>(v.info, v.ranges, v.large, v.depth, v.sorted,
-                                                                  v.max_active);
-    k_sort_huge<<<64, 1024, 0, st>>>(v.params, v.info, v.ranges, v.large, v.depth, v.sorted,
-                                     reinterpret_cast<uint32_t*>(v.temp), v.max_active);
+    // one 128 KB-LDS block per compute unit
+    static thread_local int dev_cached = -1, cus = 0;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev != dev_cached) {
+        if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+        dev_cached = dev;
+    }
+    k_sort<<<std::max(1, cus), kSortThreads, 0, st>>>(v.params, v.info, v.ranges, v.large, v.depth, v.sorted,
+                                                      reinterpret_cast<uint32_t*>(v.temp), v.max_active);
     return hipGetLastError();
 }
 
