@@ -36,6 +36,12 @@ namespace lodge {
 
 namespace {
 
+// Records of one wave: three thirds of 65 float4 (65 = 64 batch slots + the
+// sentinel), [0] u, v, -A/2, -B; [1] -C/2, o, threshold, r; [2] g, b, -, -.
+constexpr uint32_t kSlots = 65;
+constexpr uint32_t kWaveRec = 3 * kSlots;
+constexpr uint32_t kThird = kSlots * sizeof(float4);   // bytes between the thirds
+
 __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict__ fp,
                                                    const uint2* __restrict__ ranges,
                                                    const uint32_t* __restrict__ order,
@@ -44,11 +50,11 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
                                                    float* __restrict__ final_T, uint32_t* __restrict__ n_contrib,
                                                    uint4* __restrict__ wstats, uint32_t cap)
 {
-    // per wave, by batch slot: [0] u, v, -A/2, -B; [1] -C/2, o, threshold, r; [2] g, b, -, -.
-    // Slot 64 is a sentinel every pixel skips (threshold +inf): it pads the
-    // shorter sub-quadrant lists to the longest one.
-    __shared__ float4 s_rec[4][3][65];
-    __shared__ uint8_t s_idx[4][4][64];   // per wave and sub-quadrant: batch slots in list order
+    // Slot 64 of every wave is a sentinel every pixel skips (threshold
+    // +inf): it pads the shorter sub-quadrant lists to the longest.  The
+    // lists hold LDS byte offsets (from s_rec) of the first third of a slot.
+    __shared__ float4 s_rec[4 * kWaveRec];
+    __shared__ uint16_t s_idx[4][4][64];   // per wave and sub-quadrant
 
     const int32_t W = fp->cam.width, H = fp->cam.height, TX = fp->TX;
     const uint32_t tile = order[blockIdx.x];
@@ -63,15 +69,23 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
     const uint2 rg = ranges[tile];
     const uint32_t len = rg.y - rg.x;
     const unsigned long long lt = (1ull << lane) - 1ull;
-    float4* const sa = s_rec[wave][0];
-    float4* const sb = s_rec[wave][1];
-    float4* const sc = s_rec[wave][2];
-    uint8_t* const sidx = s_idx[wave][sub];
+    const uint32_t rbase = wave * kWaveRec;   // the wave's first record (float4 index)
+    float4* const sa = s_rec + rbase;
+    const char* const rec = reinterpret_cast<const char*>(s_rec);
+    const uint16_t* const sidx = s_idx[wave][sub];
+    const uint16_t own_off = (uint16_t)((rbase + lane) * sizeof(float4));
+    const uint16_t sent_off = (uint16_t)((rbase + 64u) * sizeof(float4));
+    constexpr uint32_t kNone = 0xffffffffu;
 
     if (lane == 0) {
         sa[64] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        sb[64] = make_float4(0.0f, 0.0f, INFINITY, 0.0f);
+        sa[kSlots + 64] = make_float4(0.0f, 0.0f, INFINITY, 0.0f);
+        sa[2 * kSlots + 64] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
+    // every list position starts as the sentinel, so a read ahead past the
+    // end of a list always lands on a record of this wave
+#pragma unroll
+    for (int g = 0; g < 4; g++) s_idx[wave][g][lane] = sent_off;
 
     float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
     uint32_t last = 0, nblend = 0, neval = len;
@@ -105,8 +119,8 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
         bool hit[4] = {false, false, false, false};
         if (cur) {
             sa[lane] = make_float4(q0.x, q0.y, -0.5f * q0.z, -q0.w);
-            sb[lane] = make_float4(-0.5f * q1.x, q1.y, q2.w, q1.z);
-            sc[lane] = make_float4(q1.w, q2.x, 0.0f, 0.0f);
+            sa[kSlots + lane] = make_float4(-0.5f * q1.x, q1.y, q2.w, q1.z);
+            sa[2 * kSlots + lane] = make_float4(q1.w, q2.x, 0.0f, 0.0f);
             const BoxTest bt = box_test(q0, q1, q2);
             // exact test for the quadrant, bounding boxes for its sub-quadrants
             if (reaches(bt, bx0, bx0 + 7.0f, by0, by0 + 7.0f)) {
@@ -121,52 +135,66 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
 #pragma unroll
         for (int g = 0; g < 4; g++) {
             const unsigned long long m = __ballot(hit[g]);
-            if (hit[g]) s_idx[wave][g][__popcll(m & lt)] = (uint8_t)lane;
+            if (hit[g]) s_idx[wave][g][__popcll(m & lt)] = own_off;
             cnt[g] = (uint32_t)__popcll(m);
             n_max = cnt[g] > n_max ? cnt[g] : n_max;
         }
         // pad every sub-quadrant list to the longest with the sentinel slot
 #pragma unroll
         for (int g = 0; g < 4; g++)
-            if (lane >= cnt[g] && lane < n_max) s_idx[wave][g][lane] = 64;
+            if (lane >= cnt[g] && lane < n_max) s_idx[wave][g][lane] = sent_off;
         // the wave's own LDS slice: order its writes before its reads
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // walk the lane's sub-quadrant list, predicated rather than branched, with
-        // the next entry's slot and records read one step ahead (every slot
-        // read below was written for this batch: a list position < n_max)
+        // walk the lane's sub-quadrant list two entries per trip, predicated
+        // rather than branched, each entry's records read one entry ahead
         if (n_max > 0 && __ballot(!done) != 0ull) {
-            uint32_t e = sidx[0];
-            uint32_t e_next = sidx[n_max > 1 ? 1 : 0];
-            float4 g = sa[e], c = sb[e];
-            for (uint32_t j = 0; j < n_max; j++) {
-                if (__ballot(!done) == 0ull) break;
-                const float4 gn = sa[e_next], cn = sb[e_next];
-                const uint32_t e_after = sidx[j + 2 < n_max ? j + 2 : 0];
+            uint32_t last_off = kNone, stop_off = kNone;
+            // one (pixel, splat) pair; off: the splat's record offset
+            auto step = [&](const float4& g, const float4& c, const float2& f, uint32_t off) {
                 float alpha;
                 const bool keep = splat_keep(g, c, px, py, alpha) && !done;
                 const float Tn = T * (1.0f - alpha);
                 const bool stop = keep && Tn < kTStop;
                 if (stop) {
                     done = true;
-                    neval = b0 + e + 1u;
+                    stop_off = off;
                 }
                 if (keep && !stop) {
-                    const float4 f = sc[e];
                     const float wgt = alpha * T;
                     cr = __builtin_fmaf(c.w, wgt, cr);
                     cg = __builtin_fmaf(f.x, wgt, cg);
                     cb = __builtin_fmaf(f.y, wgt, cb);
                     T = Tn;
-                    last = b0 + e + 1u;
+                    last_off = off;
                     nblend++;
                 }
-                e = e_next;
-                e_next = e_after;
-                g = gn;
-                c = cn;
+            };
+            auto load = [&](uint32_t off, float4& g, float4& c, float2& f) {
+                g = *reinterpret_cast<const float4*>(rec + off);
+                c = *reinterpret_cast<const float4*>(rec + off + kThird);
+                f = *reinterpret_cast<const float2*>(rec + off + 2 * kThird);
+            };
+            uint32_t eA = sidx[0], eB = sidx[1];
+            float4 gA, cA, gB, cB;
+            float2 fA, fB;
+            load(eA, gA, cA, fA);
+            for (uint32_t j = 0; j < n_max; j += 2) {
+                if (__ballot(!done) == 0ull) break;
+                load(eB, gB, cB, fB);
+                const uint32_t eA2 = sidx[(j + 2) & 63u];
+                step(gA, cA, fA, eA);
+                if (j + 1 >= n_max) break;
+                load(eA2, gA, cA, fA);
+                const uint32_t eB2 = sidx[(j + 3) & 63u];
+                step(gB, cB, fB, eB);
+                eA = eA2;
+                eB = eB2;
             }
+            // list offsets back to positions in the tile's run
+            if (last_off != kNone) last = b0 + (last_off / (uint32_t)sizeof(float4) - rbase) + 1u;
+            if (stop_off != kNone) neval = b0 + (stop_off / (uint32_t)sizeof(float4) - rbase) + 1u;
         }
         // every lane is past its reads before the next batch overwrites the slice
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
