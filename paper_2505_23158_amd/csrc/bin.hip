@@ -39,12 +39,13 @@ namespace {
 // One block: exclusive scans of the two per-chunk totals the projection
 // wrote (one chunk per 64 actives): tiles -> chunk instance offsets and M;
 // actives with a tile -> chunk offsets of their compaction.  The totals are
-// read as coalesced uint4 runs, kChunkScanGroup tiles of 4 x 1024 at a time,
-// all loads issued before the first tile is scanned; each tile is one block
-// scan of both totals (wave scans + wave totals in LDS) on top of the carries.
+// read as coalesced uint4 runs, kChunkScanGroup tiles of 4 x 1024 chunks at
+// a time, all loads in flight together; the wave scans of the group's
+// 2 x kChunkScanGroup per-thread sums are interleaved and share one pair of
+// barriers, and the tiles are chained by carries.
 constexpr int kChunkScanThreads = 1024;
 constexpr int kChunkScanTile = 4 * kChunkScanThreads;
-constexpr int kChunkScanGroup = 8;
+constexpr int kChunkScanGroup = 4;
 
 __device__ __forceinline__ uint4 load4(const uint32_t* __restrict__ p, uint32_t c, uint32_t nc)
 {
@@ -63,65 +64,67 @@ __device__ __forceinline__ void store4(uint32_t* __restrict__ p, uint32_t c, uin
     }
 }
 
-__device__ __forceinline__ uint4 excl4(uint32_t e0, uint4 v)
-{
-    return make_uint4(e0, e0 + v.x, e0 + v.x + v.y, e0 + v.x + v.y + v.z);
-}
-
 __global__ __launch_bounds__(kChunkScanThreads) void k_chunk_scan(FrameInfo* info, uint32_t* __restrict__ csum,
                                                                  uint32_t* __restrict__ cvis,
                                                                  const uint32_t* __restrict__ count, uint32_t cap,
                                                                  uint64_t max_instances)
 {
-    __shared__ uint32_t s_w[2][kChunkScanThreads / 64];
+    constexpr int G = kChunkScanGroup, NW = kChunkScanThreads / 64;
+    __shared__ uint32_t s_w[2 * G][NW];
     const uint32_t n = min(*count, cap);
     const uint32_t nc = (n + kProjChunk - 1) / kProjChunk;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     unsigned long long carry = 0;
     uint32_t vcarry = 0;
-    for (uint32_t g0 = 0; g0 < nc; g0 += kChunkScanTile * kChunkScanGroup) {
-        uint4 v[kChunkScanGroup], w[kChunkScanGroup];
+    for (uint32_t g0 = 0; g0 < nc; g0 += kChunkScanTile * G) {
+        uint4 v[2 * G];   // [0, G) tile totals, [G, 2G) counts of actives with a tile
 #pragma unroll
-        for (int t = 0; t < kChunkScanGroup; t++) {
+        for (int t = 0; t < G; t++) {
             const uint32_t c = g0 + t * kChunkScanTile + 4 * tid;
             v[t] = load4(csum, c, nc);
-            w[t] = load4(cvis, c, nc);
+            v[G + t] = load4(cvis, c, nc);
         }
+        uint32_t own[2 * G], inc[2 * G];
 #pragma unroll
-        for (int t = 0; t < kChunkScanGroup; t++) {
-            const uint32_t c = g0 + t * kChunkScanTile + 4 * tid;
-            if (g0 + t * kChunkScanTile >= nc) break;   // block-uniform
-            const uint32_t own = (v[t].x + v[t].y) + (v[t].z + v[t].w);
-            const uint32_t vown = (w[t].x + w[t].y) + (w[t].z + w[t].w);
-            uint32_t inc = own, vinc = vown;
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t u = __shfl_up(inc, o), vu = __shfl_up(vinc, o);
-                if ((int)lane >= o) {
-                    inc += u;
-                    vinc += vu;
-                }
+        for (int k = 0; k < 2 * G; k++) inc[k] = own[k] = (v[k].x + v[k].y) + (v[k].z + v[k].w);
+        for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+            for (int k = 0; k < 2 * G; k++) {
+                const uint32_t u = __shfl_up(inc[k], o);
+                if ((int)lane >= o) inc[k] += u;
             }
-            if (lane == 63) {
-                s_w[0][wave] = inc;
-                s_w[1][wave] = vinc;
-            }
-            __syncthreads();
+        }
+        if (lane == 63)
+#pragma unroll
+            for (int k = 0; k < 2 * G; k++) s_w[k][wave] = inc[k];
+        __syncthreads();
+        unsigned long long ct = carry;
+        uint32_t cv = vcarry;
+#pragma unroll
+        for (int t = 0; t < G; t++) {
             uint32_t before = 0, total = 0, vbefore = 0, vtotal = 0;
 #pragma unroll
-            for (int k = 0; k < kChunkScanThreads / 64; k++) {
-                const uint32_t x = s_w[0][k], y = s_w[1][k];
+            for (int k = 0; k < NW; k++) {
+                const uint32_t x = s_w[t][k], y = s_w[G + t][k];
                 before += (uint32_t)k < wave ? x : 0u;
                 total += x;
                 vbefore += (uint32_t)k < wave ? y : 0u;
                 vtotal += y;
             }
             // offsets only matter when M fits the instance capacity (< 2^32)
-            store4(csum, c, nc, excl4((uint32_t)carry + before + inc - own, v[t]));
-            store4(cvis, c, nc, excl4(vcarry + vbefore + vinc - vown, w[t]));
-            carry += total;
-            vcarry += vtotal;
-            __syncthreads();   // s_w is rewritten by the next tile
+            const uint32_t c = g0 + t * kChunkScanTile + 4 * tid;
+            const uint32_t e0 = (uint32_t)ct + before + inc[t] - own[t];
+            const uint32_t f0 = cv + vbefore + inc[G + t] - own[G + t];
+            store4(csum, c, nc, make_uint4(e0, e0 + v[t].x, e0 + v[t].x + v[t].y, e0 + v[t].x + v[t].y + v[t].z));
+            store4(cvis, c, nc,
+                   make_uint4(f0, f0 + v[G + t].x, f0 + v[G + t].x + v[G + t].y,
+                              f0 + v[G + t].x + v[G + t].y + v[G + t].z));
+            ct += total;
+            cv += vtotal;
         }
+        carry = ct;
+        vcarry = cv;
+        __syncthreads();   // s_w is rewritten by the next group
     }
     if (tid == 0) {
         info->n_instances = carry;

@@ -27,7 +27,8 @@ namespace lodge {
 
 namespace {
 
-constexpr int kSortThreads = 1024;
+constexpr int kSortThreads = 512;
+constexpr int kSortLds = 8192;   // keys of LDS per block (64 KB): two blocks per compute unit
 
 // Indices come from the emission pass; one outside [0, cap) would be a
 // binning bug, so it sorts last instead of being dereferenced.
@@ -210,7 +211,7 @@ __device__ __forceinline__ uint32_t rank_in(const uint32_t* __restrict__ b, uint
     return lo;
 }
 
-// A run longer than kSortLarge: kSortLarge-key chunks sorted in LDS, then
+// A run longer than kSortLds: kSortLds-key chunks sorted in LDS, then
 // merge passes in global memory (ping-pong with scratch) where each key
 // finds its output slot by binary search in the sibling run.
 __device__ __forceinline__ void sort_huge_run(unsigned long long* s, const float* __restrict__ proj,
@@ -219,10 +220,10 @@ __device__ __forceinline__ void sort_huge_run(unsigned long long* s, const float
 {
     uint32_t* src = run;
     uint32_t* dst = tmp;
-    for (uint32_t c0 = 0; c0 < n; c0 += kSortLarge)
-        sort_run<kSortThreads, kSortLarge>(s, proj, src + c0, min((uint32_t)kSortLarge, n - c0), cap);
+    for (uint32_t c0 = 0; c0 < n; c0 += kSortLds)
+        sort_run<kSortThreads, kSortLds>(s, proj, src + c0, min((uint32_t)kSortLds, n - c0), cap);
     // merge passes: run pairs [i, i + w) and [i + w, i + 2w)
-    for (uint32_t w = kSortLarge; w < n; w <<= 1) {
+    for (uint32_t w = kSortLds; w < n; w <<= 1) {
         for (uint32_t k = threadIdx.x; k < n; k += kSortThreads) {
             const uint32_t pair = k / (2 * w) * (2 * w);
             const uint32_t mid = min(pair + w, n), end = min(pair + 2 * w, n);
@@ -241,14 +242,16 @@ __device__ __forceinline__ void sort_huge_run(unsigned long long* s, const float
     __syncthreads();
 }
 
-// All runs in one launch.  Work items, longest first, are handed out by a
-// counter (one atomic per item, not per key):
-//   [0, n_large)   one queued run in (2048, 16384]: in registers, 1024 x 4
-//                  or 1024 x 8 keys, else the LDS network;
-//   n_huge items   one run > 16384;
-//   n_mid / 4      four queued runs in (256, 2048], one per 256 threads
+// All runs in one launch of 512-thread blocks with 64 KB of LDS, two per
+// compute unit.  Work items, longest first, are handed out by a counter
+// (one atomic per item, not per key):
+//   [0, n_large)   one queued run in (2048, 16384]: up to 4096 keys in
+//                  registers (512 x 8), up to 8192 in the LDS network,
+//                  longer by LDS chunks and merge passes;
+//   n_huge items   one run > 16384, by LDS chunks and merge passes;
+//   n_mid / 2      two queued runs in (256, 2048], one per 256 threads
 //                  (2048-key networks in step: the block barriers match);
-//   T / 16         sixteen tiles, one per wave, sorted if 1 < n <= 256.
+//   T / 8          eight tiles, one per wave, sorted if 1 < n <= 256.
 // Every block leaves once the items run out.
 __global__ __launch_bounds__(kSortThreads) void k_sort(const FrameParams* __restrict__ fp, FrameInfo* info,
                                                        const uint2* __restrict__ ranges,
@@ -256,34 +259,34 @@ __global__ __launch_bounds__(kSortThreads) void k_sort(const FrameParams* __rest
                                                        const float* __restrict__ depth, uint32_t* __restrict__ sorted,
                                                        uint32_t* __restrict__ scratch, uint32_t cap)
 {
-    __shared__ unsigned long long s[kSortLarge];
+    static_assert(2 * kSortMid <= kSortLds && 2 * 2 * kSortSmall <= kSortLds, "LDS per item");
+    constexpr uint32_t kWaves = kSortThreads / 64, kGroups = kSortThreads / 256;
+    __shared__ unsigned long long s[kSortLds];
     __shared__ uint32_t s_item;
     const uint32_t T = (uint32_t)(fp->TX * fp->TY);
     const uint32_t nl = info->n_large, nh = info->n_huge, nm = info->n_mid;
-    const uint32_t i_huge = nl, i_mid = i_huge + nh, i_wave = i_mid + (nm + 3) / 4, n_items = i_wave + (T + 15) / 16;
+    const uint32_t i_huge = nl, i_mid = i_huge + nh, i_wave = i_mid + (nm + kGroups - 1) / kGroups,
+                   n_items = i_wave + (T + kWaves - 1) / kWaves;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(&info->sort_next, 1u);
         __syncthreads();
         const uint32_t i = s_item;
         __syncthreads();
         if (i >= n_items) break;
-        if (i < i_huge) {
-            const uint2 r = ranges[queues[i]];
+        if (i < i_mid) {
+            const uint2 r = ranges[i < i_huge ? queues[i] : queues[T + (i - i_huge)]];
             const uint32_t n = r.y - r.x;
-            if (n <= (uint32_t)kSortMid) sort_run_regs<kSortThreads, kSortMid / kSortThreads, 12>(s, depth, sorted + r.x, n, cap);
-            else if (n <= 2u * kSortMid)
-                sort_run_regs<kSortThreads, 2 * kSortMid / kSortThreads, 13>(s, depth, sorted + r.x, n, cap);
-            else sort_run<kSortThreads, kSortLarge>(s, depth, sorted + r.x, n, cap);
-        } else if (i < i_mid) {
-            const uint2 r = ranges[queues[T + (i - i_huge)]];
-            sort_huge_run(s, depth, sorted + r.x, scratch + r.x, r.y - r.x, cap);
+            if (n <= (uint32_t)kSortMid)
+                sort_run_regs<kSortThreads, kSortMid / kSortThreads, 12>(s, depth, sorted + r.x, n, cap);
+            else if (n <= (uint32_t)kSortLds) sort_run<kSortThreads, kSortLds>(s, depth, sorted + r.x, n, cap);
+            else sort_huge_run(s, depth, sorted + r.x, scratch + r.x, n, cap);
         } else if (i < i_wave) {
-            const uint32_t g = threadIdx.x / 256, q = 4 * (i - i_mid) + g;
+            const uint32_t g = threadIdx.x / 256, q = kGroups * (i - i_mid) + g;
             uint2 r = make_uint2(0u, 0u);   // an empty run still steps through the network
             if (q < nm) r = ranges[queues[2 * T + q]];
             sort_run_regs<256, kSortSmall / 256, 11>(s + g * 2 * kSortSmall, depth, sorted + r.x, r.y - r.x, cap);
         } else {
-            const uint32_t t = 16 * (i - i_wave) + threadIdx.x / 64;
+            const uint32_t t = kWaves * (i - i_wave) + threadIdx.x / 64;
             const uint2 r = t < T ? ranges[t] : make_uint2(0u, 0u);
             const uint32_t n = r.y - r.x;
             uint32_t* run = sorted + r.x;
@@ -300,7 +303,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort(const FrameParams* __rest
 
 hipError_t launch_sort(const Views& v, hipStream_t st)
 {
-    // one 128 KB-LDS block per compute unit
+    // two 64 KB-LDS blocks per compute unit
     static thread_local int dev_cached = -1, cus = 0;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -309,7 +312,7 @@ hipError_t launch_sort(const Views& v, hipStream_t st)
         if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
         dev_cached = dev;
     }
-    k_sort<<<std::max(1, cus), kSortThreads, 0, st>>>(v.params, v.info, v.ranges, v.large, v.depth, v.sorted,
+    k_sort<<<std::max(1, 2 * cus), kSortThreads, 0, st>>>(v.params, v.info, v.ranges, v.large, v.depth, v.sorted,
                                                       reinterpret_cast<uint32_t*>(v.temp), v.max_active);
     return hipGetLastError();
 }
