@@ -41,6 +41,7 @@ namespace {
 constexpr uint32_t kSlots = 65;
 constexpr uint32_t kWaveRec = 3 * kSlots;
 constexpr uint32_t kThird = kSlots * sizeof(float4);   // bytes between the thirds
+constexpr uint32_t kListLen = 68;
 
 __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict__ fp,
                                                    const uint2* __restrict__ ranges,
@@ -54,7 +55,9 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
     // +inf): it pads the shorter sub-quadrant lists to the longest.  The
     // lists hold LDS byte offsets (from s_rec) of the first third of a slot.
     __shared__ float4 s_rec[4 * kWaveRec];
-    __shared__ uint16_t s_idx[4][4][64];   // per wave and sub-quadrant
+    // per wave and sub-quadrant; 4 entries past the 64 a batch can fill,
+    // always the sentinel, for the reads one trip ahead
+    __shared__ uint16_t s_idx[4][4][kListLen];
 
     const int32_t W = fp->cam.width, H = fp->cam.height, TX = fp->TX;
     const uint32_t tile = order[blockIdx.x];
@@ -85,11 +88,15 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
     // every list position starts as the sentinel, so a read ahead past the
     // end of a list always lands on a record of this wave
 #pragma unroll
-    for (int g = 0; g < 4; g++) s_idx[wave][g][lane] = sent_off;
+    for (int g = 0; g < 4; g++) {
+        s_idx[wave][g][lane] = sent_off;
+        if (lane < kListLen - 64) s_idx[wave][g][64 + lane] = sent_off;
+    }
 
     float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
     uint32_t last = 0, nblend = 0, neval = len;
-    bool done = !inside;
+    // the alpha a splat needs to count: +inf once the pixel is done (stopped, or outside the image)
+    float amin = inside ? kAlphaMin : INFINITY;
 
     // software pipeline: records of batch b in r*, of batch b + 1 in flight,
     // the list index of batch b + 2 in flight
@@ -104,7 +111,7 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
     uint32_t a_next = 64 + lane < len ? sorted[rg.x + 64 + lane] : 0u;
 
     for (uint32_t b0 = 0; b0 < len; b0 += 64) {
-        if (__ballot(!done) == 0ull) break;
+        if (__ballot(amin < INFINITY) == 0ull) break;
         const uint32_t k = b0 + lane;
         const bool cur = k < len;
         const float4 q0 = r0, q1 = r1, q2 = r2;
@@ -149,16 +156,16 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         // walk the lane's sub-quadrant list two entries per trip, predicated
         // rather than branched, each entry's records read one entry ahead
-        if (n_max > 0 && __ballot(!done) != 0ull) {
+        if (n_max > 0 && __ballot(amin < INFINITY) != 0ull) {
             uint32_t last_off = kNone, stop_off = kNone;
             // one (pixel, splat) pair; off: the splat's record offset
             auto step = [&](const float4& g, const float4& c, const float2& f, uint32_t off) {
                 float alpha;
-                const bool keep = splat_keep(g, c, px, py, alpha) && !done;
+                const bool keep = splat_keep(g, c, px, py, amin, alpha);
                 const float Tn = T * (1.0f - alpha);
                 const bool stop = keep && Tn < kTStop;
                 if (stop) {
-                    done = true;
+                    amin = INFINITY;
                     stop_off = off;
                 }
                 if (keep && !stop) {
@@ -181,13 +188,14 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
             float2 fA, fB;
             load(eA, gA, cA, fA);
             for (uint32_t j = 0; j < n_max; j += 2) {
-                if (__ballot(!done) == 0ull) break;
+                if (__ballot(amin < INFINITY) == 0ull) break;
+                const uint16_t* const p = sidx + j;   // p[2], p[3] < kListLen: j <= 63
                 load(eB, gB, cB, fB);
-                const uint32_t eA2 = sidx[(j + 2) & 63u];
+                const uint32_t eA2 = p[2];
                 step(gA, cA, fA, eA);
                 if (j + 1 >= n_max) break;
                 load(eA2, gA, cA, fA);
-                const uint32_t eB2 = sidx[(j + 3) & 63u];
+                const uint32_t eB2 = p[3];
                 step(gB, cB, fB, eB);
                 eA = eA2;
                 eB = eB2;
@@ -215,7 +223,7 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
     // per-wave counters, one slot per (tile, quadrant)
     unsigned long long ev = neval;
     uint32_t bl = nblend;
-    const uint32_t stopped = (uint32_t)__popcll(__ballot(inside && done));
+    const uint32_t stopped = (uint32_t)__popcll(__ballot(inside && !(amin < INFINITY)));
     for (int off = 32; off > 0; off >>= 1) {
         ev += __shfl_xor(ev, off);
         bl += __shfl_xor(bl, off);

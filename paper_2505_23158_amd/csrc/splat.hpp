@@ -54,13 +54,16 @@ __device__ __forceinline__ float splat_alpha(const float4& geo, const float4& co
 
 // The same decision as splat_alpha without branches: alpha (clamped at
 // kAlphaMax) and whether the pair counts; exp is evaluated either way.
-__device__ __forceinline__ bool splat_keep(const float4& geo, const float4& col, float px, float py, float& alpha)
+// amin is kAlphaMin, or +inf for a pixel that takes no more splats (every
+// finite alpha is then below it).
+__device__ __forceinline__ bool splat_keep(const float4& geo, const float4& col, float px, float py, float amin,
+                                           float& alpha)
 {
     float dx, dy;
     const float power = splat_power(geo, col, px, py, dx, dy);
     const float og = col.y * __expf(power);
     alpha = og > kAlphaMax ? kAlphaMax : og;
-    return !(power > 0.0f || power < col.z) && !(alpha < kAlphaMin);
+    return !(power > 0.0f || power < col.z) && !(alpha < amin);
 }
 
 // Culling of a splat against a box of pixel centres, shared by the
