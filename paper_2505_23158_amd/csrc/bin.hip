@@ -2,13 +2,14 @@
 // projected Gaussian is assigned to every 16 x 16 tile its rectangle
 // overlaps; each tile's Gaussians are then depth sorted).
 //
-// A counting sort by tile built without device-scope atomics (which are
-// slow on the die-spanning L2 of this part): block-local LDS histograms,
-// coalesced column passes over a [block][tile] matrix, and LDS ranks.
+// A counting sort by tile: block-local LDS histograms and LDS ranks, with
+// device-scope atomics only where they are few (one per binning block and
+// tile it touches, about 200 blocks x a few hundred tiles at 1080p).
 //
 //   k_chunk_scan  one block: exclusive scans of the per-chunk totals the
 //                 projection wrote (tiles; actives with a tile) -> chunk
-//                 offsets, the instance count M and the binned count.
+//                 offsets, the instance count M and the binned count; clears
+//                 the tile totals.
 //   k_inst_off    per chunk (one wave): scan of the tile counts + chunk
 //                 offset -> exclusive instance offsets; the actives with a
 //                 tile are compacted in index order as (first instance,
@@ -18,18 +19,17 @@
 //                 Gaussian by binary search over an LDS window of the
 //                 compacted offsets (at most C + 1 of them, since every
 //                 compacted active has an instance), writes (tile, index)
-//                 pairs and its tile histogram (packed 16-bit LDS counters)
-//                 as row b of the matrix.
-//   k_col_sum     per tile: total count over the blocks (16 tiles x 16 row
-//                 groups per block, row reads contiguous across tiles).
+//                 pairs and counts them per tile (packed 16-bit LDS
+//                 counters); for each tile it touched, one atomic add of its
+//                 count to the tile total returns the block's first slot
+//                 inside the tile's run (row b of the [block][tile] matrix).
 //   k_tile_scan   one block: exclusive scan of the tile totals -> [start,
 //                 end) per tile, a longest-first processing order, the
 //                 queues of tiles too long for the small LDS sort.
-//   k_col_offset  per tile: running offsets down the column -> each block's
-//                 first slot in each tile's run.
-//   k_scatter     block b re-reads its pairs and places each at its block's
-//                 offset plus an LDS rank.  Order inside a run is arbitrary;
-//                 the per-tile sort restores (depth bits, active index).
+//   k_scatter     block b re-reads its pairs and places each at its tile's
+//                 start + its block's slot + an LDS rank.  Order inside a run
+//                 is arbitrary; the per-tile sort restores (depth bits,
+//                 active index).
 #include "lodge_internal.hpp"
 
 namespace lodge {
@@ -64,16 +64,20 @@ __device__ __forceinline__ void store4(uint32_t* __restrict__ p, uint32_t c, uin
     }
 }
 
-__global__ __launch_bounds__(kChunkScanThreads) void k_chunk_scan(FrameInfo* info, uint32_t* __restrict__ csum,
+__global__ __launch_bounds__(kChunkScanThreads) void k_chunk_scan(const FrameParams* fp, FrameInfo* info,
+                                                                 uint32_t* __restrict__ csum,
                                                                  uint32_t* __restrict__ cvis,
                                                                  const uint32_t* __restrict__ count, uint32_t cap,
-                                                                 uint64_t max_instances)
+                                                                 uint32_t* __restrict__ tcount, uint64_t max_instances)
 {
     constexpr int G = kChunkScanGroup, NW = kChunkScanThreads / 64;
     __shared__ uint32_t s_w[2 * G][NW];
     const uint32_t n = min(*count, cap);
     const uint32_t nc = (n + kProjChunk - 1) / kProjChunk;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // tile totals: accumulated by the binning blocks' atomics
+    const uint32_t T = (uint32_t)(fp->TX * fp->TY);
+    for (uint32_t t = tid; t < T; t += kChunkScanThreads) tcount[t] = 0;
     unsigned long long carry = 0;
     uint32_t vcarry = 0;
     for (uint32_t g0 = 0; g0 < nc; g0 += kChunkScanTile * G) {
@@ -209,7 +213,8 @@ __global__ __launch_bounds__(kBinThreads) void k_emit_hist(const FrameParams* fp
                                                            const uint32_t* __restrict__ vis_id,
                                                            const uint32_t* __restrict__ bstart,
                                                            const uint2* __restrict__ rect, uint2* __restrict__ inst,
-                                                           uint32_t* __restrict__ hist, uint64_t max_instances)
+                                                           uint32_t* __restrict__ hist, uint32_t* __restrict__ tcount,
+                                                           uint64_t max_instances)
 {
     constexpr int kPer = kBinChunk / kBinThreads;   // instances per thread, processed together
     // every compacted active holds at least one instance, so a block's
@@ -266,70 +271,14 @@ __global__ __launch_bounds__(kBinThreads) void k_emit_hist(const FrameParams* fp
             hist_inc(s_hist, tile);
         }
         __syncthreads();
+        // the block's first slot in each touched tile's run (the order of
+        // blocks inside a run is that of the atomics; the sort restores it)
         uint32_t* row_out = hist + (size_t)b * T;
-        for (uint32_t t = threadIdx.x; t < T; t += kBinThreads) row_out[t] = hist_get(s_hist, t);
+        for (uint32_t t = threadIdx.x; t < T; t += kBinThreads) {
+            const uint32_t c = hist_get(s_hist, t);
+            if (c != 0u) row_out[t] = atomicAdd(&tcount[t], c);
+        }
         __syncthreads();
-    }
-}
-
-// Column passes over the [B][T] matrix: a block takes 16 tiles x 16 groups
-// of consecutive rows, so row reads are contiguous across the tile lanes and
-// every tile's column is walked by 16 threads at once.
-constexpr int kColTiles = 16, kColGroups = 16;
-
-// tile totals
-__global__ __launch_bounds__(256) void k_col_sum(const FrameParams* fp, const FrameInfo* info,
-                                                 const uint32_t* __restrict__ hist, uint32_t* __restrict__ tcount,
-                                                 uint64_t max_instances)
-{
-    __shared__ uint32_t s_part[kColGroups][kColTiles];
-    const unsigned long long M = info->n_instances;
-    const uint32_t T = (uint32_t)(fp->TX * fp->TY);
-    const uint32_t tl = threadIdx.x % kColTiles, g = threadIdx.x / kColTiles;
-    const uint32_t t = blockIdx.x * kColTiles + tl;
-    uint32_t s = 0;
-    if (t < T && M <= max_instances) {
-        const uint32_t B = blocks_of(M);
-        const uint32_t R = (B + kColGroups - 1) / kColGroups;
-        const uint32_t b0 = g * R, b1 = min(B, b0 + R);
-        for (uint32_t b = b0; b < b1; b++) s += hist[(size_t)b * T + t];
-    }
-    s_part[g][tl] = s;
-    __syncthreads();
-    if (g == 0 && t < T) {
-        uint32_t tot = 0;
-        for (int k = 0; k < kColGroups; k++) tot += s_part[k][tl];
-        tcount[t] = tot;
-    }
-}
-
-// per-(block, tile) first slot: tile start + running count down the column
-__global__ __launch_bounds__(256) void k_col_offset(const FrameParams* fp, const FrameInfo* info,
-                                                    const uint2* __restrict__ ranges, uint32_t* __restrict__ hist,
-                                                    uint64_t max_instances)
-{
-    __shared__ uint32_t s_part[kColGroups][kColTiles];
-    const unsigned long long M = info->n_instances;
-    if (M == 0 || M > max_instances) return;
-    const uint32_t T = (uint32_t)(fp->TX * fp->TY);
-    const uint32_t tl = threadIdx.x % kColTiles, g = threadIdx.x / kColTiles;
-    const uint32_t t = blockIdx.x * kColTiles + tl;
-    const uint32_t B = blocks_of(M);
-    const uint32_t R = (B + kColGroups - 1) / kColGroups;
-    const uint32_t b0 = min(B, g * R), b1 = min(B, b0 + R);
-    uint32_t s = 0;
-    if (t < T)
-        for (uint32_t b = b0; b < b1; b++) s += hist[(size_t)b * T + t];
-    s_part[g][tl] = s;
-    __syncthreads();
-    if (t >= T) return;
-    uint32_t run = ranges[t].x;
-    for (uint32_t k = 0; k < g; k++) run += s_part[k][tl];
-    for (uint32_t b = b0; b < b1; b++) {
-        const size_t i = (size_t)b * T + t;
-        const uint32_t c = hist[i];
-        hist[i] = run;
-        run += c;
     }
 }
 
@@ -455,6 +404,7 @@ __global__ __launch_bounds__(kTilesThreads) void k_tile_scan(const FrameParams* 
 __global__ __launch_bounds__(kBinThreads) void k_scatter(const FrameParams* fp, const FrameInfo* info,
                                                          const uint2* __restrict__ inst,
                                                          const uint32_t* __restrict__ hist,
+                                                         const uint2* __restrict__ ranges,
                                                          uint32_t* __restrict__ sorted, uint64_t max_instances)
 {
     __shared__ uint32_t s_rank[kMaxTiles / 2];
@@ -470,7 +420,7 @@ __global__ __launch_bounds__(kBinThreads) void k_scatter(const FrameParams* fp, 
         const uint32_t* row = hist + (size_t)b * T;
         for (uint32_t j = j0 + threadIdx.x; j < j1; j += kBinThreads) {
             const uint2 e = inst[j];
-            const uint32_t slot = row[e.x] + hist_inc(s_rank, e.x);
+            const uint32_t slot = ranges[e.x].x + row[e.x] + hist_inc(s_rank, e.x);
             if (slot < max_instances) sorted[slot] = e.y;
         }
         __syncthreads();
@@ -481,20 +431,17 @@ __global__ __launch_bounds__(kBinThreads) void k_scatter(const FrameParams* fp, 
 
 hipError_t launch_bin(const Views& v, const lodge_selection& sel, hipStream_t st)
 {
-    k_chunk_scan<<<1, kChunkScanThreads, 0, st>>>(v.info, v.chunk_sum, v.chunk_vis, sel.count, sel.cap,
-                                                  v.max_instances);
+    k_chunk_scan<<<1, kChunkScanThreads, 0, st>>>(v.params, v.info, v.chunk_sum, v.chunk_vis, sel.count, sel.cap,
+                                                  v.tcount, v.max_instances);
     const uint32_t cg = std::max<uint32_t>(1, std::min<uint32_t>(4096, (v.max_active + 255) / 256));
     k_inst_off<<<cg, 256, 0, st>>>(v.info, v.vtiles, v.chunk_sum, v.chunk_vis, sel.count, sel.cap, v.vis_off,
                                    v.vis_id, v.bstart, v.max_instances);
     const uint32_t bmax = std::max<uint32_t>(1, (uint32_t)((v.max_instances + kBinChunk - 1) / kBinChunk));
     const uint32_t grid = std::min<uint32_t>(bmax, 1024);
     k_emit_hist<<<grid, kBinThreads, 0, st>>>(v.params, v.info, v.vis_off, v.vis_id, v.bstart, v.rect, v.inst,
-                                              v.hist, v.max_instances);
-    const uint32_t tb = (v.lay.T + kColTiles - 1) / kColTiles;
-    k_col_sum<<<tb, 256, 0, st>>>(v.params, v.info, v.hist, v.tcount, v.max_instances);
+                                              v.hist, v.tcount, v.max_instances);
     k_tile_scan<<<1, kTilesThreads, 0, st>>>(v.params, v.info, v.tcount, v.ranges, v.order, v.large);
-    k_col_offset<<<tb, 256, 0, st>>>(v.params, v.info, v.ranges, v.hist, v.max_instances);
-    k_scatter<<<grid, kBinThreads, 0, st>>>(v.params, v.info, v.inst, v.hist, v.sorted, v.max_instances);
+    k_scatter<<<grid, kBinThreads, 0, st>>>(v.params, v.info, v.inst, v.hist, v.ranges, v.sorted, v.max_instances);
     return hipGetLastError();
 }
 

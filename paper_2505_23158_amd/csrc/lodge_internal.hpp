@@ -83,6 +83,16 @@ struct FrameInfo {
 
 enum : uint32_t { kOvfSelect = 1u, kOvfInstances = 2u, kOvfTile = 4u };
 
+// Element at byte offset off of a plane whose base every lane holds alike:
+// the base stays in scalar registers and only the 32-bit offset is a vector
+// operand (no 64-bit address arithmetic per load).
+typedef const __attribute__((address_space(1))) char gchar;
+typedef const __attribute__((address_space(1))) float gfloat;
+__device__ __forceinline__ float ld_plane(const float* plane, uint32_t off)
+{
+    return *(const gfloat*)((const gchar*)plane + off);
+}
+
 // Field-by-field store of a camera held in kernel arguments (a struct
 // assignment would stage the argument through private memory).
 __device__ __forceinline__ void store_camera(lodge_camera* __restrict__ d, const lodge_camera& c)

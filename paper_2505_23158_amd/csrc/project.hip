@@ -73,13 +73,7 @@ __device__ __forceinline__ const float* uniform_ptr(const float* p)
     return reinterpret_cast<const float*>(((unsigned long long)hi << 32) | lo);
 }
 
-// Element at byte offset off of a plane: scalar base + 32-bit lane offset.
-typedef const __attribute__((address_space(1))) char gchar;
-typedef const __attribute__((address_space(1))) float gfloat;
-__device__ __forceinline__ float ld(const float* plane, uint32_t off)
-{
-    return *(gfloat*)((gchar*)plane + off);
-}
+__device__ __forceinline__ float ld(const float* plane, uint32_t off) { return ld_plane(plane, off); }
 
 __device__ __forceinline__ int level_index(const LevelsArg& lv, uint32_t g)
 {

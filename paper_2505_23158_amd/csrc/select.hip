@@ -158,19 +158,33 @@ __global__ __launch_bounds__(kSelBlock) void k_select(LevelsArg lv, const FrameP
     const float co[3] = {fp->co[0], fp->co[1], fp->co[2]};
     const float lof = fp->lo_f[l], hif = fp->hi_f[l], loo = fp->lo_o[l], hio = fp->hi_o[l];
 
-    // all loads first, then the tests: block-uniform plane bases, 32-bit lane
-    // offsets, indices clamped into the level so no load sits in a branch
+    // all loads first, then the tests: block-uniform plane bases (scalar
+    // registers) plus 32-bit lane byte offsets (a level holds fewer than 2^30
+    // Gaussians), so no address is formed in 64-bit vector arithmetic; in the
+    // level's last, partial tile the indices are clamped into the level so no
+    // load sits in a branch
     float mx[kSelItems], my[kSelItems], mz[kSelItems];
     if (!all && n > 0) {
         const float* __restrict__ px = L.mean;
         const float* __restrict__ py = L.mean + n;
         const float* __restrict__ pz = L.mean + 2 * (size_t)n;
+        if (i0 + (uint32_t)kSelTile <= n) {
+            const uint32_t o0 = (i0 + tid) * 4u;
 #pragma unroll
-        for (int r = 0; r < kSelItems; r++) {
-            const uint32_t i = min(i0 + (uint32_t)r * kSelBlock + tid, n - 1);
-            mx[r] = px[i];
-            my[r] = py[i];
-            mz[r] = pz[i];
+            for (int r = 0; r < kSelItems; r++) {
+                const uint32_t o = o0 + (uint32_t)r * (kSelBlock * 4u);
+                mx[r] = ld_plane(px, o);
+                my[r] = ld_plane(py, o);
+                mz[r] = ld_plane(pz, o);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < kSelItems; r++) {
+                const uint32_t o = min(i0 + (uint32_t)r * kSelBlock + tid, n - 1) * 4u;
+                mx[r] = ld_plane(px, o);
+                my[r] = ld_plane(py, o);
+                mz[r] = ld_plane(pz, o);
+            }
         }
     } else {
 #pragma unroll

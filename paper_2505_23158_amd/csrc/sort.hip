@@ -75,9 +75,13 @@ __device__ __forceinline__ void sort_run(unsigned long long* s, const float* __r
     __syncthreads();
 }
 
-// 32-bit value of lane (lane ^ D) of the wave.  Distances 1 and 2 are quad
-// permutes and 4 and 8 two row shifts plus a select (DPP: register-speed, no
-// LDS round trip); 16 swizzles within 32 lanes; 32 goes through bpermute.
+// 32-bit value of lane (lane ^ D) of the wave, without an LDS round trip.
+// Distances 1 and 2 are quad permutes and 4 and 8 two row shifts plus a
+// select (DPP); 16 and 32 are gfx950 lane-swaps of the value with a copy of
+// itself (permlane16_swap trades rows 1 and 3 of the first operand with rows
+// 0 and 2 of the second, permlane32_swap the upper half of the first with the
+// lower half of the second), after which the partner's value sits in the
+// second result below the swapped boundary and in the first above it.
 template <int D>
 __device__ __forceinline__ uint32_t xor_lane(uint32_t v)
 {
@@ -91,9 +95,12 @@ __device__ __forceinline__ uint32_t xor_lane(uint32_t v)
         const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x110 + D, 0xF, 0xF, false);
         return (__lane_id() & D) ? dn : up;
     } else if constexpr (D == 16) {
-        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);   // bit mode: xor 16 within 32 lanes
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (__lane_id() & 16) ? r[0] : r[1];
     } else {
-        return (uint32_t)__shfl_xor((int)v, D);
+        static_assert(D == 32, "lane distance");
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (__lane_id() & 32) ? r[0] : r[1];
     }
 }
 
