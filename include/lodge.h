@@ -223,7 +223,7 @@ typedef struct {
  *   n_contrib [H][W]     1 + position (in its tile's sorted list) of the last
  *                        blended Gaussian, 0 if none
  * Stages: project (Eq. 3 filter, EWA, 2-D filter, SH, 3-sigma tile rect,
- * depth), per-tile counting, instance emission, per-tile LDS sort on
+ * depth), per-tile counting, instance emission, per-tile on-chip sort on
  * (depth bits, active index), compositing (Eq. 1; alpha = min(0.99, o G),
  * entries with alpha < 1/255 skipped, stop before T(1 - alpha) < 1e-4).
  * opts may be NULL (s2d = 0.3, compensate = 1). */
@@ -243,8 +243,8 @@ typedef struct {
     uint32_t overflow;       /* bit 0 selection cap, bit 1 instance cap */
     int32_t f, o;            /* chunk pair (-1 when unused) */
     float t;                 /* Eq. 4 weight of the nearest chunk */
-    uint32_t n_long;         /* tiles whose list took a 1024-thread LDS sort (2048 < length <= 16384) */
-    uint32_t n_merge;        /* tiles whose list took the chunked merge sort */
+    uint32_t n_long;         /* tiles whose list is longer than 2048 and at most 16384 */
+    uint32_t n_merge;        /* tiles whose list is longer than 16384 */
     uint64_t pixels_stopped; /* pixels that stopped before the end of their list (T (1 - alpha) < 1e-4) */
 } lodge_frame_info;
 

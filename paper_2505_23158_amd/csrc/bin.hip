@@ -194,8 +194,15 @@ __device__ __forceinline__ uint32_t hist_get(const uint32_t* h, uint32_t t)
 }
 
 constexpr int kBinThreads = 1024;
-// the tile histogram (16-bit counters), then the offset and id windows
-constexpr int kEmitLdsWords = kMaxTiles / 2 + 2 * (kBinChunk + 1);
+// Every compacted active holds at least one instance, so a binning block's
+// instances belong to at most kBinChunk + 1 of them.
+constexpr uint32_t kWindow = kBinChunk + 1;
+
+// Dynamic LDS of the binning kernels, sized for the frame's tile count so
+// that two blocks share a compute unit at 1080p: the tile histogram (16-bit
+// counters, (T + 1) / 2 words), then for k_emit_hist the offset and id windows.
+__host__ __device__ constexpr uint32_t emit_lds_words(uint32_t T) { return (T + 1) / 2 + 2 * kWindow; }
+__host__ __device__ constexpr uint32_t scatter_lds_words(uint32_t T) { return (T + 1) / 2; }
 
 // last index i in [0, n) with a[i] <= key (a ascending, a[0] <= key)
 __device__ __forceinline__ uint32_t last_le(const uint32_t* a, uint32_t n, uint32_t key)
@@ -217,10 +224,7 @@ __global__ __launch_bounds__(kBinThreads) void k_emit_hist(const FrameParams* fp
                                                            uint64_t max_instances)
 {
     constexpr int kPer = kBinChunk / kBinThreads;   // instances per thread, processed together
-    // every compacted active holds at least one instance, so a block's
-    // instances belong to at most kBinChunk + 1 of them
-    constexpr uint32_t kWindow = kBinChunk + 1;
-    __shared__ uint32_t s_lds[kEmitLdsWords];
+    extern __shared__ uint32_t s_lds[];   // emit_lds_words(T)
     const unsigned long long M = info->n_instances;
     if (M == 0 || M > max_instances) return;
     const uint32_t n_bin = info->n_binned;
@@ -407,7 +411,8 @@ __global__ __launch_bounds__(kBinThreads) void k_scatter(const FrameParams* fp, 
                                                          const uint2* __restrict__ ranges,
                                                          uint32_t* __restrict__ sorted, uint64_t max_instances)
 {
-    __shared__ uint32_t s_rank[kMaxTiles / 2];
+    extern __shared__ uint32_t s_lds[];   // scatter_lds_words(T)
+    uint32_t* const s_rank = s_lds;
     const unsigned long long M = info->n_instances;
     if (M == 0 || M > max_instances) return;
     const uint32_t T = (uint32_t)(fp->TX * fp->TY);
@@ -438,10 +443,24 @@ hipError_t launch_bin(const Views& v, const lodge_selection& sel, hipStream_t st
                                    v.vis_id, v.bstart, v.max_instances);
     const uint32_t bmax = std::max<uint32_t>(1, (uint32_t)((v.max_instances + kBinChunk - 1) / kBinChunk));
     const uint32_t grid = std::min<uint32_t>(bmax, 1024);
-    k_emit_hist<<<grid, kBinThreads, 0, st>>>(v.params, v.info, v.vis_off, v.vis_id, v.bstart, v.rect, v.inst,
-                                              v.hist, v.tcount, v.max_instances);
+    // more than 64 KB of dynamic LDS must be allowed explicitly (up to 4K frames)
+    static thread_local int dev_cached = -1;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev != dev_cached) {
+        if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_emit_hist),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)(4 * emit_lds_words(kMaxTiles)))) != hipSuccess)
+            return e;
+        dev_cached = dev;
+    }
+    k_emit_hist<<<grid, kBinThreads, 4 * emit_lds_words(v.lay.T), st>>>(v.params, v.info, v.vis_off, v.vis_id,
+                                                                         v.bstart, v.rect, v.inst, v.hist, v.tcount,
+                                                                         v.max_instances);
     k_tile_scan<<<1, kTilesThreads, 0, st>>>(v.params, v.info, v.tcount, v.ranges, v.order, v.large);
-    k_scatter<<<grid, kBinThreads, 0, st>>>(v.params, v.info, v.inst, v.hist, v.ranges, v.sorted, v.max_instances);
+    k_scatter<<<grid, kBinThreads, 4 * scatter_lds_words(v.lay.T), st>>>(v.params, v.info, v.inst, v.hist, v.ranges,
+                                                                          v.sorted, v.max_instances);
     return hipGetLastError();
 }
 

@@ -126,7 +126,7 @@ constexpr int kSortSmall = 2048;                    // per-tile LDS sort, 256 th
 constexpr int kSortMid = 4096;                      // per-tile LDS sort, 1024 threads, 32 KB
 constexpr int kSortLarge = 16384;                   // per-tile LDS sort, 1024 threads, 128 KB
 constexpr int kProjStride = 12;                     // floats per projected record
-constexpr int kBinChunk = 8192;                     // instances per binning block
+constexpr int kBinChunk = 4096;                     // instances per binning block
 constexpr int kProjChunk = 64;                      // actives per projection chunk: one wave (instance-scan granule)
 constexpr int kMaxTiles = 32768;                    // 16-bit-packed LDS tile histograms (e.g. 3840 x 2160)
 
