@@ -90,6 +90,7 @@ Layout make_layout(uint32_t n_total, int32_t width, int32_t height, uint32_t max
     L.wstats = take(16ull * 4 * L.T);
     L.chunk_sum = take(4ull * ((max_active + kProjChunk - 1) / kProjChunk + 1));
     L.chunk_vis = take(4ull * ((max_active + kProjChunk - 1) / kProjChunk + 1));
+    L.scan_blk = take(16ull * (((max_active + kProjChunk - 1) / kProjChunk + kScanChunks - 1) / kScanChunks + 1));
     L.bin_blocks = (uint32_t)std::max<uint64_t>(1, (max_instances + kBinChunk - 1) / kBinChunk);
     L.bstart = take(4ull * (L.bin_blocks + 1));
     L.proj = take(48ull * max_active);
@@ -128,6 +129,7 @@ Views views_of(const lodge_workspace* ws, uint32_t n_total)
     v.sel_bits = reinterpret_cast<uint32_t*>(b + v.lay.sel_bits);
     v.chunk_sum = reinterpret_cast<uint32_t*>(b + v.lay.chunk_sum);
     v.chunk_vis = reinterpret_cast<uint32_t*>(b + v.lay.chunk_vis);
+    v.scan_blk = reinterpret_cast<uint4*>(b + v.lay.scan_blk);
     v.proj = reinterpret_cast<float4*>(b + v.lay.proj);
     v.depth = reinterpret_cast<float*>(b + v.lay.depth);
     v.rect = reinterpret_cast<uint2*>(b + v.lay.rect);
@@ -172,6 +174,7 @@ __global__ void k_render_setup(FrameParams* fp, FrameInfo* info, lodge_camera ca
         info->n_mid = 0;
         info->n_binned = 0;
         info->sort_next = 0;
+        info->scan_done = 0;
     }
 }
 }  // namespace

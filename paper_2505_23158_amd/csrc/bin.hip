@@ -6,10 +6,11 @@
 // device-scope atomics only where they are few (one per binning block and
 // tile it touches, about 200 blocks x a few hundred tiles at 1080p).
 //
-//   k_chunk_scan  one block: exclusive scans of the per-chunk totals the
-//                 projection wrote (tiles; actives with a tile) -> chunk
-//                 offsets, the instance count M and the binned count; clears
-//                 the tile totals.
+//   k_chunk_scan  exclusive scans of the per-chunk totals the projection
+//                 wrote (tiles; actives with a tile): offsets inside blocks
+//                 of 4096 chunks, then, in the last block to finish, the
+//                 blocks' offsets, the instance count M and the binned
+//                 count; clears the tile totals.
 //   k_inst_off    per chunk (one wave): scan of the tile counts + chunk
 //                 offset -> exclusive instance offsets; the actives with a
 //                 tile are compacted in index order as (first instance,
@@ -36,16 +37,15 @@ namespace lodge {
 
 namespace {
 
-// One block: exclusive scans of the two per-chunk totals the projection
-// wrote (one chunk per 64 actives): tiles -> chunk instance offsets and M;
-// actives with a tile -> chunk offsets of their compaction.  The totals are
-// read as coalesced uint4 runs, kChunkScanGroup tiles of 4 x 1024 chunks at
-// a time, all loads in flight together; the wave scans of the group's
-// 2 x kChunkScanGroup per-thread sums are interleaved and share one pair of
-// barriers, and the tiles are chained by carries.
+// Exclusive scans of the two per-chunk totals the projection wrote (one
+// chunk per 64 actives): tiles -> chunk instance offsets and M; actives with
+// a tile -> chunk offsets of their compaction.  Block b takes chunks
+// [b kScanChunks, (b + 1) kScanChunks), 4 per thread (coalesced uint4), and
+// writes offsets local to the block plus its two totals; the last block to
+// finish (one atomic per block, no waiting) scans the block totals into
+// per-block offsets, M and the binned count.  Consumers add the block offset.
 constexpr int kChunkScanThreads = 1024;
-constexpr int kChunkScanTile = 4 * kChunkScanThreads;
-constexpr int kChunkScanGroup = 4;
+static_assert(kScanChunks == 4 * kChunkScanThreads, "four chunks per thread");
 
 __device__ __forceinline__ uint4 load4(const uint32_t* __restrict__ p, uint32_t c, uint32_t nc)
 {
@@ -66,74 +66,122 @@ __device__ __forceinline__ void store4(uint32_t* __restrict__ p, uint32_t c, uin
 
 __global__ __launch_bounds__(kChunkScanThreads) void k_chunk_scan(const FrameParams* fp, FrameInfo* info,
                                                                  uint32_t* __restrict__ csum,
-                                                                 uint32_t* __restrict__ cvis,
+                                                                 uint32_t* __restrict__ cvis, uint4* blk,
                                                                  const uint32_t* __restrict__ count, uint32_t cap,
                                                                  uint32_t* __restrict__ tcount, uint64_t max_instances)
 {
-    constexpr int G = kChunkScanGroup, NW = kChunkScanThreads / 64;
-    __shared__ uint32_t s_w[2 * G][NW];
+    constexpr int NW = kChunkScanThreads / 64, kPer = 8;
+    __shared__ uint32_t s_w[2][NW];
+    __shared__ unsigned long long s_t[NW];
+    __shared__ uint32_t s_last;
     const uint32_t n = min(*count, cap);
     const uint32_t nc = (n + kProjChunk - 1) / kProjChunk;
+    const uint32_t nb = max(1u, (nc + kScanChunks - 1) / kScanChunks);   // block 0 runs even with no chunk
+    const uint32_t b = blockIdx.x;
+    if (b >= nb) return;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // tile totals: accumulated by the binning blocks' atomics
-    const uint32_t T = (uint32_t)(fp->TX * fp->TY);
-    for (uint32_t t = tid; t < T; t += kChunkScanThreads) tcount[t] = 0;
-    unsigned long long carry = 0;
-    uint32_t vcarry = 0;
-    for (uint32_t g0 = 0; g0 < nc; g0 += kChunkScanTile * G) {
-        uint4 v[2 * G];   // [0, G) tile totals, [G, 2G) counts of actives with a tile
-#pragma unroll
-        for (int t = 0; t < G; t++) {
-            const uint32_t c = g0 + t * kChunkScanTile + 4 * tid;
-            v[t] = load4(csum, c, nc);
-            v[G + t] = load4(cvis, c, nc);
-        }
-        uint32_t own[2 * G], inc[2 * G];
-#pragma unroll
-        for (int k = 0; k < 2 * G; k++) inc[k] = own[k] = (v[k].x + v[k].y) + (v[k].z + v[k].w);
-        for (int o = 1; o < 64; o <<= 1) {
-#pragma unroll
-            for (int k = 0; k < 2 * G; k++) {
-                const uint32_t u = __shfl_up(inc[k], o);
-                if ((int)lane >= o) inc[k] += u;
-            }
-        }
-        if (lane == 63)
-#pragma unroll
-            for (int k = 0; k < 2 * G; k++) s_w[k][wave] = inc[k];
-        __syncthreads();
-        unsigned long long ct = carry;
-        uint32_t cv = vcarry;
-#pragma unroll
-        for (int t = 0; t < G; t++) {
-            uint32_t before = 0, total = 0, vbefore = 0, vtotal = 0;
-#pragma unroll
-            for (int k = 0; k < NW; k++) {
-                const uint32_t x = s_w[t][k], y = s_w[G + t][k];
-                before += (uint32_t)k < wave ? x : 0u;
-                total += x;
-                vbefore += (uint32_t)k < wave ? y : 0u;
-                vtotal += y;
-            }
-            // offsets only matter when M fits the instance capacity (< 2^32)
-            const uint32_t c = g0 + t * kChunkScanTile + 4 * tid;
-            const uint32_t e0 = (uint32_t)ct + before + inc[t] - own[t];
-            const uint32_t f0 = cv + vbefore + inc[G + t] - own[G + t];
-            store4(csum, c, nc, make_uint4(e0, e0 + v[t].x, e0 + v[t].x + v[t].y, e0 + v[t].x + v[t].y + v[t].z));
-            store4(cvis, c, nc,
-                   make_uint4(f0, f0 + v[G + t].x, f0 + v[G + t].x + v[G + t].y,
-                              f0 + v[G + t].x + v[G + t].y + v[G + t].z));
-            ct += total;
-            cv += vtotal;
-        }
-        carry = ct;
-        vcarry = cv;
-        __syncthreads();   // s_w is rewritten by the next group
+    if (b == 0) {
+        // tile totals: accumulated by the binning blocks' atomics
+        const uint32_t T = (uint32_t)(fp->TX * fp->TY);
+        for (uint32_t t = tid; t < T; t += kChunkScanThreads) tcount[t] = 0;
     }
+    const uint32_t c = b * kScanChunks + 4 * tid;
+    const uint4 v = load4(csum, c, nc), w = load4(cvis, c, nc);
+    const uint32_t own = (v.x + v.y) + (v.z + v.w), vown = (w.x + w.y) + (w.z + w.w);
+    uint32_t inc = own, vinc = vown;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(inc, o), vu = __shfl_up(vinc, o);
+        if ((int)lane >= o) {
+            inc += u;
+            vinc += vu;
+        }
+    }
+    if (lane == 63) {
+        s_w[0][wave] = inc;
+        s_w[1][wave] = vinc;
+    }
+    __syncthreads();
+    uint32_t before = 0, vbefore = 0, vtotal = 0;
+    unsigned long long total = 0;
+#pragma unroll
+    for (int k = 0; k < NW; k++) {
+        const uint32_t x = s_w[0][k], y = s_w[1][k];
+        before += (uint32_t)k < wave ? x : 0u;
+        total += x;
+        vbefore += (uint32_t)k < wave ? y : 0u;
+        vtotal += y;
+    }
+    // offsets only matter when M fits the instance capacity (< 2^32)
+    const uint32_t e0 = before + inc - own, f0 = vbefore + vinc - vown;
+    store4(csum, c, nc, make_uint4(e0, e0 + v.x, e0 + v.x + v.y, e0 + v.x + v.y + v.z));
+    store4(cvis, c, nc, make_uint4(f0, f0 + w.x, f0 + w.x + w.y, f0 + w.x + w.y + w.z));
     if (tid == 0) {
-        info->n_instances = carry;
-        info->n_binned = vcarry;
-        if (carry > max_instances) atomicOr(&info->overflow, kOvfInstances);
+        blk[b] = make_uint4((uint32_t)total, (uint32_t)(total >> 32), vtotal, 0u);
+        __threadfence();   // the totals are visible before the count says so
+        s_last = atomicAdd(&info->scan_done, 1u) == nb - 1 ? 1u : 0u;
+    }
+    __syncthreads();
+    if (s_last == 0u) return;
+    // the last block: exclusive scan of the nb block totals, kPer per thread
+    // (nb <= kPer x 1024 for any max_active < 2^31)
+    __threadfence();
+    const volatile uint4* vb = blk;
+    const uint32_t per = (nb + kChunkScanThreads - 1) / kChunkScanThreads;
+    const uint32_t b0 = min(nb, tid * per), b1 = min(nb, b0 + per);
+    unsigned long long bt[kPer];
+    uint32_t bv[kPer];
+    unsigned long long st = 0;
+    uint32_t sv = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; q++) {
+        bt[q] = 0;
+        bv[q] = 0;
+        if (b0 + q < b1) {
+            const uint32_t lo = vb[b0 + q].x, hi = vb[b0 + q].y;
+            bt[q] = ((unsigned long long)hi << 32) | lo;
+            bv[q] = vb[b0 + q].z;
+        }
+        st += bt[q];
+        sv += bv[q];
+    }
+    unsigned long long it = st;
+    uint32_t iv = sv;
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long ut = __shfl_up(it, o);
+        const uint32_t uv = __shfl_up(iv, o);
+        if ((int)lane >= o) {
+            it += ut;
+            iv += uv;
+        }
+    }
+    __syncthreads();
+    if (lane == 63) {
+        s_t[wave] = it;
+        s_w[1][wave] = iv;
+    }
+    __syncthreads();
+    unsigned long long tb = 0, tt = 0;
+    uint32_t vb0 = 0, vt = 0;
+#pragma unroll
+    for (int k = 0; k < NW; k++) {
+        tb += (uint32_t)k < wave ? s_t[k] : 0ull;
+        tt += s_t[k];
+        vb0 += (uint32_t)k < wave ? s_w[1][k] : 0u;
+        vt += s_w[1][k];
+    }
+    unsigned long long rt = tb + it - st;
+    uint32_t rv = vb0 + iv - sv;
+#pragma unroll
+    for (int q = 0; q < kPer; q++)
+        if (b0 + q < b1) {
+            blk[b0 + q] = make_uint4((uint32_t)rt, rv, 0u, 0u);
+            rt += bt[q];
+            rv += bv[q];
+        }
+    if (tid == 0) {
+        info->n_instances = tt;
+        info->n_binned = vt;
+        if (tt > max_instances) atomicOr(&info->overflow, kOvfInstances);
     }
 }
 
@@ -143,6 +191,7 @@ __global__ __launch_bounds__(kChunkScanThreads) void k_chunk_scan(const FramePar
 __global__ __launch_bounds__(256) void k_inst_off(const FrameInfo* info, const uint32_t* __restrict__ vt,
                                                   const uint32_t* __restrict__ coff,
                                                   const uint32_t* __restrict__ cvis,
+                                                  const uint4* __restrict__ blk,
                                                   const uint32_t* __restrict__ count, uint32_t cap,
                                                   uint32_t* __restrict__ vis_off, uint32_t* __restrict__ vis_id,
                                                   uint32_t* __restrict__ bstart, uint64_t max_instances)
@@ -162,10 +211,11 @@ __global__ __launch_bounds__(256) void k_inst_off(const FrameInfo* info, const u
             const uint32_t o = __shfl_up(inc, off);
             if ((int)lane >= off) inc += o;
         }
-        const uint32_t o = coff[c] + inc - x;
+        const uint4 bo = blk[c / kScanChunks];   // the chunk-scan block's offsets
+        const uint32_t o = bo.x + coff[c] + inc - x;
         const unsigned long long m = __ballot(x > 0u);
         if (x > 0u) {
-            const uint32_t s = cvis[c] + (uint32_t)__popcll(m & lt);
+            const uint32_t s = bo.y + cvis[c] + (uint32_t)__popcll(m & lt);
             vis_off[s] = o;
             vis_id[s] = a;
             // the binning block starting at instance b kBinChunk is owned by
@@ -243,9 +293,23 @@ __global__ __launch_bounds__(kBinThreads) void k_emit_hist(const FrameParams* fp
         const uint32_t lo = bstart[b];
         const uint32_t hi = b + 1 < B ? bstart[b + 1] : n_bin - 1;
         const uint32_t cnt = min(hi - lo + 1, kWindow);
-        for (uint32_t k = threadIdx.x; k < cnt; k += kBinThreads) {
-            s_off[k] = vis_off[lo + k];
-            s_id[k] = vis_id[lo + k];
+        // the window: every load of a pass issued before its LDS stores
+        for (uint32_t k0 = 0; k0 < cnt; k0 += kPer * kBinThreads) {
+            uint32_t o[kPer], g[kPer];
+#pragma unroll
+            for (int q = 0; q < kPer; q++) {
+                const uint32_t k = k0 + q * kBinThreads + threadIdx.x;
+                o[q] = k < cnt ? vis_off[lo + k] : 0u;
+                g[q] = k < cnt ? vis_id[lo + k] : 0u;
+            }
+#pragma unroll
+            for (int q = 0; q < kPer; q++) {
+                const uint32_t k = k0 + q * kBinThreads + threadIdx.x;
+                if (k < cnt) {
+                    s_off[k] = o[q];
+                    s_id[k] = g[q];
+                }
+            }
         }
         __syncthreads();
         // each instance's active: the last whose first instance is <= it
@@ -277,10 +341,25 @@ __global__ __launch_bounds__(kBinThreads) void k_emit_hist(const FrameParams* fp
         __syncthreads();
         // the block's first slot in each touched tile's run (the order of
         // blocks inside a run is that of the atomics; the sort restores it)
+        // (eight atomics in flight per thread before their results are stored)
         uint32_t* row_out = hist + (size_t)b * T;
-        for (uint32_t t = threadIdx.x; t < T; t += kBinThreads) {
-            const uint32_t c = hist_get(s_hist, t);
-            if (c != 0u) row_out[t] = atomicAdd(&tcount[t], c);
+        for (uint32_t t0 = 0; t0 < T; t0 += 8 * kBinThreads) {
+            uint32_t c[8], r[8];
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const uint32_t t = t0 + q * kBinThreads + threadIdx.x;
+                c[q] = t < T ? hist_get(s_hist, t) : 0u;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const uint32_t t = t0 + q * kBinThreads + threadIdx.x;
+                r[q] = c[q] != 0u ? atomicAdd(&tcount[t], c[q]) : 0u;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const uint32_t t = t0 + q * kBinThreads + threadIdx.x;
+                if (c[q] != 0u) row_out[t] = r[q];
+            }
         }
         __syncthreads();
     }
@@ -350,16 +429,32 @@ __global__ __launch_bounds__(kTilesThreads) void k_tile_scan(const FrameParams* 
 {
     __shared__ unsigned long long s_w[3][kTilesThreads / 64];
     __shared__ uint32_t s_max[kTilesThreads / 64];
+    __shared__ uint32_t s_c[kMaxTiles];   // 128 KB: this kernel is one block
     const uint32_t T = (uint32_t)(fp->TX * fp->TY);
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t per = (T + kTilesThreads - 1) / kTilesThreads;
     const uint32_t t0 = min(T, tid * per), t1 = min(T, t0 + per);
+    // the tile totals staged in LDS by coalesced loads, eight in flight per
+    // thread, so the per-thread runs below read LDS, not global memory
+    for (uint32_t g0 = 0; g0 < T; g0 += 8 * kTilesThreads) {
+        uint32_t v[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            const uint32_t t = g0 + q * kTilesThreads + tid;
+            v[q] = t < T ? tcount[t] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            const uint32_t t = g0 + q * kTilesThreads + tid;
+            if (t < T) s_c[t] = v[q];
+        }
+    }
+    __syncthreads();
     // cls: four 16-bit class counts; big: three 21-bit queue counts (large, huge, mid)
     unsigned long long sum = 0, cls = 0, big = 0;
     uint32_t lmax = 0;
-#pragma unroll 8
     for (uint32_t t = t0; t < t1; t++) {
-        const uint32_t c = tcount[t];
+        const uint32_t c = s_c[t];
         sum += c;
         lmax = max(lmax, c);
         cls += 1ull << (16 * length_class(c));
@@ -382,9 +477,8 @@ __global__ __launch_bounds__(kTilesThreads) void k_tile_scan(const FrameParams* 
     }
     uint32_t nl = (uint32_t)(bpos & kQMask), nh = (uint32_t)((bpos >> 21) & kQMask),
              nm = (uint32_t)((bpos >> 42) & kQMask);
-#pragma unroll 8
     for (uint32_t t = t0; t < t1; t++) {
-        const uint32_t c = tcount[t];   // second read: the first pass left it in cache
+        const uint32_t c = s_c[t];
         // offsets only matter when the total fits the instance capacity (< 2^32)
         ranges[t] = make_uint2((uint32_t)run, (uint32_t)(run + c));
         run += c;
@@ -423,10 +517,28 @@ __global__ __launch_bounds__(kBinThreads) void k_scatter(const FrameParams* fp, 
         for (uint32_t k = threadIdx.x; k < (T + 1) / 2; k += kBinThreads) s_rank[k] = 0;
         __syncthreads();
         const uint32_t* row = hist + (size_t)b * T;
-        for (uint32_t j = j0 + threadIdx.x; j < j1; j += kBinThreads) {
-            const uint2 e = inst[j];
-            const uint32_t slot = ranges[e.x].x + row[e.x] + hist_inc(s_rank, e.x);
-            if (slot < max_instances) sorted[slot] = e.y;
+        // the block's instances, kPer per thread: each round of loads is
+        // issued before any of its results is used
+        constexpr int kPer = kBinChunk / kBinThreads;
+        uint2 e[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; q++) {
+            const uint32_t j = j0 + q * kBinThreads + threadIdx.x;
+            e[q] = j < j1 ? inst[j] : make_uint2(0u, 0u);
+        }
+        uint32_t base[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; q++) {
+            const uint32_t j = j0 + q * kBinThreads + threadIdx.x;
+            base[q] = j < j1 ? ranges[e[q].x].x + row[e[q].x] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < kPer; q++) {
+            const uint32_t j = j0 + q * kBinThreads + threadIdx.x;
+            if (j < j1) {
+                const uint32_t slot = base[q] + hist_inc(s_rank, e[q].x);
+                if (slot < max_instances) sorted[slot] = e[q].y;
+            }
         }
         __syncthreads();
     }
@@ -436,11 +548,12 @@ __global__ __launch_bounds__(kBinThreads) void k_scatter(const FrameParams* fp, 
 
 hipError_t launch_bin(const Views& v, const lodge_selection& sel, hipStream_t st)
 {
-    k_chunk_scan<<<1, kChunkScanThreads, 0, st>>>(v.params, v.info, v.chunk_sum, v.chunk_vis, sel.count, sel.cap,
-                                                  v.tcount, v.max_instances);
+    const uint32_t sb = std::max<uint32_t>(1, ((v.max_active + kProjChunk - 1) / kProjChunk + kScanChunks - 1) / kScanChunks);
+    k_chunk_scan<<<sb, kChunkScanThreads, 0, st>>>(v.params, v.info, v.chunk_sum, v.chunk_vis, v.scan_blk, sel.count,
+                                                   sel.cap, v.tcount, v.max_instances);
     const uint32_t cg = std::max<uint32_t>(1, std::min<uint32_t>(4096, (v.max_active + 255) / 256));
-    k_inst_off<<<cg, 256, 0, st>>>(v.info, v.vtiles, v.chunk_sum, v.chunk_vis, sel.count, sel.cap, v.vis_off,
-                                   v.vis_id, v.bstart, v.max_instances);
+    k_inst_off<<<cg, 256, 0, st>>>(v.info, v.vtiles, v.chunk_sum, v.chunk_vis, v.scan_blk, sel.count, sel.cap,
+                                   v.vis_off, v.vis_id, v.bstart, v.max_instances);
     const uint32_t bmax = std::max<uint32_t>(1, (uint32_t)((v.max_instances + kBinChunk - 1) / kBinChunk));
     const uint32_t grid = std::min<uint32_t>(bmax, 1024);
     // more than 64 KB of dynamic LDS must be allowed explicitly (up to 4K frames)

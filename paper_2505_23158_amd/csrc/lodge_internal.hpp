@@ -78,7 +78,7 @@ struct FrameInfo {
     uint32_t n_mid;       // tiles sorted by the mid-length kernel
     uint32_t n_binned;    // actives with at least one tile
     uint32_t sort_next;   // next work item of the per-tile sort
-    uint32_t pad;
+    uint32_t scan_done;   // chunk-scan blocks that have written their totals
 };
 
 enum : uint32_t { kOvfSelect = 1u, kOvfInstances = 2u, kOvfTile = 4u };
@@ -127,11 +127,12 @@ constexpr int kSortMid = 4096;                      // per-tile LDS sort, 1024 t
 constexpr int kSortLarge = 16384;                   // per-tile LDS sort, 1024 threads, 128 KB
 constexpr int kProjStride = 12;                     // floats per projected record
 constexpr int kBinChunk = 4096;                     // instances per binning block
+constexpr int kScanChunks = 4096;                   // projection chunks per chunk-scan block
 constexpr int kProjChunk = 64;                      // actives per projection chunk: one wave (instance-scan granule)
 constexpr int kMaxTiles = 32768;                    // 16-bit-packed LDS tile histograms (e.g. 3840 x 2160)
 
 struct Layout {
-    size_t params, info, wstats, bstart, sel_cnt, sel_off, sel_bits, chunk_sum, chunk_vis, proj, depth, rect, vtiles, vis_off,
+    size_t params, info, wstats, bstart, sel_cnt, sel_off, sel_bits, chunk_sum, chunk_vis, scan_blk, proj, depth, rect, vtiles, vis_off,
         vis_id, inst, hist, tcount, ranges, order, large, sorted, temp, g2d, total;
     uint32_t sel_tiles, TX, TY, T, bin_blocks;
 };
@@ -148,6 +149,7 @@ struct Views {
     uint32_t* sel_bits;    // [selection tiles][kSelBlock] two membership bits per item
     uint32_t* chunk_sum;   // per projection chunk: tile total -> exclusive instance offset
     uint32_t* chunk_vis;   // per projection chunk: actives with >= 1 tile -> exclusive offset among them
+    uint4* scan_blk;       // per chunk-scan block: its totals -> its exclusive offsets
     float4* proj;          // [max_active][3]: (u, v, A, B), (C, o, r, g), (b, ex, ey, thr); visible only
     float* depth;          // [max_active] camera depth (sort key), 0 when culled
     uint2* rect;           // [max_active] tile rect (x0 | y0 << 16, x1 | y1 << 16), empty when culled

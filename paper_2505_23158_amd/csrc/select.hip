@@ -228,30 +228,50 @@ __global__ __launch_bounds__(kSelScanThreads) void k_select_scan(FrameInfo* info
                                                                  uint32_t* __restrict__ off, uint32_t ntiles,
                                                                  uint32_t cap, uint32_t* count_out)
 {
-    __shared__ uint32_t s_part[kSelScanThreads];
-    const uint32_t tid = threadIdx.x;
+    // up to kPer counts per thread are held in registers, their loads issued
+    // together; beyond that (more than kPer x 1024 tiles) the run is re-read
+    constexpr int kPer = 8;
+    __shared__ uint32_t s_w[kSelScanThreads / 64];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t per = (ntiles + kSelScanThreads - 1) / kSelScanThreads;
     const uint32_t c0 = min(ntiles, tid * per), c1 = min(ntiles, c0 + per);
+    uint32_t v[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; q++) v[q] = c0 + q < c1 ? cnt[c0 + q] : 0u;
     uint32_t local = 0;
-    for (uint32_t c = c0; c < c1; c++) local += cnt[c];
-    s_part[tid] = local;
-    __syncthreads();
-    for (int o = 1; o < kSelScanThreads; o <<= 1) {
-        const uint32_t v = tid >= (uint32_t)o ? s_part[tid - o] : 0u;
-        __syncthreads();
-        s_part[tid] += v;
-        __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; q++) local += v[q];
+    for (uint32_t c = c0 + kPer; c < c1; c++) local += cnt[c];
+    // block scan: wave scans, then the wave totals
+    uint32_t inc = local;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(inc, o);
+        if ((int)lane >= o) inc += u;
     }
-    uint32_t run = s_part[tid] - local;   // totals stay below 2^32: at most n_total Gaussians
-    for (uint32_t c = c0; c < c1; c++) {
+    if (lane == 63) s_w[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < kSelScanThreads / 64; k++) {
+        const uint32_t x = s_w[k];
+        before += (uint32_t)k < wave ? x : 0u;
+        total += x;
+    }
+    uint32_t run = before + inc - local;   // totals stay below 2^32: at most n_total Gaussians
+#pragma unroll
+    for (int q = 0; q < kPer; q++)
+        if (c0 + q < c1) {
+            off[c0 + q] = run;
+            run += v[q];
+        }
+    for (uint32_t c = c0 + kPer; c < c1; c++) {
         off[c] = run;
         run += cnt[c];
     }
-    if (tid == kSelScanThreads - 1) {
-        const uint32_t n = s_part[tid];
-        *count_out = n;
-        info->n_selected = n;
-        if (n > cap) atomicOr(&info->overflow, kOvfSelect);
+    if (tid == 0) {
+        *count_out = total;
+        info->n_selected = total;
+        if (total > cap) atomicOr(&info->overflow, kOvfSelect);
     }
 }
 
@@ -274,6 +294,9 @@ __global__ __launch_bounds__(kSelBlock) void k_select_emit(LevelsArg lv, const F
         if (j < lv.L && tile >= lv.first_block[j]) l = j;
     const uint32_t gbase = lv.lv[l].base + (tile - lv.first_block[l]) * (uint32_t)kSelTile;
     const uint32_t bits = bits_in[(size_t)tile * kSelBlock + tid];
+    // read before the barriers below, so the loads overlap the in-tile scan
+    const uint32_t excl = off[tile];
+    const float t = fp->t, w_o = fp->w_o;
 #pragma unroll
     for (int r = 0; r < kSelItems; r++) {
         const unsigned long long m = __ballot(((bits >> (2 * r)) & 3u) != 0u);
@@ -290,8 +313,6 @@ __global__ __launch_bounds__(kSelBlock) void k_select_emit(LevelsArg lv, const F
         if (lane < (uint32_t)(kSelItems * 4)) s_cnt[lane] = inc - v;
     }
     __syncthreads();
-    const uint32_t excl = off[tile];
-    const float t = fp->t, w_o = fp->w_o;
     const unsigned long long lt = (1ull << lane) - 1ull;
 #pragma unroll
     for (int r = 0; r < kSelItems; r++) {

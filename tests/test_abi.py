@@ -89,6 +89,10 @@ def test_workspace_size_and_argument_checks():
     assert nb.value >= 4_000_000 * (48 + 4 + 4 + 48) + 16_000_000 * 12 + 8160 * 24
     assert lib.lodge_workspace_size(h, 0, 1080, 10, 10, C.byref(nb)) == L.LODGE_ERR_INVALID_ARG
     assert lib.lodge_workspace_size(h, 64, 64, 10, 1 << 32, C.byref(nb)) == L.LODGE_ERR_INVALID_ARG
+    # the largest frame: 3840 x 2160 is 32400 16x16 tiles (the limit is 32768); one more tile column is too many
+    assert lib.lodge_workspace_size(h, 3840, 2160, 10, 100, C.byref(nb)) == 0
+    assert lib.lodge_workspace_size(h, 4096, 2048, 10, 100, C.byref(nb)) == 0
+    assert lib.lodge_workspace_size(h, 4097, 2048, 10, 100, C.byref(nb)) == L.LODGE_ERR_UNSUPPORTED
     assert lib.lodge_workspace_size(h, 64, 64, 10, 100, C.byref(nb)) == 0
     ws = L.lodge_workspace(base=0x10000, bytes=nb.value, width=64, height=64, max_active=10, max_instances=100)
     sel = L.lodge_selection(ids=0x2000, w=0x3000, count=0x4000, cap=10)

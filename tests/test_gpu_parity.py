@@ -66,6 +66,13 @@ def test_tiny_images(L, oracle32):
     full_parity(oracle32, sc, d, cam1, oracle.ALL, "1x1")
 
 
+def test_largest_frame_4k(L, oracle32):
+    """3840 x 2160: 32400 tiles, near the 32768-tile limit of the packed
+    16-bit tile histograms (the binning LDS is then over 64 KB)."""
+    sc = synth.plain_scene(n=20000, seed=48, width=3840, height=2160)
+    full_parity(oracle32, sc, dev(L, sc), sc.cameras[0], oracle.ALL, "plain-20k-3840x2160", max_instances=4_000_000)
+
+
 def test_nothing_selected_or_visible(L, oracle32):
     far = synth.gaussians(2000, (44, 0), synth._cube(1.0), -3.0, 0.5)
     far.mean[0] += 50.0                       # all 50 m away
