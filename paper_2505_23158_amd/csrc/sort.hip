@@ -68,7 +68,22 @@ __device__ __forceinline__ void sort_run(unsigned long long* s, const float* __r
                                          uint32_t* __restrict__ run, uint32_t n, uint32_t cap)
 {
     const uint32_t P = next_pow2(n);
-    for (uint32_t k = threadIdx.x; k < P; k += NT) s[k] = k < n ? key_of(proj, run[k], cap) : ~0ull;
+    for (uint32_t k0 = 0; k0 < P; k0 += 4 * NT) {
+        // four keys per thread in flight: index loads, then depth loads
+        uint32_t idx[4], dep[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const uint32_t k = k0 + q * NT + threadIdx.x;
+            idx[q] = k < n ? run[k] : 0xffffffffu;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) dep[q] = __float_as_uint(proj[idx[q] < cap ? idx[q] : 0u]);
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const uint32_t k = k0 + q * NT + threadIdx.x;
+            if (k < P) s[k] = idx[q] < cap ? ((unsigned long long)dep[q] << 32) | idx[q] : ~0ull;
+        }
+    }
     __syncthreads();
     bitonic_lds<NT>(s, P);
     for (uint32_t k = threadIdx.x; k < n; k += NT) run[k] = s[k] == ~0ull ? 0xffffffffu : (uint32_t)s[k];
@@ -193,11 +208,19 @@ __device__ __forceinline__ void sort_run_regs(unsigned long long* lds, const flo
 {
     unsigned long long x[E];
     const uint32_t t = threadIdx.x % NT;
+    // branch-free, so that the E index loads, then the E depth loads, are
+    // each issued together rather than one wait per key
+    uint32_t idx[E];
 #pragma unroll
     for (int e = 0; e < E; e++) {
         const uint32_t i = t * E + e;
-        x[e] = i < n ? key_of(depth, run[i], cap) : ~0ull;
+        idx[e] = i < n ? run[i] : 0xffffffffu;
     }
+    uint32_t dep[E];
+#pragma unroll
+    for (int e = 0; e < E; e++) dep[e] = __float_as_uint(depth[idx[e] < cap ? idx[e] : 0u]);
+#pragma unroll
+    for (int e = 0; e < E; e++) x[e] = idx[e] < cap ? ((unsigned long long)dep[e] << 32) | idx[e] : ~0ull;
     bitonic_regs<NT, E, LOG2P>(x, lds);
 #pragma unroll
     for (int e = 0; e < E; e++) {
