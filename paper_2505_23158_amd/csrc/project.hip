@@ -89,7 +89,8 @@ constexpr int kQueue = 128;   // per-wave colour queue: < 64 left over + one chu
 // Colour of up to 64 queued Gaussians, one per lane (lanes >= cnt idle):
 // degree-3 real SH at the view direction, + 0.5, clamped at 0; written into
 // the record's colour fields.
-__device__ __forceinline__ void colour_batch(const LevelsArg& lv, const uint32_t* qa, const uint32_t* qg,
+__device__ __forceinline__ void colour_batch(const LevelsArg& lv, const LevelDev* s_lv, const uint32_t* qa,
+                                             const uint32_t* qg,
                                              const float (*qd)[kQueue], uint32_t cnt, float4* __restrict__ proj)
 {
     const uint32_t lane = threadIdx.x & 63;
@@ -105,7 +106,7 @@ __device__ __forceinline__ void colour_batch(const LevelsArg& lv, const uint32_t
         const int l0 = __builtin_amdgcn_readlane(lvl, __ffsll((long long)pend) - 1);
         if (todo && lvl == l0) {
             todo = false;
-            const LevelDev& Lv = lv.lv[l0];
+            const LevelDev& Lv = s_lv[l0];
             const float* __restrict__ shp = uniform_ptr(Lv.sh);
             const size_t n = __builtin_amdgcn_readfirstlane(Lv.n);
             const int sh_degree = __builtin_amdgcn_readfirstlane(Lv.sh_degree);
@@ -146,6 +147,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     __shared__ uint32_t s_cnt[2][4];
     __shared__ uint32_t s_qa[4][kQueue], s_qg[4][kQueue];
     __shared__ float s_qd[4][3][kQueue];
+    // the level table in LDS: a level picked at run time is then an LDS read,
+    // not a memory round trip on every chunk and colour batch
+    __shared__ LevelDev s_lv[LODGE_MAX_LEVELS];
+    if (threadIdx.x < LODGE_MAX_LEVELS) s_lv[threadIdx.x] = lv.lv[threadIdx.x];
+    __syncthreads();
     const uint32_t n_act = min(*count, cap);
     const lodge_camera& cam = fp->cam;
     const float s2d = fp->s2d;
@@ -179,7 +185,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
           const int l0 = __builtin_amdgcn_readlane(lvl, __ffsll((long long)pend) - 1);
           if (todo && lvl == l0) {
             todo = false;
-            const LevelDev& Lv = lv.lv[l0];
+            const LevelDev& Lv = s_lv[l0];
             const float* __restrict__ mean = uniform_ptr(Lv.mean);
             const float* __restrict__ scale = uniform_ptr(Lv.scale);
             const float* __restrict__ quat = uniform_ptr(Lv.quat);
@@ -329,7 +335,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (qn >= 64) {
-            colour_batch(lv, qa, qg, qd, 64, proj);
+            colour_batch(lv, s_lv, qa, qg, qd, 64, proj);
             // move the left-over entries to the front of the queue
             const uint32_t rem = qn - 64;
             uint32_t ta = 0, tg = 0;
@@ -357,7 +363,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
-    if (qn > 0) colour_batch(lv, qa, qg, qd, qn, proj);
+    if (qn > 0) colour_batch(lv, s_lv, qa, qg, qd, qn, proj);
     // counters: wave sums, block sum, one atomic per block
     for (int o = 32; o > 0; o >>= 1) {
         n_front += __shfl_xor(n_front, o);
