@@ -121,11 +121,10 @@ __device__ __forceinline__ void store_camera(lodge_camera* __restrict__ d, const
 constexpr int kSelBlock = 256;
 constexpr int kSelItems = 16;                       // per thread
 constexpr int kSelTile = kSelBlock * kSelItems;     // Gaussians per selection block
-constexpr int kSortWave = 256;                      // per-tile register sort, one wave
-constexpr int kSortSmall = 2048;                    // per-tile LDS sort, 256 threads
-constexpr int kSortMid = 4096;                      // per-tile LDS sort, 1024 threads, 32 KB
-constexpr int kSortLarge = 16384;                   // per-tile LDS sort, 1024 threads, 128 KB
-constexpr int kProjStride = 12;                     // floats per projected record
+constexpr int kSortWave = 256;                      // runs up to this: one wave, keys in registers
+constexpr int kSortSmall = 2048;                    // runs up to this: 256 threads x 8 keys ("mid" queue)
+constexpr int kSortMid = 4096;                      // runs up to this: 512 threads x 8 keys
+constexpr int kSortLarge = 16384;                   // runs longer than this: the "huge" queue
 constexpr int kBinChunk = 4096;                     // instances per binning block
 constexpr int kScanChunks = 4096;                   // projection chunks per chunk-scan block
 constexpr int kProjChunk = 64;                      // actives per projection chunk: one wave (instance-scan granule)
