@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
     __shared__ float4 s_rec[4 * kWaveRec];
     // per wave and sub-quadrant; 4 entries past the 64 a batch can fill,
     // always the sentinel, for the reads one trip ahead
-    __shared__ uint16_t s_idx[4][4][kListLen];
+    __shared__ uint32_t s_idx[4][4][kListLen];
 
     const int32_t W = fp->cam.width, H = fp->cam.height, TX = fp->TX;
     const uint32_t tile = order[blockIdx.x];
@@ -75,9 +75,9 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
     const uint32_t rbase = wave * kWaveRec;   // the wave's first record (float4 index)
     float4* const sa = s_rec + rbase;
     const char* const rec = reinterpret_cast<const char*>(s_rec);
-    const uint16_t* const sidx = s_idx[wave][sub];
-    const uint16_t own_off = (uint16_t)((rbase + lane) * sizeof(float4));
-    const uint16_t sent_off = (uint16_t)((rbase + 64u) * sizeof(float4));
+    const uint32_t* const sidx = s_idx[wave][sub];
+    const uint32_t own_off = (rbase + lane) * (uint32_t)sizeof(float4);
+    const uint32_t sent_off = (rbase + 64u) * (uint32_t)sizeof(float4);
     constexpr uint32_t kNone = 0xffffffffu;
 
     if (lane == 0) {
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
             load(eA, gA, cA, fA);
             for (uint32_t j = 0; j < n_max; j += 2) {
                 if (__ballot(amin < INFINITY) == 0ull) break;
-                const uint16_t* const p = sidx + j;   // p[2], p[3] < kListLen: j <= 63
+                const uint32_t* const p = sidx + j;   // p[2], p[3] < kListLen: j <= 63
                 load(eB, gB, cB, fB);
                 const uint32_t eA2 = p[2];
                 step(gA, cA, fA, eA);

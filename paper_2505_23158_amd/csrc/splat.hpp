@@ -29,12 +29,13 @@ __device__ __forceinline__ void stage_splat(const float4* __restrict__ proj, uin
     gb = make_float2(r1.w, r2.x);
 }
 
+// power = dx (-A/2 dx - B dy) + (-C/2 dy) dy, in five operations
 __device__ __forceinline__ float splat_power(const float4& geo, const float4& col, float px, float py, float& dx,
                                              float& dy)
 {
     dx = geo.x - px;
     dy = geo.y - py;
-    return __builtin_fmaf(geo.z * dx, dx, __builtin_fmaf(col.x * dy, dy, (geo.w * dx) * dy));
+    return __builtin_fmaf(dx, __builtin_fmaf(geo.w, dy, geo.z * dx), (col.x * dy) * dy);
 }
 
 // alpha of the splat at this pixel, or a negative value if it is skipped
@@ -62,7 +63,7 @@ __device__ __forceinline__ bool splat_keep(const float4& geo, const float4& col,
     float dx, dy;
     const float power = splat_power(geo, col, px, py, dx, dy);
     const float og = col.y * __expf(power);
-    alpha = og > kAlphaMax ? kAlphaMax : og;
+    alpha = fminf(og, kAlphaMax);
     return !(power > 0.0f || power < col.z) && !(alpha < amin);
 }
 
