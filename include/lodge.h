@@ -261,10 +261,11 @@ lodge_status lodge_check(const lodge_workspace* ws, uint32_t* needed_active, uin
  *   sorted_ids [n_instances]  active index of each instance, tile-major,
  *                             each tile's run in ascending (depth bits, index)
  *   tile_ranges[TX*TY][2]     [start, end) of each tile's run (any start when empty)
- *   proj       [max_active][12]  per visible active index: u, v, conic A, B, C,
- *                             o_eff, r, g, b, then the compositing aids ex, ey
- *                             (half-extents of the ellipse where alpha can reach
- *                             1/255) and thr (the power below which it cannot)
+ *   proj       [max_active][12]  per visible active index, in the form the
+ *                             compositor reads: u, v, -A/2, -B, -C/2 (conic
+ *                             A, B, C), o_eff, thr (the power below which alpha
+ *                             cannot reach 1/255), r, g, b, ex, ey (half-extents
+ *                             of the ellipse where it can)
  *   depth      [max_active]   camera depth (0 when culled)
  *   rect       [max_active][2] tile rect as x0 | y0 << 16, x1 | y1 << 16
  *                             (x0 >= x1 or y0 >= y1: culled) */

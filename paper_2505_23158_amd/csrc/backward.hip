@@ -97,9 +97,9 @@ __global__ __launch_bounds__(256) void k_composite_bwd(const FrameParams* __rest
             uint32_t a = sorted[rg.x + k];
             a = a < cap ? a : 0u;   // an index outside the active set would be a binning bug
             const float4 r0 = proj[3 * (size_t)a], r1 = proj[3 * (size_t)a + 1], r2 = proj[3 * (size_t)a + 2];
-            sa[lane] = make_float4(r0.x, r0.y, -0.5f * r0.z, -r0.w);
-            sb[lane] = make_float4(-0.5f * r1.x, r1.y, r2.w, r1.z);
-            sc[lane] = make_float4(r1.w, r2.x, 0.0f, 0.0f);
+            sa[lane] = r0;
+            sb[lane] = r1;
+            sc[lane] = make_float4(r2.x, r2.y, 0.0f, 0.0f);
             s_a[wave][lane] = a;
             hit = reaches(box_test(r0, r1, r2), bx0, bx0 + 7.0f, by0, by0 + 7.0f);
         }

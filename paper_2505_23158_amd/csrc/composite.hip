@@ -37,7 +37,8 @@ namespace lodge {
 namespace {
 
 // Records of one wave: three thirds of 65 float4 (65 = 64 batch slots + the
-// sentinel), [0] u, v, -A/2, -B; [1] -C/2, o, threshold, r; [2] g, b, -, -.
+// sentinel), each third one float4 of the projected record in its stored
+// form: [0] u, v, -A/2, -B; [1] -C/2, o, threshold, r; [2] g, b, ex, ey.
 constexpr uint32_t kSlots = 65;
 constexpr uint32_t kWaveRec = 3 * kSlots;
 constexpr uint32_t kThird = kSlots * sizeof(float4);   // bytes between the thirds
@@ -125,9 +126,9 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
 
         bool hit[4] = {false, false, false, false};
         if (cur) {
-            sa[lane] = make_float4(q0.x, q0.y, -0.5f * q0.z, -q0.w);
-            sa[kSlots + lane] = make_float4(-0.5f * q1.x, q1.y, q2.w, q1.z);
-            sa[2 * kSlots + lane] = make_float4(q1.w, q2.x, 0.0f, 0.0f);
+            sa[lane] = q0;
+            sa[kSlots + lane] = q1;
+            sa[2 * kSlots + lane] = q2;
             const BoxTest bt = box_test(q0, q1, q2);
             // exact test for the quadrant, bounding boxes for its sub-quadrants
             if (reaches(bt, bx0, bx0 + 7.0f, by0, by0 + 7.0f)) {

@@ -131,8 +131,8 @@ __device__ __forceinline__ void colour_batch(const LevelsArg& lv, const LevelDev
                 rgb[ch] = acc > 0.0f ? acc : 0.0f;
             }
             float* r = reinterpret_cast<float*>(proj + 3 * (size_t)a);
-            *reinterpret_cast<float2*>(r + 6) = make_float2(rgb[0], rgb[1]);
-            r[8] = rgb[2];
+            r[7] = rgb[0];
+            *reinterpret_cast<float2*>(r + 8) = make_float2(rgb[1], rgb[2]);
         }
     }
 }
@@ -288,9 +288,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                         const float rho = -2.0f * thr;
                         const float ex = rho > 0.0f ? sqrtf(rho * aa) : -1.0f;
                         const float ey = rho > 0.0f ? sqrtf(rho * cc) : -1.0f;
-                        r0 = make_float4(u, v, A, B);
-                        r1 = make_float4(C, o_eff, 0.0f, 0.0f);
-                        r2 = make_float4(0.0f, ex, ey, thr);
+                        // the record in the form the compositor reads it: the conic
+                        // pre-scaled to the power's coefficients (exact scalings)
+                        r0 = make_float4(u, v, -0.5f * A, -B);
+                        r1 = make_float4(-0.5f * C, o_eff, thr, 0.0f);
+                        r2 = make_float4(0.0f, 0.0f, ex, ey);
                         dep = tz;
                     }
                 }

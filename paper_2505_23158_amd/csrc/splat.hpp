@@ -1,13 +1,14 @@
 // Per-(pixel, splat) evaluation shared by the compositing kernel and its
 // adjoint, so both take exactly the same skip / clamp / stop decisions.
 //
-// A staged splat is three LDS words: geo = (u, v, -A/2, -B),
-// col = (-C/2, o_eff, skip threshold, r), gb = (g, b), where (A, B, C) is the
-// conic and the skip threshold, from the projection, is ln(1 / (255 o_eff))
-// - 1e-3 (+inf when o_eff <= 0): a power below it cannot give alpha >= 1/255,
-// so exp is not evaluated for it.  Explicit fmaf keeps the arithmetic
-// identical wherever this is inlined (the files are built without FMA
-// contraction).
+// A projected record is three float4, in the form the compositor reads:
+// (u, v, -A/2, -B), (-C/2, o_eff, skip threshold, r), (g, b, ex, ey), where
+// (A, B, C) is the conic, (ex, ey) the half-extents of the ellipse where
+// alpha can reach 1/255, and the skip threshold, from the projection, is
+// ln(1 / (255 o_eff)) - 1e-3 (+inf when o_eff <= 0): a power below it cannot
+// give alpha >= 1/255, so exp is not evaluated for it.  Explicit fmaf keeps
+// the arithmetic identical wherever this is inlined (the files are built
+// without FMA contraction).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,18 +19,6 @@ constexpr float kAlphaMax = 0.99f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTStop = 0.0001f;
 
-__device__ __forceinline__ void stage_splat(const float4* __restrict__ proj, uint32_t a, float4& geo, float4& col,
-                                            float2& gb)
-{
-    const float4 r0 = proj[3 * (size_t)a];
-    const float4 r1 = proj[3 * (size_t)a + 1];
-    const float4 r2 = proj[3 * (size_t)a + 2];
-    geo = make_float4(r0.x, r0.y, -0.5f * r0.z, -r0.w);
-    col = make_float4(-0.5f * r1.x, r1.y, r2.w, r1.z);
-    gb = make_float2(r1.w, r2.x);
-}
-
-// power = dx (-A/2 dx - B dy) + (-C/2 dy) dy, in five operations
 __device__ __forceinline__ float splat_power(const float4& geo, const float4& col, float px, float py, float& dx,
                                              float& dy)
 {
@@ -78,20 +67,21 @@ struct BoxTest {
     bool any;             // alpha can reach 1/255 somewhere
 };
 
-// r0 = (u, v, A, B), r1 = (C, ...), r2 = (.., ex, ey, thr) as written by the
-// projection; alpha >= 1/255 needs q(d) = A dx^2 + 2B dx dy + C dy^2 <= -2 thr.
+// r0, r1, r2: a projected record (above); alpha >= 1/255 needs
+// q(d) = A dx^2 + 2B dx dy + C dy^2 <= -2 thr.  The conic is recovered by
+// exact scalings of the stored coefficients.
 __device__ __forceinline__ BoxTest box_test(const float4& r0, const float4& r1, const float4& r2)
 {
     BoxTest b;
-    const float ex = r2.y, ey = r2.z;
+    const float ex = r2.z, ey = r2.w;
     b.any = ex >= 0.0f;   // false: alpha below 1/255 everywhere (or a non-finite record)
     b.u = r0.x;
     b.v = r0.y;
     b.mx = ex + 1e-3f * ex + 0.01f;
     b.my = ey + 1e-3f * ey + 0.01f;
-    b.A = r0.z;
-    b.B = r0.w;
-    b.C = r1.x;
+    b.A = -2.0f * r0.z;
+    b.B = -r0.w;
+    b.C = -2.0f * r1.x;
     // an approximate reciprocal moves an edge minimiser by an ulp, which
     // changes the form only to second order: far inside the margin below
     b.nba = -b.B * __builtin_amdgcn_rcpf(b.A);
@@ -99,7 +89,7 @@ __device__ __forceinline__ BoxTest box_test(const float4& r0, const float4& r1, 
     // rounding of the minimum and of the per-pixel power both grow with the
     // conditioning of the form; lam bounds the largest covariance eigenvalue
     // (approximate reciprocals: their ulp errors are far inside these margins)
-    const float rho = -2.0f * r2.w;
+    const float rho = -2.0f * r1.z;
     const float lam = (ex * ex + ey * ey) * __builtin_amdgcn_rcpf(rho);
     const float gamma = 1.001e-5f * (1.0f + lam);
     b.lim = gamma < 0.5f ? (rho + 1e-3f * rho) * __builtin_amdgcn_rcpf(1.0f - gamma) : INFINITY;

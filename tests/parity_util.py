@@ -60,7 +60,9 @@ def compare_projection(g, proj: oracle.Projection):
     assert np.array_equal(rect_g[vis_o], proj.rect[vis_o].astype(np.uint32)), "tile rectangles differ"
     # depth is a sort key: bit-exact
     assert np.array_equal(g["depth"][vis_o].view(np.uint32), proj.depth[vis_o].astype(np.float32).view(np.uint32))
-    got = np.concatenate([P[vis_o, 0:2], P[vis_o, 2:5], P[vis_o, 5:6], P[vis_o, 6:9]], axis=1)
+    # record: u, v, -A/2, -B, -C/2, o_eff, thr, r, g, b, ex, ey (the conic by exact scalings)
+    conic = np.stack([-2.0 * P[vis_o, 2], -P[vis_o, 3], -2.0 * P[vis_o, 4]], axis=1)
+    got = np.concatenate([P[vis_o, 0:2], conic, P[vis_o, 5:6], P[vis_o, 7:10]], axis=1)
     exp = np.concatenate([proj.uv[vis_o], proj.conic[vis_o], proj.o_eff[vis_o, None], proj.rgb[vis_o]], axis=1)
     err = np.abs(got - exp) / np.maximum(1.0, np.abs(exp))
     assert err.max(initial=0.0) <= 1e-5, f"projected values differ (max rel {err.max()})"
