@@ -90,9 +90,10 @@ __device__ __forceinline__ void sort_run(unsigned long long* s, const float* __r
     __syncthreads();
 }
 
-// 32-bit value of lane (lane ^ D) of the wave, without an LDS round trip.
-// Distances 1 and 2 are quad permutes and 4 and 8 two row shifts plus a
-// select (DPP); 16 and 32 are gfx950 lane-swaps of the value with a copy of
+// 32-bit value of lane (lane ^ D) of the wave.  Distances 1 and 2 are quad
+// permutes (DPP); 4 and 8 are swizzles through the LDS unit (no memory
+// access, and no VALU slot, which this VALU-bound network is short of); 16
+// and 32 are gfx950 lane-swaps of the value with a copy of
 // itself (permlane16_swap trades rows 1 and 3 of the first operand with rows
 // 0 and 2 of the second, permlane32_swap the upper half of the first with the
 // lower half of the second), after which the partner's value sits in the
@@ -105,10 +106,9 @@ __device__ __forceinline__ uint32_t xor_lane(uint32_t v)
     } else if constexpr (D == 2) {
         return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
     } else if constexpr (D == 4 || D == 8) {
-        // row_shl:D reads lane + D, row_shr:D reads lane - D (both stay inside the 16-lane row here)
-        const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x100 + D, 0xF, 0xF, false);
-        const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x110 + D, 0xF, 0xF, false);
-        return (__lane_id() & D) ? dn : up;
+        // swizzle in bit mode (and 0x1f, xor D inside 32 lanes): one LDS-unit
+        // instruction instead of two row shifts and a select on the VALU
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (D << 10) | 0x1F);
     } else if constexpr (D == 16) {
         const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
         return (__lane_id() & 16) ? r[0] : r[1];
