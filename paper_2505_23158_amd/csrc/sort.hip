@@ -241,6 +241,70 @@ __device__ __forceinline__ uint32_t rank_in(const uint32_t* __restrict__ b, uint
     return lo;
 }
 
+// A run of up to 8 x 512 keys (512 threads): each wave sorts 512 keys of it
+// in registers (64 lanes x 8, the bitonic network with no LDS stage and no
+// barrier; waves past the run's end only pad), then three merge-path rounds
+// in LDS double the sorted runs (512 -> 1024 -> 2048 -> 4096).  Each thread
+// makes 8 outputs of a round: a binary search on its diagonal finds how many
+// come from the left run (equal keys go left first), then 8 merge steps.
+// Only the ceil(n / 512) chunks that hold keys are sorted; the rest are
+// all-padding (~0, sorting last).
+__device__ __forceinline__ void sort_run_merge(unsigned long long* s, const float* __restrict__ depth,
+                                               uint32_t* __restrict__ run, uint32_t n, uint32_t cap)
+{
+    constexpr int E = 8, CH = 64 * E, P = 8 * CH;
+    static_assert(kSortThreads == 8 * 64 && 2 * P <= kSortLds, "eight waves, two LDS buffers of P keys");
+    const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t nch = (n + CH - 1) / CH;
+    unsigned long long x[E];
+    if (w < nch) {   // wave-uniform
+        const uint32_t c0 = w * CH, m = min(n - c0, (uint32_t)CH);
+        uint32_t idx[E], dep[E];
+#pragma unroll
+        for (int e = 0; e < E; e++) {
+            const uint32_t i = lane * E + e;
+            idx[e] = i < m ? run[c0 + i] : 0xffffffffu;
+        }
+#pragma unroll
+        for (int e = 0; e < E; e++) dep[e] = __float_as_uint(depth[idx[e] < cap ? idx[e] : 0u]);
+#pragma unroll
+        for (int e = 0; e < E; e++) x[e] = idx[e] < cap ? ((unsigned long long)dep[e] << 32) | idx[e] : ~0ull;
+        bitonic_regs<64, E, 9>(x, nullptr);
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; e++) x[e] = ~0ull;
+    }
+#pragma unroll
+    for (int e = 0; e < E; e++) s[w * CH + lane * E + e] = x[e];
+    __syncthreads();
+    unsigned long long* src = s;
+    unsigned long long* dst = s + P;
+#pragma unroll 1
+    for (uint32_t L = CH; L < (uint32_t)P; L <<= 1) {
+        const uint32_t o0 = threadIdx.x * E;
+        const uint32_t pair0 = o0 & ~(2 * L - 1), d = o0 - pair0;
+        const unsigned long long* A = src + pair0;
+        const unsigned long long* B = A + L;
+        uint32_t lo = d > L ? d - L : 0u, hi = d < L ? d : L;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (A[mid] <= B[d - mid - 1]) lo = mid + 1; else hi = mid;
+        }
+        uint32_t i = lo, j = d - lo;
+#pragma unroll
+        for (int e = 0; e < E; e++) {
+            const unsigned long long a = i < L ? A[i] : ~0ull, b = j < L ? B[j] : ~0ull;
+            const bool take_a = i < L && (j >= L || a <= b);
+            dst[o0 + e] = take_a ? a : b;
+            i += take_a ? 1u : 0u;
+            j += take_a ? 0u : 1u;
+        }
+        __syncthreads();
+        unsigned long long* t = src; src = dst; dst = t;
+    }
+    for (uint32_t p = threadIdx.x; p < n; p += kSortThreads) run[p] = src[p] == ~0ull ? 0xffffffffu : (uint32_t)src[p];
+}
+
 // A run longer than kSortLds: kSortLds-key chunks sorted in LDS, then
 // merge passes in global memory (ping-pong with scratch) where each key
 // finds its output slot by binary search in the sibling run.
@@ -307,7 +371,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort(const FrameParams* __rest
             const uint2 r = ranges[i < i_huge ? queues[i] : queues[T + (i - i_huge)]];
             const uint32_t n = r.y - r.x;
             if (n <= (uint32_t)kSortMid)
-                sort_run_regs<kSortThreads, kSortMid / kSortThreads, 12>(s, depth, sorted + r.x, n, cap);
+                sort_run_merge(s, depth, sorted + r.x, n, cap);
             else if (n <= (uint32_t)kSortLds) sort_run<kSortThreads, kSortLds>(s, depth, sorted + r.x, n, cap);
             else sort_huge_run(s, depth, sorted + r.x, scratch + r.x, n, cap);
         } else if (i < i_wave) {
