@@ -6,19 +6,18 @@
 // so the bit pattern orders like the value, and the index makes the order
 // total (ties in depth are broken by active index, i.e. by global id).
 //
-// Runs up to 8192 keys are sorted by a bitonic network held in registers:
-// each thread keeps E consecutive keys; stages whose partner is in the same
-// thread compare registers, stages whose partner is in another lane of the
-// wave exchange keys with lane shuffles (DPP where the distance allows), and
-// only stages whose partner is in another wave go through LDS
-// (double-buffered, one barrier per stage).  One launch, k_sort, sorts every
-// run, by length band:
+// Short runs are sorted by bitonic networks held in registers: each thread
+// keeps E consecutive keys; stages whose partner is in the same thread
+// compare registers, and stages whose partner is in another lane exchange
+// keys with lane permutes (DPP quad permutes, swizzles, gfx950 lane swaps).
+// Longer runs are cut into 512-key pieces, each sorted by one wave in
+// registers, and the pieces are merged in LDS by merge-path rounds.  One
+// launch, k_sort, sorts every run, by length band:
 //   <= 256         one wave, 1-4 keys per lane: no LDS, no barrier;
-//   (256, 2048]    256 threads x 8 keys (four runs per block, in step);
-//   (2048, 4096]   1024 threads x 4 keys;
-//   (4096, 8192]   1024 threads x 8 keys;
-//   (8192, 16384]  the bitonic network in 128 KB of LDS;
-//   > 16384        16384-key chunks sorted in LDS, then merge passes in
+//   (256, 2048]    four waves: 512-key wave sorts, two merge rounds;
+//   (2048, 4096]   eight waves: 512-key wave sorts, three merge rounds;
+//   (4096, 8192]   the bitonic network in the block's 64 KB of LDS;
+//   > 8192         8192-key chunks sorted in LDS, then merge passes in
 //                  global memory where each key finds its output slot by
 //                  binary search in the sibling run.
 #include "lodge_internal.hpp"
@@ -241,20 +240,24 @@ __device__ __forceinline__ uint32_t rank_in(const uint32_t* __restrict__ b, uint
     return lo;
 }
 
-// A run of up to 8 x 512 keys (512 threads): each wave sorts 512 keys of it
-// in registers (64 lanes x 8, the bitonic network with no LDS stage and no
-// barrier; waves past the run's end only pad), then three merge-path rounds
-// in LDS double the sorted runs (512 -> 1024 -> 2048 -> 4096).  Each thread
-// makes 8 outputs of a round: a binary search on its diagonal finds how many
-// come from the left run (equal keys go left first), then 8 merge steps.
-// Only the ceil(n / 512) chunks that hold keys are sorted; the rest are
-// all-padding (~0, sorting last).
+// A run of up to NW x 512 keys, sorted by a group of NW waves (the NW x 64
+// threads from group_base on): each wave sorts 512 keys of it in registers
+// (64 lanes x 8, the bitonic network with no LDS stage and no barrier; waves
+// past the run's end only pad), then log2(NW) merge-path rounds in LDS
+// double the sorted runs.  Each thread makes 8 outputs of a round: a binary
+// search on its diagonal finds how many come from the left run (equal keys
+// go left first), then 8 merge steps.  Only the ceil(n / 512) chunks that
+// hold keys are sorted; the rest are all-padding (~0, sorting last).  s: 2 x
+// NW x 512 keys of LDS for the group.  Every thread of the block calls this
+// (the rounds end at block barriers), with the same NW.
+template <int NW>
 __device__ __forceinline__ void sort_run_merge(unsigned long long* s, const float* __restrict__ depth,
                                                uint32_t* __restrict__ run, uint32_t n, uint32_t cap)
 {
-    constexpr int E = 8, CH = 64 * E, P = 8 * CH;
-    static_assert(kSortThreads == 8 * 64 && 2 * P <= kSortLds, "eight waves, two LDS buffers of P keys");
-    const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    constexpr int E = 8, CH = 64 * E, P = NW * CH, NT = NW * 64;
+    static_assert(kSortThreads % NT == 0, "groups tile the block");
+    const uint32_t t = threadIdx.x % NT;
+    const uint32_t w = t >> 6, lane = t & 63;
     const uint32_t nch = (n + CH - 1) / CH;
     unsigned long long x[E];
     if (w < nch) {   // wave-uniform
@@ -281,7 +284,7 @@ __device__ __forceinline__ void sort_run_merge(unsigned long long* s, const floa
     unsigned long long* dst = s + P;
 #pragma unroll 1
     for (uint32_t L = CH; L < (uint32_t)P; L <<= 1) {
-        const uint32_t o0 = threadIdx.x * E;
+        const uint32_t o0 = t * E;
         const uint32_t pair0 = o0 & ~(2 * L - 1), d = o0 - pair0;
         const unsigned long long* A = src + pair0;
         const unsigned long long* B = A + L;
@@ -300,9 +303,9 @@ __device__ __forceinline__ void sort_run_merge(unsigned long long* s, const floa
             j += take_a ? 0u : 1u;
         }
         __syncthreads();
-        unsigned long long* t = src; src = dst; dst = t;
+        unsigned long long* tmp = src; src = dst; dst = tmp;
     }
-    for (uint32_t p = threadIdx.x; p < n; p += kSortThreads) run[p] = src[p] == ~0ull ? 0xffffffffu : (uint32_t)src[p];
+    for (uint32_t p = t; p < n; p += NT) run[p] = src[p] == ~0ull ? 0xffffffffu : (uint32_t)src[p];
 }
 
 // A run longer than kSortLds: kSortLds-key chunks sorted in LDS, then
@@ -339,12 +342,12 @@ __device__ __forceinline__ void sort_huge_run(unsigned long long* s, const float
 // All runs in one launch of 512-thread blocks with 64 KB of LDS, two per
 // compute unit.  Work items, longest first, are handed out by a counter
 // (one atomic per item, not per key):
-//   [0, n_large)   one queued run in (2048, 16384]: up to 4096 keys in
-//                  registers (512 x 8), up to 8192 in the LDS network,
+//   [0, n_large)   one queued run in (2048, 16384]: up to 4096 keys by
+//                  wave sorts and merges, up to 8192 in the LDS network,
 //                  longer by LDS chunks and merge passes;
 //   n_huge items   one run > 16384, by LDS chunks and merge passes;
 //   n_mid / 2      two queued runs in (256, 2048], one per 256 threads
-//                  (2048-key networks in step: the block barriers match);
+//                  (their merge rounds in step: the block barriers match);
 //   T / 8          eight tiles, one per wave, sorted if 1 < n <= 256.
 // Every block leaves once the items run out.
 __global__ __launch_bounds__(kSortThreads) void k_sort(const FrameParams* __restrict__ fp, FrameInfo* info,
@@ -371,14 +374,14 @@ __global__ __launch_bounds__(kSortThreads) void k_sort(const FrameParams* __rest
             const uint2 r = ranges[i < i_huge ? queues[i] : queues[T + (i - i_huge)]];
             const uint32_t n = r.y - r.x;
             if (n <= (uint32_t)kSortMid)
-                sort_run_merge(s, depth, sorted + r.x, n, cap);
+                sort_run_merge<kSortThreads / 64>(s, depth, sorted + r.x, n, cap);
             else if (n <= (uint32_t)kSortLds) sort_run<kSortThreads, kSortLds>(s, depth, sorted + r.x, n, cap);
             else sort_huge_run(s, depth, sorted + r.x, scratch + r.x, n, cap);
         } else if (i < i_wave) {
             const uint32_t g = threadIdx.x / 256, q = kGroups * (i - i_mid) + g;
             uint2 r = make_uint2(0u, 0u);   // an empty run still steps through the network
             if (q < nm) r = ranges[queues[2 * T + q]];
-            sort_run_regs<256, kSortSmall / 256, 11>(s + g * 2 * kSortSmall, depth, sorted + r.x, r.y - r.x, cap);
+            sort_run_merge<kSortSmall / 512>(s + g * 2 * kSortSmall, depth, sorted + r.x, r.y - r.x, cap);
         } else {
             const uint32_t t = kWaves * (i - i_wave) + threadIdx.x / 64;
             const uint2 r = t < T ? ranges[t] : make_uint2(0u, 0u);
