@@ -93,6 +93,12 @@ __device__ __forceinline__ float ld_plane(const float* plane, uint32_t off)
     return *(const gfloat*)((const gchar*)plane + off);
 }
 
+// The same, marked as streamed once (non-temporal: not kept in the caches).
+__device__ __forceinline__ float ld_plane_stream(const float* plane, uint32_t off)
+{
+    return __builtin_nontemporal_load((const gfloat*)((const gchar*)plane + off));
+}
+
 // Field-by-field store of a camera held in kernel arguments (a struct
 // assignment would stage the argument through private memory).
 __device__ __forceinline__ void store_camera(lodge_camera* __restrict__ d, const lodge_camera& c)

@@ -173,17 +173,17 @@ __global__ __launch_bounds__(kSelBlock) void k_select(LevelsArg lv, const FrameP
 #pragma unroll
             for (int r = 0; r < kSelItems; r++) {
                 const uint32_t o = o0 + (uint32_t)r * (kSelBlock * 4u);
-                mx[r] = ld_plane(px, o);
-                my[r] = ld_plane(py, o);
-                mz[r] = ld_plane(pz, o);
+                mx[r] = ld_plane_stream(px, o);
+                my[r] = ld_plane_stream(py, o);
+                mz[r] = ld_plane_stream(pz, o);
             }
         } else {
 #pragma unroll
             for (int r = 0; r < kSelItems; r++) {
                 const uint32_t o = min(i0 + (uint32_t)r * kSelBlock + tid, n - 1) * 4u;
-                mx[r] = ld_plane(px, o);
-                my[r] = ld_plane(py, o);
-                mz[r] = ld_plane(pz, o);
+                mx[r] = ld_plane_stream(px, o);
+                my[r] = ld_plane_stream(py, o);
+                mz[r] = ld_plane_stream(pz, o);
             }
         }
     } else {
