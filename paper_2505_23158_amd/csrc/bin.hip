@@ -205,7 +205,7 @@ __global__ __launch_bounds__(256) void k_inst_off(const FrameInfo* info, const u
     const uint32_t waves = gridDim.x * (blockDim.x >> 6);
     for (uint32_t c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < nc; c += waves) {
         const uint32_t a = c * kProjChunk + lane;
-        const uint32_t x = a < n ? vt[a] : 0u;
+        const uint32_t x = a < n ? __builtin_nontemporal_load(vt + a) : 0u;   // read once
         uint32_t inc = x;
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t o = __shfl_up(inc, off);
@@ -299,8 +299,8 @@ __global__ __launch_bounds__(kBinThreads) void k_emit_hist(const FrameParams* fp
 #pragma unroll
             for (int q = 0; q < kPer; q++) {
                 const uint32_t k = k0 + q * kBinThreads + threadIdx.x;
-                o[q] = k < cnt ? vis_off[lo + k] : 0u;
-                g[q] = k < cnt ? vis_id[lo + k] : 0u;
+                o[q] = k < cnt ? __builtin_nontemporal_load(vis_off + lo + k) : 0u;   // read once
+                g[q] = k < cnt ? __builtin_nontemporal_load(vis_id + lo + k) : 0u;
             }
 #pragma unroll
             for (int q = 0; q < kPer; q++) {
@@ -524,7 +524,9 @@ __global__ __launch_bounds__(kBinThreads) void k_scatter(const FrameParams* fp, 
 #pragma unroll
         for (int q = 0; q < kPer; q++) {
             const uint32_t j = j0 + q * kBinThreads + threadIdx.x;
-            e[q] = j < j1 ? inst[j] : make_uint2(0u, 0u);
+            unsigned long long v = 0;
+            if (j < j1) v = __builtin_nontemporal_load(reinterpret_cast<const unsigned long long*>(inst) + j);   // read once
+            e[q] = make_uint2((uint32_t)v, (uint32_t)(v >> 32));
         }
         uint32_t base[kPer];
 #pragma unroll

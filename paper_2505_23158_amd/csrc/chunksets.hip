@@ -102,8 +102,9 @@ __global__ __launch_bounds__(kSelBlock) void k_sets_mark(const FrameParams* fp, 
     const uint32_t tile = blockIdx.x;
     if (tile >= ntiles) return;
     const int32_t f = fp->f, o = fp->o;
-    const uint32_t wf = sets[((size_t)f * ntiles + tile) * kSelBlock + tid];
-    const uint32_t wo = o >= 0 ? sets[((size_t)o * ntiles + tile) * kSelBlock + tid] : 0u;
+    // the two sets are streamed (read once per frame)
+    const uint32_t wf = __builtin_nontemporal_load(sets + ((size_t)f * ntiles + tile) * kSelBlock + tid);
+    const uint32_t wo = o >= 0 ? __builtin_nontemporal_load(sets + ((size_t)o * ntiles + tile) * kSelBlock + tid) : 0u;
     const uint32_t bits = spread16(wf) | (spread16(wo) << 1);
     uint32_t mine = (uint32_t)__popc(wf | wo);
     for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off);

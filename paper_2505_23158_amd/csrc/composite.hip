@@ -213,11 +213,12 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
     if (inside) {
         const size_t p = (size_t)y * W + x;
         const size_t HW = (size_t)W * H;
-        image[p] = cr + T * fp->cam.bg[0];
-        image[HW + p] = cg + T * fp->cam.bg[1];
-        image[2 * HW + p] = cb + T * fp->cam.bg[2];
-        final_T[p] = T;
-        n_contrib[p] = last;
+        // outputs, not read again by this frame: streamed past the caches
+        __builtin_nontemporal_store(cr + T * fp->cam.bg[0], image + p);
+        __builtin_nontemporal_store(cg + T * fp->cam.bg[1], image + HW + p);
+        __builtin_nontemporal_store(cb + T * fp->cam.bg[2], image + 2 * HW + p);
+        __builtin_nontemporal_store(T, final_T + p);
+        __builtin_nontemporal_store(last, n_contrib + p);
     } else {
         neval = 0;
     }

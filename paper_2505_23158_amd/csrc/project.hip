@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
         float dep = 0.0f, d0n = 0.0f, d1n = 0.0f, d2n = 0.0f;
         int32_t x0 = 0, y0 = 0, x1 = 0, y1 = 0;
-        const uint32_t g = a < n_act ? ids[a] : 0u;
+        const uint32_t g = a < n_act ? __builtin_nontemporal_load(ids + a) : 0u;
         const int lvl = level_index(lv, g);
         bool todo = a < n_act;
         // one pass per level present in the wave (almost always one): the
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                         d0n = d0 / dn;
                         d1n = d1 / dn;
                         d2n = d2 / dn;
-                        const float o_eff = ((ld(opac, off) * wsel[a]) * comp3) * comp2;
+                        const float o_eff = ((ld(opac, off) * __builtin_nontemporal_load(wsel + a)) * comp3) * comp2;
                         // compositing aids: below power thr alpha cannot reach 1/255 (margin 1e-3);
                         // (ex, ey) half-extents of the ellipse where it can: d^T conic d <= -2 thr
                         const float thr = o_eff > 0.0f ? -logf(255.0f * o_eff) - 1e-3f : INFINITY;

@@ -293,7 +293,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select_emit(LevelsArg lv, const F
     for (int j = 1; j < LODGE_MAX_LEVELS; j++)
         if (j < lv.L && tile >= lv.first_block[j]) l = j;
     const uint32_t gbase = lv.lv[l].base + (tile - lv.first_block[l]) * (uint32_t)kSelTile;
-    const uint32_t bits = bits_in[(size_t)tile * kSelBlock + tid];
+    const uint32_t bits = __builtin_nontemporal_load(bits_in + (size_t)tile * kSelBlock + tid);   // read once
     // read before the barriers below, so the loads overlap the in-tile scan
     const uint32_t excl = off[tile];
     const float t = fp->t, w_o = fp->w_o;
