@@ -172,6 +172,7 @@ __global__ void k_render_setup(FrameParams* fp, FrameInfo* info, lodge_camera ca
         info->n_large = 0;
         info->n_huge = 0;
         info->n_mid = 0;
+        info->n_xl = 0;
         info->n_binned = 0;
         info->sort_next = 0;
         info->scan_done = 0;
@@ -467,7 +468,7 @@ lodge_status read_info(const lodge_workspace* ws, lodge_frame_info* out, void* s
     out->f = fi.f;
     out->o = fi.o;
     out->t = fi.t;
-    out->n_long = fi.n_large;
+    out->n_long = fi.n_large + fi.n_xl;
     out->n_merge = fi.n_huge;
     return LODGE_OK;
 }

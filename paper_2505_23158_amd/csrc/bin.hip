@@ -369,13 +369,16 @@ __global__ __launch_bounds__(kBinThreads) void k_emit_hist(const FrameParams* fp
 // long-list queues, longest list.
 constexpr int kTilesThreads = 1024;
 
-// Sort queue of a tile list, as one unit in a packed count: large (2048,
-// 16384] in bits 0-20, huge above in bits 21-41, mid (256, 2048] in 42-62.
-constexpr unsigned long long kQMask = (1ull << 21) - 1;
+// Sort queue of a tile list, as one unit in a packed count of four 16-bit
+// fields (T <= kMaxTiles < 2^16): (kSortSmall, kSortMid] in bits 0-15, huge
+// (above kSortLarge) in 16-31, mid (kSortWave, kSortSmall] in 32-47, and
+// (kSortMid, kSortLarge] in 48-63.
+constexpr unsigned long long kQMask = 0xffffull;
 __device__ __forceinline__ unsigned long long queue_unit(uint32_t c)
 {
-    return c > (uint32_t)kSortLarge ? 1ull << 21
-         : c > (uint32_t)kSortSmall ? 1ull : c > (uint32_t)kSortWave ? 1ull << 42 : 0ull;
+    return c > (uint32_t)kSortLarge ? 1ull << 16
+         : c > (uint32_t)kSortMid   ? 1ull << 48
+         : c > (uint32_t)kSortSmall ? 1ull : c > (uint32_t)kSortWave ? 1ull << 32 : 0ull;
 }
 
 // Length class of a tile list in the compositing order (longest first).
@@ -475,8 +478,8 @@ __global__ __launch_bounds__(kTilesThreads) void k_tile_scan(const FrameParams* 
             b += (uint32_t)(cls_tot >> (16 * k)) & 0xffffu;
         }
     }
-    uint32_t nl = (uint32_t)(bpos & kQMask), nh = (uint32_t)((bpos >> 21) & kQMask),
-             nm = (uint32_t)((bpos >> 42) & kQMask);
+    uint32_t nl = (uint32_t)(bpos & kQMask), nh = (uint32_t)((bpos >> 16) & kQMask),
+             nm = (uint32_t)((bpos >> 32) & kQMask), nx = (uint32_t)((bpos >> 48) & kQMask);
     for (uint32_t t = t0; t < t1; t++) {
         const uint32_t c = s_c[t];
         // offsets only matter when the total fits the instance capacity (< 2^32)
@@ -485,7 +488,9 @@ __global__ __launch_bounds__(kTilesThreads) void k_tile_scan(const FrameParams* 
         const uint32_t q = length_class(c);
         order[base[q] + ((uint32_t)(cpos >> (16 * q)) & 0xffffu)] = t;
         cpos += 1ull << (16 * q);
+        // (kSortMid, kSortLarge] fills the first region from its end
         if (c > (uint32_t)kSortLarge) large[T + nh++] = t;
+        else if (c > (uint32_t)kSortMid) large[T - 1 - nx++] = t;
         else if (c > (uint32_t)kSortSmall) large[nl++] = t;
         else if (c > (uint32_t)kSortWave) large[2 * T + nm++] = t;
     }
@@ -494,8 +499,9 @@ __global__ __launch_bounds__(kTilesThreads) void k_tile_scan(const FrameParams* 
         for (int w = 0; w < kTilesThreads / 64; w++) m = max(m, s_max[w]);
         info->max_tile_len = m;
         info->n_large = (uint32_t)(big_tot & kQMask);
-        info->n_huge = (uint32_t)((big_tot >> 21) & kQMask);
-        info->n_mid = (uint32_t)((big_tot >> 42) & kQMask);
+        info->n_huge = (uint32_t)((big_tot >> 16) & kQMask);
+        info->n_mid = (uint32_t)((big_tot >> 32) & kQMask);
+        info->n_xl = (uint32_t)((big_tot >> 48) & kQMask);
     }
 }
 

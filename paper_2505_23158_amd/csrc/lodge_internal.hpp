@@ -73,9 +73,10 @@ struct FrameInfo {
     uint32_t overflow;
     int32_t f, o;
     float t;
-    uint32_t n_large;     // tiles sorted by the large-list kernel
-    uint32_t n_huge;      // tiles sorted by the merge fallback
-    uint32_t n_mid;       // tiles sorted by the mid-length kernel
+    uint32_t n_large;     // tiles with a list in (kSortSmall, kSortMid]
+    uint32_t n_huge;      // tiles with a list longer than kSortLarge
+    uint32_t n_mid;       // tiles with a list in (kSortWave, kSortSmall]
+    uint32_t n_xl;        // tiles with a list in (kSortMid, kSortLarge]
     uint32_t n_binned;    // actives with at least one tile
     uint32_t sort_next;   // next work item of the per-tile sort
     uint32_t scan_done;   // chunk-scan blocks that have written their totals

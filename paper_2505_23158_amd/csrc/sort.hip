@@ -342,10 +342,10 @@ __device__ __forceinline__ void sort_huge_run(unsigned long long* s, const float
 // All runs in one launch of 512-thread blocks with 64 KB of LDS, two per
 // compute unit.  Work items, longest first, are handed out by a counter
 // (one atomic per item, not per key):
-//   [0, n_large)   one queued run in (2048, 16384]: up to 4096 keys by
-//                  wave sorts and merges, up to 8192 in the LDS network,
-//                  longer by LDS chunks and merge passes;
 //   n_huge items   one run > 16384, by LDS chunks and merge passes;
+//   n_xl items     one run in (4096, 16384]: up to 8192 in the LDS network,
+//                  longer by LDS chunks and merge passes;
+//   n_large items  one run in (2048, 4096], by wave sorts and merges;
 //   n_mid / 2      two queued runs in (256, 2048], one per 256 threads
 //                  (their merge rounds in step: the block barriers match);
 //   T / 8          eight tiles, one per wave, sorted if 1 < n <= 256.
@@ -361,9 +361,10 @@ __global__ __launch_bounds__(kSortThreads) void k_sort(const FrameParams* __rest
     __shared__ unsigned long long s[kSortLds];
     __shared__ uint32_t s_item;
     const uint32_t T = (uint32_t)(fp->TX * fp->TY);
-    const uint32_t nl = info->n_large, nh = info->n_huge, nm = info->n_mid;
-    const uint32_t i_huge = nl, i_mid = i_huge + nh, i_wave = i_mid + (nm + kGroups - 1) / kGroups,
-                   n_items = i_wave + (T + kWaves - 1) / kWaves;
+    const uint32_t nl = info->n_large, nh = info->n_huge, nm = info->n_mid, nx = info->n_xl;
+    // the longest runs first: huge, then (4096, 16384], then (2048, 4096]
+    const uint32_t i_xl = nh, i_large = i_xl + nx, i_mid = i_large + nl,
+                   i_wave = i_mid + (nm + kGroups - 1) / kGroups, n_items = i_wave + (T + kWaves - 1) / kWaves;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(&info->sort_next, 1u);
         __syncthreads();
@@ -371,7 +372,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort(const FrameParams* __rest
         __syncthreads();
         if (i >= n_items) break;
         if (i < i_mid) {
-            const uint2 r = ranges[i < i_huge ? queues[i] : queues[T + (i - i_huge)]];
+            const uint32_t tile = i < i_xl ? queues[T + i] : i < i_large ? queues[T - 1 - (i - i_xl)] : queues[i - i_large];
+            const uint2 r = ranges[tile];
             const uint32_t n = r.y - r.x;
             if (n <= (uint32_t)kSortMid)
                 sort_run_merge<kSortThreads / 64>(s, depth, sorted + r.x, n, cap);
