@@ -16,8 +16,9 @@
 //   <= 256         one wave, 1-4 keys per lane: no LDS, no barrier;
 //   (256, 2048]    four waves: 512-key wave sorts, two merge rounds;
 //   (2048, 4096]   eight waves: 512-key wave sorts, three merge rounds;
-//   (4096, 8192]   the bitonic network in the block's 64 KB of LDS;
-//   > 8192         8192-key chunks sorted in LDS, then merge passes in
+//   (4096, 8192]   both halves sorted so, then one merge-path merge of the
+//                  two from the block's 64 KB of LDS into the run;
+//   > 8192         8192-key chunks sorted so, then merge passes in
 //                  global memory where each key finds its output slot by
 //                  binary search in the sibling run.
 #include "lodge_internal.hpp"
@@ -35,58 +36,6 @@ __device__ __forceinline__ unsigned long long key_of(const float* __restrict__ d
 {
     if (a >= cap) return ~0ull;
     return ((unsigned long long)__float_as_uint(depth[a]) << 32) | a;
-}
-
-__device__ __forceinline__ uint32_t next_pow2(uint32_t n)
-{
-    uint32_t p = 1;
-    while (p < n) p <<= 1;
-    return p;
-}
-
-// Ascending bitonic sort of s[0, P), P a power of two; all threads of the block take part.
-template <int NT>
-__device__ __forceinline__ void bitonic_lds(unsigned long long* s, uint32_t P)
-{
-    for (uint32_t k = 2; k <= P; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t p = threadIdx.x; p < (P >> 1); p += NT) {
-                const uint32_t i = (p / j) * (2 * j) + (p % j);
-                const uint32_t q = i + j;
-                const unsigned long long x = s[i], y = s[q];
-                const bool up = (i & k) == 0;
-                if ((x > y) == up) { s[i] = y; s[q] = x; }
-            }
-            __syncthreads();
-        }
-    }
-}
-
-template <int NT, int CAP>
-__device__ __forceinline__ void sort_run(unsigned long long* s, const float* __restrict__ proj,
-                                         uint32_t* __restrict__ run, uint32_t n, uint32_t cap)
-{
-    const uint32_t P = next_pow2(n);
-    for (uint32_t k0 = 0; k0 < P; k0 += 4 * NT) {
-        // four keys per thread in flight: index loads, then depth loads
-        uint32_t idx[4], dep[4];
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const uint32_t k = k0 + q * NT + threadIdx.x;
-            idx[q] = k < n ? run[k] : 0xffffffffu;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; q++) dep[q] = __float_as_uint(proj[idx[q] < cap ? idx[q] : 0u]);
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const uint32_t k = k0 + q * NT + threadIdx.x;
-            if (k < P) s[k] = idx[q] < cap ? ((unsigned long long)dep[q] << 32) | idx[q] : ~0ull;
-        }
-    }
-    __syncthreads();
-    bitonic_lds<NT>(s, P);
-    for (uint32_t k = threadIdx.x; k < n; k += NT) run[k] = s[k] == ~0ull ? 0xffffffffu : (uint32_t)s[k];
-    __syncthreads();
 }
 
 // 32-bit value of lane (lane ^ D) of the wave.  Distances 1 and 2 are quad
@@ -308,7 +257,62 @@ __device__ __forceinline__ void sort_run_merge(unsigned long long* s, const floa
     for (uint32_t p = t; p < n; p += NT) run[p] = src[p] == ~0ull ? 0xffffffffu : (uint32_t)src[p];
 }
 
-// A run longer than kSortLds: kSortLds-key chunks sorted in LDS, then
+// A run in (kSortMid, kSortLds]: both halves (the first kSortMid keys and
+// the rest) are sorted in place by the merge sort above, then read back into
+// LDS as keys, which just fills it, and merged by merge path straight into
+// the run: each thread finds where its E outputs start on the diagonal and
+// writes them in order.
+__device__ __forceinline__ void sort_run_halves(unsigned long long* s, const float* __restrict__ depth,
+                                                uint32_t* __restrict__ run, uint32_t n, uint32_t cap)
+{
+    constexpr uint32_t H = kSortMid, E = kSortLds / kSortThreads;
+    sort_run_merge<kSortThreads / 64>(s, depth, run, H, cap);
+    __syncthreads();   // the first sort's last LDS reads, before the second's writes
+    sort_run_merge<kSortThreads / 64>(s, depth, run + H, n - H, cap);
+    __syncthreads();   // the sorted halves are in the run, for every thread
+    const uint32_t m = n - H;
+    // keys back into LDS, eight per thread in flight: index loads, then depth loads
+#pragma unroll 1
+    for (uint32_t e0 = 0; e0 < E; e0 += 8) {
+        uint32_t idx[8], dep[8];
+#pragma unroll
+        for (uint32_t e = 0; e < 8; e++) {
+            const uint32_t k = (e0 + e) * kSortThreads + threadIdx.x;
+            idx[e] = k < n ? run[k] : 0xffffffffu;
+        }
+#pragma unroll
+        for (uint32_t e = 0; e < 8; e++) dep[e] = __float_as_uint(depth[idx[e] < cap ? idx[e] : 0u]);
+#pragma unroll
+        for (uint32_t e = 0; e < 8; e++) {
+            const uint32_t k = (e0 + e) * kSortThreads + threadIdx.x;
+            if (k < n) s[k] = idx[e] < cap ? ((unsigned long long)dep[e] << 32) | idx[e] : ~0ull;
+        }
+    }
+    __syncthreads();
+    const unsigned long long* A = s;
+    const unsigned long long* B = s + H;
+    const uint32_t d = threadIdx.x * E;
+    if (d < n) {
+        uint32_t lo = d > m ? d - m : 0u, hi = d < H ? d : H;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (A[mid] <= B[d - mid - 1]) lo = mid + 1; else hi = mid;
+        }
+        uint32_t i = lo, j = d - lo;
+#pragma unroll 2
+        for (uint32_t e = 0; e < E; e++) {
+            const unsigned long long a = i < H ? A[i] : ~0ull, b = j < m ? B[j] : ~0ull;
+            const bool take_a = i < H && (j >= m || a <= b);
+            const unsigned long long x = take_a ? a : b;
+            if (d + e < n) run[d + e] = x == ~0ull ? 0xffffffffu : (uint32_t)x;
+            i += take_a ? 1u : 0u;
+            j += take_a ? 0u : 1u;
+        }
+    }
+    __syncthreads();   // LDS and the run are free for the next step
+}
+
+// A run longer than kSortLds: kSortLds-key chunks sorted as above, then
 // merge passes in global memory (ping-pong with scratch) where each key
 // finds its output slot by binary search in the sibling run.
 __device__ __forceinline__ void sort_huge_run(unsigned long long* s, const float* __restrict__ proj,
@@ -317,8 +321,15 @@ __device__ __forceinline__ void sort_huge_run(unsigned long long* s, const float
 {
     uint32_t* src = run;
     uint32_t* dst = tmp;
-    for (uint32_t c0 = 0; c0 < n; c0 += kSortLds)
-        sort_run<kSortThreads, kSortLds>(s, proj, src + c0, min((uint32_t)kSortLds, n - c0), cap);
+    for (uint32_t c0 = 0; c0 < n; c0 += kSortLds) {
+        const uint32_t len = min((uint32_t)kSortLds, n - c0);
+        if (len > (uint32_t)kSortMid) {
+            sort_run_halves(s, proj, src + c0, len, cap);
+        } else {
+            sort_run_merge<kSortThreads / 64>(s, proj, src + c0, len, cap);
+            __syncthreads();
+        }
+    }
     // merge passes: run pairs [i, i + w) and [i + w, i + 2w)
     for (uint32_t w = kSortLds; w < n; w <<= 1) {
         for (uint32_t k = threadIdx.x; k < n; k += kSortThreads) {
@@ -343,8 +354,8 @@ __device__ __forceinline__ void sort_huge_run(unsigned long long* s, const float
 // compute unit.  Work items, longest first, are handed out by a counter
 // (one atomic per item, not per key):
 //   n_huge items   one run > 16384, by LDS chunks and merge passes;
-//   n_xl items     one run in (4096, 16384]: up to 8192 in the LDS network,
-//                  longer by LDS chunks and merge passes;
+//   n_xl items     one run in (4096, 16384]: up to 8192 by two merge sorts
+//                  and an LDS merge, longer by such chunks and merge passes;
 //   n_large items  one run in (2048, 4096], by wave sorts and merges;
 //   n_mid / 2      two queued runs in (256, 2048], one per 256 threads
 //                  (their merge rounds in step: the block barriers match);
@@ -377,7 +388,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort(const FrameParams* __rest
             const uint32_t n = r.y - r.x;
             if (n <= (uint32_t)kSortMid)
                 sort_run_merge<kSortThreads / 64>(s, depth, sorted + r.x, n, cap);
-            else if (n <= (uint32_t)kSortLds) sort_run<kSortThreads, kSortLds>(s, depth, sorted + r.x, n, cap);
+            else if (n <= (uint32_t)kSortLds) sort_run_halves(s, depth, sorted + r.x, n, cap);
             else sort_huge_run(s, depth, sorted + r.x, scratch + r.x, n, cap);
         } else if (i < i_wave) {
             const uint32_t g = threadIdx.x / 256, q = kGroups * (i - i_mid) + g;
