@@ -10,9 +10,14 @@ per-tile sort, compositing), inputs resident in HBM.  Prints ONE JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload large|lod|plain]
 
+"value" is the path's throughput with --in-flight frames (default 3) in
+flight: one renderer (workspace, selection, image) and one stream per frame
+slot, frames handed out round robin, so that one frame's compositing (VALU
+bound) overlaps the next frame's selection and projection (HBM bound).  The
+same K frames one after another on one stream, with events between the
+stages, give "serial" and the stage times behind "stages" and "roofline".
 The frames/s protocol of the paper's evaluation (median of 7 per image,
-FPS = 1 / mean time) is reported beside the steady-state number as
-"paper_protocol_fps".
+FPS = 1 / mean time) is reported beside them as "paper_protocol_fps".
 """
 from __future__ import annotations
 
@@ -195,6 +200,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--no-paper-protocol", action="store_true", help="skip the median-of-7 pass")
+    ap.add_argument("--in-flight", type=int, default=3,
+                    help="frames in flight for the throughput pass: one renderer (workspace, outputs) and one "
+                         "stream each, frames handed out round robin")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed region, one device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -218,6 +226,11 @@ def main():
     log(f"[bench] {desc['workload']}: generated in {time.perf_counter() - t0:.1f} s")
     dev = L.Scene.from_synth(sc)
     R = L.Renderer(dev, cams[0].width, cams[0].height, max_active=max_active, max_instances=max_inst)
+    F = max(1, args.in_flight)
+    # frames in flight: renderer 0 is R; each has its own stream at the default priority
+    rens = [R] + [L.Renderer(dev, cams[0].width, cams[0].height, max_active=max_active, max_instances=max_inst)
+                  for _ in range(F - 1)]
+    streams = [torch.cuda.Stream() for _ in range(F)]
     torch.cuda.synchronize()
     log("[bench] scene resident on the device")
 
@@ -234,10 +247,25 @@ def main():
              "max_tile_len")}
     log(f"[bench] per-frame means over {len(stats)} frames: " + ", ".join(f"{k}={v:.4g}" for k, v in mean.items()))
 
-    # warm-up
-    for k in range(args.warmup):
-        R.frame(cams[k % len(cams)], mode)
+    # warm-up, on every renderer and stream
+    for k in range(max(args.warmup, F)):
+        rens[k % F].frame(cams[k % len(cams)], mode, stream=streams[k % F])
     torch.cuda.synchronize()
+
+    def throughput(select):
+        """K frames of the path with F in flight: frame k goes to renderer k % F on its own stream, so one
+        frame's compositing overlaps the next frames' selection and projection.  Every frame is whole (select,
+        project, bin, sort, composite into its renderer's image)."""
+        K = args.steps
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(K):
+            r, st = rens[k % F], streams[k % F]
+            cam = cams[k % len(cams)]
+            select(cam, r, st)
+            L.lodge_render(dev, r.sel, cam, r.ws, r.image, r.final_T, r.n_contrib, stream=st)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
 
     def timed(select):
         """K frames back to back on one stream, per-stage events recorded live."""
@@ -261,12 +289,17 @@ def main():
         frame_ms_events = float(np.mean([ev[k][0].elapsed_time(ev[k][5]) for k in range(K)]))
         return elapsed, stage_ms, frame_ms_events
 
-    # timed region: per-frame selection from the Gaussians' means (every frame re-derives the active set)
+    # timed regions: per-frame selection from the Gaussians' means (every frame re-derives the active set).
+    # value: F frames in flight; stage times and the roofline: frames one after another on one stream with
+    # events between the stages, so that no other frame's kernels share the device while a stage is timed
     K = args.steps
     stage_names = ["select", "project", "bin", "sort", "composite"]
-    elapsed, stage_ms, frame_ms_events = timed(lambda cam: L.lodge_select(dev, cam, mode, R.ws, R.sel))
+    elapsed = throughput(lambda cam, r, st: L.lodge_select(dev, cam, mode, r.ws, r.sel, st))
     fps = K / elapsed
-    log(f"[bench] {K} frames in {elapsed:.3f} s -> {fps:.1f} frames/s; stage ms " +
+    log(f"[bench] {K} frames, {F} in flight, in {elapsed:.3f} s -> {fps:.1f} frames/s")
+    el_serial, stage_ms, frame_ms_events = timed(lambda cam: L.lodge_select(dev, cam, mode, R.ws, R.sel))
+    fps_serial = K / el_serial
+    log(f"[bench] {K} frames one after another in {el_serial:.3f} s -> {fps_serial:.1f} frames/s; stage ms " +
         ", ".join(f"{k}={v:.3f}" for k, v in stage_ms.items()))
 
     # the paper's protocol: per frame the median of 7 timings, FPS = 1 / mean
@@ -287,12 +320,15 @@ def main():
     chunk_sets = None
     if mode == L.SELECT_CHUNKED:
         sets = L.ChunkSets(dev)
-        for k in range(args.warmup):
-            R.frame(cams[k % len(cams)], mode, sets=sets)
+        for k in range(max(args.warmup, F)):
+            rens[k % F].frame(cams[k % len(cams)], mode, stream=streams[k % F], sets=sets)
         torch.cuda.synchronize()
+        el_f = throughput(lambda cam, r, st: L.lodge_select_chunk_sets(dev, sets, cam, r.ws, r.sel, st))
         el2, st2, fm2 = timed(lambda cam: L.lodge_select_chunk_sets(dev, sets, cam, R.ws, R.sel))
         sets_bytes = 0.25 * sc.n_total + 8.0 * mean["n_selected"]   # two 16-bit words per 16 Gaussians + ids, w
-        chunk_sets = {"frames_per_s": round(K / el2, 2), "ms_per_step": round(1000.0 * el2 / K, 4),
+        chunk_sets = {"frames_per_s": round(K / el_f, 2), "ms_per_step": round(1000.0 * el_f / K, 4),
+                      "frames_in_flight": F,
+                      "serial": {"frames_per_s": round(K / el2, 2), "ms_per_step": round(1000.0 * el2 / K, 4)},
                       "frame_ms_events": round(fm2, 4), "stage_ms": {k: round(v, 4) for k, v in st2.items()},
                       "select_bytes": sets_bytes, "sets_bytes_resident": sets.bytes,
                       "select_achieved_GBs": round(sets_bytes / (st2["select"] * 1e-3) / 1e9, 2)}
@@ -366,8 +402,10 @@ def main():
         "config": desc,
         "gaussians_composited_per_s": round(mean["pairs_evaluated"] * fps, 1),
         "gaussians_blended_per_s": round(mean["pairs_blended"] * fps, 1),
+        "frames_in_flight": F,
+        "serial": {"frames_per_s": round(fps_serial, 2), "ms_per_step": round(1000.0 * el_serial / K, 4),
+                   "frame_ms_events": round(frame_ms_events, 4)},
         "paper_protocol_fps": round(paper_fps, 2) if paper_fps else None,
-        "frame_ms_events": round(frame_ms_events, 4),
         "per_frame": {k: round(v, 1) for k, v in mean.items()},
         "stages": stages,
         "roofline": roofline,
