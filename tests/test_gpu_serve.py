@@ -1,6 +1,7 @@
 """The served form on the GPU: captured-graph replays re-read the pinned
 camera and equal eager renders; requests served concurrently in a mix of
-resolutions equal the same requests rendered alone."""
+resolutions equal the same requests rendered alone; frames in flight on
+several streams equal the same frames rendered one at a time."""
 import numpy as np
 import pytest
 
@@ -78,3 +79,36 @@ def test_capacity_overflow_is_retried_outside_the_graph(env):
     rep, be = serve(dev, [Request(0, 0.0, cam)], L.SELECT_CHUNKED, tiny, prewarm=1, keep_images=True)
     assert rep.results[0].retried
     assert torch.equal(be.images[0], alone(L, dev, cam))
+
+
+def test_frames_in_flight_equal_frames_one_at_a_time(env):
+    """Consecutive frames of a camera path on three renderers and three
+    streams, handed out round robin (the throughput form of the benchmark),
+    give the same images, final T and n_contrib as the same frames rendered
+    one after another."""
+    import torch
+    L, sc, dev = env
+    cams = sc.cameras
+    W, H = cams[0].width, cams[0].height
+    F = 3
+    rens = [L.Renderer(dev, W, H, *CAPS[(W, H)]) for _ in range(F)]
+    streams = [torch.cuda.Stream() for _ in range(F)]
+    serial = L.Renderer(dev, W, H, *CAPS[(W, H)])
+    n = len(cams)
+    got = []
+    for k in range(n):
+        rens[k % F].frame(cams[k], L.SELECT_CHUNKED, stream=streams[k % F])
+        if k % F == F - 1 or k == n - 1:
+            # the slots are reused from the next round on: copy this round's outputs first
+            torch.cuda.synchronize()
+            for j in range(k - k % F, k + 1):
+                r = rens[j % F]
+                assert L.lodge_check(r.ws)[0] == L.LODGE_OK
+                got.append((r.image.clone(), r.final_T.clone(), r.n_contrib.clone()))
+    for k in range(n):
+        serial.frame(cams[k], L.SELECT_CHUNKED)
+        torch.cuda.synchronize()
+        img, T, nc = got[k]
+        assert torch.equal(img, serial.image) and torch.equal(T, serial.final_T), f"frame {k}"
+        assert torch.equal(nc, serial.n_contrib), f"frame {k}"
+    log(f"[in-flight] {n} frames on {F} streams equal the serial renders")
