@@ -48,7 +48,7 @@ typedef enum {
     LODGE_ERR_INVALID_ARG = 1,   /* a pointer, size or value outside its stated range */
     LODGE_ERR_CAPACITY = 2,      /* a workspace / selection capacity was exceeded */
     LODGE_ERR_HIP = 3,           /* the HIP runtime reported an error (see lodge_last_error) */
-    LODGE_ERR_UNSUPPORTED = 4    /* a valid request this build does not handle */
+    LODGE_ERR_UNSUPPORTED = 4    /* a valid request the library does not handle */
 } lodge_status;
 
 /* Static description of a status code. */

@@ -28,8 +28,8 @@
  *          projection weight t, opacity modulation of the symmetric difference
  *   Supp. "Details on training the full representation"   -- 2-D filter of the
  *          renderer (Mip-Splatting style)
- * Readings where the paper is silent or garbled are listed in the design doc's
- * "Readings of the paper" table and restated at each use below.
+ * Where the paper is silent or garbled, the reading taken is stated at each
+ * use below.
  */
 #include <math.h>
 #include <stdint.h>
