@@ -104,6 +104,26 @@ def test_long_tile_lists(L, oracle32, n):
         assert g["info"]["n_long"] > 0
 
 
+@pytest.mark.parametrize("n", [4096, 4097, 8192, 8193])
+def test_sort_band_edges(L, oracle32, n):
+    """Exactly n instances in one tile, at the edges of the sort's length
+    bands: 4096 (wave sorts and merge rounds), 4097 (two halves, the second
+    of one key, and the LDS merge), 8192 (two full halves), 8193 (an
+    8192-key chunk, a one-key chunk and a merge pass in global memory)."""
+    lv = synth.gaussians(n, (47, n), synth._cube(0.05), -6.0, 0.3, morton=False)
+    cam = synth.look_at((0, 0, 0), (0, 0, 1), (0, -1, 0), 64, 64)
+    z = 10.0
+    # all projected within 2.5 px of the centre of tile (1, 1): one tile each
+    lv.mean[2] += z
+    lv.mean[0] += (24.0 - cam.cx) * z / cam.fx
+    lv.mean[1] += (24.0 - cam.cy) * z / cam.fy
+    sc = Scene(levels=[lv], d=[])
+    g, r = full_parity(oracle32, sc, dev(L, sc), cam, oracle.ALL, f"sort-band-{n}", compensate=False)
+    lens = r["binned"].ranges[:, 1] - r["binned"].ranges[:, 0]
+    assert int(lens.max()) == n and int((lens > 0).sum()) == 1
+    assert g["info"]["max_tile_len"] == n
+
+
 def test_chunk_weights_at_band_edges(L, oracle32):
     """Cameras across the blend band of two chunks (t from 0 ... 1)."""
     sc = synth.lod_city_scene(counts=(40000, 10000), half_xy=30.0, d=(8.0,), grid=2, spacing=20.0, chunk_z=1.0,
