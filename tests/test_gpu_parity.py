@@ -104,12 +104,14 @@ def test_long_tile_lists(L, oracle32, n):
         assert g["info"]["n_long"] > 0
 
 
-@pytest.mark.parametrize("n", [4096, 4097, 8192, 8193])
+@pytest.mark.parametrize("n", [64, 65, 128, 129, 256, 257, 512, 513, 2048, 2049, 4096, 4097, 8192, 8193, 16384, 16385])
 def test_sort_band_edges(L, oracle32, n):
     """Exactly n instances in one tile, at the edges of the sort's length
-    bands: 4096 (wave sorts and merge rounds), 4097 (two halves, the second
-    of one key, and the LDS merge), 8192 (two full halves), 8193 (an
-    8192-key chunk, a one-key chunk and a merge pass in global memory)."""
+    bands: one wave with 1, 2 or 4 keys per lane up to 64, 128 and 256; four
+    waves and their merge rounds up to 2048; eight up to 4096; 4097 (two
+    halves, the second of one key, and the LDS merge); 8192 (two full
+    halves); 8193 (an 8192-key chunk, a one-key chunk and a merge pass in
+    global memory); past 16384 the queue of the longest runs."""
     lv = synth.gaussians(n, (47, n), synth._cube(0.05), -6.0, 0.3, morton=False)
     cam = synth.look_at((0, 0, 0), (0, 0, 1), (0, -1, 0), 64, 64)
     z = 10.0
@@ -122,6 +124,8 @@ def test_sort_band_edges(L, oracle32, n):
     lens = r["binned"].ranges[:, 1] - r["binned"].ranges[:, 0]
     assert int(lens.max()) == n and int((lens > 0).sum()) == 1
     assert g["info"]["max_tile_len"] == n
+    assert g["info"]["n_merge"] == (1 if n > 16384 else 0)
+    assert g["info"]["n_long"] == (1 if 2048 < n <= 16384 else 0)
 
 
 def test_chunk_weights_at_band_edges(L, oracle32):
