@@ -122,7 +122,10 @@ typedef struct lodge_scene lodge_scene;
  * and d_L = infinity implicitly; d may be NULL when L = 1).  chunks may be
  * NULL (then only LODGE_SELECT_ALL and LODGE_SELECT_LOD_CAMERA work).
  * Validates: n >= 0, sum of n < 2^32, d strictly increasing and > 0,
- * sh_degree in 0..3, non-NULL planes when n > 0, filter3d_var >= 0;
+ * sh_degree in 0..3, non-NULL planes when n > 0, filter3d_var >= 0; chunk
+ * centres finite and pairwise distinct (the squared FP32 distance of every
+ * pair finite and > 0, since Eq. 4 divides by it), offsets finite and >= 0,
+ * band finite;
  * LODGE_ERR_UNSUPPORTED for a level of 2^30 or more Gaussians (its planes
  * are addressed with 32-bit byte offsets).
  * Allocates host memory only.  *out is NULL on failure. */
@@ -292,7 +295,12 @@ typedef struct {
  * from n_contrib - 1, recovering the transmittance before each entry by
  * division T_k = T_{k+1} / (1 - alpha_k) from final_T instead of storing it.
  * ws must still hold the forward's intermediates (same scene, selection,
- * camera and options).  grads is an array of L entries. */
+ * camera and options).  grads is an array of L entries.
+ * Accumulation is a plain read-add-write per Gaussian (one thread owns each
+ * selected Gaussian within a call), not an atomic: two calls that run at
+ * the same time (different streams) into the same gradient planes race and
+ * lose updates.  Serialise such calls on one stream, or give each its own
+ * planes and sum them afterwards. */
 lodge_status lodge_render_backward(const lodge_scene* scene, const lodge_selection* sel, const lodge_camera* cam,
                                    const lodge_render_opts* opts, const lodge_workspace* ws, const float* final_T,
                                    const uint32_t* n_contrib, const float* dL_dimage, int32_t grad_level,

@@ -285,6 +285,28 @@ lodge_status lodge_scene_create(const lodge_level* levels, int32_t L, const floa
             delete s;
             return fail(LODGE_ERR_INVALID_ARG, "chunks: need 1..128 centres and offsets");
         }
+        if (!std::isfinite(chunks->band)) {
+            delete s;
+            return fail(LODGE_ERR_INVALID_ARG, "chunk blend band must be finite");
+        }
+        // Eq. 4 divides by |m_f - m_o|^2: centres must be finite and pairwise distinct
+        for (int k = 0; k < chunks->k; k++) {
+            const float* ck = chunks->center + 3 * k;
+            if (!std::isfinite(ck[0]) || !std::isfinite(ck[1]) || !std::isfinite(ck[2])) {
+                delete s;
+                return fail(LODGE_ERR_INVALID_ARG, "chunk centres must be finite");
+            }
+            for (int j = 0; j < k; j++) {
+                const float* cj = chunks->center + 3 * j;
+                const float g0 = ck[0] - cj[0], g1 = ck[1] - cj[1], g2 = ck[2] - cj[2];
+                const float den = (g0 * g0 + g1 * g1) + g2 * g2;
+                if (!(den > 0.0f) || !std::isfinite(den)) {
+                    delete s;
+                    return fail(LODGE_ERR_INVALID_ARG, "chunk centres must be pairwise distinct (and their squared "
+                                                       "distances finite and non-zero in FP32)");
+                }
+            }
+        }
         s->chunks.K = chunks->k;
         s->chunks.band = chunks->band;
         for (int k = 0; k < chunks->k; k++) {

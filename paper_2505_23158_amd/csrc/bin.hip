@@ -453,7 +453,9 @@ __global__ __launch_bounds__(kTilesThreads) void k_tile_scan(const FrameParams* 
         }
     }
     __syncthreads();
-    // cls: four 16-bit class counts; big: three 21-bit queue counts (large, huge, mid)
+    // cls: four 16-bit length-class counts; big: four 16-bit queue counts
+    // (bits 0-15 runs in (2048, 4096], 16-31 over 16384, 32-47 in (256, 2048],
+    // 48-63 in (4096, 16384]; see queue_unit)
     unsigned long long sum = 0, cls = 0, big = 0;
     uint32_t lmax = 0;
     for (uint32_t t = t0; t < t1; t++) {

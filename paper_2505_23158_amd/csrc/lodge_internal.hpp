@@ -156,7 +156,7 @@ struct Views {
     uint32_t* chunk_sum;   // per projection chunk: tile total -> exclusive instance offset
     uint32_t* chunk_vis;   // per projection chunk: actives with >= 1 tile -> exclusive offset among them
     uint4* scan_blk;       // per chunk-scan block: its totals -> its exclusive offsets
-    float4* proj;          // [max_active][3]: (u, v, A, B), (C, o, r, g), (b, ex, ey, thr); visible only
+    float4* proj;          // [max_active][3]: (u, v, -A/2, -B), (-C/2, o, thr, r), (g, b, ex, ey); visible only
     float* depth;          // [max_active] camera depth (sort key), 0 when culled
     uint2* rect;           // [max_active] tile rect (x0 | y0 << 16, x1 | y1 << 16), empty when culled
     uint32_t* vtiles;      // tiles touched per active index

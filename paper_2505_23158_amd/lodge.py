@@ -333,7 +333,8 @@ def lodge_check(ws: Workspace, stream=None):
 
 def lodge_debug_views(ws: Workspace, n_instances: int):
     """Views into ws: sorted_ids [M] int32, tile_ranges [T, 2] int32, proj [max_active, 12] float32
-    (u, v, A, B, C, o, r, g, b, ex, ey, thr), depth [max_active] float32, rect [max_active, 2] int32."""
+    (u, v, -A/2, -B, -C/2, o_eff, thr, r, g, b, ex, ey: the conic (A, B, C) pre-scaled as the
+    compositor reads it), depth [max_active] float32, rect [max_active, 2] int32."""
     torch = _torch()
     s, r, p, d, rc = C.c_void_p(), C.c_void_p(), C.c_void_p(), C.c_void_p(), C.c_void_p()
     _check(lib().lodge_debug_views(C.byref(ws.desc), C.byref(s), C.byref(r), C.byref(p), C.byref(d), C.byref(rc)))

@@ -71,10 +71,22 @@ def test_scene_validation():
     r = np.zeros(200, np.float32)
     ch = L.lodge_chunks(k=200, center=c.ctypes.data, offset=r.ctypes.data, band=0.0)
     assert _create([_fake_level()], chunks=ch)[0] == L.LODGE_ERR_INVALID_ARG
+    # 64 coincident centres: Eq. 4 would divide by |m_f - m_o|^2 = 0
     ch = L.lodge_chunks(k=64, center=c.ctypes.data, offset=r.ctypes.data, band=10.0)
+    assert _create([_fake_level()], chunks=ch)[0] == L.LODGE_ERR_INVALID_ARG
+    c[:64, 0] = np.arange(64, dtype=np.float32) * 5.0
     st, h = _create([_fake_level()], chunks=ch)
     assert st == L.LODGE_OK
     lib.lodge_scene_destroy(h)
+    c[7] = c[40]                       # one coincident pair among distinct centres
+    assert _create([_fake_level()], chunks=ch)[0] == L.LODGE_ERR_INVALID_ARG
+    c[7] = (35.0, 0.0, 0.0)
+    c[9, 2] = np.inf
+    assert _create([_fake_level()], chunks=ch)[0] == L.LODGE_ERR_INVALID_ARG
+    c[9, 2] = 0.0
+    for band in (np.nan, np.inf):
+        chb = L.lodge_chunks(k=64, center=c.ctypes.data, offset=r.ctypes.data, band=band)
+        assert _create([_fake_level()], chunks=chb)[0] == L.LODGE_ERR_INVALID_ARG
     r[3] = -1.0
     assert _create([_fake_level()], chunks=ch)[0] == L.LODGE_ERR_INVALID_ARG
 

@@ -558,3 +558,213 @@ def test_chunked_selection_is_union_of_stored_chunk_sets(oracle32):
         expect = [1.0 if (g in stored[f] and g in stored[o]) else (t32 if g in stored[f] else np.float32(1) - t32)
                   for g in union]
         assert np.array_equal(w, np.asarray(expect, np.float32))
+
+
+# ---------------------------------------------------------------------------
+# the threshold-flip acceptance rule of the image comparison
+# ---------------------------------------------------------------------------
+
+def _bisect_flip(decides, lo, hi, iters=80):
+    """Largest / smallest float32 opacity on either side of the oracle's own
+    decision boundary: decides(lo) is False, decides(hi) is True."""
+    lo, hi = float(np.float32(lo)), float(np.float32(hi))
+    assert not decides(lo) and decides(hi)
+    for _ in range(iters):
+        mid = float(np.float32(0.5 * (lo + hi)))
+        if mid in (lo, hi):
+            break
+        if decides(mid):
+            hi = mid
+        else:
+            lo = mid
+    return lo, hi
+
+
+def _accept(O, r, cam, x, y, probe, tol=1e-4):
+    return O.pixel_accept(r["proj"], r["binned"], cam, x, y, np.asarray(probe, np.float64), tol)
+
+
+def _iso_alpha(o, sigma, z, f, dx, dy, s2d=0.3):
+    """alpha of an isotropic on-axis Gaussian at pixel offset (dx, dy), float64 closed form."""
+    a = (f * float(np.float32(sigma)) / z) ** 2 + s2d
+    return min(0.99, float(np.float32(o)) * math.exp(-0.5 * (dx * dx + dy * dy) / a))
+
+
+def test_pixel_accept_alpha_threshold_flip(oracle32):
+    """One Gaussian whose alpha at a pixel is within a few ulp of 1/255 (its
+    opacity bisected onto the oracle's own decision boundary): the rule
+    accepts the colour with the splat blended and the colour with it skipped,
+    and rejects either one moved by 2e-4."""
+    W = H = 64
+    f, z, sigma, k = 80.0, 5.0, 0.3, 0.7
+    cam = axis_camera(W, H, f)
+    px, py = 36, 32
+
+    def frame(o):
+        lv = make_level([[0.0, 0.0, z]], sigma, opac=[o], dc=k)
+        return oracle32.render(one_level_scene(lv), cam, oracle.ALL, compensate=False)
+
+    lo, hi = _bisect_flip(lambda o: frame(o)["n_contrib"][py, px] > 0, 1e-3, 1.0)
+    rgb = C0 * float(np.float32(k)) + 0.5
+    dx, dy = 32.0 - (px + 0.5), 32.0 - (py + 0.5)
+    for o in (lo, hi):
+        r = frame(o)
+        assert r["near"][py, px] == 1, "the boundary pixel must carry a near-threshold decision"
+        a = _iso_alpha(o, sigma, z, f, dx, dy)
+        assert abs(a - 1.0 / 255.0) < 1e-6
+        blended, skipped = np.full(3, rgb * a), np.zeros(3)
+        for probe in (blended, skipped):
+            assert _accept(oracle32, r, cam, px, py, probe)
+            assert not _accept(oracle32, r, cam, px, py, probe + 2e-4)
+            assert not _accept(oracle32, r, cam, px, py, probe - 2e-4)
+        # half-way between the two outcomes is neither
+        assert not _accept(oracle32, r, cam, px, py, 0.5 * (blended + skipped))
+
+
+def test_pixel_accept_stop_threshold_flip(oracle32):
+    """Three wide layers on the axis (alpha 0.99 clamped, 0.9, ~0.9): the
+    third's opacity is bisected onto the oracle's T (1 - alpha) < 1e-4 stop
+    boundary.  The rule accepts the colour with the third layer blended and
+    the colour with the pixel stopped before it, rejects either moved by
+    2e-4, and rejects the colour without the second layer (a decision far
+    from every threshold: flipping it is not a legitimate difference)."""
+    W = H = 64
+    f, sigma = 80.0, 0.6
+    cam = axis_camera(W, H, f)
+    px, py = 32, 32
+    dx = dy = 32.0 - 32.5
+    zs = (5.0, 6.0, 7.0)
+    cols = (0.2, 0.5, 0.9)
+    dcs = [(c - 0.5) / C0 for c in cols]
+    a_of = lambda z: (f * float(np.float32(sigma)) / z) ** 2 + 0.3
+    G = [math.exp(-0.5 * (dx * dx + dy * dy) / a_of(z)) for z in zs]
+    o2 = float(np.float32(0.9 / G[1]))
+
+    def frame(o3):
+        # storage order back to front: the sort, not the storage, orders them
+        lv = make_level([[0.0, 0.0, zs[2]], [0.0, 0.0, zs[1]], [0.0, 0.0, zs[0]]], sigma, opac=[o3, o2, 1.0],
+                        dc=[[dcs[2]] * 3, [dcs[1]] * 3, [dcs[0]] * 3])
+        return oracle32.render(one_level_scene(lv), cam, oracle.ALL, compensate=False)
+
+    def stops(o3):
+        r = frame(o3)
+        assert r["n_contrib"][py, px] >= 2
+        return r["n_contrib"][py, px] == 2
+
+    lo, hi = _bisect_flip(stops, 0.5, 0.99)
+    c = [float(np.float32(d)) * C0 + 0.5 for d in dcs]
+    a1 = 0.99
+    a2 = _iso_alpha(o2, sigma, zs[1], f, dx, dy)
+    T1 = 1.0 - a1
+    T2 = T1 * (1.0 - a2)
+    for o3 in (lo, hi):
+        r = frame(o3)
+        assert r["near"][py, px] == 1
+        a3 = _iso_alpha(o3, sigma, zs[2], f, dx, dy)
+        assert abs(T2 * (1.0 - a3) - 1e-4) < 1e-8
+        stopped = np.full(3, c[0] * a1 + c[1] * a2 * T1)
+        blended = stopped + c[2] * a3 * T2
+        assert float(blended[0] - stopped[0]) > 5e-4
+        for probe in (blended, stopped):
+            assert _accept(oracle32, r, cam, px, py, probe)
+            assert not _accept(oracle32, r, cam, px, py, probe + 2e-4)
+            assert not _accept(oracle32, r, cam, px, py, probe - 2e-4)
+        without_second = np.full(3, c[0] * a1 + c[2] * a3 * T1)
+        assert not _accept(oracle32, r, cam, px, py, without_second)
+
+
+def test_pixel_accept_rejects_off_values_without_near_decisions(oracle32):
+    """Pixels of a random scene with no near-threshold decision: a probe
+    within tol of the oracle's value is accepted, one off by more than tol
+    in any channel is rejected."""
+    sc = synth.plain_scene(n=1500, seed=25, width=64, height=48)
+    cam = sc.cameras[0]
+    r = oracle32.render(sc, cam, oracle.ALL)
+    img = r["image"].astype(np.float64)
+    cand = np.argwhere((r["near"] == 0) & (r["n_contrib"] > 0))
+    assert len(cand) > 100
+    rng = np.random.default_rng(3)
+    for y, x in cand[rng.choice(len(cand), 40, replace=False)]:
+        v = img[:, y, x]
+        assert _accept(oracle32, r, cam, int(x), int(y), v + 0.5e-4)
+        for ch in range(3):
+            for s in (1.5e-4, -1.5e-4, 3e-3):
+                p = v.copy()
+                p[ch] += s
+                assert not _accept(oracle32, r, cam, int(x), int(y), p), (x, y, ch, s)
+
+
+# ---------------------------------------------------------------------------
+# the Jacobian clamp of the EWA projection (off-screen means)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_jacobian_clamp_closed_form(oracle64, oracle32, axis):
+    """An isotropic Gaussian whose mean sits at twice the clamp limit
+    (|x/z| = 2 lim): the Jacobian is evaluated at the limit, J02 = -f lim / z
+    (not -f x / z^2), so Sigma' = v [[(f/z)^2 + (f lim / z)^2, 0], [0, (f/z)^2]]
+    + s2d I.  The projected centre itself is not clamped.  Conic, radius,
+    tile rectangle and the alpha at a pixel of the visible edge follow."""
+    W = H = 64
+    f, z, sigma, o = 80.0, 5.0, 1.4, 0.9
+    cam = axis_camera(W, H, f)
+    lim = 1.3 * 32.0 / f          # as the camera carries it
+    X = 2.0 * lim * z
+    pos = [X, 0.0, z] if axis == "x" else [0.0, X, z]
+    lv = make_level([pos], sigma, opac=[o], dc=0.3)
+    X32, z32 = float(np.float32(X)), float(np.float32(z))
+    v = float(np.float32(sigma)) ** 2
+    big = v * ((f / z32) ** 2 + (f * lim / z32) ** 2) + 0.3
+    small = v * (f / z32) ** 2 + 0.3
+    a, c = (big, small) if axis == "x" else (small, big)
+    uc = f * X32 / z32 + 32.0
+    u, vv = (uc, 32.0) if axis == "x" else (32.0, uc)
+    r = math.ceil(3.0 * math.sqrt(max(a, c)))
+    x0, x1 = max(0, math.floor((u - r) / 16)), min(4, math.floor((u + r) / 16) + 1)
+    y0, y1 = max(0, math.floor((vv - r) / 16)), min(4, math.floor((vv + r) / 16) + 1)
+    assert x0 < x1 and y0 < y1, "the clamped Gaussian reaches the image"
+    # the unclamped form would be wider along the clamped axis
+    assert v * ((f / z32) ** 2 + (f * X32 / z32 ** 2) ** 2) + 0.3 > 1.5 * max(a, c)
+    for O, tol in ((oracle64, 1e-12), (oracle32, 3e-6)):
+        res = O.render(one_level_scene(lv), cam, oracle.ALL, compensate=False)
+        p = res["proj"]
+        assert p.radius[0] == r
+        assert tuple(p.rect[0]) == (x0, y0, x1, y1)
+        assert abs(p.uv[0, 0] - u) <= 1e-4 and abs(p.uv[0, 1] - vv) <= 1e-4
+        assert np.allclose(p.conic[0], [1 / a, 0.0, 1 / c], rtol=tol * 10, atol=tol)
+        # a pixel on the image edge nearest the centre
+        px, py = (63, 32) if axis == "x" else (32, 63)
+        dx, dy = u - (px + 0.5), vv - (py + 0.5)
+        al = float(np.float32(o)) * math.exp(-0.5 * (dx * dx / a + dy * dy / c))
+        assert al > 1 / 255
+        rgb = C0 * float(np.float32(0.3)) + 0.5
+        assert abs(res["image"][0, py, px] - rgb * al) <= 10 * tol
+
+
+def test_jacobian_clamp_adjoint_matches_central_differences(oracle64):
+    """Central differences of the FP64 forward on two clamped Gaussians (one
+    past the x limit, one past the y limit) and one unclamped: the adjoint's
+    clamped branches (the clamped Jacobian entry depends on depth only)."""
+    W = H = 64
+    f = 80.0
+    cam = axis_camera(W, H, f)
+    lim = 1.3 * 32.0 / f
+    rng = np.random.default_rng(41)
+    means = [[2.0 * lim * 5.0, 0.3, 5.0], [-0.2, -2.2 * lim * 5.5, 5.5], [0.4, 0.2, 6.0]]
+    q = rng.normal(size=(3, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    lv = make_level(means, [[1.5, 1.2, 1.3], [1.4, 1.6, 1.2], [0.3, 0.2, 0.25]], quats=q, opac=[0.8, 0.7, 0.6],
+                    dc=[[0.4, 0.6, 0.2], [0.1, 0.3, 0.8], [0.5, 0.5, 0.5]], var=0.002)
+    for fld in ("mean", "scale", "quat", "opacity", "sh"):
+        setattr(lv, fld, getattr(lv, fld).astype(np.float64))
+    sc = one_level_scene(lv)
+    r = oracle64.render(sc, cam, oracle.ALL)
+    assert np.all(r["proj"].tiles > 0)
+    rep = _fd_check(oracle64, sc, cam, ["mean", "scale", "quat", "opacity"], rng, n_coords=12)
+    for key, (fd, an, skipped) in rep.items():
+        assert len(fd) >= min(6, getattr(lv, key[0]).size), (key, skipped)
+        nrm = np.linalg.norm(fd)
+        assert nrm > 0, key
+        rel = np.linalg.norm(fd - an) / nrm
+        assert rel <= 1e-3, (key, rel)
+        assert np.all(np.abs(fd - an) <= 1e-3 * (np.abs(fd) + np.sqrt(np.mean(fd ** 2)))), key
