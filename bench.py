@@ -10,14 +10,20 @@ per-tile sort, compositing), inputs resident in HBM.  Prints ONE JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload large|lod|plain]
 
+The K timed frames are spread evenly over the path (frame k * P // K of a
+P-frame path), and every per-frame count the roofline divides by is the mean
+over exactly those K frames (an untimed pass that also checks capacities).
+
 "value" is the path's throughput with --in-flight frames (default 3) in
 flight: one renderer (workspace, selection, image) and one stream per frame
 slot, frames handed out round robin, so that one frame's compositing (VALU
 bound) overlaps the next frame's selection and projection (HBM bound).  The
+timed region is repeated --repeats times and the median is reported.  The
 same K frames one after another on one stream, with events between the
 stages, give "serial" and the stage times behind "stages" and "roofline".
-The frames/s protocol of the paper's evaluation (median of 7 per image,
-FPS = 1 / mean time) is reported beside them as "paper_protocol_fps".
+"paper_comparable" holds the figures comparable with the paper's FPS, which
+times one image at a time: the serial rate, and the paper's own protocol
+(median of 7 per image, FPS = 1 / mean time).
 """
 from __future__ import annotations
 
@@ -109,43 +115,90 @@ def workload(name, n_frames):
     return sc, desc, mode, caps
 
 
-def cpu_baseline(sc, cams, mode_oracle, frames):
-    """The oracle as it stands, single-threaded, on `frames` frames of the path."""
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(sc, cams, mode_oracle, frames, reps, single_frames):
+    """The oracle as it stands, timed on the host: its OpenMP timing build (the same source and
+    arithmetic, per-Gaussian and per-pixel loops over all host cores) on `frames` frames spread over
+    the path, median of `reps` runs each, and the plain single-threaded build on `single_frames`
+    of them.  Frames/s = 1 / mean of the per-frame medians."""
     import oracle
-    O = oracle.Oracle("f32")
-    t0 = time.perf_counter()
-    pairs = 0
-    for cam in cams[:frames]:
-        r = O.render(sc, cam, mode_oracle)
-        pairs += int(r["n_eval"].astype("int64").sum())
-    dt = time.perf_counter() - t0
-    return {"value": round(frames / dt, 4), "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": f"{frames} frame(s) of the same path at full resolution (select+project+sort+composite), "
-                      f"single-threaded C oracle, {dt:.1f} s",
-            "pairs_per_s": round(pairs / dt, 1), "host_cpu": platform.processor() or platform.machine(),
-            "host_nproc": os.cpu_count()}
+    nproc = os.cpu_count() or 1
+    threads = int(os.environ.get("OMP_NUM_THREADS", nproc))
+    ks = [k * len(cams) // frames for k in range(frames)]
+
+    def run(tag, ks, reps):
+        O = oracle.Oracle(tag)
+        per, pairs = [], 0
+        for k in ks:
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                r = O.render(sc, cams[k], mode_oracle)
+                ts.append(time.perf_counter() - t0)
+            per.append(statistics.median(ts))
+            pairs += int(r["n_eval"].astype("int64").sum())
+        return per, pairs
+
+    per_mt, pairs_mt = run("f32omp", ks, reps)
+    per_st, _ = run("f32", ks[:single_frames], 1) if single_frames else ([], 0)
+    fps_mt = 1.0 / float(statistics.mean(per_mt))
+    out = {"value": round(fps_mt, 4), "unit": "frames/s", "cores": threads, "kind": "oracle",
+           "sample": f"frames {ks} of the same 1080p path (select+project+sort+composite), median of {reps} "
+                     f"runs each, the oracle's OpenMP timing build on {threads} threads; "
+                     f"{sum(per_mt) * reps:.1f} s of work",
+           "pairs_per_s": round(pairs_mt / sum(per_mt), 1), "per_frame_s": [round(t, 3) for t in per_mt],
+           "host_cpu": host_cpu_model(), "host_nproc": nproc}
+    if per_st:
+        out["single_thread"] = {"frames_per_s": round(1.0 / float(statistics.mean(per_st)), 4), "cores": 1,
+                                "frames": ks[:single_frames], "per_frame_s": [round(t, 3) for t in per_st]}
+    return out
 
 
 SERVE_CAPS = {(640, 360): (8_000_000, 8_000_000), (1280, 720): (8_000_000, 16_000_000),
               (1920, 1080): (8_000_000, 32_000_000)}
 
 
-def serving_section(dev, n=256, rate=120.0):
+def serving_section(dev, n=256, rate=120.0, sweep=(1000.0, 3000.0, 10000.0)):
     """The served form on the resident scene: Poisson arrivals, mixed resolutions,
-    per-slot graph replay; latency = completion - arrival (no device-to-host copy)."""
+    per-slot graph replay; latency = completion - arrival (no device-to-host copy).
+    The configured load (n requests at `rate`), then the same request mix at higher
+    rates on the same slots, to show where continuous batching saturates."""
     import synth
     from paper_2505_23158_amd import lodge as L
-    from paper_2505_23158_amd.serve import Request, serve
-    reqs = synth.serving_requests(n, rate=rate, half_xy=500.0, seed=4)
-    requests = [Request(i, t, cam) for i, (t, cam) in enumerate(reqs)]
-    rep, _ = serve(dev, requests, L.SELECT_CHUNKED, SERVE_CAPS, mem_budget=96 << 30, max_slots_per_class=8,
-                   prewarm=2)
-    s = rep.summary()
-    return {"requests": n, "arrival_rate_per_s": rate, "resolutions": ["640x360", "1280x720", "1920x1080"],
-            "p50_ms": round(s["p50_ms"], 3), "p99_ms": round(s["p99_ms"], 3), "mean_ms": round(s["mean_ms"], 3),
-            "frames_per_s": round(s["frames_per_s"], 2), "makespan_s": round(s["makespan_s"], 3),
-            "peak_in_flight": s["peak_in_flight"], "slots": s["slots"], "retries": s["retries"],
-            "graph_replay": True}
+    from paper_2505_23158_amd.serve import GpuBackend, Request, Scheduler
+    import torch
+    be = GpuBackend(dev, L.SELECT_CHUNKED, SERVE_CAPS, use_graphs=True)
+    pre = {res: be.prewarm(res, 4) for res in sorted(SERVE_CAPS)}
+    torch.cuda.synchronize()
+    budget = 96 << 30
+
+    def run(r):
+        reqs = synth.serving_requests(n, rate=r, half_xy=500.0, seed=4)
+        requests = [Request(i, t, cam) for i, (t, cam) in enumerate(reqs)]
+        free = {res: list(s) for res, s in pre.items()}
+        rep = Scheduler(be, budget, max_slots_per_class=8, prewarmed=free).run(requests)
+        for res in pre:                 # slots opened during this run serve the next one too
+            pre[res] = sorted({sid for sid, sl in enumerate(be.slots) if sl["res"] == res})
+        s = rep.summary()
+        return {"arrival_rate_per_s": r, "p50_ms": round(s["p50_ms"], 3), "p99_ms": round(s["p99_ms"], 3),
+                "mean_ms": round(s["mean_ms"], 3), "frames_per_s": round(s["frames_per_s"], 2),
+                "makespan_s": round(s["makespan_s"], 4), "peak_in_flight": s["peak_in_flight"],
+                "slots": s["slots"], "retries": s["retries"]}
+
+    base = run(rate)
+    out = {"requests": n, "resolutions": ["640x360", "1280x720", "1920x1080"], "graph_replay": True, **base}
+    out["saturation_sweep"] = [run(r) for r in sweep]
+    return out
 
 
 def diff_section(n=1_000_000, views=8, width=1280, height=720, steps=3):
@@ -165,10 +218,9 @@ def diff_section(n=1_000_000, views=8, width=1280, height=720, steps=3):
     def step():
         for p in dr.parameters():
             p.grad = None
-        loss = 0.0
-        for v, cam in enumerate(sc.cameras):
-            loss = loss + (dr.render(cam, L.SELECT_ALL, slot=v) - tgt[v]).abs().mean()
-        (loss / views).backward()
+        img = dr.render_views(sc.cameras, L.SELECT_ALL)
+        loss = (img - tgt).abs().mean()
+        loss.backward()
         return loss
 
     step()
@@ -195,8 +247,11 @@ def main():
     ap.add_argument("--workload", choices=["large", "lod", "plain"], default="large")
     ap.add_argument("--frames", type=int, default=300, help="camera path length")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-frames", type=int, default=1)
-    ap.add_argument("--stats-every", type=int, default=10)
+    ap.add_argument("--cpu-frames", type=int, default=10, help="oracle frames, spread over the path")
+    ap.add_argument("--cpu-reps", type=int, default=3, help="oracle runs per frame (median)")
+    ap.add_argument("--cpu-single-frames", type=int, default=1,
+                    help="of those frames, how many the single-threaded oracle build also times")
+    ap.add_argument("--repeats", type=int, default=5, help="timed regions of K frames (median reported)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--no-paper-protocol", action="store_true", help="skip the median-of-7 pass")
@@ -234,9 +289,13 @@ def main():
     torch.cuda.synchronize()
     log("[bench] scene resident on the device")
 
-    # statistics pass (untimed): counters of every stats_every-th frame, capacity check
+    # the K timed frames, spread evenly over the path
+    K = args.steps
+    frames = [k * len(cams) // K for k in range(K)]
+    # statistics pass (untimed) over exactly the timed frames: the per-frame counts the roofline divides by,
+    # and a capacity check of every one of them
     stats = []
-    for k in range(0, len(cams), args.stats_every):
+    for k in frames:
         R.frame(cams[k], mode)
         st, na, ni = L.lodge_check(R.ws)
         if st != L.LODGE_OK:
@@ -245,23 +304,23 @@ def main():
     mean = {k: float(np.mean([s[k] for s in stats])) for k in
             ("n_selected", "n_front", "n_visible", "n_instances", "pairs_evaluated", "pairs_blended", "pixels_stopped",
              "max_tile_len")}
-    log(f"[bench] per-frame means over {len(stats)} frames: " + ", ".join(f"{k}={v:.4g}" for k, v in mean.items()))
+    log(f"[bench] per-frame means over the {len(stats)} timed frames: " +
+        ", ".join(f"{k}={v:.4g}" for k, v in mean.items()))
 
     # warm-up, on every renderer and stream
     for k in range(max(args.warmup, F)):
-        rens[k % F].frame(cams[k % len(cams)], mode, stream=streams[k % F])
+        rens[k % F].frame(cams[frames[k % K]], mode, stream=streams[k % F])
     torch.cuda.synchronize()
 
     def throughput(select):
         """K frames of the path with F in flight: frame k goes to renderer k % F on its own stream, so one
         frame's compositing overlaps the next frames' selection and projection.  Every frame is whole (select,
         project, bin, sort, composite into its renderer's image)."""
-        K = args.steps
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(K):
             r, st = rens[k % F], streams[k % F]
-            cam = cams[k % len(cams)]
+            cam = cams[frames[k]]
             select(cam, r, st)
             L.lodge_render(dev, r.sel, cam, r.ws, r.image, r.final_T, r.n_contrib, stream=st)
         torch.cuda.synchronize()
@@ -269,7 +328,6 @@ def main():
 
     def timed(select):
         """K frames back to back on one stream, per-stage events recorded live."""
-        K = args.steps
         ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(K)]
         for row in ev:            # torch creates the HIP event at its first record
             for e in row:
@@ -279,25 +337,34 @@ def main():
         for k in range(K):
             e = ev[k]
             e[0].record()
-            select(cams[k % len(cams)])
-            L.lodge_render(dev, R.sel, cams[k % len(cams)], R.ws, R.image, R.final_T, R.n_contrib,
+            select(cams[frames[k]])
+            L.lodge_render(dev, R.sel, cams[frames[k]], R.ws, R.image, R.final_T, R.n_contrib,
                            stage_events=e[1:6])
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
-        stage_ms = {n: float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(K)]))
-                    for i, n in enumerate(stage_names)}
-        frame_ms_events = float(np.mean([ev[k][0].elapsed_time(ev[k][5]) for k in range(K)]))
-        return elapsed, stage_ms, frame_ms_events
+        stage = {n: [ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(K)] for i, n in enumerate(stage_names)}
+        frame = [ev[k][0].elapsed_time(ev[k][5]) for k in range(K)]
+        return elapsed, stage, frame
+
+    def repeated(fn, select):
+        """args.repeats timed regions; the median elapsed time, and per-stage means over every timed frame."""
+        runs = [fn(select) for _ in range(max(1, args.repeats))]
+        if fn is throughput:
+            return statistics.median(runs), [round(r, 5) for r in runs]
+        el = statistics.median([r[0] for r in runs])
+        stage_ms = {n: float(np.mean([x for r in runs for x in r[1][n]])) for n in stage_names}
+        frame_ms = float(np.mean([x for r in runs for x in r[2]]))
+        return el, stage_ms, frame_ms
 
     # timed regions: per-frame selection from the Gaussians' means (every frame re-derives the active set).
     # value: F frames in flight; stage times and the roofline: frames one after another on one stream with
     # events between the stages, so that no other frame's kernels share the device while a stage is timed
-    K = args.steps
     stage_names = ["select", "project", "bin", "sort", "composite"]
-    elapsed = throughput(lambda cam, r, st: L.lodge_select(dev, cam, mode, r.ws, r.sel, st))
+    elapsed, elapsed_runs = repeated(throughput, lambda cam, r, st: L.lodge_select(dev, cam, mode, r.ws, r.sel, st))
     fps = K / elapsed
-    log(f"[bench] {K} frames, {F} in flight, in {elapsed:.3f} s -> {fps:.1f} frames/s")
-    el_serial, stage_ms, frame_ms_events = timed(lambda cam: L.lodge_select(dev, cam, mode, R.ws, R.sel))
+    log(f"[bench] {K} frames, {F} in flight, in {elapsed:.4f} s (median of {len(elapsed_runs)}) -> "
+        f"{fps:.1f} frames/s")
+    el_serial, stage_ms, frame_ms_events = repeated(timed, lambda cam: L.lodge_select(dev, cam, mode, R.ws, R.sel))
     fps_serial = K / el_serial
     log(f"[bench] {K} frames one after another in {el_serial:.3f} s -> {fps_serial:.1f} frames/s; stage ms " +
         ", ".join(f"{k}={v:.3f}" for k, v in stage_ms.items()))
@@ -321,10 +388,10 @@ def main():
     if mode == L.SELECT_CHUNKED:
         sets = L.ChunkSets(dev)
         for k in range(max(args.warmup, F)):
-            rens[k % F].frame(cams[k % len(cams)], mode, stream=streams[k % F], sets=sets)
+            rens[k % F].frame(cams[frames[k % K]], mode, stream=streams[k % F], sets=sets)
         torch.cuda.synchronize()
-        el_f = throughput(lambda cam, r, st: L.lodge_select_chunk_sets(dev, sets, cam, r.ws, r.sel, st))
-        el2, st2, fm2 = timed(lambda cam: L.lodge_select_chunk_sets(dev, sets, cam, R.ws, R.sel))
+        el_f, _ = repeated(throughput, lambda cam, r, st: L.lodge_select_chunk_sets(dev, sets, cam, r.ws, r.sel, st))
+        el2, st2, fm2 = repeated(timed, lambda cam: L.lodge_select_chunk_sets(dev, sets, cam, R.ws, R.sel))
         sets_bytes = 0.25 * sc.n_total + 8.0 * mean["n_selected"]   # two 16-bit words per 16 Gaussians + ids, w
         chunk_sets = {"frames_per_s": round(K / el_f, 2), "ms_per_step": round(1000.0 * el_f / K, 4),
                       "frames_in_flight": F,
@@ -392,7 +459,7 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host")
         mo = {L.SELECT_ALL: oracle.ALL, L.SELECT_LOD_CAMERA: oracle.LOD_CAMERA, L.SELECT_CHUNKED: oracle.CHUNKED}[mode]
-        cpu = cpu_baseline(sc, cams, mo, args.cpu_frames)
+        cpu = cpu_baseline(sc, cams, mo, args.cpu_frames, args.cpu_reps, args.cpu_single_frames)
 
     out = {
         "metric": "frames/s and Gaussians composited/s at 1080p; serving p50/p99 latency",
@@ -403,9 +470,16 @@ def main():
         "gaussians_composited_per_s": round(mean["pairs_evaluated"] * fps, 1),
         "gaussians_blended_per_s": round(mean["pairs_blended"] * fps, 1),
         "frames_in_flight": F,
+        "timed_frames": frames,
+        "repeats_s": elapsed_runs,
         "serial": {"frames_per_s": round(fps_serial, 2), "ms_per_step": round(1000.0 * el_serial / K, 4),
                    "frame_ms_events": round(frame_ms_events, 4)},
         "paper_protocol_fps": round(paper_fps, 2) if paper_fps else None,
+        "paper_comparable": {
+            "note": "the paper's FPS times one image at a time (FPS = 1 / mean render time, median of 7 per "
+                    "image); `value` overlaps consecutive frames and is not comparable with it",
+            "fps_one_frame_at_a_time": round(fps_serial, 2),
+            "fps_paper_protocol": round(paper_fps, 2) if paper_fps else None},
         "per_frame": {k: round(v, 1) for k, v in mean.items()},
         "stages": stages,
         "roofline": roofline,

@@ -275,6 +275,36 @@ lodge_status lodge_check(const lodge_workspace* ws, uint32_t* needed_active, uin
 lodge_status lodge_debug_views(const lodge_workspace* ws, const uint32_t** sorted_ids, const uint32_t** tile_ranges,
                                const float** proj, const float** depth, const uint32_t** rect);
 
+/* ------------------------------------------------- no-allocation rendering */
+
+/* For callers that cannot allocate device memory, not even a workspace: code
+ * under HIP graph capture, serving loops that must not allocate, harnesses
+ * that forbid hipMalloc.  ASYNC.  lodge_render's kernels and outputs, with the
+ * workspace replaced by a scratch array inside the library:
+ * LODGE_STATIC_SCRATCH_BYTES of device memory on each GPU the library runs
+ * on, held from the first use on that GPU until the process ends.  The call
+ * allocates nothing.  Every call on a GPU shares that GPU's array (it keeps
+ * the last call's contents; each call clears what it needs), so calls that
+ * overlap on one GPU -- other streams, other host threads -- race: serialise
+ * them.
+ *   cam       required (nothing is stored between calls); its size is the
+ *             frame's
+ *   sel       as for lodge_render (ids, weights, device count, cap); the
+ *             workspace's max_active is sel->cap
+ *   overflow  NULL, or a device word set when the frame completes: bit 0 the
+ *             selection count exceeded sel->cap (the first cap entries were
+ *             rendered), bit 1 the (Gaussian, tile) instances exceeded what
+ *             the scratch holds (the frame is then background only).  The
+ *             instance capacity is what remains of the scratch after the
+ *             per-active and per-tile regions: about 28 bytes per instance at
+ *             1080p after 120 bytes per selected Gaussian.
+ * LODGE_ERR_INVALID_ARG, with the sizes in lodge_last_error(), when the
+ * image size and sel->cap leave no room for instances. */
+#define LODGE_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+lodge_status lodge_render_static(const lodge_scene* scene, const lodge_selection* sel, const lodge_camera* cam,
+                                 const lodge_render_opts* opts, float* image, float* final_T, uint32_t* n_contrib,
+                                 uint32_t* overflow, void* stream);
+
 /* ---------------------------------------------------------- differentiation */
 
 /* Gradient planes of one level, device memory, same shapes as the level's

@@ -26,16 +26,21 @@ ALL, LOD_CAMERA, CHUNKED = 0, 1, 2
 TILE = 16
 
 
+# tag -> (REAL, extra flags).  "f32omp" is the benchmark's timing build: the same source and
+# arithmetic as "f32", with the per-Gaussian and per-pixel loops spread over the host cores.
+VARIANTS = {"f32": ("float", []), "f64": ("double", []), "f32omp": ("float", ["-fopenmp"])}
+
+
 def build(force: bool = False) -> None:
-    """Compile liblodge_oracle_{f32,f64}.so with gcc (no FMA contraction, no fast-math)."""
+    """Compile liblodge_oracle_{f32,f64,f32omp}.so with gcc (no FMA contraction, no fast-math)."""
     os.makedirs(BUILD, exist_ok=True)
-    for tag, real in (("f32", "float"), ("f64", "double")):
+    for tag, (real, extra) in VARIANTS.items():
         out = os.path.join(BUILD, f"liblodge_oracle_{tag}.so")
         if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(SRC):
             continue
         tmp = out + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-Wall",
-                               "-fPIC", "-shared", f"-DREAL={real}", SRC, "-o", tmp, "-lm"])
+                               "-fPIC", "-shared", f"-DREAL={real}", *extra, SRC, "-o", tmp, "-lm"])
         os.replace(tmp, out)
 
 
@@ -97,10 +102,10 @@ class Oracle:
     """The oracle in one precision ('f32' decides like the FP32 renderer; 'f64' for the adjoint)."""
 
     def __init__(self, precision: str = "f32"):
-        assert precision in ("f32", "f64")
+        assert precision in VARIANTS
         self.tag = precision
-        self.dt = np.float32 if precision == "f32" else np.float64
-        self.real = C.c_float if precision == "f32" else C.c_double
+        self.dt = np.float64 if precision == "f64" else np.float32
+        self.real = C.c_double if precision == "f64" else C.c_float
         self.L, self.Cam, self.G = _structs(self.real)
         self.lib = _lib(precision)
         self._keep = []
@@ -218,6 +223,22 @@ class Oracle:
                                      _p(img), _p(T), _p(nc))
         return {"image": img, "final_T": T, "n_contrib": nc}
 
+    def composite_pixels(self, proj: Projection, binned: Binned, cam, xs, ys):
+        """The per-pixel walk at the listed pixels only: colour [n, 3], final_T, n_contrib, near."""
+        xs = np.ascontiguousarray(xs, np.int32)
+        ys = np.ascontiguousarray(ys, np.int32)
+        n = len(xs)
+        col = np.empty((max(n, 1), 3), self.dt)
+        T = np.empty(max(n, 1), self.dt)
+        nc = np.empty(max(n, 1), np.uint32)
+        near = np.empty(max(n, 1), np.uint8)
+        c = self.camera(cam)
+        val = binned.val if binned.M else np.zeros(1, np.uint32)
+        self.lib.orc_composite_pixels(C.byref(c), _p(proj.uv), _p(proj.conic), _p(proj.o_eff), _p(proj.rgb),
+                                      _p(binned.ranges), _p(val), C.c_int64(n), _p(xs), _p(ys), _p(col), _p(T),
+                                      _p(nc), _p(near))
+        return {"color": col[:n], "final_T": T[:n], "n_contrib": nc[:n], "near": near[:n]}
+
     def pixel_accept(self, proj: Projection, binned: Binned, cam, x: int, y: int, probe, tol: float) -> bool:
         c = self.camera(cam)
         probe = self._arr(np.asarray(probe))
@@ -259,6 +280,14 @@ class Oracle:
         return grads
 
     # -- whole frame -------------------------------------------------------------
+    def lists(self, scene, cam, mode: int, s2d=0.3, compensate=True):
+        """select -> project -> bin/sort, without compositing (for sampled-pixel checks)."""
+        ids, w, fot = self.select(scene, mode, cam.pos)
+        proj = self.project(scene, ids, w, cam, s2d, compensate)
+        binned = self.bin_sort(proj, cam)
+        self._keep.clear()
+        return dict(ids=ids, w=w, fot=fot, proj=proj, binned=binned)
+
     def render(self, scene, cam, mode: int, s2d=0.3, compensate=True, brute=False):
         """select -> project -> bin/sort -> composite, all intermediates returned."""
         ids, w, fot = self.select(scene, mode, cam.pos)
@@ -271,9 +300,13 @@ class Oracle:
         self._keep.clear()
         return out
 
-    def render_grad(self, scene, cam, mode: int, dL_dimage, s2d=0.3, compensate=True, grad_level=-1):
-        """Forward, then the adjoint of L = sum(dL_dimage * image) w.r.t. activated params."""
-        fwd = self.render(scene, cam, mode, s2d, compensate)
+    def render_grad(self, scene, cam, mode: int, dL_dimage, s2d=0.3, compensate=True, grad_level=-1,
+                    composite=True):
+        """Forward, then the adjoint of L = sum(dL_dimage * image) w.r.t. activated params.
+        composite=False skips the forward image (the adjoint recomputes each pixel's trace; pixels
+        with a zero loss gradient are skipped), for large frames with sparse dL_dimage."""
+        fwd = self.render(scene, cam, mode, s2d, compensate) if composite else self.lists(scene, cam, mode, s2d,
+                                                                                            compensate)
         g2 = self.grad2d(fwd["proj"], fwd["binned"], cam, dL_dimage)
         grads = self.project_grad(scene, fwd["ids"], fwd["w"], cam, g2, s2d, compensate, grad_level)
         self._keep.clear()

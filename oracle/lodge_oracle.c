@@ -50,6 +50,19 @@ typedef REAL real;
 #define TILE 16
 #define NSH 16
 
+/* The timing build of the benchmark's CPU baseline compiles this same source
+ * with -fopenmp: ORC_PARALLEL_FOR then spreads the independent per-Gaussian
+ * projections and per-pixel walks over the host cores.  Each iteration writes
+ * only its own outputs, so the results are those of the plain builds; the
+ * arithmetic is untouched.  Without -fopenmp it expands to nothing. */
+#ifdef _OPENMP
+#define ORC_PARALLEL_FOR _Pragma("omp parallel for schedule(dynamic, 256)")
+#define ORC_PARALLEL_ROWS _Pragma("omp parallel for schedule(dynamic, 1)")
+#else
+#define ORC_PARALLEL_FOR
+#define ORC_PARALLEL_ROWS
+#endif
+
 /* ------------------------------------------------------------------------ */
 /* inputs                                                                   */
 /* ------------------------------------------------------------------------ */
@@ -453,6 +466,7 @@ void orc_project(const orc_level* lv, int32_t L, const uint32_t* ids, const real
                  const orc_camera* cam, real s2d, int32_t compensate, real* depth, real* uv, real* conic,
                  real* o_eff, real* rgb, int32_t* rect, uint32_t* tiles, real* radius)
 {
+    ORC_PARALLEL_FOR
     for (int64_t a = 0; a < count; a++) {
         int64_t i;
         int64_t l = level_of(lv, L, ids[a], &i);
@@ -621,6 +635,7 @@ void orc_composite(const orc_camera* cam, const real* uv, const real* conic, con
                    uint32_t* n_blend, uint32_t* n_eval, uint8_t* near)
 {
     int32_t W = cam->width, H = cam->height, TX = (W + TILE - 1) / TILE;
+    ORC_PARALLEL_ROWS
     for (int32_t y = 0; y < H; y++)
         for (int32_t x = 0; x < W; x++) {
             int32_t t = (y / TILE) * TX + (x / TILE);
@@ -635,6 +650,28 @@ void orc_composite(const orc_camera* cam, const real* uv, const real* conic, con
             if (n_eval) n_eval[p] = S.n_eval;
             if (near) near[p] = (uint8_t)S.near;
         }
+}
+
+/* The same per-pixel walk for listed pixels only (x[k], y[k]): colour
+ * rgb[k][3] = C + T bg, final_T[k], n_contrib[k], near[k].  Used to check
+ * sampled pixels of full-size frames. */
+void orc_composite_pixels(const orc_camera* cam, const real* uv, const real* conic, const real* o_eff,
+                          const real* rgb, const uint32_t* ranges, const uint32_t* vals, int64_t n,
+                          const int32_t* xs, const int32_t* ys, real* color, real* final_T, uint32_t* n_contrib,
+                          uint8_t* near)
+{
+    int32_t TX = (cam->width + TILE - 1) / TILE;
+    for (int64_t k = 0; k < n; k++) {
+        int32_t x = xs[k], y = ys[k];
+        int32_t t = (y / TILE) * TX + (x / TILE);
+        pix_t S; memset(&S, 0, sizeof(S));
+        composite_pixel(vals + ranges[2 * t], (int64_t)ranges[2 * t + 1] - ranges[2 * t], (real)x + (real)0.5,
+                        (real)y + (real)0.5, uv, conic, o_eff, rgb, &S);
+        for (int ch = 0; ch < 3; ch++) color[3 * k + ch] = S.C[ch] + S.T * cam->bg[ch];
+        final_T[k] = S.T;
+        n_contrib[k] = S.n_contrib;
+        near[k] = (uint8_t)S.near;
+    }
 }
 
 /* Brute-force compositor: for each pixel, every visible Gaussian whose tile
@@ -744,6 +781,10 @@ void orc_composite_grad2d(const orc_camera* cam, const real* uv, const real* con
     real* tr_G = (real*)malloc(sizeof(real) * (size_t)maxlen);
     for (int32_t y = 0; y < H; y++)
         for (int32_t x = 0; x < W; x++) {
+            int64_t p = (int64_t)y * W + x;
+            /* a pixel whose loss gradient is zero adds nothing to any gradient */
+            if (dL_dimage[p] == 0 && dL_dimage[(int64_t)H * W + p] == 0 && dL_dimage[2 * (int64_t)H * W + p] == 0)
+                continue;
             int32_t t = (y / TILE) * TX + (x / TILE);
             const uint32_t* list = vals + ranges[2 * t];
             int64_t len = (int64_t)ranges[2 * t + 1] - ranges[2 * t];
@@ -752,7 +793,6 @@ void orc_composite_grad2d(const orc_camera* cam, const real* uv, const real* con
             S.cap_trace = maxlen; S.tr_pos = tr_pos; S.tr_alpha = tr_alpha; S.tr_T = tr_T; S.tr_clamped = tr_cl;
             S.tr_G = tr_G;
             composite_pixel(list, len, px, py, uv, conic, o_eff, rgb, &S);
-            int64_t p = (int64_t)y * W + x;
             real dC[3];
             for (int ch = 0; ch < 3; ch++) dC[ch] = dL_dimage[(int64_t)ch * H * W + p];
             real Sfx[3];

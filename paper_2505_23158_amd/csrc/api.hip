@@ -11,17 +11,12 @@
 
 #include "lodge_internal.hpp"
 
-struct lodge_scene {
-    lodge::LevelsArg levels;
-    lodge::ChunksArg chunks;
-    bool has_chunks;
-};
-
 namespace lodge {
 
 namespace {
-
 thread_local std::string g_last_error;
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+}  // namespace
 
 lodge_status fail(lodge_status s, const std::string& msg)
 {
@@ -34,9 +29,55 @@ lodge_status hip_fail(hipError_t e, const char* where)
     return fail(LODGE_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
-
 uint64_t tiles_of(int32_t w, int32_t h) { return (uint64_t)((w + kTile - 1) / kTile) * (uint64_t)((h + kTile - 1) / kTile); }
+
+lodge_status check_cam(const lodge_camera* c, const lodge_workspace* ws)
+{
+    if (!c) return LODGE_OK;   // the camera already set on the workspace
+    if (ws && (c->width != ws->width || c->height != ws->height))
+        return fail(LODGE_ERR_INVALID_ARG, "camera size differs from the workspace's");
+    const float v[] = {c->fx, c->fy, c->cx, c->cy, c->znear, c->lim_x, c->lim_y};
+    for (float x : v)
+        if (!std::isfinite(x)) return fail(LODGE_ERR_INVALID_ARG, "camera has a non-finite intrinsic");
+    if (!(c->fx > 0) || !(c->fy > 0) || !(c->znear > 0) || !(c->lim_x > 0) || !(c->lim_y > 0))
+        return fail(LODGE_ERR_INVALID_ARG, "camera focal lengths, znear and limits must be > 0");
+    return LODGE_OK;
+}
+
+lodge_status check_render_opts(const lodge_render_opts* opts, lodge_render_opts* o)
+{
+    *o = lodge_render_opts{0.3f, 1, nullptr};
+    if (opts) *o = *opts;
+    if (!(o->s2d >= 0.0f) || !std::isfinite(o->s2d)) return fail(LODGE_ERR_INVALID_ARG, "s2d must be finite and >= 0");
+    return LODGE_OK;
+}
+
+// The stages of lodge_render on the views of a workspace: setup (camera,
+// options, counters), projection, binning, sort, compositing.
+lodge_status render_stages(const lodge_scene* scene, const lodge_selection& sel, const lodge_camera* cam,
+                           const lodge_render_opts& o, const Views& v, bool keep_select_flag, float* image,
+                           float* final_T, uint32_t* n_contrib, hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    auto mark = [&](int k) -> hipError_t {
+        return o.stage_events ? hipEventRecord(static_cast<hipEvent_t>(o.stage_events[k]), st) : hipSuccess;
+    };
+    if ((e = launch_render_setup(o, cam, v, keep_select_flag, st)) != hipSuccess)
+        return hip_fail(e, "lodge_render: setup");
+    if ((e = mark(0)) != hipSuccess) return hip_fail(e, "lodge_render: event");
+    if ((e = launch_project(scene->levels, sel, v, st)) != hipSuccess) return hip_fail(e, "lodge_render: project");
+    if ((e = mark(1)) != hipSuccess) return hip_fail(e, "lodge_render: event");
+    if ((e = launch_bin(v, sel, st)) != hipSuccess) return hip_fail(e, "lodge_render: bin");
+    if ((e = mark(2)) != hipSuccess) return hip_fail(e, "lodge_render: event");
+    if ((e = launch_sort(v, st)) != hipSuccess) return hip_fail(e, "lodge_render: sort");
+    if ((e = mark(3)) != hipSuccess) return hip_fail(e, "lodge_render: event");
+    if ((e = launch_composite(v, image, final_T, n_contrib, st)) != hipSuccess)
+        return hip_fail(e, "lodge_render: composite");
+    if ((e = mark(4)) != hipSuccess) return hip_fail(e, "lodge_render: event");
+    return LODGE_OK;
+}
+
+namespace {
 
 lodge_status check_ws(const lodge_scene* s, const lodge_workspace* ws)
 {
@@ -50,19 +91,6 @@ lodge_status check_ws(const lodge_scene* s, const lodge_workspace* ws)
         return fail(LODGE_ERR_UNSUPPORTED, "image has more than 32768 16x16 tiles");
     const Layout L = make_layout(s->levels.total, ws->width, ws->height, ws->max_active, ws->max_instances);
     if (ws->bytes < L.total) return fail(LODGE_ERR_INVALID_ARG, "workspace smaller than lodge_workspace_size()");
-    return LODGE_OK;
-}
-
-lodge_status check_cam(const lodge_camera* c, const lodge_workspace* ws)
-{
-    if (!c) return LODGE_OK;   // the camera already set on the workspace
-    if (ws && (c->width != ws->width || c->height != ws->height))
-        return fail(LODGE_ERR_INVALID_ARG, "camera size differs from the workspace's");
-    const float v[] = {c->fx, c->fy, c->cx, c->cy, c->znear, c->lim_x, c->lim_y};
-    for (float x : v)
-        if (!std::isfinite(x)) return fail(LODGE_ERR_INVALID_ARG, "camera has a non-finite intrinsic");
-    if (!(c->fx > 0) || !(c->fy > 0) || !(c->znear > 0) || !(c->lim_x > 0) || !(c->lim_y > 0))
-        return fail(LODGE_ERR_INVALID_ARG, "camera focal lengths, znear and limits must be > 0");
     return LODGE_OK;
 }
 
@@ -155,7 +183,7 @@ Views views_of(const lodge_workspace* ws, uint32_t n_total)
 // captured graph holds no memset.
 namespace {
 __global__ void k_render_setup(FrameParams* fp, FrameInfo* info, lodge_camera cam, int32_t has_cam, float s2d,
-                               int32_t compensate, int32_t TX, int32_t TY)
+                               int32_t compensate, int32_t TX, int32_t TY, uint32_t keep_flags)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) {
@@ -168,7 +196,7 @@ __global__ void k_render_setup(FrameParams* fp, FrameInfo* info, lodge_camera ca
         info->n_visible = 0;
         info->n_instances = 0;
         info->max_tile_len = 0;
-        info->overflow &= kOvfSelect;
+        info->overflow &= keep_flags;
         info->n_large = 0;
         info->n_huge = 0;
         info->n_mid = 0;
@@ -195,12 +223,13 @@ hipError_t launch_set_camera(const lodge_camera& cam, const Views& v, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_render_setup(const lodge_render_opts& o, const lodge_camera* cam, const Views& v, hipStream_t st)
+hipError_t launch_render_setup(const lodge_render_opts& o, const lodge_camera* cam, const Views& v,
+                               bool keep_select_flag, hipStream_t st)
 {
     lodge_camera c{};
     if (cam) c = *cam;
     k_render_setup<<<1, 64, 0, st>>>(v.params, v.info, c, cam ? 1 : 0, o.s2d, o.compensate, (int32_t)v.lay.TX,
-                                     (int32_t)v.lay.TY);
+                                     (int32_t)v.lay.TY, keep_select_flag ? kOvfSelect : 0u);
     return hipGetLastError();
 }
 
@@ -424,27 +453,10 @@ lodge_status lodge_render(const lodge_scene* scene, const lodge_selection* sel, 
     if ((s = check_cam(cam, ws)) != LODGE_OK) return s;
     if ((s = check_sel(sel, ws)) != LODGE_OK) return s;
     if (!image || !final_T || !n_contrib) return fail(LODGE_ERR_INVALID_ARG, "output buffers are NULL");
-    lodge_render_opts o{0.3f, 1, nullptr};
-    if (opts) o = *opts;
-    if (!(o.s2d >= 0.0f) || !std::isfinite(o.s2d)) return fail(LODGE_ERR_INVALID_ARG, "s2d must be finite and >= 0");
-    hipStream_t st = static_cast<hipStream_t>(stream);
+    lodge_render_opts o;
+    if ((s = check_render_opts(opts, &o)) != LODGE_OK) return s;
     const Views v = views_of(ws, scene->levels.total);
-    hipError_t e = hipSuccess;
-    auto mark = [&](int k) -> hipError_t {
-        return o.stage_events ? hipEventRecord(static_cast<hipEvent_t>(o.stage_events[k]), st) : hipSuccess;
-    };
-    if ((e = launch_render_setup(o, cam, v, st)) != hipSuccess) return hip_fail(e, "lodge_render: setup");
-    if ((e = mark(0)) != hipSuccess) return hip_fail(e, "lodge_render: event");
-    if ((e = launch_project(scene->levels, *sel, v, st)) != hipSuccess) return hip_fail(e, "lodge_render: project");
-    if ((e = mark(1)) != hipSuccess) return hip_fail(e, "lodge_render: event");
-    if ((e = launch_bin(v, *sel, st)) != hipSuccess) return hip_fail(e, "lodge_render: bin");
-    if ((e = mark(2)) != hipSuccess) return hip_fail(e, "lodge_render: event");
-    if ((e = launch_sort(v, st)) != hipSuccess) return hip_fail(e, "lodge_render: sort");
-    if ((e = mark(3)) != hipSuccess) return hip_fail(e, "lodge_render: event");
-    if ((e = launch_composite(v, image, final_T, n_contrib, st)) != hipSuccess)
-        return hip_fail(e, "lodge_render: composite");
-    if ((e = mark(4)) != hipSuccess) return hip_fail(e, "lodge_render: event");
-    return LODGE_OK;
+    return render_stages(scene, *sel, cam, o, v, true, image, final_T, n_contrib, static_cast<hipStream_t>(stream));
 }
 
 namespace {

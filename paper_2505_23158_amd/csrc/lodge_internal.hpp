@@ -190,7 +190,9 @@ hipError_t launch_select(const LevelsArg& lv, const Views& v, const lodge_select
 hipError_t launch_select_finish(const LevelsArg& lv, const Views& v, const lodge_selection& sel, hipStream_t st);
 hipError_t launch_sets_build(const LevelsArg& lv, const ChunksArg& ch, uint16_t* sets, hipStream_t st);
 hipError_t launch_sets_mark(const LevelsArg& lv, const Views& v, const uint16_t* sets, hipStream_t st);
-hipError_t launch_render_setup(const lodge_render_opts& o, const lodge_camera* cam, const Views& v, hipStream_t st);
+// keep_select_flag: keep the selection-overflow bit a lodge_select on the same workspace set
+hipError_t launch_render_setup(const lodge_render_opts& o, const lodge_camera* cam, const Views& v,
+                               bool keep_select_flag, hipStream_t st);
 hipError_t launch_project(const LevelsArg& lv, const lodge_selection& sel, const Views& v, hipStream_t st);
 hipError_t launch_bin(const Views& v, const lodge_selection& sel, hipStream_t st);
 hipError_t launch_sort(const Views& v, hipStream_t st);
@@ -203,6 +205,34 @@ hipError_t launch_activate(int64_t n, const float* ls, const float* qr, const fl
 hipError_t launch_activate_backward(int64_t n, const float* qr, const float* s, const float* o, const float* gs,
                                     const float* gq, const float* go, float* gls, float* gqr, float* gol,
                                     hipStream_t st);
+
+// ------------------------------------------------------------ host helpers (api.hip)
+
+// Records msg as the calling thread's last error and returns s.
+lodge_status fail(lodge_status s, const std::string& msg);
+lodge_status hip_fail(hipError_t e, const char* where);
+uint64_t tiles_of(int32_t w, int32_t h);
+// cam may be NULL (then OK); ws may be NULL (then the size is not checked).
+lodge_status check_cam(const lodge_camera* c, const lodge_workspace* ws);
+// Defaults (s2d 0.3, compensation on) for opts == NULL; validates s2d.
+lodge_status check_render_opts(const lodge_render_opts* opts, lodge_render_opts* o);
+
+}  // namespace lodge
+
+// The scene behind the opaque handle of include/lodge.h.
+struct lodge_scene {
+    lodge::LevelsArg levels;
+    lodge::ChunksArg chunks;
+    bool has_chunks;
+};
+
+namespace lodge {
+
+// The stages of lodge_render (setup, project, bin, sort, composite) on the
+// views of a workspace; keep_select_flag as for launch_render_setup.
+lodge_status render_stages(const lodge_scene* scene, const lodge_selection& sel, const lodge_camera* cam,
+                           const lodge_render_opts& o, const Views& v, bool keep_select_flag, float* image,
+                           float* final_T, uint32_t* n_contrib, hipStream_t st);
 
 // ------------------------------------------------------------ device helpers
 

@@ -118,6 +118,8 @@ def lib():
             "lodge_render_backward": (st, [vp, C.POINTER(lodge_selection), vp, C.POINTER(lodge_render_opts),
                                            C.POINTER(lodge_workspace), vp, vp, vp, C.c_int32,
                                            C.POINTER(lodge_grads), vp]),
+            "lodge_render_static": (st, [vp, C.POINTER(lodge_selection), vp, C.POINTER(lodge_render_opts), vp, vp,
+                                         vp, vp, vp]),
             "lodge_activate": (st, [C.c_int64, vp, vp, vp, vp, vp, vp, vp]),
             "lodge_activate_backward": (st, [C.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         }
@@ -137,7 +139,9 @@ def _check(status: int):
 EXPORTED = ["lodge_status_string", "lodge_last_error", "lodge_version", "lodge_scene_create", "lodge_scene_destroy",
             "lodge_scene_total", "lodge_workspace_size", "lodge_set_camera", "lodge_select", "lodge_chunk_sets_size",
             "lodge_chunk_sets_build", "lodge_select_chunk_sets", "lodge_render", "lodge_frame_info_read",
-            "lodge_check", "lodge_debug_views", "lodge_render_backward", "lodge_activate", "lodge_activate_backward"]
+            "lodge_check", "lodge_debug_views", "lodge_render_backward", "lodge_activate", "lodge_activate_backward",
+            "lodge_render_static"]
+STATIC_SCRATCH_BYTES = 256 << 20
 
 
 # --------------------------------------------------------------------------- helpers
@@ -317,6 +321,18 @@ def lodge_render(scene: Scene, sel: Selection, cam, ws: Workspace, image, final_
     opts = lodge_render_opts(s2d=s2d, compensate=int(compensate), stage_events=C.cast(evs, C.c_void_p) if evs else None)
     _check(lib().lodge_render(scene.handle, C.byref(sel.desc), cp, C.byref(opts), C.byref(ws.desc), _ptr(image),
                               _ptr(final_T), _ptr(n_contrib), _stream_ptr(stream)))
+
+
+def lodge_render_static(scene: Scene, sel: Selection, cam, image, final_T, n_contrib, overflow=None, s2d: float = 0.3,
+                        compensate: bool = True, stream=None):
+    """lodge_render with the library's static scratch in place of a workspace (allocates nothing);
+    overflow: None or a device int32 tensor of one element that receives the overflow bits."""
+    if cam is None:
+        raise ValueError("lodge_render_static needs a camera")
+    cp, keep = _cam_arg(cam)
+    opts = lodge_render_opts(s2d=s2d, compensate=int(compensate))
+    _check(lib().lodge_render_static(scene.handle, C.byref(sel.desc), cp, C.byref(opts), _ptr(image), _ptr(final_T),
+                                     _ptr(n_contrib), _ptr(overflow), _stream_ptr(stream)))
 
 
 def lodge_frame_info_read(ws: Workspace, stream=None) -> dict:

@@ -12,7 +12,12 @@ the GPU run concurrently.
 Completion is detected by polling the slot's event; latency is completion
 minus arrival (the device-to-host copy of the image is not included, as in
 the paper's timing protocol).  A frame whose capacities overflowed is
-re-rendered outside the graph with capacities grown to what it needed.
+rendered again on its slot, which is rebuilt with capacities grown to what
+the frame needed: the slot stays busy meanwhile (other slots keep being
+admitted and polled), the grown slot renders eagerly from then on, the
+class's capacities grow for slots created later, and the extra device bytes
+count against the memory budget.  A request that still overflows after a
+few growths fails loudly.
 
 The scheduler talks to a backend with four calls (slot_bytes, new_slot,
 launch, poll), so its admission and bookkeeping are tested on the CPU with
@@ -111,7 +116,8 @@ class Scheduler:
                 fin = be.poll(sid)
                 if fin is not None:
                     req, start = busy.pop(sid)
-                    done_t, retried = fin
+                    done_t, retried, grown = fin
+                    mem += grown
                     results.append(Result(req.rid, req.arrival, start, done_t - t0, sid, req.resolution, retried))
                     free.setdefault(req.resolution, []).append(sid)
                     progressed = True
@@ -149,7 +155,7 @@ class SimulatedBackend:
     in a device queue), which is how overlapping streams behave."""
 
     def __init__(self, service: Dict[Tuple[int, int], float], slot_mem: Dict[Tuple[int, int], int], parallel: int = 4,
-                 fail_first: Optional[set] = None):
+                 fail_first: Optional[set] = None, grow_bytes: int = 0):
         self.service = service
         self.mem = slot_mem
         self.parallel = parallel
@@ -159,6 +165,7 @@ class SimulatedBackend:
         self.done_at: Dict[int, float] = {}
         self.order: List[Tuple[int, int]] = []    # (rid, sid) launch order
         self.fail_first = set(fail_first or ())
+        self.grow_bytes = grow_bytes          # device bytes a retried request's slot grows by
         self.retried: Dict[int, bool] = {}
 
     def now(self):
@@ -184,7 +191,8 @@ class SimulatedBackend:
     def poll(self, sid):
         if sid in self.done_at:
             t = self.done_at.pop(sid)
-            return t, self.retried.pop(sid)
+            r = self.retried.pop(sid)
+            return t, r, self.grow_bytes if r else 0
         return None
 
     def idle(self, t0, next_arrival, any_busy):
@@ -207,35 +215,40 @@ class SimulatedBackend:
 class GpuBackend:
     """Slots on the GPU: per-slot workspace, pinned camera, stream and graph."""
 
+    MAX_GROWTHS = 4
+
     def __init__(self, scene, mode: int, caps: Dict[Tuple[int, int], Tuple[int, int]], use_graphs: bool = True,
                  keep_images: bool = False):
         import torch
         from . import lodge as L
         self.torch, self.L = torch, L
-        self.scene, self.mode, self.caps = scene, mode, caps
+        self.scene, self.mode = scene, mode
+        self.caps = dict(caps)
         self.use_graphs = use_graphs
         self.keep_images = keep_images
         self.slots = []
         self.images: Dict[int, object] = {}
+        self.outputs: Dict[int, dict] = {}
 
     def now(self):
         return time.perf_counter()
 
-    def slot_bytes(self, res):
-        w, h = res
-        ma, mi = self.caps[res]
-        L = self.L
+    def _bytes(self, res, caps):
         import ctypes as C
+        w, h = res
+        ma, mi = caps
+        L = self.L
         nb = C.c_size_t()
         L._check(L.lib().lodge_workspace_size(self.scene.handle, w, h, ma, mi, C.byref(nb)))
         return int(nb.value) + 8 * ma + 4 * 5 * w * h
 
+    def slot_bytes(self, res):
+        return self._bytes(res, self.caps[res])
+
     def _make(self, res, caps):
         torch, L = self.torch, self.L
         w, h = res
-        R = L.Renderer(self.scene, w, h, max_active=caps[0], max_instances=caps[1])
-        stream = torch.cuda.Stream()
-        return R, stream
+        return L.Renderer(self.scene, w, h, max_active=caps[0], max_instances=caps[1])
 
     def prewarm(self, res, k: int):
         """Creates k slots of a class ahead of the run (returned to the scheduler's free lists)."""
@@ -243,7 +256,9 @@ class GpuBackend:
 
     def new_slot(self, res):
         torch, L = self.torch, self.L
-        R, stream = self._make(res, self.caps[res])
+        caps = self.caps[res]
+        R = self._make(res, caps)
+        stream = torch.cuda.Stream()
         graph = None
         if self.use_graphs:
             # any valid camera of this size; the graph reads whatever camera is set before a replay
@@ -258,20 +273,45 @@ class GpuBackend:
                 R.frame(None, self.mode)
         done = torch.cuda.Event()
         sid = len(self.slots)
-        self.slots.append({"res": res, "R": R, "stream": stream, "graph": graph, "done": done, "req": None})
+        self.slots.append({"res": res, "R": R, "caps": caps, "stream": stream, "graph": graph, "done": done,
+                           "req": None, "growths": 0, "grown_bytes": 0})
         return sid
 
-    def launch(self, sid, req):
-        torch = self.torch
-        s = self.slots[sid]
-        s["req"] = req
-        with torch.cuda.stream(s["stream"]):
+    def _render(self, s, cam):
+        with self.torch.cuda.stream(s["stream"]):
             if s["graph"] is not None:
-                self.L.lodge_set_camera(s["R"].ws, req.cam, s["stream"])
+                self.L.lodge_set_camera(s["R"].ws, cam, s["stream"])
                 s["graph"].replay()
             else:
-                s["R"].frame(req.cam, self.mode)
+                s["R"].frame(cam, self.mode, stream=s["stream"])
             s["done"].record()
+
+    def launch(self, sid, req):
+        s = self.slots[sid]
+        s["req"] = req
+        s["growths"] = 0
+        self._render(s, req.cam)
+
+    def _grow(self, s, na, ni):
+        """Replaces the slot's renderer by one with the capacities the frame needed (a selection overflow
+        truncates the projected set, so its instance count is only a lower bound: the instance capacity at
+        least doubles then).  The grown slot renders eagerly from now on."""
+        res = s["res"]
+        ma, mi = s["caps"]
+        sel_ovf = na > ma
+        new_ma = max(ma, na)
+        new_mi = max(mi, int(ni * 1.25) + 1)
+        if sel_ovf:
+            new_mi = max(new_mi, 2 * mi)
+        new_mi = min(new_mi, (1 << 32) - 1)
+        caps = (new_ma, new_mi)
+        grown = self._bytes(res, caps) - self._bytes(res, s["caps"])
+        s["R"] = self._make(res, caps)
+        s["graph"] = None
+        s["caps"] = caps
+        s["grown_bytes"] += grown
+        cur = self.caps[res]
+        self.caps[res] = (max(cur[0], caps[0]), max(cur[1], caps[1]))
 
     def poll(self, sid):
         s = self.slots[sid]
@@ -280,23 +320,27 @@ class GpuBackend:
         t = time.perf_counter()
         L = self.L
         st, na, ni = L.lodge_check(s["R"].ws, stream=s["stream"])
-        retried = False
         if st == L.LODGE_ERR_CAPACITY:
-            # grow to what the frame needed and render it again outside the graph
-            res = s["res"]
-            caps = (max(na, self.caps[res][0]), max(int(ni * 1.25), self.caps[res][1]))
-            R, stream = self._make(res, caps)
-            with self.torch.cuda.stream(stream):
-                R.frame(s["req"].cam, self.mode)
-            stream.synchronize()
-            t = time.perf_counter()
-            retried = True
-            if self.keep_images:
-                self.images[s["req"].rid] = R.image.clone()
-        elif self.keep_images:
+            if s["growths"] >= self.MAX_GROWTHS:
+                raise RuntimeError(f"request {s['req'].rid}: capacity still exceeded after {s['growths']} growths "
+                                   f"(needs {na} active, {ni} instances)")
+            s["growths"] += 1
+            self._grow(s, na, ni)
+            self._render(s, s["req"].cam)     # the slot stays busy until the re-render completes
+            return None
+        if st != L.LODGE_OK:
+            L._check(st)
+        if self.keep_images:
+            # copies ordered on the slot's stream, before its next launch overwrites the outputs
+            R = s["R"]
             with self.torch.cuda.stream(s["stream"]):
-                self.images[s["req"].rid] = s["R"].image.clone()
-        return t, retried
+                n = min(int(R.sel.count[0].item()), R.sel.cap)
+                self.images[s["req"].rid] = R.image.clone()
+                self.outputs[s["req"].rid] = {"image": R.image.clone(), "final_T": R.final_T.clone(),
+                                              "n_contrib": R.n_contrib.clone(), "ids": R.sel.ids[:n].clone(),
+                                              "w": R.sel.w[:n].clone(), "caps": s["caps"]}
+        grown, s["grown_bytes"] = s["grown_bytes"], 0
+        return t, s["growths"] > 0, grown
 
     def idle(self, t0, next_arrival, any_busy):
         if not any_busy and next_arrival is not None:

@@ -200,3 +200,115 @@ def test_full_size_large_lod_frame(L, oracle32):
     cam = sc.cameras[10]
     full_parity(oracle32, sc, d, cam, oracle.CHUNKED, "lod4-26.55M-frame10", max_active=6_000_000,
                 max_instances=24_000_000)
+
+
+def _copies(lv, k):
+    return [lv] * k
+
+
+@pytest.mark.parametrize("mode", [oracle.ALL, oracle.LOD_CAMERA])
+def test_identical_levels_exact_depth_ties(L, oracle32, mode):
+    """Three identical copies of one level: in ALL mode every Gaussian is
+    selected three times with the same depth, so every sort key ties three
+    ways and the active index alone orders them; in LOD_CAMERA mode the
+    copies partition the Gaussians by distance (Gaussians placed exactly on
+    the switch distances included)."""
+    base = synth.gaussians(3000, (901, 0), synth._cube(4.0), -3.0, 0.5, morton=False)
+    base.mean[:, 0] = [2.0, 0.0, 0.0]
+    base.mean[:, 1] = [0.0, 4.0, 0.0]
+    base.mean[:, 2] = [0.0, 0.0, 2.0]
+    sc = Scene(levels=_copies(base, 3), d=[2.0, 4.0])
+    cam = synth.look_at((0.0, 0.5, -6.0), (0.0, 0.0, 0.0), (0, -1, 0), 96, 80)
+    if mode == oracle.LOD_CAMERA:
+        cam = synth.look_at((0.0, 0.0, 0.0), (0.0, 0.3, 1.0), (0, -1, 0), 96, 80)
+    g, r = full_parity(oracle32, sc, dev(L, sc), cam, mode, f"identical-levels-mode{mode}")
+    if mode == oracle.ALL:
+        bn = r["binned"]
+        same = (bn.dkey[1:] == bn.dkey[:-1]) & (bn.tile[1:] == bn.tile[:-1])
+        assert same.sum() >= bn.M // 2, "most sort keys tie"
+
+
+@pytest.mark.parametrize("n", [64, 65, 256, 257, 2048, 2049, 4096, 4097, 8192, 8193, 16385])
+def test_tied_depths_at_sort_band_edges(L, oracle32, n):
+    """Exactly n instances in one tile, built from duplicated Gaussians (two
+    identical levels, plus a third of one Gaussian for odd n): every depth
+    occurs twice, in every length band of the sort."""
+    h = n // 2
+    cam = synth.look_at((0, 0, 0), (0, 0, 1), (0, -1, 0), 64, 64)
+    z = 10.0
+
+    def level(m, key):
+        lv = synth.gaussians(m, (49, key), synth._cube(0.05), -6.0, 0.3, morton=False)
+        lv.mean[2] += z
+        lv.mean[0] += (24.0 - cam.cx) * z / cam.fx
+        lv.mean[1] += (24.0 - cam.cy) * z / cam.fy
+        return lv
+
+    base = level(h, n)
+    levels = [base, base] + ([level(1, n + 1)] if n % 2 else [])
+    sc = Scene(levels=levels, d=[1e3, 2e3][:len(levels) - 1])
+    g, r = full_parity(oracle32, sc, dev(L, sc), cam, oracle.ALL, f"tied-sort-band-{n}", compensate=False)
+    lens = r["binned"].ranges[:, 1] - r["binned"].ranges[:, 0]
+    assert int(lens.max()) == n and int((lens > 0).sum()) == 1
+    dk = r["binned"].dkey
+    assert int((dk[1:] == dk[:-1]).sum()) >= h
+
+
+def _signed_perms(v):
+    import itertools
+    out = set()
+    for p in itertools.permutations(v):
+        for s in itertools.product((1, -1), repeat=3):
+            out.add(tuple(a * b for a, b in zip(p, s)))
+    return sorted(out)
+
+
+def test_gaussians_on_switch_distances_camera_mode(L, oracle32):
+    """Gaussians at exactly d_1 = 7 and d_2 = 9 from the camera centre (integer
+    offsets of those norms, exact in FP32) among random ones, in three
+    identical levels: each boundary Gaussian belongs to the level whose
+    interval starts at its distance (inclusive lower bound of Eq. 2)."""
+    p = np.array([0.5, -0.25, 1.0])
+    offs = _signed_perms((2, 3, 6)) + _signed_perms((1, 4, 8)) + _signed_perms((4, 4, 7))
+    rng = np.random.default_rng(71)
+    fill = rng.uniform(-12, 12, (4000, 3))
+    pts = np.concatenate([p + np.asarray(offs, np.float64), p + fill])
+    lv = synth.gaussians(len(pts), (71, 0), synth._cube(1.0), -2.5, 0.4, morton=False)
+    lv.mean[:] = pts.T.astype(np.float32)
+    sc = Scene(levels=_copies(lv, 3), d=[7.0, 9.0])
+    cam = synth.look_at(p, p + np.array([0.2, 0.1, 1.0]), (0, -1, 0), 160, 120)
+    assert np.array_equal(cam.pos, p.astype(np.float32))
+    g, r = full_parity(oracle32, sc, dev(L, sc), cam, oracle.LOD_CAMERA, "switch-distances-camera")
+    n = lv.n
+    lvl = dict(zip((r["ids"] % n).tolist(), (r["ids"] // n).tolist()))
+    nb = len(offs)
+    for i, o in enumerate(offs):
+        dist = int(round(np.linalg.norm(o)))
+        assert lvl[i] == (1 if dist == 7 else 2), (o, lvl[i])
+
+
+def test_gaussians_on_switch_distances_chunked(L, oracle32):
+    """2 x 2 chunks 20 m apart (offset r = 20) and d_1 = 6: Gaussians at exactly
+    d_1 + r = 26 from each chunk centre (offsets (6, 8, 24), (0, 10, 24) and
+    their signed permutations), in two identical levels, for cameras on
+    either side of the bisectors."""
+    ch = synth.chunk_grid(2, 20.0, 1.0, band=4.0)
+    assert np.all(ch.offsets == 20.0)
+    offs = np.asarray(_signed_perms((6, 8, 24)) + _signed_perms((0, 10, 24)), np.float64)
+    rng = np.random.default_rng(72)
+    pts = [c + offs for c in ch.centers.astype(np.float64)] + [rng.uniform(-40, 40, (6000, 3)) * [1, 1, 0.1]]
+    pts = np.concatenate(pts)
+    lv = synth.gaussians(len(pts), (72, 0), synth._cube(1.0), -2.0, 0.4, morton=False)
+    lv.mean[:] = pts.T.astype(np.float32)
+    sc = Scene(levels=_copies(lv, 2), d=[6.0], chunks=ch)
+    d = dev(L, sc)
+    for eye in ((-3.0, -12.0, 1.5), (1.0, 4.0, 1.2), (14.0, 9.0, 2.0)):
+        cam = synth.look_at(eye, (eye[0] + 5.0, eye[1] + 20.0, 0.0), (0, 0, 1), 160, 96)
+        g, r = full_parity(oracle32, sc, d, cam, oracle.CHUNKED, f"switch-distances-chunked-{eye}")
+        f, o, t = r["fot"]
+        n = lv.n
+        ids = set(r["ids"].tolist())
+        # a boundary Gaussian of chunk f sits in level 1 about f (inclusive), not in level 0 about f
+        for j in range(len(offs)):
+            i = f * len(offs) + j
+            assert (n + i) in ids

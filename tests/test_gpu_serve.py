@@ -5,9 +5,10 @@ several streams equal the same frames rendered one at a time."""
 import numpy as np
 import pytest
 
+import oracle
 import synth
 
-from parity_util import log
+from parity_util import compare_image, log
 
 pytestmark = pytest.mark.gpu
 
@@ -79,6 +80,76 @@ def test_capacity_overflow_is_retried_outside_the_graph(env):
     rep, be = serve(dev, [Request(0, 0.0, cam)], L.SELECT_CHUNKED, tiny, prewarm=1, keep_images=True)
     assert rep.results[0].retried
     assert torch.equal(be.images[0], alone(L, dev, cam))
+    assert be.caps[(640, 360)][1] > 2_000
+
+
+def test_selection_overflow_grows_the_slot_until_the_frame_fits(env, oracle32):
+    """Both capacities far too small: the selection overflows first (so the
+    first instance count covers only the truncated set), the slot grows until
+    lodge_check passes, later requests of the class reuse the grown slot, and
+    every served result equals the oracle."""
+    import torch
+    from paper_2505_23158_amd.serve import Request, serve
+    L, sc, dev = env
+    tiny = {(640, 360): (1_000, 1_000)}
+    cams = synth.config3_path(5, 640, 360)[1:4]
+    reqs = [Request(i, 0.004 * i, c) for i, c in enumerate(cams)]
+    rep, be = serve(dev, reqs, L.SELECT_CHUNKED, tiny, prewarm=1, keep_images=True, max_slots_per_class=1)
+    assert rep.results[0].retried
+    ma, mi = be.caps[(640, 360)]
+    assert ma > 1_000 and mi > 1_000
+    assert rep.mem_bytes > be._bytes((640, 360), (1_000, 1_000))
+    for r in reqs:
+        out = be.outputs[r.rid]
+        ref = oracle32.render(sc, r.cam, oracle.CHUNKED)
+        assert np.array_equal(out["ids"].cpu().numpy().astype(np.uint32), ref["ids"])
+        g = {k: out[k].cpu().numpy() for k in ("image", "final_T", "n_contrib")}
+        g["n_contrib"] = g["n_contrib"].astype(np.uint32)
+        compare_image(oracle32, g, ref, r.cam)
+
+
+@pytest.fixture(scope="module")
+def env5():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_23158_amd import lodge as L
+    sc = synth.config3_scene(frac=0.05, n_frames=4)
+    return L, sc, L.Scene.from_synth(sc)
+
+
+def test_served_requests_match_the_oracle(env5, oracle32):
+    """Requests at the serving poses (1.5-50 m up, pitch 0 to -45 degrees,
+    mixed resolutions) served concurrently through captured graphs on a
+    1.33M-Gaussian scene: each served selection equals the oracle's bit for
+    bit and each served image, final T and n_contrib the oracle's within the
+    image tolerance."""
+    import torch
+    from paper_2505_23158_amd.serve import Request, serve
+    L, sc, dev = env5
+    reqs = synth.serving_requests(24, rate=3000.0, half_xy=60.0, seed=13)
+    requests = [Request(i, t, cam) for i, (t, cam) in enumerate(reqs)]
+    caps = {(640, 360): (600_000, 4_000_000), (1280, 720): (600_000, 8_000_000),
+            (1920, 1080): (600_000, 12_000_000)}
+    rep, be = serve(dev, requests, L.SELECT_CHUNKED, caps, max_slots_per_class=3, prewarm=2, keep_images=True)
+    torch.cuda.synchronize()
+    assert rep.peak_in_flight >= 2
+    chosen, seen = [], {}
+    for r in requests:
+        if seen.get(r.resolution, 0) < 3:
+            chosen.append(r)
+            seen[r.resolution] = seen.get(r.resolution, 0) + 1
+    assert len(seen) == 3 and len(chosen) >= 6
+    for r in chosen:
+        out = be.outputs[r.rid]
+        ref = oracle32.render(sc, r.cam, oracle.CHUNKED)
+        assert np.array_equal(out["ids"].cpu().numpy().astype(np.uint32), ref["ids"]), r.rid
+        assert np.array_equal(out["w"].cpu().numpy().view(np.uint32), ref["w"].astype(np.float32).view(np.uint32))
+        g = {k: out[k].cpu().numpy() for k in ("image", "final_T", "n_contrib")}
+        g["n_contrib"] = g["n_contrib"].astype(np.uint32)
+        flips, err = compare_image(oracle32, g, ref, r.cam)
+        log(f"[serve-oracle] request {r.rid} {r.resolution} eye_z={r.cam.pos[2]:.1f}: active={len(ref['ids'])} "
+            f"M={ref['binned'].M} flips={flips} max_err={err:.2e}")
 
 
 def test_frames_in_flight_equal_frames_one_at_a_time(env):

@@ -62,6 +62,20 @@ def test_retry_after_capacity_overflow_is_counted():
     assert rep.summary()["retries"] == 1
 
 
+def test_grown_slot_counts_against_the_memory_budget():
+    # request 0 overflows and its slot grows by 2 units (reported when it completes, at 6 ms): with a
+    # budget of 3, request 2 (arriving while request 1 holds slot 0) cannot get a slot of its own
+    be = SimulatedBackend({R360: 0.003}, {R360: 1}, parallel=4, fail_first={0}, grow_bytes=2)
+    rep = Scheduler(be, mem_budget=3, max_slots_per_class=4).run(reqs([0.0, 0.007, 0.0071], [R360] * 3))
+    assert rep.results[0].retried and rep.mem_bytes == 3
+    assert rep.slots_created[R360] == 1
+    assert be.order == [(0, 0), (1, 0), (2, 0)]
+    # without the growth the same arrivals open a second slot
+    be2 = SimulatedBackend({R360: 0.003}, {R360: 1}, parallel=4, fail_first={0}, grow_bytes=0)
+    rep2 = Scheduler(be2, mem_budget=3, max_slots_per_class=4).run(reqs([0.0, 0.007, 0.0071], [R360] * 3))
+    assert rep2.slots_created[R360] == 2
+
+
 def test_budget_below_one_slot_is_an_error():
     be = SimulatedBackend({R1080: 0.01}, {R1080: 1000}, parallel=4)
     with pytest.raises(RuntimeError):
