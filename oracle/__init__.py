@@ -169,6 +169,23 @@ class Oracle:
             raise ValueError("select: bad arguments")
         return ids[:n].copy(), w[:n].copy(), (f.value, o.value, t.value)
 
+    def select_chunk(self, scene, k: int):
+        """The stored active set of chunk k alone (Eq. 2 at the chunk centre, offsets r_k), weight 1."""
+        lv = self.levels(scene.levels)
+        d = self._arr(np.asarray(scene.d if scene.d else [0.0]))
+        ch = scene.chunks
+        centers, offs = self._arr(ch.centers), self._arr(ch.offsets)
+        cap = max(scene.n_total, 1)
+        ids = np.empty(cap, np.uint32)
+        w = np.empty(cap, self.dt)
+        fn = self.lib.orc_select_chunk
+        fn.restype = C.c_int64
+        n = fn(lv, C.c_int32(len(scene.levels)), _p(d), _p(centers), _p(offs), C.c_int32(len(ch.centers)),
+               C.c_int32(k), _p(ids), _p(w), C.c_int64(cap))
+        if n < 0:
+            raise ValueError("select_chunk: bad chunk index")
+        return ids[:n].copy(), w[:n].copy()
+
     def project(self, scene, ids, w, cam, s2d=0.3, compensate=True) -> Projection:
         lv = self.levels(scene.levels)
         n = len(ids)
@@ -247,6 +264,23 @@ class Oracle:
                                               _p(binned.ranges), _p(val), C.c_int32(x), C.c_int32(y), _p(probe),
                                               self.real(tol)))
 
+    def importance(self, proj: Projection, binned: Binned, cam, ids, n_total: int, score=None, amb=None):
+        """Max-accumulates each Gaussian's largest blending weight alpha T over the view's pixels into
+        score[global id] (Sec. 3 "Preliminaries: Importance pruning"); amb[global id] marks weights
+        that a near-threshold decision leaves open.  Returns (score, amb)."""
+        if score is None:
+            score = np.zeros(n_total, self.dt)
+        if amb is None:
+            amb = np.zeros(n_total, np.uint8)
+        assert score.dtype == self.dt and score.flags.c_contiguous and len(score) == n_total
+        assert amb.dtype == np.uint8 and amb.flags.c_contiguous and len(amb) == n_total
+        c = self.camera(cam)
+        ids = np.ascontiguousarray(ids, np.uint32)
+        val = binned.val if binned.M else np.zeros(1, np.uint32)
+        self.lib.orc_importance(C.byref(c), _p(proj.uv), _p(proj.conic), _p(proj.o_eff), _p(proj.rgb),
+                                _p(binned.ranges), _p(val), _p(ids), _p(score), _p(amb))
+        return score, amb
+
     def sh_basis(self, x, y, z):
         Y = np.empty(16, self.dt)
         self.lib.orc_sh_basis(self.real(x), self.real(y), self.real(z), _p(Y))
@@ -300,6 +334,14 @@ class Oracle:
         self._keep.clear()
         return out
 
+    def view_importance(self, scene, ids, w, cam, score=None, amb=None, s2d=0.3, compensate=True):
+        """project -> bin/sort -> importance for a given selection (ids, w) seen from cam."""
+        proj = self.project(scene, ids, w, cam, s2d, compensate)
+        binned = self.bin_sort(proj, cam)
+        out = self.importance(proj, binned, cam, ids, scene.n_total, score, amb)
+        self._keep.clear()
+        return out
+
     def render_grad(self, scene, cam, mode: int, dL_dimage, s2d=0.3, compensate=True, grad_level=-1,
                     composite=True):
         """Forward, then the adjoint of L = sum(dL_dimage * image) w.r.t. activated params.
@@ -311,3 +353,31 @@ class Oracle:
         grads = self.project_grad(scene, fwd["ids"], fwd["w"], cam, g2, s2d, compensate, grad_level)
         self._keep.clear()
         return fwd, g2, grads
+
+
+# -- visibility filtering of the stored chunk sets (Sec. 3 "Visibility filtering") -------------------------
+
+
+def prune_chunk_set(ids, score, threshold):
+    """Chunk set after visibility filtering: the members whose importance score reaches the threshold
+    (Gaussians scoring below it are removed).  ids ascending global ids, score by global id."""
+    ids = np.asarray(ids, np.uint32)
+    return ids[np.asarray(score)[ids] >= threshold]
+
+
+def union_select(n_total, set_f, set_o, t):
+    """The two-chunk selection from stored sets A_f, A_o (ascending global ids): their union in ascending
+    id, weight 1 in both, t in A_f only and 1 - t (one FP32 rounding) in A_o only (Eq. 4 and its text:
+    only the symmetric difference is re-weighted).  set_o None: A_f alone, weight 1."""
+    in_f = np.zeros(n_total, bool)
+    in_f[np.asarray(set_f, np.int64)] = True
+    in_o = np.zeros(n_total, bool)
+    if set_o is not None:
+        in_o[np.asarray(set_o, np.int64)] = True
+    ids = np.nonzero(in_f | in_o)[0].astype(np.uint32)
+    t32 = np.float32(t)
+    w = np.where(in_f[ids] & in_o[ids], np.float32(1.0),
+                 np.where(in_f[ids], t32, np.float32(1.0) - t32)).astype(np.float32)
+    if set_o is None:
+        w[:] = 1.0
+    return ids, w

@@ -226,6 +226,35 @@ int64_t orc_select(const orc_level* lv, int32_t L, const real* d, int32_t mode,
     return count;
 }
 
+/* The stored active set of chunk k alone (Sec. 3 "Reducing memory with
+ * chunk-based rendering": Eq. 2 evaluated at the chunk centre m_k, every
+ * switch distance offset by the chunk's r_k), weight 1 for every member.
+ * This is the set the per-chunk visibility filtering renders and prunes.
+ * Writes min(count, cap) entries; returns count (-1 on bad arguments). */
+int64_t orc_select_chunk(const orc_level* lv, int32_t L, const real* d, const real* centers, const real* offsets,
+                         int32_t K, int32_t k, uint32_t* ids, real* w, int64_t cap)
+{
+    if (k < 0 || k >= K) return -1;
+    int64_t count = 0, base = 0;
+    for (int32_t l = 0; l < L; l++) {
+        real lo, hi;
+        bounds(d, L, l, offsets[k], &lo, &hi);
+        for (int64_t i = 0; i < lv[l].n; i++) {
+            real mu[3] = {lv[l].mean[i], lv[l].mean[lv[l].n + i], lv[l].mean[2 * lv[l].n + i]};
+            real d2 = dist2(mu, centers + 3 * k);
+            if (lo <= d2 && d2 < hi) {
+                if (count < cap) {
+                    ids[count] = (uint32_t)(base + i);
+                    w[count] = 1;
+                }
+                count++;
+            }
+        }
+        base += lv[l].n;
+    }
+    return count;
+}
+
 /* ------------------------------------------------------------------------ */
 /* real spherical harmonics to degree 3                                      */
 /* ------------------------------------------------------------------------ */
@@ -564,6 +593,7 @@ typedef struct {
     /* flips: decision indices (counted over all threshold decisions) to invert */
     const int* flip; int nflip;
     int ndec;           /* number of near decisions seen */
+    int64_t first_near; /* list position of the first near decision (len if none) */
     int dec_near[64];   /* decision indices of near decisions */
     /* optional per-entry trace for the adjoint */
     int64_t cap_trace;  int64_t ntrace;
@@ -583,6 +613,7 @@ static void composite_pixel(const uint32_t* list, int64_t len, real px, real py,
     S->C[0] = S->C[1] = S->C[2] = 0;
     S->T = 1;
     S->n_contrib = 0; S->n_blend = 0; S->n_eval = 0; S->near = 0; S->ndec = 0; S->ntrace = 0;
+    S->first_near = len;
     int dec = 0;
     for (int64_t k = 0; k < len; k++) {
         uint32_t a = list[k];
@@ -591,7 +622,7 @@ static void composite_pixel(const uint32_t* list, int64_t len, real px, real py,
         real A = conic[3 * a], B = conic[3 * a + 1], C = conic[3 * a + 2];
         real power = (real)-0.5 * ((A * dx) * dx + (C * dy) * dy) - (B * dx) * dy;
         int skip = power > 0;
-        if ((power > 0 ? power : -power) < NEAR_POW) { if (S->ndec < 64) S->dec_near[S->ndec++] = dec; S->near = 1; }
+        if ((power > 0 ? power : -power) < NEAR_POW) { if (S->ndec < 64) S->dec_near[S->ndec++] = dec; if (!S->near) S->first_near = k; S->near = 1; }
         if (flipped(S, dec)) skip = !skip;
         dec++;
         if (skip) continue;
@@ -600,14 +631,14 @@ static void composite_pixel(const uint32_t* list, int64_t len, real px, real py,
         real alpha = og < ALPHA_MAX ? og : ALPHA_MAX;
         int lowa = alpha < ALPHA_MIN;
         real da = alpha - ALPHA_MIN;
-        if ((da > 0 ? da : -da) <= NEAR_REL * ALPHA_MIN) { if (S->ndec < 64) S->dec_near[S->ndec++] = dec; S->near = 1; }
+        if ((da > 0 ? da : -da) <= NEAR_REL * ALPHA_MIN) { if (S->ndec < 64) S->dec_near[S->ndec++] = dec; if (!S->near) S->first_near = k; S->near = 1; }
         if (flipped(S, dec)) lowa = !lowa;
         dec++;
         if (lowa) continue;
         real Tn = S->T * ((real)1 - alpha);
         int stop = Tn < T_STOP;
         real dt = Tn - T_STOP;
-        if ((dt > 0 ? dt : -dt) <= NEAR_REL * T_STOP) { if (S->ndec < 64) S->dec_near[S->ndec++] = dec; S->near = 1; }
+        if ((dt > 0 ? dt : -dt) <= NEAR_REL * T_STOP) { if (S->ndec < 64) S->dec_near[S->ndec++] = dec; if (!S->near) S->first_near = k; S->near = 1; }
         if (flipped(S, dec)) stop = !stop;
         dec++;
         if (stop) break;
@@ -751,6 +782,58 @@ int orc_pixel_accept(const orc_camera* cam, const real* uv, const real* conic, c
     }
 #undef ACCEPTS
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* importance scores (Sec. 3 "Preliminaries: Importance pruning",            */
+/* "Visibility filtering")                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* The importance of a Gaussian is the largest blending weight it receives
+ * in any pixel of any view: for an entry blended at a pixel, alpha times
+ * the transmittance in front of it (its contribution to the pixel colour
+ * per unit colour).  Entries that are skipped (alpha < 1/255) or that stop
+ * the pixel contribute nothing and have weight 0.
+ *
+ * For one view (its tiled lists): every pixel walks its list as the
+ * compositor does, and score[ids[a]] = max(score[ids[a]], alpha T) over its
+ * blended entries a.  score is indexed by global id and max-accumulated, so
+ * calls over several views give the maximum over all of them (the caller
+ * starts it at 0).  amb (optional, by global id, OR-accumulated) marks the
+ * Gaussians listed at or after the first near-threshold decision of some
+ * pixel: there a correct FP32 renderer may branch the other way, and the
+ * Gaussian's weight in that pixel is not fixed to rounding. */
+void orc_importance(const orc_camera* cam, const real* uv, const real* conic, const real* o_eff, const real* rgb,
+                    const uint32_t* ranges, const uint32_t* vals, const uint32_t* ids, real* score, uint8_t* amb)
+{
+    int32_t W = cam->width, H = cam->height, TX = (W + TILE - 1) / TILE, TY = (H + TILE - 1) / TILE;
+    int64_t maxlen = 1;
+    for (int32_t t = 0; t < TX * TY; t++) {
+        int64_t len = (int64_t)ranges[2 * t + 1] - ranges[2 * t];
+        if (len > maxlen) maxlen = len;
+    }
+    int64_t* pos = (int64_t*)malloc(sizeof(int64_t) * (size_t)maxlen);
+    real* ta = (real*)malloc(sizeof(real) * (size_t)maxlen);
+    real* tT = (real*)malloc(sizeof(real) * (size_t)maxlen);
+    int* tc = (int*)malloc(sizeof(int) * (size_t)maxlen);
+    real* tG = (real*)malloc(sizeof(real) * (size_t)maxlen);
+    for (int32_t y = 0; y < H; y++)
+        for (int32_t x = 0; x < W; x++) {
+            int32_t t = (y / TILE) * TX + (x / TILE);
+            const uint32_t* list = vals + ranges[2 * t];
+            int64_t len = (int64_t)ranges[2 * t + 1] - ranges[2 * t];
+            pix_t S; memset(&S, 0, sizeof(S));
+            S.cap_trace = maxlen; S.tr_pos = pos; S.tr_alpha = ta; S.tr_T = tT; S.tr_clamped = tc; S.tr_G = tG;
+            composite_pixel(list, len, (real)x + (real)0.5, (real)y + (real)0.5, uv, conic, o_eff, rgb, &S);
+            for (int64_t j = 0; j < S.ntrace; j++) {
+                uint32_t g = ids[list[pos[j]]];
+                real wgt = ta[j] * tT[j];
+                if (wgt > score[g]) score[g] = wgt;
+            }
+            if (amb)
+                for (int64_t k = S.first_near; k < len; k++) amb[ids[list[k]]] = 1;
+        }
+    free(pos); free(ta); free(tT); free(tc); free(tG);
 }
 
 /* ------------------------------------------------------------------------ */

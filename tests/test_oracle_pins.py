@@ -768,3 +768,131 @@ def test_jacobian_clamp_adjoint_matches_central_differences(oracle64):
         rel = np.linalg.norm(fd - an) / nrm
         assert rel <= 1e-3, (key, rel)
         assert np.all(np.abs(fd - an) <= 1e-3 * (np.abs(fd) + np.sqrt(np.mean(fd ** 2)))), key
+
+
+# ---------------------------------------------------------------------------
+# importance scores and per-chunk visibility filtering
+# (Sec. 3 "Preliminaries: Importance pruning", "Visibility filtering")
+# ---------------------------------------------------------------------------
+
+def _importance(O, sc, cam, compensate=False):
+    ids, w, _ = O.select(sc, oracle.ALL, cam.pos)
+    return O.view_importance(sc, ids, w, cam, compensate=compensate)
+
+
+@pytest.mark.parametrize("o", [0.7, 1.0])
+def test_importance_lone_gaussian_at_a_pixel_centre(oracle64, oracle32, o):
+    """One Gaussian whose mean projects exactly onto a pixel centre: nothing
+    lies in front of it, so its weight there is its alpha at G = 1, i.e.
+    min(0.99, o), and no pixel gives more."""
+    cam = axis_camera(32, 32, 40.0)
+    # u = f X / z + c = 40 * 0.0625 / 5 + 16 = 16.5, a pixel centre (exact in binary)
+    lv = make_level([[0.0625, 0.0625, 5.0]], 0.05, opac=[o])
+    for O in (oracle64, oracle32):
+        score, amb = _importance(O, one_level_scene(lv), cam)
+        assert score[0] == O.dt(min(0.99, float(np.float32(o)))), (O.tag, score)
+        # power = 0 exactly at the centre pixel sits on the skip test (power > 0):
+        # a near decision, so this Gaussian's weight is marked as open to rounding
+        assert amb[0] == 1
+
+
+def test_importance_single_pixel_stack_with_termination(oracle64):
+    """A 1 x 1 view of wide Gaussians centred on the optical axis (G = 1 at
+    the only pixel), stored back to front: the k-th nearest weighs
+    alpha_k prod_{j<k} (1 - alpha_j); the one that would take T below 1e-4
+    stops the pixel and, like every Gaussian behind it, weighs nothing."""
+    cam = axis_camera(1, 1, 2.0)
+    zs = [3.0, 4.0, 5.0, 6.0, 7.0]
+    ops = [0.95, 0.6, 0.95, 0.95, 0.5]
+    lv = make_level([[0.0, 0.0, z] for z in zs[::-1]], 0.5, opac=ops[::-1])
+    score, amb = _importance(oracle64, one_level_scene(lv), cam)
+    score = score[::-1]                       # nearest first
+    a = [float(np.float32(x)) for x in ops]
+    T, expect = 1.0, []
+    for k in range(len(zs)):
+        if T * (1 - a[k]) < 1e-4 or (expect and expect[-1] == 0.0):
+            expect.append(0.0)
+            continue
+        expect.append(a[k] * T)
+        T *= 1 - a[k]
+    # 0.95, 0.6*0.05, 0.95*0.02, then T = 0.001 * 0.05 < 1e-4 stops at the fourth
+    assert expect[3] == 0.0 and expect[4] == 0.0 and expect[2] > 0
+    assert np.allclose(score, expect, rtol=0, atol=1e-12), (score, expect)
+    # the first entry's power is exactly 0 (a near decision at list position 0): all are marked
+    assert amb.all()
+
+
+def test_importance_of_a_gaussian_behind_an_opaque_one(oracle64):
+    """A wide front Gaussian of opacity 1 clamps to alpha 0.99 over the whole
+    footprint of a small one behind it: the back one weighs 0.01 times its
+    own alpha at its centre pixel, the front one 0.99."""
+    cam = axis_camera(16, 16, 40.0)
+    front = [0.0, 0.0, 3.0]
+    back = [0.125, 0.125, 10.0]   # u = 40 * 0.125 / 10 + 8 = 8.5: a pixel centre
+    lv = make_level([back, front], [[0.03] * 3, [5.0] * 3], opac=[0.8, 1.0])
+    score, _ = _importance(oracle64, one_level_scene(lv), cam)
+    assert score[1] == 0.99
+    assert abs(score[0] - 0.01 * float(np.float32(0.8))) < 1e-9, score
+    # and with the front one removed the back one weighs its full alpha
+    lv1 = make_level([back], [0.03], opac=[0.8])
+    s1, _ = _importance(oracle64, one_level_scene(lv1), cam)
+    assert abs(s1[0] - float(np.float32(0.8))) < 1e-12
+
+
+def test_importance_invariant_to_storage_order_and_bounded(oracle32):
+    sc = synth.plain_scene(n=1500, seed=25, width=64, height=48)
+    cam = sc.cameras[0]
+    score, amb = _importance(oracle32, sc, cam, compensate=True)
+    perm = np.random.default_rng(26).permutation(sc.n_total)
+    lv = sc.levels[0]
+    pl = Level(mean=lv.mean[:, perm].copy(), scale=lv.scale[:, perm].copy(), quat=lv.quat[:, perm].copy(),
+               opacity=lv.opacity[perm].copy(), sh=lv.sh[:, :, perm].copy(), sh_degree=lv.sh_degree,
+               filter3d_var=lv.filter3d_var)
+    sp, ap = _importance(oracle32, one_level_scene(pl), cam, compensate=True)
+    assert np.array_equal(sp, score[perm]) and np.array_equal(ap, amb[perm])
+    # a weight is alpha T <= alpha <= min(0.99, o); most Gaussians of this view are seen
+    assert np.all(score <= np.minimum(0.99, lv.opacity) + 1e-7)
+    assert (score > 0).mean() > 0.3
+    # max over views: scores of two views accumulate to their elementwise maximum
+    cam2 = synth.look_at((3.0, -2.0, -14.0), (0, 0, 0), (0, -1, 0), 64, 48)
+    s2, _ = _importance(oracle32, sc, cam2, compensate=True)
+    ids, w, _ = oracle32.select(sc, oracle.ALL, cam.pos)
+    acc = score.copy()
+    oracle32.view_importance(sc, ids, w, cam2, score=acc)
+    assert np.array_equal(acc, np.maximum(score, s2))
+
+
+def test_single_chunk_set_and_union_of_stored_sets(oracle32):
+    """A chunk's stored set (Eq. 2 at its centre with offset thresholds) and
+    the two-chunk selection rebuilt from stored sets (Eq. 4 weights) equal the
+    per-frame chunked selection bit for bit."""
+    sc = synth.lod_city_scene(counts=(20000, 5000, 1250), half_xy=40.0, d=(6.0, 18.0), grid=4, spacing=20.0,
+                              chunk_z=1.7, band=5.0, seed=21)
+    K = len(sc.chunks.centers)
+    sets = [oracle32.select_chunk(sc, k) for k in range(K)]
+    for k in (0, 5, K - 1):
+        only_k = Scene(levels=sc.levels, d=sc.d,
+                       chunks=Chunks(centers=sc.chunks.centers[k:k + 1], offsets=sc.chunks.offsets[k:k + 1]))
+        ids_k, w_k, _ = oracle32.select(only_k, oracle.CHUNKED, np.zeros(3, np.float32))
+        assert np.array_equal(sets[k][0], ids_k) and np.all(sets[k][1] == 1.0)
+    rng = np.random.default_rng(27)
+    for _ in range(6):
+        pos = np.array([rng.uniform(-40, 40), rng.uniform(-40, 40), 1.7], np.float32)
+        ids, w, (f, o, t) = oracle32.select(sc, oracle.CHUNKED, pos)
+        uid, uw = oracle.union_select(sc.n_total, sets[f][0], sets[o][0], t)
+        assert np.array_equal(uid, ids) and np.array_equal(uw, w)
+    with pytest.raises(ValueError):
+        oracle32.select_chunk(sc, K)
+
+
+def test_pruned_chunk_sets(oracle32):
+    """Visibility filtering removes exactly the members scoring below the
+    threshold; the union of pruned sets keeps Eq. 4's weights by membership
+    of the pruned sets."""
+    ids = np.array([2, 3, 5, 8, 13], np.uint32)
+    score = np.zeros(16, np.float32)
+    score[[2, 5, 13]] = [0.5, 0.02, 0.019999]
+    assert oracle.prune_chunk_set(ids, score, 0.02).tolist() == [2, 5]
+    uid, uw = oracle.union_select(16, [2, 5], [5, 7], 0.75)
+    assert uid.tolist() == [2, 5, 7]
+    assert uw.tolist() == [np.float32(0.75), 1.0, np.float32(1.0) - np.float32(0.75)]
