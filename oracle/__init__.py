@@ -381,3 +381,45 @@ def union_select(n_total, set_f, set_o, t):
     if set_o is None:
         w[:] = 1.0
     return ids, w
+
+
+# -- depth-threshold selection (Sec. 3 "Selecting depth thresholds") ---------------------------------------
+
+
+def lod_instances(O: "Oracle", scene, d, n_levels: int, cam, s2d=0.3, compensate=True) -> int:
+    """Tile instances of one LOD frame: levels 0..n_levels-1 of the scene with switch distances d
+    (n_levels - 1 values), Eq. 2 about the camera, every selected Gaussian counted once per 16 x 16
+    tile its projected rectangle covers (the Gaussians each tile processes)."""
+    from synth import Scene
+    sub = Scene(levels=list(scene.levels[:n_levels]), d=[float(x) for x in d], chunks=None)
+    ids, w, _ = O.select(sub, LOD_CAMERA, cam.pos)
+    proj = O.project(sub, ids, w, cam, s2d, compensate)
+    O._keep.clear()
+    return int(proj.tiles.astype(np.int64).sum())
+
+
+def tiles_of(cam) -> int:
+    return ((cam.width + TILE - 1) // TILE) * ((cam.height + TILE - 1) // TILE)
+
+
+def threshold_cost(O: "Oracle", scene, d, n_levels: int, cams, s2d=0.3, compensate=True) -> float:
+    """The cost the search minimises: the average number of Gaussians per tile over the views."""
+    return float(np.mean([lod_instances(O, scene, d, n_levels, c, s2d, compensate) / tiles_of(c) for c in cams]))
+
+
+def greedy_thresholds(cost, candidates, n_levels: int):
+    """Greedy 1-D search: d_1 is the candidate minimising cost((d_1,)) over two levels; with d_1..d_{l-1}
+    fixed, d_l is the candidate above d_{l-1} minimising cost((d_1, ..., d_l)) over levels 0..l.  Ties go
+    to the smaller candidate.  cost(d) takes the tuple of thresholds (its length fixes the level count).
+    Returns (thresholds, per-step list of (candidate, cost) pairs)."""
+    cands = sorted(float(c) for c in candidates)
+    chosen, curves = [], []
+    for l in range(1, n_levels):
+        lo = chosen[-1] if chosen else -np.inf
+        curve = [(c, cost(tuple(chosen) + (c,))) for c in cands if c > lo]
+        if not curve:
+            raise ValueError("no candidate above the previous threshold")
+        best = min(curve, key=lambda p: (p[1], p[0]))
+        chosen.append(best[0])
+        curves.append(curve)
+    return chosen, curves

@@ -363,3 +363,42 @@ def permuted(level: Level, perm: np.ndarray) -> Level:
                  quat=np.ascontiguousarray(level.quat[:, perm]), opacity=np.ascontiguousarray(level.opacity[perm]),
                  sh=np.ascontiguousarray(level.sh[:, :, perm]), sh_degree=level.sh_degree,
                  filter3d_var=level.filter3d_var)
+
+
+def chunk_views(chunks: Chunks, k: int, n_positions: int = 4, n_orientations: int = 3, width: int = 320,
+                height: int = 180, spread: float = 0.5, height_range=(1.5, 3.0), seed: int = 7):
+    """Views of chunk k for its visibility filtering: camera positions drawn
+    around the chunk centre (uniform in a disc of radius spread * r_k in the
+    ground plane, heights uniform in height_range), standing in for the
+    training cameras the chunk was clustered from, each seen under
+    n_orientations random orientations (yaw uniform, pitch uniform in
+    [-30, 10] degrees).  Returns a list of Cameras."""
+    rng = _rng((seed, k, 98, 0))
+    c = np.asarray(chunks.centers[k], np.float64)
+    r = float(chunks.offsets[k]) * spread
+    cams = []
+    for _ in range(n_positions):
+        rho = r * math.sqrt(rng.uniform(0.0, 1.0))
+        phi = rng.uniform(0.0, 2.0 * math.pi)
+        eye = np.array([c[0] + rho * math.cos(phi), c[1] + rho * math.sin(phi), rng.uniform(*height_range)])
+        for _ in range(n_orientations):
+            yaw = rng.uniform(0.0, 2.0 * math.pi)
+            pitch = math.radians(rng.uniform(-30.0, 10.0))
+            fwd = np.array([math.cos(yaw) * math.cos(pitch), math.sin(yaw) * math.cos(pitch), math.sin(pitch)])
+            cams.append(look_at(eye, eye + fwd, (0, 0, 1), width, height))
+    return cams
+
+
+def threshold_views(n: int = 4, half_xy: float = 100.0, width: int = 320, height: int = 180, seed: int = 8):
+    """Views for the depth-threshold search, standing in for a subset of
+    training views: eyes uniform over the ground at 1.5-10 m, random yaw,
+    pitch uniform in [-20, 0] degrees."""
+    rng = _rng((seed, 0, 97, 0))
+    cams = []
+    for _ in range(n):
+        eye = np.array([rng.uniform(-half_xy, half_xy), rng.uniform(-half_xy, half_xy), rng.uniform(1.5, 10.0)])
+        yaw = rng.uniform(0.0, 2.0 * math.pi)
+        pitch = math.radians(rng.uniform(-20.0, 0.0))
+        fwd = np.array([math.cos(yaw) * math.cos(pitch), math.sin(yaw) * math.cos(pitch), math.sin(pitch)])
+        cams.append(look_at(eye, eye + fwd, (0, 0, 1), width, height))
+    return cams

@@ -896,3 +896,69 @@ def test_pruned_chunk_sets(oracle32):
     uid, uw = oracle.union_select(16, [2, 5], [5, 7], 0.75)
     assert uid.tolist() == [2, 5, 7]
     assert uw.tolist() == [np.float32(0.75), 1.0, np.float32(1.0) - np.float32(0.75)]
+
+
+# ---------------------------------------------------------------------------
+# depth-threshold selection (Sec. 3 "Selecting depth thresholds")
+# ---------------------------------------------------------------------------
+
+def _small_city():
+    return synth.lod_city_scene(counts=(20000, 5000, 1250), half_xy=40.0, d=(6.0, 18.0), grid=2, spacing=20.0,
+                                chunk_z=1.7, band=5.0, seed=41)
+
+
+def test_lod_instances_sum_per_gaussian_tiles_over_distance_bands(oracle32):
+    """The instance count of an LOD frame is the sum, over levels, of the tile
+    counts of the Gaussians whose camera distance falls in that level's band
+    [d_l, d_{l+1}): each level is projected whole once and banded by float64
+    distances (an independent route to the same number)."""
+    sc = _small_city()
+    cams = synth.threshold_views(3, half_xy=40.0, width=160, height=96, seed=42)
+    for cam in cams:
+        per_level = []
+        for lv in sc.levels:
+            one = one_level_scene(lv)
+            ids, w, _ = oracle32.select(one, oracle.ALL, cam.pos)
+            p = oracle32.project(one, ids, w, cam)
+            dist = np.linalg.norm(lv.mean.T.astype(np.float64) - np.asarray(cam.pos, np.float64), axis=1)
+            per_level.append((p.tiles.astype(np.int64), dist))
+        for d in ((5.0, 12.0), (3.0, 30.0), (10.0, 11.0)):
+            bounds = [0.0, *d, np.inf]
+            expect = sum(int(t[(dist >= bounds[l]) & (dist < bounds[l + 1])].sum())
+                         for l, (t, dist) in enumerate(per_level))
+            assert oracle.lod_instances(oracle32, sc, d, 3, cam) == expect, d
+        # limits: every Gaussian nearer than d_1 -> level 0 alone; none nearer -> level 1 alone
+        assert oracle.lod_instances(oracle32, sc, (1e6,), 2, cam) == int(per_level[0][0].sum())
+        assert oracle.lod_instances(oracle32, sc, (1e-3,), 2, cam) == int(per_level[1][0][per_level[1][1] >= 1e-3].sum())
+
+
+def test_greedy_threshold_search_on_known_costs():
+    """The greedy search finds d_1 from the two-level cost, then d_2 above it
+    from the three-level cost; ties go to the smaller candidate."""
+    cands = [5.0 * k for k in range(1, 21)]
+
+    def separable(d):
+        return (d[0] - 30.0) ** 2 + (0.0 if len(d) < 2 else (d[1] - 70.0) ** 2)
+    chosen, curves = oracle.greedy_thresholds(separable, cands, 3)
+    assert chosen == [30.0, 70.0]
+    assert [c for c, _ in curves[1]] == [c for c in cands if c > 30.0]
+
+    # the second step only looks above the first threshold, even when lower would be cheaper
+    def below(d):
+        return abs(d[0] - 50.0) if len(d) == 1 else abs(d[1] - 10.0)
+    chosen, _ = oracle.greedy_thresholds(below, cands, 3)
+    assert chosen == [50.0, 55.0]
+
+    def flat(d):
+        return 1.0
+    assert oracle.greedy_thresholds(flat, cands, 4)[0] == [5.0, 10.0, 15.0]
+    with pytest.raises(ValueError):
+        oracle.greedy_thresholds(flat, [5.0], 3)
+
+
+def test_threshold_cost_is_mean_gaussians_per_tile(oracle32):
+    sc = _small_city()
+    cams = synth.threshold_views(2, half_xy=40.0, width=100, height=50, seed=43)   # 7 x 4 tiles, ragged
+    c = oracle.threshold_cost(oracle32, sc, (6.0, 18.0), 3, cams)
+    m = [oracle.lod_instances(oracle32, sc, (6.0, 18.0), 3, cam) for cam in cams]
+    assert c == pytest.approx(np.mean(m) / 28.0, rel=0, abs=1e-12)
