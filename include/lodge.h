@@ -275,6 +275,44 @@ lodge_status lodge_check(const lodge_workspace* ws, uint32_t* needed_active, uin
 lodge_status lodge_debug_views(const lodge_workspace* ws, const uint32_t** sorted_ids, const uint32_t** tile_ranges,
                                const float** proj, const float** depth, const uint32_t** rect);
 
+/* ------------------------------------------------- visibility filtering */
+
+/* ASYNC.  The stored active set of chunk k alone (Sec. 3 "Reducing memory
+ * with chunk-based rendering": Eq. 2 at the chunk centre m_k with every
+ * switch distance offset by r_k), every member with weight 1: the set that
+ * the per-chunk visibility filtering (Sec. 3 "Visibility filtering") renders
+ * and prunes.  sets: NULL to evaluate the set from the means, or a buffer
+ * from lodge_chunk_sets_build (then the result reflects any pruning already
+ * applied to it).  0 <= k < the scene's chunk count; sel->cap must equal
+ * ws->max_active.  The workspace's camera is not used or changed. */
+lodge_status lodge_select_chunk(const lodge_scene* scene, const void* sets, int32_t k, const lodge_workspace* ws,
+                                lodge_selection* sel, void* stream);
+
+/* ASYNC.  Importance scores (Sec. 3 "Preliminaries: Importance pruning"):
+ * lodge_render's projection, binning and sort, then its compositing walk
+ * without an image: every entry blended at a pixel contributes its weight
+ * alpha T (alpha = min(0.99, o G), T the transmittance in front of it), and
+ *   score[id] = max(score[id], weight)
+ * for the entry's global id, over every pixel of the view.  score (device,
+ * lodge_scene_total() floats, caller-owned, >= 0; the caller sets it to 0
+ * before the first view) accumulates the maximum over successive calls, so a
+ * set of views gives each Gaussian its largest weight in any of them.
+ * Entries skipped (alpha < 1/255) or stopping a pixel (T (1 - alpha) < 1e-4)
+ * weigh nothing.  Overflows are reported by lodge_check as for
+ * lodge_render.  Calls on different streams into one score array are safe
+ * (the maximum is taken with atomics). */
+lodge_status lodge_importance(const lodge_scene* scene, const lodge_selection* sel, const lodge_camera* cam,
+                              const lodge_render_opts* opts, const lodge_workspace* ws, float* score, void* stream);
+
+/* ASYNC.  Visibility filtering of chunk k's stored set (Sec. 3 "Visibility
+ * filtering"): every member whose score (device, by global id, as left by
+ * lodge_importance) is below threshold is removed from chunk k's set in
+ * `sets` (from lodge_chunk_sets_build); other chunks are untouched.  A frame
+ * then loads the filtered sets through lodge_select_chunk_sets (Eq. 4
+ * weights by membership of the filtered sets).  threshold must be finite. */
+lodge_status lodge_chunk_sets_prune(const lodge_scene* scene, void* sets, size_t bytes, int32_t k, const float* score,
+                                    float threshold, void* stream);
+
 /* ------------------------------------------------- no-allocation rendering */
 
 /* For callers that cannot allocate device memory, not even a workspace: code

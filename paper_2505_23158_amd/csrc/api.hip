@@ -56,7 +56,7 @@ lodge_status check_render_opts(const lodge_render_opts* opts, lodge_render_opts*
 // options, counters), projection, binning, sort, compositing.
 lodge_status render_stages(const lodge_scene* scene, const lodge_selection& sel, const lodge_camera* cam,
                            const lodge_render_opts& o, const Views& v, bool keep_select_flag, float* image,
-                           float* final_T, uint32_t* n_contrib, hipStream_t st)
+                           float* final_T, uint32_t* n_contrib, hipStream_t st, float* score)
 {
     hipError_t e = hipSuccess;
     auto mark = [&](int k) -> hipError_t {
@@ -71,8 +71,11 @@ lodge_status render_stages(const lodge_scene* scene, const lodge_selection& sel,
     if ((e = mark(2)) != hipSuccess) return hip_fail(e, "lodge_render: event");
     if ((e = launch_sort(v, st)) != hipSuccess) return hip_fail(e, "lodge_render: sort");
     if ((e = mark(3)) != hipSuccess) return hip_fail(e, "lodge_render: event");
-    if ((e = launch_composite(v, image, final_T, n_contrib, st)) != hipSuccess)
+    if (score) {
+        if ((e = launch_importance(v, sel.ids, score, st)) != hipSuccess) return hip_fail(e, "lodge_importance");
+    } else if ((e = launch_composite(v, image, final_T, n_contrib, st)) != hipSuccess) {
         return hip_fail(e, "lodge_render: composite");
+    }
     if ((e = mark(4)) != hipSuccess) return hip_fail(e, "lodge_render: event");
     return LODGE_OK;
 }
@@ -441,6 +444,65 @@ lodge_status lodge_select_chunk_sets(const lodge_scene* scene, const void* sets,
     if ((e = launch_select_finish(scene->levels, v, *sel, st)) != hipSuccess)
         return hip_fail(e, "lodge_select_chunk_sets");
     return LODGE_OK;
+}
+
+lodge_status lodge_select_chunk(const lodge_scene* scene, const void* sets, int32_t k, const lodge_workspace* ws,
+                                lodge_selection* sel, void* stream)
+{
+    if (!scene) return fail(LODGE_ERR_INVALID_ARG, "scene is NULL");
+    if (!scene->has_chunks) return fail(LODGE_ERR_INVALID_ARG, "the scene has no chunks");
+    if (k < 0 || k >= scene->chunks.K) return fail(LODGE_ERR_INVALID_ARG, "chunk index out of range");
+    lodge_status s;
+    if ((s = check_ws(scene, ws)) != LODGE_OK) return s;
+    if ((s = check_sel(sel, ws)) != LODGE_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Views v = views_of(ws, scene->levels.total);
+    hipError_t e = hipSuccess;
+    if ((e = launch_select_setup(scene->levels, scene->chunks, LODGE_SELECT_CHUNKED, nullptr, v, st, k)) !=
+        hipSuccess)
+        return hip_fail(e, "lodge_select_chunk: setup");
+    if (sets) {
+        if ((e = launch_sets_mark(scene->levels, v, static_cast<const uint16_t*>(sets), st)) != hipSuccess)
+            return hip_fail(e, "lodge_select_chunk: mark");
+        if ((e = launch_select_finish(scene->levels, v, *sel, st)) != hipSuccess)
+            return hip_fail(e, "lodge_select_chunk");
+    } else if ((e = launch_select(scene->levels, v, *sel, st)) != hipSuccess) {
+        return hip_fail(e, "lodge_select_chunk");
+    }
+    return LODGE_OK;
+}
+
+lodge_status lodge_chunk_sets_prune(const lodge_scene* scene, void* sets, size_t bytes, int32_t k, const float* score,
+                                    float threshold, void* stream)
+{
+    size_t need = 0;
+    lodge_status s = lodge_chunk_sets_size(scene, &need);
+    if (s != LODGE_OK) return s;
+    if (!sets || bytes < need) return fail(LODGE_ERR_INVALID_ARG, "chunk-set buffer is NULL or too small");
+    if (reinterpret_cast<uintptr_t>(sets) % 4) return fail(LODGE_ERR_INVALID_ARG, "chunk-set buffer must be 4-byte aligned");
+    if (k < 0 || k >= scene->chunks.K) return fail(LODGE_ERR_INVALID_ARG, "chunk index out of range");
+    if (!score) return fail(LODGE_ERR_INVALID_ARG, "score is NULL");
+    if (!std::isfinite(threshold)) return fail(LODGE_ERR_INVALID_ARG, "threshold must be finite");
+    const hipError_t e = launch_sets_prune(scene->levels, static_cast<uint16_t*>(sets), k, score, threshold,
+                                           static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LODGE_OK : hip_fail(e, "lodge_chunk_sets_prune");
+}
+
+lodge_status lodge_importance(const lodge_scene* scene, const lodge_selection* sel, const lodge_camera* cam,
+                              const lodge_render_opts* opts, const lodge_workspace* ws, float* score, void* stream)
+{
+    if (!scene) return fail(LODGE_ERR_INVALID_ARG, "scene is NULL");
+    lodge_status s;
+    if ((s = check_ws(scene, ws)) != LODGE_OK) return s;
+    if ((s = check_cam(cam, ws)) != LODGE_OK) return s;
+    if ((s = check_sel(sel, ws)) != LODGE_OK) return s;
+    if (!score) return fail(LODGE_ERR_INVALID_ARG, "score is NULL");
+    if (reinterpret_cast<uintptr_t>(score) % 4) return fail(LODGE_ERR_INVALID_ARG, "score must be 4-byte aligned");
+    lodge_render_opts o;
+    if ((s = check_render_opts(opts, &o)) != LODGE_OK) return s;
+    const Views v = views_of(ws, scene->levels.total);
+    return render_stages(scene, *sel, cam, o, v, true, nullptr, nullptr, nullptr, static_cast<hipStream_t>(stream),
+                         score);
 }
 
 lodge_status lodge_render(const lodge_scene* scene, const lodge_selection* sel, const lodge_camera* cam,

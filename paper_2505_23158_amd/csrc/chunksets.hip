@@ -117,7 +117,39 @@ __global__ __launch_bounds__(kSelBlock) void k_sets_mark(const FrameParams* fp, 
     if (total != 0u) bits_out[(size_t)tile * kSelBlock + tid] = bits;
 }
 
+// Visibility filtering of one chunk's stored set: every member of chunk k
+// whose importance score (by global id) is below the threshold leaves it.
+__global__ __launch_bounds__(kSelBlock) void k_sets_prune(LevelsArg lv, uint32_t ntiles, uint16_t* __restrict__ sets,
+                                                          int32_t k, const float* __restrict__ score, float thr)
+{
+    const uint32_t tid = threadIdx.x;
+    const uint32_t tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    int l = 0;
+#pragma unroll
+    for (int j = 1; j < LODGE_MAX_LEVELS; j++)
+        if (j < lv.L && tile >= lv.first_block[j]) l = j;
+    const uint32_t gbase = lv.lv[l].base + (tile - lv.first_block[l]) * (uint32_t)kSelTile;
+    uint16_t* const wp = sets + ((size_t)k * ntiles + tile) * kSelBlock + tid;
+    const uint32_t word = *wp;
+    if (word == 0u) return;
+    uint32_t keep = word;
+#pragma unroll
+    for (int r = 0; r < kSelItems; r++)
+        if ((word >> r) & 1u)
+            if (!(score[gbase + (uint32_t)r * kSelBlock + tid] >= thr)) keep &= ~(1u << r);
+    if (keep != word) *wp = (uint16_t)keep;
+}
+
 }  // namespace
+
+hipError_t launch_sets_prune(const LevelsArg& lv, uint16_t* sets, int32_t k, const float* score, float threshold,
+                             hipStream_t st)
+{
+    const uint32_t ntiles = std::max<uint32_t>(lv.sel_blocks, 1);
+    k_sets_prune<<<ntiles, kSelBlock, 0, st>>>(lv, ntiles, sets, k, score, threshold);
+    return hipGetLastError();
+}
 
 hipError_t launch_sets_build(const LevelsArg& lv, const ChunksArg& ch, uint16_t* sets, hipStream_t st)
 {

@@ -44,13 +44,20 @@ constexpr uint32_t kWaveRec = 3 * kSlots;
 constexpr uint32_t kThird = kSlots * sizeof(float4);   // bytes between the thirds
 constexpr uint32_t kListLen = 68;
 
+// kScore: the importance variant.  Instead of the image it max-accumulates
+// each blended entry's weight alpha T into score[ids[a]] (float bits,
+// non-negative, so unsigned order is float order): per batch, every lane
+// takes an LDS max on its entry's slot; after the walk each slot's maximum
+// over the wave's pixels goes out with one global atomic max.
+template <bool kScore>
 __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict__ fp,
                                                    const uint2* __restrict__ ranges,
                                                    const uint32_t* __restrict__ order,
                                                    const uint32_t* __restrict__ sorted,
                                                    const float4* __restrict__ proj, float* __restrict__ image,
                                                    float* __restrict__ final_T, uint32_t* __restrict__ n_contrib,
-                                                   uint4* __restrict__ wstats, uint32_t cap)
+                                                   uint4* __restrict__ wstats, uint32_t cap,
+                                                   const uint32_t* __restrict__ sel_ids, uint32_t* __restrict__ score)
 {
     // Slot 64 of every wave is a sentinel every pixel skips (threshold
     // +inf): it pads the shorter sub-quadrant lists to the longest.  The
@@ -59,6 +66,8 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
     // per wave and sub-quadrant; 4 entries past the 64 a batch can fill,
     // always the sentinel, for the reads one trip ahead
     __shared__ uint32_t s_idx[4][4][kListLen];
+    // importance variant: per wave and batch slot, the largest weight (float bits)
+    __shared__ uint32_t s_wmax[kScore ? 4 : 1][kScore ? kSlots : 1];
 
     const int32_t W = fp->cam.width, H = fp->cam.height, TX = fp->TX;
     const uint32_t tile = order[blockIdx.x];
@@ -110,12 +119,17 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
         r2 = proj[3 * (size_t)a + 2];
     }
     uint32_t a_next = 64 + lane < len ? sorted[rg.x + 64 + lane] : 0u;
+    // importance variant: the active index of the lane's entry in the current batch
+    uint32_t a_cur = 0;
+    if (kScore && lane < len) a_cur = sorted[rg.x + lane];
 
     for (uint32_t b0 = 0; b0 < len; b0 += 64) {
         if (__ballot(amin < INFINITY) == 0ull) break;
         const uint32_t k = b0 + lane;
         const bool cur = k < len;
         const float4 q0 = r0, q1 = r1, q2 = r2;
+        const uint32_t a_batch = a_cur;
+        if (kScore) a_cur = a_next;
         if (b0 + 64 + lane < len) {
             const uint32_t a = a_next < cap ? a_next : 0u;
             r0 = proj[3 * (size_t)a];
@@ -123,6 +137,7 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
             r2 = proj[3 * (size_t)a + 2];
         }
         a_next = b0 + 128 + lane < len ? sorted[rg.x + b0 + 128 + lane] : 0u;
+        if (kScore) s_wmax[wave][lane] = 0u;
 
         bool hit[4] = {false, false, false, false};
         if (cur) {
@@ -171,6 +186,7 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
                 }
                 if (keep && !stop) {
                     const float wgt = alpha * T;
+                    if (kScore) atomicMax(&s_wmax[wave][(off / (uint32_t)sizeof(float4)) - rbase], __float_as_uint(wgt));
                     cr = __builtin_fmaf(c.w, wgt, cr);
                     cg = __builtin_fmaf(f.x, wgt, cg);
                     cb = __builtin_fmaf(f.y, wgt, cb);
@@ -209,7 +225,12 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (kScore && cur) {
+            const uint32_t m = s_wmax[wave][lane];
+            if (m != 0u) atomicMax(score + sel_ids[a_batch < cap ? a_batch : 0u], m);
+        }
     }
+    if (kScore) return;
     if (inside) {
         const size_t p = (size_t)y * W + x;
         const size_t HW = (size_t)W * H;
@@ -237,8 +258,16 @@ __global__ __launch_bounds__(256) void k_composite(const FrameParams* __restrict
 
 hipError_t launch_composite(const Views& v, float* image, float* final_T, uint32_t* n_contrib, hipStream_t st)
 {
-    k_composite<<<v.lay.T, 256, 0, st>>>(v.params, v.ranges, v.order, v.sorted, v.proj, image, final_T, n_contrib,
-                                         v.wstats, v.max_active);
+    k_composite<false><<<v.lay.T, 256, 0, st>>>(v.params, v.ranges, v.order, v.sorted, v.proj, image, final_T,
+                                                n_contrib, v.wstats, v.max_active, nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_importance(const Views& v, const uint32_t* sel_ids, float* score, hipStream_t st)
+{
+    k_composite<true><<<v.lay.T, 256, 0, st>>>(v.params, v.ranges, v.order, v.sorted, v.proj, nullptr, nullptr,
+                                               nullptr, v.wstats, v.max_active, sel_ids,
+                                               reinterpret_cast<uint32_t*>(score));
     return hipGetLastError();
 }
 

@@ -183,13 +183,17 @@ Views views_of(const lodge_workspace* ws, uint32_t n_total);
 // Each returns hipGetLastError() after enqueueing on `st`.
 
 hipError_t launch_set_camera(const lodge_camera& cam, const Views& v, hipStream_t st);
+// only_chunk >= 0: the set of that chunk alone (mode must be chunked): f = only_chunk, no second chunk, t = 1
 hipError_t launch_select_setup(const LevelsArg& lv, const ChunksArg& ch, int32_t mode, const lodge_camera* cam,
-                              const Views& v, hipStream_t st);
+                              const Views& v, hipStream_t st, int32_t only_chunk = -1);
 hipError_t launch_select(const LevelsArg& lv, const Views& v, const lodge_selection& sel, hipStream_t st);
 // scan + emit of the selection from the per-tile counts and packed bits already in the workspace
 hipError_t launch_select_finish(const LevelsArg& lv, const Views& v, const lodge_selection& sel, hipStream_t st);
 hipError_t launch_sets_build(const LevelsArg& lv, const ChunksArg& ch, uint16_t* sets, hipStream_t st);
 hipError_t launch_sets_mark(const LevelsArg& lv, const Views& v, const uint16_t* sets, hipStream_t st);
+// clears chunk k's bit of every member whose score (by global id) is below threshold
+hipError_t launch_sets_prune(const LevelsArg& lv, uint16_t* sets, int32_t k, const float* score, float threshold,
+                             hipStream_t st);
 // keep_select_flag: keep the selection-overflow bit a lodge_select on the same workspace set
 hipError_t launch_render_setup(const lodge_render_opts& o, const lodge_camera* cam, const Views& v,
                                bool keep_select_flag, hipStream_t st);
@@ -197,6 +201,8 @@ hipError_t launch_project(const LevelsArg& lv, const lodge_selection& sel, const
 hipError_t launch_bin(const Views& v, const lodge_selection& sel, hipStream_t st);
 hipError_t launch_sort(const Views& v, hipStream_t st);
 hipError_t launch_composite(const Views& v, float* image, float* final_T, uint32_t* n_contrib, hipStream_t st);
+// the compositor's walk, max-accumulating each blended weight alpha T into score[sel_ids[a]]
+hipError_t launch_importance(const Views& v, const uint32_t* sel_ids, float* score, hipStream_t st);
 hipError_t launch_backward(const LevelsArg& lv, const lodge_selection& sel, const Views& v, const float* final_T,
                            const uint32_t* n_contrib, const float* dL_dimage, int32_t grad_level,
                            const lodge_grads* grads, hipStream_t st);
@@ -230,9 +236,10 @@ namespace lodge {
 
 // The stages of lodge_render (setup, project, bin, sort, composite) on the
 // views of a workspace; keep_select_flag as for launch_render_setup.
+// With score non-NULL the last stage is the importance walk (no image).
 lodge_status render_stages(const lodge_scene* scene, const lodge_selection& sel, const lodge_camera* cam,
                            const lodge_render_opts& o, const Views& v, bool keep_select_flag, float* image,
-                           float* final_T, uint32_t* n_contrib, hipStream_t st);
+                           float* final_T, uint32_t* n_contrib, hipStream_t st, float* score = nullptr);
 
 // ------------------------------------------------------------ device helpers
 

@@ -48,8 +48,11 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 
 // One wave.  With a camera argument (has_cam) the kernel also stores it into
 // the frame parameters, which saves a launch.
+// only_chunk >= 0 (chunked mode): the set of that chunk alone, f = only_chunk,
+// no second chunk, t = 1 (every member weighs 1).
 __global__ __launch_bounds__(64) void k_select_setup(ChunksArg ch, LevelsArg lv, int32_t mode, lodge_camera cam,
-                                                     int32_t has_cam, FrameParams* fp, FrameInfo* info)
+                                                     int32_t has_cam, FrameParams* fp, FrameInfo* info,
+                                                     int32_t only_chunk)
 {
     const int lane = threadIdx.x;
     const float px = has_cam ? cam.pos[0] : fp->cam.pos[0];
@@ -57,7 +60,9 @@ __global__ __launch_bounds__(64) void k_select_setup(ChunksArg ch, LevelsArg lv,
     const float pz = has_cam ? cam.pos[2] : fp->cam.pos[2];
     int f = -1, o = -1;
     float t = 1.0f;
-    if (mode == LODGE_SELECT_CHUNKED) {
+    if (mode == LODGE_SELECT_CHUNKED && only_chunk >= 0) {
+        f = only_chunk;
+    } else if (mode == LODGE_SELECT_CHUNKED) {
         float d = INFINITY;
         int k = 0x7fffffff;
         for (int c = lane; c < ch.K; c += 64) {
@@ -331,11 +336,11 @@ __global__ __launch_bounds__(kSelBlock) void k_select_emit(LevelsArg lv, const F
 }  // namespace
 
 hipError_t launch_select_setup(const LevelsArg& lv, const ChunksArg& ch, int32_t mode, const lodge_camera* cam,
-                              const Views& v, hipStream_t st)
+                              const Views& v, hipStream_t st, int32_t only_chunk)
 {
     lodge_camera c{};
     if (cam) c = *cam;
-    k_select_setup<<<1, 64, 0, st>>>(ch, lv, mode, c, cam ? 1 : 0, v.params, v.info);
+    k_select_setup<<<1, 64, 0, st>>>(ch, lv, mode, c, cam ? 1 : 0, v.params, v.info, only_chunk);
     return hipGetLastError();
 }
 

@@ -109,6 +109,11 @@ def lib():
             "lodge_chunk_sets_build": (st, [vp, vp, C.c_size_t, vp]),
             "lodge_select_chunk_sets": (st, [vp, vp, vp, C.POINTER(lodge_workspace), C.POINTER(lodge_selection),
                                              vp]),
+            "lodge_select_chunk": (st, [vp, vp, C.c_int32, C.POINTER(lodge_workspace), C.POINTER(lodge_selection),
+                                        vp]),
+            "lodge_importance": (st, [vp, C.POINTER(lodge_selection), vp, C.POINTER(lodge_render_opts),
+                                      C.POINTER(lodge_workspace), vp, vp]),
+            "lodge_chunk_sets_prune": (st, [vp, vp, C.c_size_t, C.c_int32, vp, C.c_float, vp]),
             "lodge_render": (st, [vp, C.POINTER(lodge_selection), vp, C.POINTER(lodge_render_opts),
                                   C.POINTER(lodge_workspace), vp, vp, vp, vp]),
             "lodge_frame_info_read": (st, [C.POINTER(lodge_workspace), C.POINTER(lodge_frame_info), vp]),
@@ -140,7 +145,7 @@ EXPORTED = ["lodge_status_string", "lodge_last_error", "lodge_version", "lodge_s
             "lodge_scene_total", "lodge_workspace_size", "lodge_set_camera", "lodge_select", "lodge_chunk_sets_size",
             "lodge_chunk_sets_build", "lodge_select_chunk_sets", "lodge_render", "lodge_frame_info_read",
             "lodge_check", "lodge_debug_views", "lodge_render_backward", "lodge_activate", "lodge_activate_backward",
-            "lodge_render_static"]
+            "lodge_render_static", "lodge_select_chunk", "lodge_importance", "lodge_chunk_sets_prune"]
 STATIC_SCRATCH_BYTES = 256 << 20
 
 
@@ -309,6 +314,27 @@ def lodge_select_chunk_sets(scene: Scene, sets: ChunkSets, cam, ws: Workspace, s
     cp, keep = _cam_arg(cam)
     _check(lib().lodge_select_chunk_sets(scene.handle, _ptr(sets.buf), cp, C.byref(ws.desc), C.byref(sel.desc),
                                          _stream_ptr(stream)))
+
+
+def lodge_select_chunk(scene: Scene, sets: Optional[ChunkSets], k: int, ws: Workspace, sel: Selection, stream=None):
+    _check(lib().lodge_select_chunk(scene.handle, _ptr(sets.buf) if sets is not None else None, int(k),
+                                    C.byref(ws.desc), C.byref(sel.desc), _stream_ptr(stream)))
+
+
+def lodge_importance(scene: Scene, sel: Selection, cam, ws: Workspace, score, s2d: float = 0.3,
+                     compensate: bool = True, stream=None):
+    """score: float32 CUDA tensor of scene.total elements, max-accumulated by global id."""
+    if score.numel() != scene.total or score.dtype != _torch().float32 or not score.is_contiguous():
+        raise ValueError("score must be a contiguous float32 tensor of scene.total elements")
+    cp, keep = _cam_arg(cam)
+    opts = lodge_render_opts(s2d=s2d, compensate=int(compensate))
+    _check(lib().lodge_importance(scene.handle, C.byref(sel.desc), cp, C.byref(opts), C.byref(ws.desc),
+                                  _ptr(score), _stream_ptr(stream)))
+
+
+def lodge_chunk_sets_prune(scene: Scene, sets: ChunkSets, k: int, score, threshold: float, stream=None):
+    _check(lib().lodge_chunk_sets_prune(scene.handle, _ptr(sets.buf), C.c_size_t(sets.bytes), int(k), _ptr(score),
+                                        float(threshold), _stream_ptr(stream)))
 
 
 def lodge_render(scene: Scene, sel: Selection, cam, ws: Workspace, image, final_T, n_contrib, s2d: float = 0.3,

@@ -1,0 +1,219 @@
+"""Per-chunk visibility filtering on the GPU (Sec. 3 "Visibility filtering",
+"Preliminaries: Importance pruning") against the oracle:
+
+* a chunk's stored set (lodge_select_chunk) bit for bit;
+* importance scores (lodge_importance): within 1e-4 of the oracle's for every
+  Gaussian whose weights no near-threshold decision leaves open, and within
+  the bound of one flipped decision for the few that are open;
+* pruning (lodge_chunk_sets_prune) and the two-chunk selection from pruned
+  sets (lodge_select_chunk_sets) bit for bit, given the same scores;
+* the whole filtering pass: keep-masks equal to the oracle's except where a
+  score is within tolerance of the threshold or open to a flip."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+from parity_util import log
+
+pytestmark = pytest.mark.gpu
+
+SCORE_TOL = 1e-4
+# one flipped threshold decision changes a weight by at most 1/255 of the
+# transmittance (an entry at alpha ~ 1/255 blended or skipped), or changes
+# later transmittances by a factor (1 - 1/255), or lets a pixel run on below
+# T = 1e-4; two such flips bound the difference for an open Gaussian
+OPEN_TOL = 2.0 / 255.0
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_23158_amd import lodge
+    lodge.lib()
+    return lodge
+
+
+@pytest.fixture(scope="module")
+def city():
+    return synth.lod_city_scene(counts=(200000, 50000, 12500), half_xy=100.0, d=(20.0, 60.0), grid=4,
+                                spacing=50.0, chunk_z=1.7, band=10.0, seed=31)
+
+
+def compare_scores(s_g, s_o, amb, label):
+    d = np.abs(s_g.astype(np.float64) - s_o)
+    bad = d > SCORE_TOL
+    closed_bad = bad & (amb == 0)
+    assert not closed_bad.any(), (label, np.flatnonzero(closed_bad)[:10], d[closed_bad][:10])
+    assert np.all(d[bad] <= OPEN_TOL), (label, d[bad].max())
+    seen = int((s_o > 0).sum())
+    assert bad.sum() <= max(8, 1e-3 * seen), (label, int(bad.sum()), seen)
+    log(f"[vis] {label}: {seen} scored, max err {d[~bad].max(initial=0.0):.2e}, {int(bad.sum())} open flips")
+
+
+def gpu_scores(L, dev, ids_sel, views, R, mode=None, k=None, sets=None):
+    import torch
+    score = torch.zeros(dev.total, dtype=torch.float32, device="cuda")
+    if k is not None:
+        L.lodge_select_chunk(dev, sets, k, R.ws, R.sel)
+    for cam in views:
+        if mode is not None:
+            L.lodge_select(dev, cam, mode, R.ws, R.sel)
+        L.lodge_importance(dev, R.sel, cam, R.ws, score)
+        torch.cuda.synchronize()
+        assert L.lodge_check(R.ws)[0] == L.LODGE_OK
+    return score.cpu().numpy()
+
+
+def test_select_chunk_matches_oracle(L, oracle32, city):
+    import torch
+    dev = L.Scene.from_synth(city)
+    sets = L.ChunkSets(dev)
+    R = L.Renderer(dev, 64, 64)
+    for k in (0, 5, 10, 15):
+        ids_o, w_o = oracle32.select_chunk(city, k)
+        for use_sets in (False, True):
+            L.lodge_select_chunk(dev, sets if use_sets else None, k, R.ws, R.sel)
+            torch.cuda.synchronize()
+            n = int(R.sel.count.item())
+            assert n == len(ids_o), (k, use_sets, n, len(ids_o))
+            assert np.array_equal(R.sel.ids[:n].cpu().numpy().astype(np.uint32), ids_o)
+            assert np.all(R.sel.w[:n].cpu().numpy() == 1.0)
+        log(f"[vis] chunk {k}: {len(ids_o)} members")
+    with pytest.raises(L.LodgeError):
+        L.lodge_select_chunk(dev, sets, 16, R.ws, R.sel)
+    with pytest.raises(L.LodgeError):
+        L.lodge_select_chunk(dev, sets, -1, R.ws, R.sel)
+
+
+@pytest.mark.parametrize("W,H", [(256, 256), (17, 9), (100, 37)])
+def test_importance_plain_scene(L, oracle32, W, H):
+    """The 10k-Gaussian plain scene, every Gaussian active, one and two views."""
+    sc = synth.plain_scene(n=10000, seed=1, width=W, height=H)
+    cams = [sc.cameras[0], synth.look_at((4.0, -3.0, -13.0), (0, 0, 0), (0, -1, 0), W, H)]
+    dev = L.Scene.from_synth(sc)
+    R = L.Renderer(dev, W, H)
+    for nv in (1, 2):
+        s_g = gpu_scores(L, dev, None, cams[:nv], R, mode=L.SELECT_ALL)
+        ids, w, _ = oracle32.select(sc, oracle.ALL, cams[0].pos)
+        s_o = np.zeros(sc.n_total, np.float32)
+        amb = np.zeros(sc.n_total, np.uint8)
+        for cam in cams[:nv]:
+            oracle32.view_importance(sc, ids, w, cam, score=s_o, amb=amb)
+        compare_scores(s_g, s_o, amb, f"plain {W}x{H} views={nv}")
+        assert np.all(s_g <= np.minimum(0.99, sc.levels[0].opacity) + 1e-6)
+
+
+def test_importance_empty_selection_and_errors(L):
+    import torch
+    sc = synth.plain_scene(n=500, seed=3, width=32, height=32)
+    dev = L.Scene.from_synth(sc)
+    R = L.Renderer(dev, 32, 32)
+    # a camera looking away from every Gaussian: nothing visible, all scores stay 0
+    away = synth.look_at((0, 0, -15), (0, 0, -30), (0, -1, 0), 32, 32)
+    s = gpu_scores(L, dev, None, [away], R, mode=L.SELECT_ALL)
+    assert not s.any()
+    with pytest.raises(ValueError):
+        L.lodge_importance(dev, R.sel, away, R.ws, torch.zeros(10, device="cuda"))
+
+
+def test_importance_of_chunk_views(L, oracle32, city):
+    """Chunk sets rendered from their views (random orientations at camera
+    positions about the centre), scores max-accumulated over the views."""
+    dev = L.Scene.from_synth(city)
+    sets = L.ChunkSets(dev)
+    R = L.Renderer(dev, 320, 180, max_active=city.n_total)
+    for k in (5, 12):
+        views = synth.chunk_views(city.chunks, k, 2, 2, 320, 180)
+        s_g = gpu_scores(L, dev, None, views, R, k=k, sets=sets)
+        ids, w = oracle32.select_chunk(city, k)
+        s_o = np.zeros(city.n_total, np.float32)
+        amb = np.zeros(city.n_total, np.uint8)
+        for cam in views:
+            oracle32.view_importance(city, ids, w, cam, score=s_o, amb=amb)
+        compare_scores(s_g, s_o, amb, f"chunk {k}, 4 views")
+        outside = np.ones(city.n_total, bool)
+        outside[ids] = False
+        assert not s_g[outside].any()   # only the chunk's members are rendered
+
+
+def test_prune_and_select_from_pruned_sets_bit_exact(L, oracle32, city):
+    """Given the same scores, pruning two neighbouring chunks and selecting
+    from the pruned sets equals the oracle's pruned sets and their Eq. 4
+    union bit for bit."""
+    import torch
+    dev = L.Scene.from_synth(city)
+    sets = L.ChunkSets(dev)
+    R = L.Renderer(dev, 64, 64, max_active=city.n_total)
+    K = len(city.chunks.centers)
+    stored = [oracle32.select_chunk(city, k)[0] for k in range(K)]
+    thr = 0.02
+    pruned = list(stored)
+    for k in (5, 6):
+        views = synth.chunk_views(city.chunks, k, 2, 2, 160, 90)
+        s_o = np.zeros(city.n_total, np.float32)
+        for cam in views:
+            oracle32.view_importance(city, stored[k], np.ones(len(stored[k]), np.float32), cam, score=s_o)
+        pruned[k] = oracle.prune_chunk_set(stored[k], s_o, thr)
+        assert 0 < len(pruned[k]) < len(stored[k])
+        L.lodge_chunk_sets_prune(dev, sets, k, torch.from_numpy(s_o).cuda(), thr)
+        L.lodge_select_chunk(dev, sets, k, R.ws, R.sel)
+        torch.cuda.synchronize()
+        n = int(R.sel.count.item())
+        assert np.array_equal(R.sel.ids[:n].cpu().numpy().astype(np.uint32), pruned[k]), k
+        log(f"[vis] chunk {k}: {len(stored[k])} -> {len(pruned[k])} members at threshold {thr}")
+    # frames between and around the two pruned chunks
+    c5, c6 = city.chunks.centers[5].astype(np.float64), city.chunks.centers[6].astype(np.float64)
+    poses = [c5 + (c6 - c5) * a for a in (0.0, 0.3, 0.5, 0.55, 0.8)] + [c5 + np.array([0.0, 20.0, 0.0])]
+    for pos in poses:
+        cam = synth.look_at(pos, pos + np.array([1.0, 0.2, -0.1]), (0, 0, 1), 64, 64)
+        L.lodge_select_chunk_sets(dev, sets, cam, R.ws, R.sel)
+        torch.cuda.synchronize()
+        f, o, t = oracle32.chunk_pair(city.chunks.centers, city.chunks.band, np.asarray(cam.pos, np.float32))
+        ids, w = oracle.union_select(city.n_total, pruned[f], pruned[o], t)
+        n = int(R.sel.count.item())
+        assert n == len(ids)
+        assert np.array_equal(R.sel.ids[:n].cpu().numpy().astype(np.uint32), ids)
+        assert np.array_equal(R.sel.w[:n].cpu().numpy().view(np.uint32), w.view(np.uint32))
+
+
+def test_filtering_pass_matches_oracle(L, oracle32, city):
+    """The full per-chunk pass (paper_2505_23158_amd.visibility) over all 16
+    chunks, four 160 x 90 views each: every chunk's filtered set equals the
+    oracle's except for members whose oracle score is within the score
+    tolerance of the threshold, or open to a flipped decision."""
+    import torch
+    from paper_2505_23158_amd import visibility
+    dev = L.Scene.from_synth(city)
+    sets = L.ChunkSets(dev)
+    R = L.Renderer(dev, 160, 90, max_active=city.n_total)
+    K = len(city.chunks.centers)
+    views = [synth.chunk_views(city.chunks, k, 2, 2, 160, 90) for k in range(K)]
+    thr = 0.02
+    counts = visibility.filter_chunk_sets(dev, sets, views, thr, R.ws, R.sel)
+    torch.cuda.synchronize()
+    total_diff = 0
+    for k in range(K):
+        ids, w = oracle32.select_chunk(city, k)
+        s_o = np.zeros(city.n_total, np.float32)
+        amb = np.zeros(city.n_total, np.uint8)
+        for cam in views[k]:
+            oracle32.view_importance(city, ids, w, cam, score=s_o, amb=amb)
+        keep_o = np.zeros(city.n_total, bool)
+        keep_o[oracle.prune_chunk_set(ids, s_o, thr)] = True
+        L.lodge_select_chunk(dev, sets, k, R.ws, R.sel)
+        torch.cuda.synchronize()
+        n = int(R.sel.count.item())
+        keep_g = np.zeros(city.n_total, bool)
+        keep_g[R.sel.ids[:n].cpu().numpy()] = True
+        diff = keep_g != keep_o
+        near = np.abs(s_o.astype(np.float64) - thr) <= SCORE_TOL
+        open_ = (amb != 0) & (np.abs(s_o.astype(np.float64) - thr) <= OPEN_TOL)
+        assert not (diff & ~near & ~open_).any(), (k, np.flatnonzero(diff & ~near & ~open_)[:10])
+        assert counts[k] == (len(ids), n)
+        total_diff += int(diff.sum())
+    log(f"[vis] 16 chunks filtered: {sum(c[0] for c in counts)} -> {sum(c[1] for c in counts)} members, "
+        f"{total_diff} threshold-ambiguous differences")
