@@ -423,3 +423,88 @@ def greedy_thresholds(cost, candidates, n_levels: int):
         chosen.append(best[0])
         curves.append(curve)
     return chosen, curves
+
+
+# -- LOD-level construction (supplementary "LOD structure optimization steps") --------------------------------
+# float64 throughout; the parameters of a level are raw (pre-activation): mean [3][n], log_scale [3][n],
+# quat_raw [4][n], opacity_logit [n], sh [16][3][n].
+
+RAW_KEYS = ("mean", "log_scale", "quat_raw", "opacity_logit", "sh")
+
+
+def activate(raw):
+    """3DGS parameterisation: scale = exp(log_scale), q = q_raw / |q_raw|, opacity = 1 / (1 + exp(-logit))."""
+    q = np.asarray(raw["quat_raw"], np.float64)
+    return {"mean": np.asarray(raw["mean"], np.float64), "scale": np.exp(np.asarray(raw["log_scale"], np.float64)),
+            "quat": q / np.linalg.norm(q, axis=0), "opacity": 1.0 / (1.0 + np.exp(-np.asarray(raw["opacity_logit"],
+                                                                                              np.float64))),
+            "sh": np.asarray(raw["sh"], np.float64)}
+
+
+def activate_adjoint(raw, g):
+    """Gradients w.r.t. the raw parameters from gradients w.r.t. the activated ones (chain rule of
+    activate): d/dlog_scale = g_scale * scale; d/dq_raw = (g_q - u (u . g_q)) / |q_raw| with u = q_raw/|q_raw|;
+    d/dlogit = g_opacity * o (1 - o)."""
+    act = activate(raw)
+    q = np.asarray(raw["quat_raw"], np.float64)
+    qn = np.linalg.norm(q, axis=0)
+    u = q / qn
+    return {"mean": g["mean"], "log_scale": g["scale"] * act["scale"],
+            "quat_raw": (g["quat"] - u * np.sum(u * g["quat"], axis=0)) / qn,
+            "opacity_logit": g["opacity"] * act["opacity"] * (1.0 - act["opacity"]), "sh": g["sh"]}
+
+
+def l1_loss_grad(image, target):
+    """Mean L1 loss over all values and its gradient sign(image - target) / N (0 where equal)."""
+    d = np.asarray(image, np.float64) - np.asarray(target, np.float64)
+    return float(np.mean(np.abs(d))), np.sign(d) / d.size
+
+
+def adam_update(p, g, m, v, lr, t, beta1=0.9, beta2=0.999, eps=1e-15):
+    """One Adam step (Kingma and Ba, Algorithm 1) at step t >= 1: returns the new (p, m, v)."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mh = m / (1.0 - beta1 ** t)
+    vh = v / (1.0 - beta2 ** t)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def lod_level_scene(levels_raw, sh_degrees, filter_vars, d):
+    """A Scene (float64, activated) of the given raw levels and switch distances."""
+    from synth import Level, Scene
+    lv = []
+    for raw, deg, var in zip(levels_raw, sh_degrees, filter_vars):
+        a = activate(raw)
+        sh = np.zeros((16, 3, a["mean"].shape[1]))
+        nsh = (deg + 1) ** 2
+        sh[:nsh] = np.asarray(raw["sh"], np.float64).reshape(nsh, 3, -1)
+        lv.append(Level(mean=a["mean"], scale=a["scale"], quat=a["quat"], opacity=a["opacity"], sh=sh,
+                        sh_degree=deg, filter3d_var=var))
+    return Scene(levels=lv, d=[float(x) for x in d], chunks=None)
+
+
+def finetune_grad(O64: "Oracle", levels_raw, sh_degrees, filter_vars, d, l, cam, target, d_factor, dL=None):
+    """The gradient of one fine-tuning step of level l w.r.t. level l's raw parameters: render levels
+    0..l with Eq. 2 about the camera and d_l replaced by d_factor * d_l (both rounded to FP32 like the
+    switch distances a scene stores), mean L1 loss against target, adjoint restricted to level l.
+    dL: use this dL/dimage instead of the loss's (to follow another renderer's sign decisions).
+    Returns (loss, dL/dimage, raw gradient of level l)."""
+    dd = [float(np.float32(x)) for x in d[:l]]
+    dd[l - 1] = float(np.float32(np.float32(dd[l - 1]) * np.float32(d_factor)))
+    sc = lod_level_scene(levels_raw[:l + 1], sh_degrees[:l + 1], filter_vars[:l + 1], dd)
+    fwd = O64.render(sc, cam, LOD_CAMERA)
+    loss, g_img = l1_loss_grad(fwd["image"], target)
+    if dL is not None:
+        g_img = dL
+    g2 = O64.grad2d(fwd["proj"], fwd["binned"], cam, g_img)
+    grads = O64.project_grad(sc, fwd["ids"], fwd["w"], cam, g2, grad_level=l)
+    O64._keep.clear()
+    nsh = (sh_degrees[l] + 1) ** 2
+    g = dict(grads[l])
+    g["sh"] = g["sh"][:nsh].reshape(nsh * 3, -1)
+    return loss, g_img, activate_adjoint(levels_raw[l], g)
+
+
+def keep_indices(score, threshold):
+    """Importance pruning: indices (ascending) of the items whose score reaches the threshold."""
+    return np.flatnonzero(np.asarray(score) >= threshold).astype(np.uint32)

@@ -402,3 +402,27 @@ def threshold_views(n: int = 4, half_xy: float = 100.0, width: int = 320, height
         fwd = np.array([math.cos(yaw) * math.cos(pitch), math.sin(yaw) * math.cos(pitch), math.sin(pitch)])
         cams.append(look_at(eye, eye + fwd, (0, 0, 1), width, height))
     return cams
+
+
+def lod_build_workload(n: int = 400, n_views: int = 6, width: int = 48, height: int = 32, d=(4.0,),
+                       seed: int = 61, steps_per_round: int = 4, rounds: int = 3):
+    """Inputs of the LOD-level construction loop: the finest level G^(0) as raw
+    parameters (cube [-2,2]^3, log-scale N(-2.5, 0.3)), training views at 3-9 m
+    from the centre looking at it, and the random draws of every fine-tuning
+    step: for level l and round r, a list of (training view index, factor u
+    ~ U(0.7, 1.3) of d_l).  Returns (base raw dict with mean/log_scale/
+    quat_raw/opacity_logit/sh [16*3][n] as float32, cams, d, schedule)."""
+    lv = gaussians(n, (seed, 0), _cube(2.0), -2.5, 0.3, keep_raw=True, morton=False)
+    base = {"mean": lv.mean, "log_scale": lv.raw["log_scale"], "quat_raw": lv.raw["quat"],
+            "opacity_logit": lv.raw["opacity_logit"], "sh": np.ascontiguousarray(lv.sh.reshape(-1, n))}
+    rng = _rng((seed, 1, 96, 0))
+    cams = []
+    for _ in range(n_views):
+        r = rng.uniform(3.0, 9.0)
+        th = rng.uniform(0.0, 2.0 * math.pi)
+        el = rng.uniform(-0.4, 0.4)
+        eye = (r * math.cos(el) * math.sin(th), r * math.sin(el), -r * math.cos(el) * math.cos(th))
+        cams.append(look_at(eye, (0, 0, 0), (0, -1, 0), width, height))
+    schedule = [[[(int(rng.integers(0, n_views)), float(rng.uniform(0.7, 1.3))) for _ in range(steps_per_round)]
+                 for _ in range(rounds)] for _ in d]
+    return base, cams, list(d), schedule

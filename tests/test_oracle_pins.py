@@ -962,3 +962,126 @@ def test_threshold_cost_is_mean_gaussians_per_tile(oracle32):
     c = oracle.threshold_cost(oracle32, sc, (6.0, 18.0), 3, cams)
     m = [oracle.lod_instances(oracle32, sc, (6.0, 18.0), 3, cam) for cam in cams]
     assert c == pytest.approx(np.mean(m) / 28.0, rel=0, abs=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# LOD-level construction (supplementary "LOD structure optimization steps")
+# ---------------------------------------------------------------------------
+
+def test_adam_update_matches_torch_optimizer():
+    """Kingma and Ba's Adam, checked against torch.optim.Adam in float64 over
+    several steps with varying gradients (including zeros and sign changes)."""
+    import torch
+    rng = np.random.default_rng(51)
+    p0 = rng.normal(size=40)
+    grads = [rng.normal(size=40) * 10.0 ** rng.uniform(-6, 1, 40) for _ in range(6)]
+    grads[2][:5] = 0.0
+    p, m, v = p0.copy(), np.zeros(40), np.zeros(40)
+    tp = torch.tensor(p0.copy(), dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([tp], lr=2e-3, betas=(0.9, 0.999), eps=1e-15)
+    for t, g in enumerate(grads, start=1):
+        p, m, v = oracle.adam_update(p, g, m, v, 2e-3, t)
+        tp.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        assert np.allclose(p, tp.detach().numpy(), rtol=0, atol=1e-14), t
+    # the first step moves every coordinate with a non-zero gradient by lr against its sign
+    p1, _, _ = oracle.adam_update(p0, grads[0], np.zeros(40), np.zeros(40), 2e-3, 1)
+    assert np.allclose(p1 - p0, -2e-3 * np.sign(grads[0]), rtol=1e-5, atol=0)
+
+
+def test_l1_loss_gradient_matches_torch_autograd():
+    import torch
+    rng = np.random.default_rng(52)
+    img, tgt = rng.random((3, 8, 10)), rng.random((3, 8, 10))
+    img[0, 0, :3] = tgt[0, 0, :3]     # equal values: gradient 0
+    loss, g = oracle.l1_loss_grad(img, tgt)
+    ti = torch.tensor(img, requires_grad=True)
+    tl = torch.nn.functional.l1_loss(ti, torch.tensor(tgt))
+    tl.backward()
+    assert loss == pytest.approx(float(tl.detach()), rel=1e-15)
+    assert np.array_equal(g, ti.grad.numpy())
+
+
+def test_activation_adjoint_by_central_differences():
+    rng = np.random.default_rng(53)
+    raw = {"mean": rng.normal(size=(3, 5)), "log_scale": rng.normal(-2, 0.3, (3, 5)),
+           "quat_raw": rng.normal(size=(4, 5)), "opacity_logit": rng.normal(size=5), "sh": rng.normal(size=(48, 5))}
+    w = {k: rng.normal(size=np.shape(v)) for k, v in oracle.activate(raw).items()}
+
+    def f(r):
+        a = oracle.activate(r)
+        return sum(float(np.sum(w[k] * a[k])) for k in a)
+    g = oracle.activate_adjoint(raw, {"mean": w["mean"], "scale": w["scale"], "quat": w["quat"],
+                                      "opacity": w["opacity"], "sh": w["sh"]})
+    for k in oracle.RAW_KEYS:
+        flat = raw[k].reshape(-1)
+        for j in range(0, flat.size, 3):
+            th = flat[j]
+            flat[j] = th + 1e-6
+            fp = f(raw)
+            flat[j] = th - 1e-6
+            fm = f(raw)
+            flat[j] = th
+            assert abs((fp - fm) / 2e-6 - g[k].reshape(-1)[j]) <= 1e-6 * max(1.0, abs(g[k].reshape(-1)[j])), (k, j)
+
+
+def test_finetune_gradient_of_level_l_by_central_differences(oracle64):
+    """The gradient of a fine-tuning step (levels 0..l rendered with Eq. 2
+    about the camera, d_l scaled by the step's draw, mean L1 loss) w.r.t.
+    level l's raw parameters, against central differences of that loss; the
+    scaled switch distance is the one the render uses."""
+    base, cams, d, sched = synth.lod_build_workload(n=48, n_views=3, width=24, height=16, d=(5.0,), seed=62)
+    base = {k: np.asarray(v, np.float64) for k, v in base.items()}
+    lvl1 = {k: v.copy() for k, v in base.items()}
+    rng = np.random.default_rng(54)
+    lvl1["mean"] = lvl1["mean"] + rng.normal(0, 0.05, lvl1["mean"].shape)
+    levels = [base, lvl1]
+    degs, vars_ = [3, 3], [0.0, synth.filter_var(5.0)]
+    cam = cams[0]
+    tgt = synth.target_images(1, 24, 16, seed=63)[0].astype(np.float64)
+    u = 0.83
+    loss, dL, g = oracle.finetune_grad(oracle64, levels, degs, vars_, d, 1, cam, tgt, u)
+    dd = [float(np.float32(np.float32(5.0) * np.float32(u)))]
+    sc0 = oracle.lod_level_scene(levels, degs, vars_, dd)
+    sel_ids, _, _ = oracle64.select(sc0, oracle.LOD_CAMERA, cam.pos)
+    base_sig = None
+
+    def loss_sig():
+        sc = oracle.lod_level_scene(levels, degs, vars_, dd)
+        r = oracle64.render(sc, cam, oracle.LOD_CAMERA)
+        return oracle.l1_loss_grad(r["image"], tgt)[0], (r["n_contrib"], r["n_blend"], r["proj"].tiles, r["ids"],
+                                                          np.sign(r["image"] - tgt))
+    l0, base_sig = loss_sig()
+    assert l0 == pytest.approx(loss, rel=1e-14)
+    assert np.any(sel_ids >= 48) and np.any(sel_ids < 48)   # both levels take part
+    checked = 0
+    for k in ("mean", "log_scale", "quat_raw", "opacity_logit", "sh"):
+        flat = lvl1[k].reshape(-1)
+        fd, an = [], []
+        for j in rng.choice(flat.size, size=min(25, flat.size), replace=False):
+            th = flat[j]
+            h = 1e-6 * max(1.0, abs(th))
+            flat[j] = th + h
+            lp, sp = loss_sig()
+            flat[j] = th - h
+            lm, sm = loss_sig()
+            flat[j] = th
+            if any(not np.array_equal(a, b) for s in (sp, sm) for a, b in zip(s, base_sig)):
+                continue
+            fd.append((lp - lm) / (2 * h))
+            an.append(g[k].reshape(-1)[j])
+        fd, an = np.asarray(fd), np.asarray(an)
+        assert len(fd) >= 8, k
+        if np.linalg.norm(fd) > 0:
+            assert np.linalg.norm(fd - an) <= 1e-3 * np.linalg.norm(fd), k
+            checked += 1
+    assert checked >= 4
+
+
+def test_keep_indices_and_workload_draws():
+    s = np.array([0.5, 0.01, 0.02, 0.0, 0.3], np.float32)
+    assert oracle.keep_indices(s, 0.02).tolist() == [0, 2, 4]
+    base, cams, d, sched = synth.lod_build_workload(d=(4.0, 9.0), steps_per_round=50)
+    assert len(sched) == 2 and all(len(r) == 3 and len(r[0]) == 50 for r in sched)
+    us = np.array([u for lv in sched for r in lv for _, u in r])
+    assert us.min() >= 0.7 and us.max() < 1.3 and abs(us.mean() - 1.0) < 0.05
