@@ -136,6 +136,26 @@ void lodge_scene_destroy(lodge_scene* scene);
  * id = sum_{j<l} n_j + i for Gaussian i of level l). */
 int64_t lodge_scene_total(const lodge_scene* scene);
 
+/* A packed copy of the levels for the projection: per Gaussian, its scale,
+ * opacity and rotation as two 16-byte words, and its SH coefficients as one
+ * contiguous run of 16-byte words ([basis][channel] order, zero-padded to a
+ * multiple of four floats).  A layout change only: frames render the same
+ * result bit for bit, reading 2 + ceil(3 (d+1)^2 / 4) contiguous words per
+ * Gaussian instead of 8 + 3 (d+1)^2 separate planes.  The means stay in the
+ * caller's planes (the selection streams them).
+ * lodge_pack_size: bytes of device memory the copy needs (224 per Gaussian
+ * at degree 3, each level's part 256-byte aligned). */
+lodge_status lodge_pack_size(const lodge_scene* scene, size_t* bytes);
+
+/* ASYNC.  Fills `pack` (device, caller-owned, >= lodge_pack_size() bytes,
+ * 256-byte aligned, kept alive until the scene is destroyed or detached)
+ * from the level planes and makes the scene's projection read it.  It is a
+ * snapshot: after the caller changes scale, rotation, opacity or SH of a
+ * level, pack again (or detach).  pack = NULL detaches (the projection reads
+ * the planes again).  Call it before frames on the scene are enqueued, on a
+ * stream ordered before them: it changes the scene that later calls read. */
+lodge_status lodge_scene_pack(lodge_scene* scene, void* pack, size_t bytes, void* stream);
+
 /* -------------------------------------------------------------- workspace */
 
 /* Caller-allocated device scratch for one frame in flight, laid out by the
@@ -386,6 +406,49 @@ lodge_status lodge_activate(int64_t n, const float* log_scale, const float* quat
 lodge_status lodge_activate_backward(int64_t n, const float* quat_raw, const float* scale, const float* opacity,
                                      const float* g_scale, const float* g_quat, const float* g_opacity,
                                      float* g_log_scale, float* g_quat_raw, float* g_opacity_logit, void* stream);
+
+/* ------------------------------------------------ LOD-level construction */
+
+/* The per-level fine-tuning of the supplementary "LOD structure
+ * optimization steps" renders with lodge_select/lodge_render, takes the
+ * loss gradient with lodge_l1_grad, back-propagates with
+ * lodge_render_backward (grad_level = the level being built) and
+ * lodge_activate_backward, and updates the level with lodge_adam; after each
+ * importance pruning (lodge_importance over the training views) the level's
+ * parameters and optimiser moments are compacted with lodge_keep_indices and
+ * lodge_gather_planes. */
+
+/* ASYNC.  Gradient of the L1 loss scale * sum |image - target| over n
+ * values: grad[i] = scale * sign(image[i] - target[i]) (0 where equal).
+ * scale = 1/n gives the mean L1.  loss: NULL, or a device float that the
+ * call ADDS scale * sum |image - target| to (one atomic per block, so its
+ * rounding depends on block order). */
+lodge_status lodge_l1_grad(int64_t n, const float* image, const float* target, float scale, float* grad, float* loss,
+                           void* stream);
+
+/* ASYNC.  One Adam step (Kingma and Ba) on n parameters in place, with its
+ * moments m and v (device, caller-owned, zero before step 1):
+ *   m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
+ *   p = p - lr (m / (1 - beta1^step)) / (sqrt(v / (1 - beta2^step)) + eps).
+ * step counts from 1; 0 <= beta < 1, eps >= 0. */
+lodge_status lodge_adam(int64_t n, float* param, const float* grad, float* m, float* v, float lr, float beta1,
+                        float beta2, float eps, int32_t step, void* stream);
+
+/* Bytes of device scratch lodge_keep_indices needs for n items (n < 2^32). */
+lodge_status lodge_keep_scratch_size(int64_t n, size_t* bytes);
+
+/* ASYNC.  Importance pruning of one level: idx (device, n entries of room)
+ * receives, ascending, the indices i < n with score[i] >= threshold, and
+ * *count (device) their number.  scratch: device, lodge_keep_scratch_size
+ * bytes, caller-owned. */
+lodge_status lodge_keep_indices(int64_t n, const float* score, float threshold, uint32_t* idx, uint32_t* count,
+                                void* scratch, size_t scratch_bytes, void* stream);
+
+/* ASYNC.  Compaction of `planes` planes of n_in floats (in: [planes][n_in],
+ * device) to the kept items: out[p][j] = in[p][idx[j]] for j < min(*count,
+ * n_out) (out: [planes][n_out], device).  Indices >= n_in are skipped. */
+lodge_status lodge_gather_planes(int32_t planes, int64_t n_in, int64_t n_out, const float* in, const uint32_t* idx,
+                                 const uint32_t* count, float* out, void* stream);
 
 #ifdef __cplusplus
 }

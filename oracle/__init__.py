@@ -488,7 +488,7 @@ def finetune_grad(O64: "Oracle", levels_raw, sh_degrees, filter_vars, d, l, cam,
     0..l with Eq. 2 about the camera and d_l replaced by d_factor * d_l (both rounded to FP32 like the
     switch distances a scene stores), mean L1 loss against target, adjoint restricted to level l.
     dL: use this dL/dimage instead of the loss's (to follow another renderer's sign decisions).
-    Returns (loss, dL/dimage, raw gradient of level l)."""
+    Returns (loss, dL/dimage, raw gradient of level l, rendered image)."""
     dd = [float(np.float32(x)) for x in d[:l]]
     dd[l - 1] = float(np.float32(np.float32(dd[l - 1]) * np.float32(d_factor)))
     sc = lod_level_scene(levels_raw[:l + 1], sh_degrees[:l + 1], filter_vars[:l + 1], dd)
@@ -502,7 +502,7 @@ def finetune_grad(O64: "Oracle", levels_raw, sh_degrees, filter_vars, d, l, cam,
     nsh = (sh_degrees[l] + 1) ** 2
     g = dict(grads[l])
     g["sh"] = g["sh"][:nsh].reshape(nsh * 3, -1)
-    return loss, g_img, activate_adjoint(levels_raw[l], g)
+    return loss, g_img, activate_adjoint(levels_raw[l], g), fwd["image"]
 
 
 def keep_indices(score, threshold):

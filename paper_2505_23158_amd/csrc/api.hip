@@ -373,6 +373,54 @@ lodge_status lodge_workspace_size(const lodge_scene* scene, int32_t width, int32
     return LODGE_OK;
 }
 
+namespace {
+uint32_t sh_stride4(int32_t deg) { return (uint32_t)((3 * (deg + 1) * (deg + 1) + 3) / 4); }
+}  // namespace
+
+lodge_status lodge_pack_size(const lodge_scene* scene, size_t* bytes)
+{
+    if (!scene || !bytes) return fail(LODGE_ERR_INVALID_ARG, "scene or bytes is NULL");
+    size_t b = 0;
+    for (int l = 0; l < scene->levels.L; l++) {
+        const LevelDev& L = scene->levels.lv[l];
+        b += (size_t)L.n * (32 + 16 * (size_t)sh_stride4(L.sh_degree));
+        b = (b + 255) & ~(size_t)255;
+    }
+    *bytes = b;
+    return LODGE_OK;
+}
+
+lodge_status lodge_scene_pack(lodge_scene* scene, void* pack, size_t bytes, void* stream)
+{
+    if (!scene) return fail(LODGE_ERR_INVALID_ARG, "scene is NULL");
+    if (!pack) {   // detach: the projection reads the level planes again
+        for (int l = 0; l < LODGE_MAX_LEVELS; l++) scene->levels.pk[l] = PackDev{nullptr, nullptr, 0};
+        scene->levels.packed = 0;
+        return LODGE_OK;
+    }
+    size_t need = 0;
+    lodge_pack_size(scene, &need);
+    if (bytes < need) return fail(LODGE_ERR_INVALID_ARG, "pack buffer smaller than lodge_pack_size()");
+    if (reinterpret_cast<uintptr_t>(pack) & 255) return fail(LODGE_ERR_INVALID_ARG, "pack buffer not 256-byte aligned");
+    LevelsArg lv = scene->levels;
+    char* b = static_cast<char*>(pack);
+    size_t off = 0;
+    for (int l = 0; l < lv.L; l++) {
+        const LevelDev& L = lv.lv[l];
+        PackDev& P = lv.pk[l];
+        P.sh_stride4 = sh_stride4(L.sh_degree);
+        P.pgeo = reinterpret_cast<const float4*>(b + off);
+        P.psh = reinterpret_cast<const float4*>(b + off + 32 * (size_t)L.n);
+        off += (size_t)L.n * (32 + 16 * (size_t)P.sh_stride4);
+        off = (off + 255) & ~(size_t)255;
+    }
+    const hipError_t e = launch_pack(lv, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "lodge_scene_pack");
+    lv.packed = 1;
+    scene->levels = lv;
+    return LODGE_OK;
+}
+
 lodge_status lodge_set_camera(const lodge_workspace* ws, const lodge_camera* cam, void* stream)
 {
     if (!ws || !ws->base) return fail(LODGE_ERR_INVALID_ARG, "workspace is NULL");

@@ -30,6 +30,15 @@ struct LevelDev {
     float var;          // Eq. 3 filter variance
 };
 
+// A level's packed copy (lodge_scene_pack), null when absent: per Gaussian
+// two float4 (scale xyz, opacity), (quaternion wxyz), and sh_stride4 float4
+// of its SH coefficients in [basis][channel] order.
+struct PackDev {
+    const float4* pgeo;
+    const float4* psh;
+    uint32_t sh_stride4;
+};
+
 struct LevelsArg {
     LevelDev lv[LODGE_MAX_LEVELS];
     int32_t L;
@@ -37,6 +46,8 @@ struct LevelsArg {
     float d[LODGE_MAX_LEVELS];   // d_1 .. d_{L-1}
     uint32_t first_block[LODGE_MAX_LEVELS + 1];   // selection blocks: level l owns [first_block[l], first_block[l+1])
     uint32_t sel_blocks;
+    int32_t packed;     // 1: the projection reads the packed copy of every level
+    PackDev pk[LODGE_MAX_LEVELS];
 };
 
 struct ChunksArg {
@@ -206,6 +217,8 @@ hipError_t launch_importance(const Views& v, const uint32_t* sel_ids, float* sco
 hipError_t launch_backward(const LevelsArg& lv, const lodge_selection& sel, const Views& v, const float* final_T,
                            const uint32_t* n_contrib, const float* dL_dimage, int32_t grad_level,
                            const lodge_grads* grads, hipStream_t st);
+// fills the packed copy of every level (layout in LevelDev)
+hipError_t launch_pack(const LevelsArg& lv, hipStream_t st);
 hipError_t launch_activate(int64_t n, const float* ls, const float* qr, const float* ol, float* s, float* q, float* o,
                            hipStream_t st);
 hipError_t launch_activate_backward(int64_t n, const float* qr, const float* s, const float* o, const float* gs,

@@ -86,9 +86,17 @@ __device__ __forceinline__ int level_index(const LevelsArg& lv, uint32_t g)
 
 constexpr int kQueue = 128;   // per-wave colour queue: < 64 left over + one chunk of 64
 
+// A float4 pointer every active lane holds the same value of, in scalar registers.
+__device__ __forceinline__ const float4* uniform_ptr4(const float4* p)
+{
+    return reinterpret_cast<const float4*>(uniform_ptr(reinterpret_cast<const float*>(p)));
+}
+
 // Colour of up to 64 queued Gaussians, one per lane (lanes >= cnt idle):
 // degree-3 real SH at the view direction, + 0.5, clamped at 0; written into
-// the record's colour fields.
+// the record's colour fields.  kPacked: the coefficients come from the
+// level's packed copy (one contiguous run per Gaussian) instead of its planes.
+template <bool kPacked>
 __device__ __forceinline__ void colour_batch(const LevelsArg& lv, const LevelDev* s_lv, const uint32_t* qa,
                                              const uint32_t* qg,
                                              const float (*qd)[kQueue], uint32_t cnt, float4* __restrict__ proj)
@@ -107,18 +115,40 @@ __device__ __forceinline__ void colour_batch(const LevelsArg& lv, const LevelDev
         if (todo && lvl == l0) {
             todo = false;
             const LevelDev& Lv = s_lv[l0];
-            const float* __restrict__ shp = uniform_ptr(Lv.sh);
-            const size_t n = __builtin_amdgcn_readfirstlane(Lv.n);
             const int sh_degree = __builtin_amdgcn_readfirstlane(Lv.sh_degree);
-            const uint32_t off = (g - __builtin_amdgcn_readfirstlane(Lv.base)) * 4u;
-            // all (d+1)^2 x 3 coefficients are loaded before the first use; planes past
-            // the level's degree are clamped in bounds and contribute an exact zero
             const int nb = (sh_degree + 1) * (sh_degree + 1);
             float coef[kMaxSh][3];
+            if constexpr (kPacked) {
+                // the Gaussian's run of stride4 words; words past it are never read
+                const PackDev& P = lv.pk[l0];
+                const uint32_t stride4 = __builtin_amdgcn_readfirstlane(P.sh_stride4);
+                const float4* __restrict__ h =
+                    uniform_ptr4(P.psh) + (size_t)stride4 * (g - __builtin_amdgcn_readfirstlane(Lv.base));
+                float c[4 * kMaxSh * 3 / 4];
 #pragma unroll
-            for (int k = 0; k < kMaxSh; k++)
+                for (int j = 0; j < kMaxSh * 3 / 4; j++) {
+                    const float4 w = (uint32_t)j < stride4 ? h[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    c[4 * j] = w.x;
+                    c[4 * j + 1] = w.y;
+                    c[4 * j + 2] = w.z;
+                    c[4 * j + 3] = w.w;
+                }
 #pragma unroll
-                for (int ch = 0; ch < 3; ch++) coef[k][ch] = ld(shp + (size_t)((k < nb ? k : nb - 1) * 3 + ch) * n, off);
+                for (int k = 0; k < kMaxSh; k++)
+#pragma unroll
+                    for (int ch = 0; ch < 3; ch++) coef[k][ch] = k < nb ? c[3 * k + ch] : 0.0f;
+            } else {
+                const float* __restrict__ shp = uniform_ptr(Lv.sh);
+                const size_t n = __builtin_amdgcn_readfirstlane(Lv.n);
+                const uint32_t off = (g - __builtin_amdgcn_readfirstlane(Lv.base)) * 4u;
+                // all (d+1)^2 x 3 coefficients are loaded before the first use; planes past
+                // the level's degree are clamped in bounds and contribute an exact zero
+#pragma unroll
+                for (int k = 0; k < kMaxSh; k++)
+#pragma unroll
+                    for (int ch = 0; ch < 3; ch++)
+                        coef[k][ch] = ld(shp + (size_t)((k < nb ? k : nb - 1) * 3 + ch) * n, off);
+            }
             float Y[kMaxSh];
             sh_basis(dx, dy, dz, Y);
             float rgb[3];
@@ -137,6 +167,8 @@ __device__ __forceinline__ void colour_batch(const LevelsArg& lv, const LevelDev
     }
 }
 
+// kPacked: scale, rotation, opacity and SH come from the levels' packed copy.
+template <bool kPacked>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_project(LevelsArg lv, const uint32_t* __restrict__ ids,
                                                  const float* __restrict__ wsel, const uint32_t* __restrict__ count,
                                                  uint32_t cap, const FrameParams* __restrict__ fp, FrameInfo* info,
@@ -201,9 +233,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             const float tz = ((W[6] * mx + W[7] * my) + W[8] * mz) + cam.t[2];
             if (tz > cam.znear) {
                 front = true;
-                const float s0 = ld(scale, off), s1 = ld(scale + n, off), s2 = ld(scale + 2 * n, off);
-                const float qw = ld(quat, off), qx = ld(quat + n, off), qy = ld(quat + 2 * n, off),
-                            qz = ld(quat + 3 * n, off);
+                float s0, s1, s2, qw, qx, qy, qz, op_p;
+                if constexpr (kPacked) {
+                    const float4* __restrict__ pg =
+                        uniform_ptr4(lv.pk[l0].pgeo) + 2 * (size_t)(g - __builtin_amdgcn_readfirstlane(Lv.base));
+                    const float4 ga = pg[0], gb = pg[1];
+                    s0 = ga.x; s1 = ga.y; s2 = ga.z; op_p = ga.w;
+                    qw = gb.x; qx = gb.y; qy = gb.z; qz = gb.w;
+                } else {
+                    s0 = ld(scale, off); s1 = ld(scale + n, off); s2 = ld(scale + 2 * n, off);
+                    qw = ld(quat, off); qx = ld(quat + n, off); qy = ld(quat + 2 * n, off); qz = ld(quat + 3 * n, off);
+                    op_p = 0.0f;
+                }
                 // rotation of the quaternion (w, x, y, z) as given
                 const float xx = qx * qx, yy = qy * qy, zz = qz * qz;
                 const float xy = qx * qy, xz = qx * qz, yz = qy * qz;
@@ -281,7 +322,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                         d0n = d0 / dn;
                         d1n = d1 / dn;
                         d2n = d2 / dn;
-                        const float o_eff = ((ld(opac, off) * __builtin_nontemporal_load(wsel + a)) * comp3) * comp2;
+                        float op;
+                        if constexpr (kPacked) op = op_p;
+                        else op = ld(opac, off);
+                        const float o_eff = ((op * __builtin_nontemporal_load(wsel + a)) * comp3) * comp2;
                         // compositing aids: below power thr alpha cannot reach 1/255 (margin 1e-3);
                         // (ex, ey) half-extents of the ellipse where it can: d^T conic d <= -2 thr
                         const float thr = o_eff > 0.0f ? -logf(255.0f * o_eff) - 1e-3f : INFINITY;
@@ -337,7 +381,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (qn >= 64) {
-            colour_batch(lv, s_lv, qa, qg, qd, 64, proj);
+            colour_batch<kPacked>(lv, s_lv, qa, qg, qd, 64, proj);
             // move the left-over entries to the front of the queue
             const uint32_t rem = qn - 64;
             uint32_t ta = 0, tg = 0;
@@ -365,7 +409,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
-    if (qn > 0) colour_batch(lv, s_lv, qa, qg, qd, qn, proj);
+    if (qn > 0) colour_batch<kPacked>(lv, s_lv, qa, qg, qd, qn, proj);
     // counters: wave sums, block sum, one atomic per block
     for (int o = 32; o > 0; o >>= 1) {
         n_front += __shfl_xor(n_front, o);
@@ -388,22 +432,30 @@ hipError_t launch_project(const LevelsArg& lv, const lodge_selection& sel, const
     // persistent waves: exactly as many blocks as the device holds at once, so
     // every wave's queue spans many chunks and no second partial round is left
     static thread_local int dev_cached = -1;
-    static thread_local uint32_t resident = 0;
+    static thread_local uint32_t resident[2] = {0, 0};
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     if (dev != dev_cached) {
-        int per_cu = 0, cus = 0;
-        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_project, 256, 0)) != hipSuccess) return e;
+        int per_cu[2] = {0, 0}, cus = 0;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[0], k_project<false>, 256, 0)) != hipSuccess)
+            return e;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[1], k_project<true>, 256, 0)) != hipSuccess)
+            return e;
         if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-        resident = (uint32_t)std::max(1, per_cu * cus);
+        resident[0] = (uint32_t)std::max(1, per_cu[0] * cus);
+        resident[1] = (uint32_t)std::max(1, per_cu[1] * cus);
         dev_cached = dev;
     }
     uint32_t blocks = (v.max_active + 255) / 256;
     if (blocks < 1) blocks = 1;
-    if (blocks > resident) blocks = resident;
-    k_project<<<blocks, 256, 0, st>>>(lv, sel.ids, sel.w, sel.count, sel.cap, v.params, v.info, v.proj, v.depth,
-                                      v.rect, v.vtiles, v.chunk_sum, v.chunk_vis);
+    if (blocks > resident[lv.packed ? 1 : 0]) blocks = resident[lv.packed ? 1 : 0];
+    if (lv.packed)
+        k_project<true><<<blocks, 256, 0, st>>>(lv, sel.ids, sel.w, sel.count, sel.cap, v.params, v.info, v.proj,
+                                                v.depth, v.rect, v.vtiles, v.chunk_sum, v.chunk_vis);
+    else
+        k_project<false><<<blocks, 256, 0, st>>>(lv, sel.ids, sel.w, sel.count, sel.cap, v.params, v.info, v.proj,
+                                                 v.depth, v.rect, v.vtiles, v.chunk_sum, v.chunk_vis);
     return hipGetLastError();
 }
 

@@ -103,6 +103,8 @@ def lib():
             "lodge_scene_destroy": (None, [vp]),
             "lodge_scene_total": (C.c_int64, [vp]),
             "lodge_workspace_size": (st, [vp, C.c_int32, C.c_int32, C.c_uint32, C.c_uint64, C.POINTER(C.c_size_t)]),
+            "lodge_pack_size": (st, [vp, C.POINTER(C.c_size_t)]),
+            "lodge_scene_pack": (st, [vp, vp, C.c_size_t, vp]),
             "lodge_set_camera": (st, [C.POINTER(lodge_workspace), vp, vp]),
             "lodge_select": (st, [vp, vp, C.c_int32, C.POINTER(lodge_workspace), C.POINTER(lodge_selection), vp]),
             "lodge_chunk_sets_size": (st, [vp, C.POINTER(C.c_size_t)]),
@@ -125,6 +127,12 @@ def lib():
                                            C.POINTER(lodge_grads), vp]),
             "lodge_render_static": (st, [vp, C.POINTER(lodge_selection), vp, C.POINTER(lodge_render_opts), vp, vp,
                                          vp, vp, vp]),
+            "lodge_l1_grad": (st, [C.c_int64, vp, vp, C.c_float, vp, vp, vp]),
+            "lodge_adam": (st, [C.c_int64, vp, vp, vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32,
+                                vp]),
+            "lodge_keep_scratch_size": (st, [C.c_int64, C.POINTER(C.c_size_t)]),
+            "lodge_keep_indices": (st, [C.c_int64, vp, C.c_float, vp, vp, vp, C.c_size_t, vp]),
+            "lodge_gather_planes": (st, [C.c_int32, C.c_int64, C.c_int64, vp, vp, vp, vp, vp]),
             "lodge_activate": (st, [C.c_int64, vp, vp, vp, vp, vp, vp, vp]),
             "lodge_activate_backward": (st, [C.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         }
@@ -145,7 +153,9 @@ EXPORTED = ["lodge_status_string", "lodge_last_error", "lodge_version", "lodge_s
             "lodge_scene_total", "lodge_workspace_size", "lodge_set_camera", "lodge_select", "lodge_chunk_sets_size",
             "lodge_chunk_sets_build", "lodge_select_chunk_sets", "lodge_render", "lodge_frame_info_read",
             "lodge_check", "lodge_debug_views", "lodge_render_backward", "lodge_activate", "lodge_activate_backward",
-            "lodge_render_static", "lodge_select_chunk", "lodge_importance", "lodge_chunk_sets_prune"]
+            "lodge_render_static", "lodge_select_chunk", "lodge_importance", "lodge_chunk_sets_prune",
+            "lodge_l1_grad", "lodge_adam", "lodge_keep_scratch_size", "lodge_keep_indices", "lodge_gather_planes",
+            "lodge_pack_size", "lodge_scene_pack"]
 STATIC_SCRATCH_BYTES = 256 << 20
 
 
@@ -224,6 +234,23 @@ class Scene:
                                         C.byref(ch) if ch is not None else None, C.byref(h)))
         self.handle = h
         self.total = int(lib().lodge_scene_total(h))
+
+    def pack(self, stream=None):
+        """Fills a packed copy of the levels (lodge_scene_pack) that the projection then reads; the copy is
+        owned by this object.  Call again after changing the level parameters."""
+        torch = _torch()
+        nb = C.c_size_t()
+        _check(lib().lodge_pack_size(self.handle, C.byref(nb)))
+        if getattr(self, "_pack", None) is None or self._pack.numel() < int(nb.value) + 256:
+            self._pack = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device="cuda")
+        base = self._pack.data_ptr()
+        off = (-base) % 256
+        _check(lib().lodge_scene_pack(self.handle, C.c_void_p(base + off), C.c_size_t(nb.value), _stream_ptr(stream)))
+        return int(nb.value)
+
+    def unpack(self):
+        _check(lib().lodge_scene_pack(self.handle, None, 0, None))
+        self._pack = None
 
     @classmethod
     def from_synth(cls, sc, device="cuda"):
@@ -415,6 +442,46 @@ def lodge_activate_backward(quat_raw, scale, opacity, g_scale, g_quat, g_opacity
     _check(lib().lodge_activate_backward(n, _ptr(quat_raw), _ptr(scale), _ptr(opacity), _ptr(g_scale), _ptr(g_quat),
                                          _ptr(g_opacity), _ptr(g_log_scale), _ptr(g_quat_raw),
                                          _ptr(g_opacity_logit), _stream_ptr(stream)))
+
+
+def lodge_l1_grad(image, target, grad, scale: float, loss=None, stream=None):
+    n = int(image.numel())
+    if target.numel() != n or grad.numel() != n:
+        raise ValueError("image, target and grad must have the same size")
+    _check(lib().lodge_l1_grad(n, _ptr(image), _ptr(target), float(scale), _ptr(grad), _ptr(loss),
+                               _stream_ptr(stream)))
+
+
+def lodge_adam(param, grad, m, v, lr: float, step: int, beta1: float = 0.9, beta2: float = 0.999,
+               eps: float = 1e-15, stream=None):
+    n = int(param.numel())
+    if not (grad.numel() == m.numel() == v.numel() == n):
+        raise ValueError("param, grad, m and v must have the same size")
+    _check(lib().lodge_adam(n, _ptr(param), _ptr(grad), _ptr(m), _ptr(v), float(lr), float(beta1), float(beta2),
+                            float(eps), int(step), _stream_ptr(stream)))
+
+
+def lodge_keep_indices(score, threshold: float, idx, count, scratch=None, stream=None):
+    """idx: int32 tensor (>= score.numel()), count: int32 tensor [1]; returns the scratch used."""
+    torch = _torch()
+    n = int(score.numel())
+    nb = C.c_size_t()
+    _check(lib().lodge_keep_scratch_size(n, C.byref(nb)))
+    if scratch is None or scratch.numel() * scratch.element_size() < nb.value:
+        scratch = torch.empty(max(4, int(nb.value)), dtype=torch.uint8, device=score.device)
+    _check(lib().lodge_keep_indices(n, _ptr(score), float(threshold), _ptr(idx), _ptr(count), _ptr(scratch),
+                                    C.c_size_t(scratch.numel()), _stream_ptr(stream)))
+    return scratch
+
+
+def lodge_gather_planes(inp, idx, count, out, stream=None):
+    """inp [P, n_in] -> out [P, n_out] (float32, contiguous)."""
+    P, n_in = inp.shape
+    P2, n_out = out.shape
+    if P != P2:
+        raise ValueError("plane counts differ")
+    _check(lib().lodge_gather_planes(int(P), int(n_in), int(n_out), _ptr(inp), _ptr(idx), _ptr(count), _ptr(out),
+                                     _stream_ptr(stream)))
 
 
 # --------------------------------------------------------------------------- one frame

@@ -1040,7 +1040,7 @@ def test_finetune_gradient_of_level_l_by_central_differences(oracle64):
     cam = cams[0]
     tgt = synth.target_images(1, 24, 16, seed=63)[0].astype(np.float64)
     u = 0.83
-    loss, dL, g = oracle.finetune_grad(oracle64, levels, degs, vars_, d, 1, cam, tgt, u)
+    loss, dL, g, _ = oracle.finetune_grad(oracle64, levels, degs, vars_, d, 1, cam, tgt, u)
     dd = [float(np.float32(np.float32(5.0) * np.float32(u)))]
     sc0 = oracle.lod_level_scene(levels, degs, vars_, dd)
     sel_ids, _, _ = oracle64.select(sc0, oracle.LOD_CAMERA, cam.pos)
