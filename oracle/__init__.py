@@ -483,10 +483,12 @@ def lod_level_scene(levels_raw, sh_degrees, filter_vars, d):
     return Scene(levels=lv, d=[float(x) for x in d], chunks=None)
 
 
-def finetune_grad(O64: "Oracle", levels_raw, sh_degrees, filter_vars, d, l, cam, target, d_factor, dL=None):
+def finetune_grad(O64: "Oracle", levels_raw, sh_degrees, filter_vars, d, l, cam, target, d_factor, dL=None,
+                  lam=0.0):
     """The gradient of one fine-tuning step of level l w.r.t. level l's raw parameters: render levels
     0..l with Eq. 2 about the camera and d_l replaced by d_factor * d_l (both rounded to FP32 like the
-    switch distances a scene stores), mean L1 loss against target, adjoint restricted to level l.
+    switch distances a scene stores), loss (1 - lam) mean L1 + lam (1 - mean SSIM) against target,
+    adjoint restricted to level l.
     dL: use this dL/dimage instead of the loss's (to follow another renderer's sign decisions).
     Returns (loss, dL/dimage, raw gradient of level l, rendered image)."""
     dd = [float(np.float32(x)) for x in d[:l]]
@@ -494,6 +496,10 @@ def finetune_grad(O64: "Oracle", levels_raw, sh_degrees, filter_vars, d, l, cam,
     sc = lod_level_scene(levels_raw[:l + 1], sh_degrees[:l + 1], filter_vars[:l + 1], dd)
     fwd = O64.render(sc, cam, LOD_CAMERA)
     loss, g_img = l1_loss_grad(fwd["image"], target)
+    loss, g_img = (1.0 - lam) * loss, (1.0 - lam) * g_img
+    if lam:
+        ls, gs = dssim_grad(fwd["image"], target)
+        loss, g_img = loss + lam * ls, g_img + lam * gs
     if dL is not None:
         g_img = dL
     g2 = O64.grad2d(fwd["proj"], fwd["binned"], cam, g_img)
@@ -508,3 +514,64 @@ def finetune_grad(O64: "Oracle", levels_raw, sh_degrees, filter_vars, d, l, cam,
 def keep_indices(score, threshold):
     """Importance pruning: indices (ascending) of the items whose score reaches the threshold."""
     return np.flatnonzero(np.asarray(score) >= threshold).astype(np.uint32)
+
+
+# -- the D-SSIM term of the construction loss (3DGS's L = (1 - lambda) L1 + lambda (1 - SSIM)) -----------------
+
+SSIM_C1 = 0.01 ** 2
+SSIM_C2 = 0.03 ** 2
+
+
+def ssim_window(size=11, sigma=1.5):
+    """Normalised 1-D Gaussian window (the separable factor of SSIM's 11 x 11 window)."""
+    x = np.arange(size, dtype=np.float64) - size // 2
+    w = np.exp(-(x * x) / (2.0 * sigma * sigma))
+    return w / w.sum()
+
+
+def _blur(img):
+    """Separable window filter of each channel with zero padding outside the image ('same' size)."""
+    w = ssim_window()
+    h = len(w) // 2
+
+    def same(r):   # the centred part of the full convolution: also for lines shorter than the window
+        return np.convolve(r, w, mode="full")[h:h + len(r)]
+    out = np.empty_like(img, dtype=np.float64)
+    for c in range(img.shape[0]):
+        rows = np.apply_along_axis(same, 1, img[c].astype(np.float64))
+        out[c] = np.apply_along_axis(same, 0, rows)
+    return out
+
+
+def ssim_map(x, y):
+    """Per-pixel SSIM of two images [C][H][W] (Wang et al. 2004 with the 11 x 11 Gaussian window of
+    sigma 1.5, C1 = 0.01^2, C2 = 0.03^2, local statistics by zero-padded filtering)."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    mx, my = _blur(x), _blur(y)
+    sxx = _blur(x * x) - mx * mx
+    syy = _blur(y * y) - my * my
+    sxy = _blur(x * y) - mx * my
+    return ((2 * mx * my + SSIM_C1) * (2 * sxy + SSIM_C2)) / ((mx * mx + my * my + SSIM_C1) * (sxx + syy + SSIM_C2))
+
+
+def dssim_grad(x, y):
+    """(1 - mean SSIM) and its gradient w.r.t. x.  With m the SSIM map, mu_x = w * x, E_xx = w * x^2,
+    E_xy = w * (x y) (w the window, * zero-padded filtering), the chain rule through the three filtered
+    maps and the window's symmetry give
+        d(mean m)/dx = w * (g dm/dmu_x) + 2 x (w * (g dm/dE_xx)) + y (w * (g dm/dE_xy)),  g = 1 / N."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    mx, my = _blur(x), _blur(y)
+    exx, eyy, exy = _blur(x * x), _blur(y * y), _blur(x * y)
+    a1 = 2 * mx * my + SSIM_C1
+    a2 = 2 * (exy - mx * my) + SSIM_C2
+    b1 = mx * mx + my * my + SSIM_C1
+    b2 = (exx - mx * mx) + (eyy - my * my) + SSIM_C2
+    m = (a1 * a2) / (b1 * b2)
+    g = 1.0 / m.size
+    d_mx = (2 * my * a2 - 2 * my * a1) / (b1 * b2) - m * (2 * mx) / b1 + m * (2 * mx) / b2
+    d_exx = -m / b2
+    d_exy = 2 * a1 / (b1 * b2)
+    grad = _blur(g * d_mx) + 2 * x * _blur(g * d_exx) + y * _blur(g * d_exy)
+    return float(1.0 - m.mean()), -grad

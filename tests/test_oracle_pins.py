@@ -1027,7 +1027,7 @@ def test_activation_adjoint_by_central_differences():
 
 def test_finetune_gradient_of_level_l_by_central_differences(oracle64):
     """The gradient of a fine-tuning step (levels 0..l rendered with Eq. 2
-    about the camera, d_l scaled by the step's draw, mean L1 loss) w.r.t.
+    about the camera, d_l scaled by the step's draw, 0.8 mean L1 + 0.2 D-SSIM) w.r.t.
     level l's raw parameters, against central differences of that loss; the
     scaled switch distance is the one the render uses."""
     base, cams, d, sched = synth.lod_build_workload(n=48, n_views=3, width=24, height=16, d=(5.0,), seed=62)
@@ -1040,7 +1040,8 @@ def test_finetune_gradient_of_level_l_by_central_differences(oracle64):
     cam = cams[0]
     tgt = synth.target_images(1, 24, 16, seed=63)[0].astype(np.float64)
     u = 0.83
-    loss, dL, g, _ = oracle.finetune_grad(oracle64, levels, degs, vars_, d, 1, cam, tgt, u)
+    lam = 0.2
+    loss, dL, g, _ = oracle.finetune_grad(oracle64, levels, degs, vars_, d, 1, cam, tgt, u, lam=lam)
     dd = [float(np.float32(np.float32(5.0) * np.float32(u)))]
     sc0 = oracle.lod_level_scene(levels, degs, vars_, dd)
     sel_ids, _, _ = oracle64.select(sc0, oracle.LOD_CAMERA, cam.pos)
@@ -1049,8 +1050,8 @@ def test_finetune_gradient_of_level_l_by_central_differences(oracle64):
     def loss_sig():
         sc = oracle.lod_level_scene(levels, degs, vars_, dd)
         r = oracle64.render(sc, cam, oracle.LOD_CAMERA)
-        return oracle.l1_loss_grad(r["image"], tgt)[0], (r["n_contrib"], r["n_blend"], r["proj"].tiles, r["ids"],
-                                                          np.sign(r["image"] - tgt))
+        lv = (1 - lam) * oracle.l1_loss_grad(r["image"], tgt)[0] + lam * (1 - oracle.ssim_map(r["image"], tgt).mean())
+        return lv, (r["n_contrib"], r["n_blend"], r["proj"].tiles, r["ids"], np.sign(r["image"] - tgt))
     l0, base_sig = loss_sig()
     assert l0 == pytest.approx(loss, rel=1e-14)
     assert np.any(sel_ids >= 48) and np.any(sel_ids < 48)   # both levels take part
@@ -1085,3 +1086,54 @@ def test_keep_indices_and_workload_draws():
     assert len(sched) == 2 and all(len(r) == 3 and len(r[0]) == 50 for r in sched)
     us = np.array([u for lv in sched for r in lv for _, u in r])
     assert us.min() >= 0.7 and us.max() < 1.3 and abs(us.mean() - 1.0) < 0.05
+
+
+def test_ssim_identity_symmetry_and_constant_patches():
+    """SSIM(x, x) = 1 everywhere; SSIM is symmetric; on constant images a, b the
+    pixels at least 5 away from the border (where the window sees only the image)
+    take the closed form (2ab + C1) / (a^2 + b^2 + C1)."""
+    rng = np.random.default_rng(81)
+    x = rng.random((3, 20, 24))
+    y = rng.random((3, 20, 24))
+    assert np.allclose(oracle.ssim_map(x, x), 1.0, atol=1e-12)
+    assert np.allclose(oracle.ssim_map(x, y), oracle.ssim_map(y, x), atol=1e-14)
+    a, b = 0.3, 0.7
+    m = oracle.ssim_map(np.full((1, 16, 16), a), np.full((1, 16, 16), b))
+    expect = (2 * a * b + 0.01 ** 2) / (a * a + b * b + 0.01 ** 2)
+    assert np.allclose(m[0, 5:11, 5:11], expect, rtol=1e-12)
+    assert oracle.ssim_window().sum() == pytest.approx(1.0, abs=1e-15)
+    assert oracle.ssim_window()[5] == oracle.ssim_window().max()
+
+
+def test_dssim_gradient_by_central_differences():
+    rng = np.random.default_rng(82)
+    x = rng.random((3, 13, 17))
+    y = rng.random((3, 13, 17))
+    loss, g = oracle.dssim_grad(x, y)
+    assert loss == pytest.approx(1.0 - oracle.ssim_map(x, y).mean(), abs=1e-14)
+    for idx in [(0, 0, 0), (1, 6, 8), (2, 12, 16), (0, 3, 15), (1, 12, 0), (2, 7, 2)]:
+        h = 1e-6
+        xp = x.copy(); xp[idx] += h
+        xm = x.copy(); xm[idx] -= h
+        fd = ((1 - oracle.ssim_map(xp, y).mean()) - (1 - oracle.ssim_map(xm, y).mean())) / (2 * h)
+        assert g[idx] == pytest.approx(fd, rel=1e-6, abs=1e-12), idx
+
+
+def test_ssim_window_filter_by_brute_force_including_images_smaller_than_the_window():
+    """The zero-padded window filter behind SSIM, against a direct double sum
+    over the 11 x 11 window, on images narrower and lower than the window."""
+    rng = np.random.default_rng(83)
+    w = oracle.ssim_window()
+    for H, W in ((3, 5), (13, 4), (12, 17)):
+        img = rng.random((2, H, W))
+        got = oracle._blur(img)
+        ref = np.zeros_like(img)
+        for c in range(2):
+            for i in range(H):
+                for j in range(W):
+                    for a in range(11):
+                        for b in range(11):
+                            ii, jj = i + a - 5, j + b - 5
+                            if 0 <= ii < H and 0 <= jj < W:
+                                ref[c, i, j] += w[a] * w[b] * img[c, ii, jj]
+        assert np.allclose(got, ref, rtol=0, atol=1e-14), (H, W)
