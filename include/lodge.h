@@ -434,6 +434,23 @@ lodge_status lodge_l1_grad(int64_t n, const float* image, const float* target, f
 lodge_status lodge_adam(int64_t n, float* param, const float* grad, float* m, float* v, float lr, float beta1,
                         float beta2, float eps, int32_t step, void* stream);
 
+/* Bytes of device scratch lodge_dssim_grad needs for one image (ten maps of
+ * channels x height x width floats). */
+lodge_status lodge_dssim_scratch_size(int32_t width, int32_t height, int32_t channels, size_t* bytes);
+
+/* ASYNC.  The D-SSIM term of the construction loss (the paper's DSSIM + L1):
+ * SSIM of image and target ([channels][height][width], device) per channel
+ * with the 11 x 11 Gaussian window of sigma 1.5, C1 = 0.01^2, C2 = 0.03^2 and
+ * zero padding; grad (device, same shape) receives
+ *   grad += weight * d(1 - mean SSIM) / d image,
+ * and loss (device float, NULL to skip) += weight * (1 - mean SSIM) (one
+ * atomic per block).  Run lodge_l1_grad first with scale (1 - lambda) / n and
+ * this with weight lambda for the 3DGS loss (1 - lambda) L1 + lambda D-SSIM.
+ * scratch: device, lodge_dssim_scratch_size bytes, caller-owned. */
+lodge_status lodge_dssim_grad(int32_t width, int32_t height, int32_t channels, const float* image, const float* target,
+                              float weight, float* grad, float* loss, void* scratch, size_t scratch_bytes,
+                              void* stream);
+
 /* Bytes of device scratch lodge_keep_indices needs for n items (n < 2^32). */
 lodge_status lodge_keep_scratch_size(int64_t n, size_t* bytes);
 

@@ -16,6 +16,13 @@
 //                 compaction at the block's offset.
 //   k_gather      out[p][j] = in[p][idx[j]] for P planes (a level's
 //                 parameters and optimiser moments after pruning).
+//   k_ssim_rows / k_blur / k_ssim_map / k_ssim_grad
+//                 the D-SSIM term of the loss and its gradient: separable
+//                 window filtering of x, y, x^2, y^2, x y, the SSIM map and
+//                 g times its derivatives w.r.t. the filtered statistics,
+//                 the same filtering of those (the window is symmetric, so
+//                 it is its own adjoint), and the gradient
+//                 -(w * d_mu + 2 x (w * d_xx) + y (w * d_xy)).
 //
 // Built with -ffp-contract=off like the rest of the library.
 #include <algorithm>
@@ -159,6 +166,102 @@ __global__ __launch_bounds__(256) void k_gather(uint32_t planes, uint32_t n_in, 
     }
 }
 
+// ---- the D-SSIM term: SSIM (Wang et al.) with an 11 x 11 Gaussian window of
+// sigma 1.5, separable, zero padding outside the image ('same' size).
+constexpr int kWin = 11;
+constexpr float kC1 = 0.0001f;   // (0.01)^2
+constexpr float kC2 = 0.0009f;   // (0.03)^2
+struct Window {
+    float w[kWin];
+};
+
+// Horizontal pass over the five local-statistics inputs of each pixel:
+// x, y, x^2, y^2, x y (maps [5][C][H][W]).
+__global__ __launch_bounds__(256) void k_ssim_rows(uint32_t C, uint32_t H, uint32_t W, const float* __restrict__ x,
+                                                   const float* __restrict__ y, float* __restrict__ out, Window win)
+{
+    const uint64_t N = (uint64_t)C * H * W;
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t j = (uint32_t)(p % W);
+        float s[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < kWin; k++) {
+            const int jj = (int)j + k - kWin / 2;
+            if (jj < 0 || jj >= (int)W) continue;
+            const uint64_t q = p - j + (uint32_t)jj;
+            const float a = x[q], b = y[q], w = win.w[k];
+            s[0] += w * a;
+            s[1] += w * b;
+            s[2] += w * (a * a);
+            s[3] += w * (b * b);
+            s[4] += w * (a * b);
+        }
+#pragma unroll
+        for (int m = 0; m < 5; m++) out[(uint64_t)m * N + p] = s[m];
+    }
+}
+
+// Generic separable pass over P maps [P][C][H][W]: along rows (vertical = 0)
+// or along columns (vertical = 1).
+__global__ __launch_bounds__(256) void k_blur(uint32_t P, uint32_t C, uint32_t H, uint32_t W, int32_t vertical,
+                                              const float* __restrict__ in, float* __restrict__ out, Window win)
+{
+    const uint64_t N = (uint64_t)C * H * W;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (uint64_t)P * N;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t p = t % N;
+        const uint32_t j = (uint32_t)(p % W), i = (uint32_t)((p / W) % H);
+        const uint32_t pos = vertical ? i : j, len = vertical ? H : W;
+        const uint64_t step = vertical ? W : 1;
+        float s = 0.f;
+#pragma unroll
+        for (int k = 0; k < kWin; k++) {
+            const int q = (int)pos + k - kWin / 2;
+            if (q < 0 || q >= (int)len) continue;
+            s += win.w[k] * in[t - (uint64_t)pos * step + (uint64_t)q * step];
+        }
+        out[t] = s;
+    }
+}
+
+// Per pixel, from the filtered statistics (mu_x, mu_y, E_xx, E_yy, E_xy):
+// the SSIM value m and g times its derivatives w.r.t. mu_x, E_xx, E_xy.
+__global__ __launch_bounds__(256) void k_ssim_map(uint64_t N, const float* __restrict__ st, float g,
+                                                  float* __restrict__ d, float* __restrict__ loss, float weight)
+{
+    __shared__ float s_part[4];
+    float acc = 0.0f;
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (uint64_t)gridDim.x * blockDim.x) {
+        const float mx = st[p], my = st[N + p], exx = st[2 * N + p], eyy = st[3 * N + p], exy = st[4 * N + p];
+        const float a1 = 2.0f * mx * my + kC1;
+        const float a2 = 2.0f * (exy - mx * my) + kC2;
+        const float b1 = mx * mx + my * my + kC1;
+        const float b2 = (exx - mx * mx) + (eyy - my * my) + kC2;
+        const float den = b1 * b2;
+        const float m = (a1 * a2) / den;
+        d[p] = g * ((2.0f * my * a2 - 2.0f * my * a1) / den - m * (2.0f * mx) / b1 + m * (2.0f * mx) / b2);
+        d[N + p] = g * (-m / b2);
+        d[2 * N + p] = g * (2.0f * a1 / den);
+        acc += m;
+    }
+    if (!loss) return;
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    // weight (1 - mean m): block 0 also adds the constant term
+    if (threadIdx.x == 0)
+        atomicAdd(loss, (blockIdx.x == 0 ? weight : 0.0f) - weight * ((s_part[0] + s_part[1]) + (s_part[2] + s_part[3])) * g);
+}
+
+// grad += weight * -(w * d0 + 2 x (w * d1) + y (w * d2))  (bd: the filtered derivative maps)
+__global__ __launch_bounds__(256) void k_ssim_grad(uint64_t N, const float* __restrict__ x,
+                                                   const float* __restrict__ y, const float* __restrict__ bd,
+                                                   float weight, float* __restrict__ grad)
+{
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (uint64_t)gridDim.x * blockDim.x)
+        grad[p] = grad[p] - weight * ((bd[p] + 2.0f * x[p] * bd[N + p]) + y[p] * bd[2 * N + p]);
+}
+
 uint32_t grid_for(uint64_t n) { return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, (n + 255) / 256), 8192); }
 
 }  // namespace
@@ -236,6 +339,48 @@ lodge_status lodge_gather_planes(int32_t planes, int64_t n_in, int64_t n_out, co
         (uint32_t)planes, (uint32_t)n_in, (uint32_t)n_out, in, idx, count, out);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? LODGE_OK : hip_fail(e, "lodge_gather_planes");
+}
+
+lodge_status lodge_dssim_scratch_size(int32_t width, int32_t height, int32_t channels, size_t* bytes)
+{
+    if (width <= 0 || height <= 0 || channels <= 0 || !bytes) return fail(LODGE_ERR_INVALID_ARG, "dssim: bad size");
+    *bytes = 10 * sizeof(float) * (size_t)width * (size_t)height * (size_t)channels;
+    return LODGE_OK;
+}
+
+lodge_status lodge_dssim_grad(int32_t width, int32_t height, int32_t channels, const float* image, const float* target,
+                              float weight, float* grad, float* loss, void* scratch, size_t scratch_bytes,
+                              void* stream)
+{
+    size_t need = 0;
+    lodge_status s = lodge_dssim_scratch_size(width, height, channels, &need);
+    if (s != LODGE_OK) return s;
+    if (!image || !target || !grad || !scratch || scratch_bytes < need)
+        return fail(LODGE_ERR_INVALID_ARG, "dssim: NULL buffer or scratch too small");
+    if (!std::isfinite(weight)) return fail(LODGE_ERR_INVALID_ARG, "dssim: weight must be finite");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Window win;
+    {
+        double w[kWin], sum = 0.0;
+        for (int k = 0; k < kWin; k++) {
+            const double x = (double)(k - kWin / 2);
+            w[k] = std::exp(-(x * x) / (2.0 * 1.5 * 1.5));
+            sum += w[k];
+        }
+        for (int k = 0; k < kWin; k++) win.w[k] = (float)(w[k] / sum);
+    }
+    const uint32_t C = (uint32_t)channels, H = (uint32_t)height, W = (uint32_t)width;
+    const uint64_t N = (uint64_t)C * H * W;
+    float* a = static_cast<float*>(scratch);   // 5 maps
+    float* b = a + 5 * N;                      // 5 maps
+    k_ssim_rows<<<grid_for(N), 256, 0, st>>>(C, H, W, image, target, a, win);
+    k_blur<<<grid_for(5 * N), 256, 0, st>>>(5, C, H, W, 1, a, b, win);
+    k_ssim_map<<<grid_for(N), 256, 0, st>>>(N, b, (float)(1.0 / (double)N), a, loss, weight);
+    k_blur<<<grid_for(3 * N), 256, 0, st>>>(3, C, H, W, 0, a, b, win);
+    k_blur<<<grid_for(3 * N), 256, 0, st>>>(3, C, H, W, 1, b, a, win);
+    k_ssim_grad<<<grid_for(N), 256, 0, st>>>(N, image, target, a, weight, grad);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LODGE_OK : hip_fail(e, "lodge_dssim_grad");
 }
 
 }  // extern "C"

@@ -17,8 +17,9 @@ the L1 loss gradient, the adjoint restricted to level l, the activation's
 adjoint, Adam, importance scores, and the compaction after pruning.  This
 module holds the host loop and the parameter buffers (torch tensors).
 
-Readings (the paper is silent on them): the loss is the L1 term of the
-paper's DSSIM + L1; importance scores for pruning come from LOD renders of
+Readings (the paper is silent on them): the loss is 3DGS's
+(1 - lambda) L1 + lambda D-SSIM with lambda = 0.2 (the paper's "DSSIM + L1");
+importance scores for pruning come from LOD renders of
 levels 0..l at the nominal switch distances over the training views; Adam
 (beta 0.9 / 0.999, eps 1e-15) uses the 3DGS learning rates per parameter
 group and its moments follow the kept Gaussians through a pruning; the
@@ -110,7 +111,7 @@ class LodBuilder:
     """Renders, losses and updates for building level l on top of levels 0..l-1."""
 
     def __init__(self, levels: List[LevelState], d: Sequence[float], cams: Sequence, targets, max_active=None,
-                 max_instances=None):
+                 max_instances=None, lambda_dssim: float = 0.2):
         torch = L._torch()
         self.levels = levels
         self.d = [float(x) for x in d]
@@ -125,6 +126,8 @@ class LodBuilder:
         self.dL = torch.empty((3, H, W), dtype=torch.float32, device="cuda")
         self.loss = torch.zeros(1, dtype=torch.float32, device="cuda")
         self.step = {}
+        self.lam = float(lambda_dssim)
+        self.ssim_scratch = None
 
     def _renderer(self, scene: L.Scene) -> L.Renderer:
         if self.R is None or self.R.scene.total < scene.total:
@@ -144,7 +147,8 @@ class LodBuilder:
 
     def finetune_step(self, l: int, view: int, d_factor: float):
         """One fine-tuning step of level l: d_l scaled by d_factor (a draw from U(0.7, 1.3)), the given
-        training view, mean L1 loss, gradients of level l only, one Adam step per parameter group."""
+        training view, loss (1 - lambda) mean L1 + lambda D-SSIM, gradients of level l only, one Adam step
+        per parameter group."""
         import numpy as np
         torch = L._torch()
         lv = self.levels[l]
@@ -154,7 +158,10 @@ class LodBuilder:
         sc, R = self.render(l, d, cam)
         n_px = 3 * self.W * self.H
         self.loss.zero_()
-        L.lodge_l1_grad(R.image, self.targets[view], self.dL, 1.0 / n_px, self.loss)
+        L.lodge_l1_grad(R.image, self.targets[view], self.dL, (1.0 - self.lam) / n_px, self.loss)
+        if self.lam:
+            self.ssim_scratch = L.lodge_dssim_grad(R.image, self.targets[view], self.dL, self.lam, self.loss,
+                                                   self.ssim_scratch)
         g = {"mean": torch.zeros((3, lv.n), dtype=torch.float32, device="cuda"),
              "scale": torch.zeros((3, lv.n), dtype=torch.float32, device="cuda"),
              "quat": torch.zeros((4, lv.n), dtype=torch.float32, device="cuda"),
@@ -218,11 +225,12 @@ class LodBuilder:
 
 
 def build_levels(base: LevelState, d: Sequence[float], filter_vars: Sequence[float], cams, targets, gamma: float,
-                 schedule, steps_per_round: int, rounds=(0.2, 0.6, 1.0), max_instances=None) -> LodBuilder:
+                 schedule, steps_per_round: int, rounds=(0.2, 0.6, 1.0), max_instances=None,
+                 lambda_dssim: float = 0.2) -> LodBuilder:
     """Builds levels 1..len(d) on top of base (level 0).  schedule[l-1][r] is the list of (view, d factor)
     draws of round r of level l (steps_per_round of them)."""
     levels = [base]
-    B = LodBuilder(levels, d, cams, targets, max_instances=max_instances)
+    B = LodBuilder(levels, d, cams, targets, max_instances=max_instances, lambda_dssim=lambda_dssim)
     for l in range(1, len(d) + 1):
         levels.append(copy_with_filter(base, filter_vars[l - 1]))
         for r, frac in enumerate(rounds):

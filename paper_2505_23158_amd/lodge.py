@@ -131,6 +131,9 @@ def lib():
             "lodge_adam": (st, [C.c_int64, vp, vp, vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32,
                                 vp]),
             "lodge_keep_scratch_size": (st, [C.c_int64, C.POINTER(C.c_size_t)]),
+            "lodge_dssim_scratch_size": (st, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+            "lodge_dssim_grad": (st, [C.c_int32, C.c_int32, C.c_int32, vp, vp, C.c_float, vp, vp, vp, C.c_size_t,
+                                      vp]),
             "lodge_keep_indices": (st, [C.c_int64, vp, C.c_float, vp, vp, vp, C.c_size_t, vp]),
             "lodge_gather_planes": (st, [C.c_int32, C.c_int64, C.c_int64, vp, vp, vp, vp, vp]),
             "lodge_activate": (st, [C.c_int64, vp, vp, vp, vp, vp, vp, vp]),
@@ -155,7 +158,7 @@ EXPORTED = ["lodge_status_string", "lodge_last_error", "lodge_version", "lodge_s
             "lodge_check", "lodge_debug_views", "lodge_render_backward", "lodge_activate", "lodge_activate_backward",
             "lodge_render_static", "lodge_select_chunk", "lodge_importance", "lodge_chunk_sets_prune",
             "lodge_l1_grad", "lodge_adam", "lodge_keep_scratch_size", "lodge_keep_indices", "lodge_gather_planes",
-            "lodge_pack_size", "lodge_scene_pack"]
+            "lodge_pack_size", "lodge_scene_pack", "lodge_dssim_scratch_size", "lodge_dssim_grad"]
 STATIC_SCRATCH_BYTES = 256 << 20
 
 
@@ -349,12 +352,16 @@ def lodge_select_chunk(scene: Scene, sets: Optional[ChunkSets], k: int, ws: Work
 
 
 def lodge_importance(scene: Scene, sel: Selection, cam, ws: Workspace, score, s2d: float = 0.3,
-                     compensate: bool = True, stream=None):
-    """score: float32 CUDA tensor of scene.total elements, max-accumulated by global id."""
+                     compensate: bool = True, stream=None, stage_events=None):
+    """score: float32 CUDA tensor of scene.total elements, max-accumulated by global id.
+    stage_events: None or STAGE_EVENTS torch.cuda.Event objects (the last two bracket the importance walk)."""
     if score.numel() != scene.total or score.dtype != _torch().float32 or not score.is_contiguous():
         raise ValueError("score must be a contiguous float32 tensor of scene.total elements")
     cp, keep = _cam_arg(cam)
-    opts = lodge_render_opts(s2d=s2d, compensate=int(compensate))
+    evs = None
+    if stage_events is not None:
+        evs = (C.c_void_p * STAGE_EVENTS)(*[e.cuda_event for e in stage_events])
+    opts = lodge_render_opts(s2d=s2d, compensate=int(compensate), stage_events=C.cast(evs, C.c_void_p) if evs else None)
     _check(lib().lodge_importance(scene.handle, C.byref(sel.desc), cp, C.byref(opts), C.byref(ws.desc),
                                   _ptr(score), _stream_ptr(stream)))
 
@@ -459,6 +466,20 @@ def lodge_adam(param, grad, m, v, lr: float, step: int, beta1: float = 0.9, beta
         raise ValueError("param, grad, m and v must have the same size")
     _check(lib().lodge_adam(n, _ptr(param), _ptr(grad), _ptr(m), _ptr(v), float(lr), float(beta1), float(beta2),
                             float(eps), int(step), _stream_ptr(stream)))
+
+
+def lodge_dssim_grad(image, target, grad, weight: float, loss=None, scratch=None, stream=None):
+    """image, target, grad: [C, H, W] float32 CUDA tensors; grad += weight * d(1 - mean SSIM)/d image.
+    Returns the scratch tensor used (pass it back to reuse it)."""
+    torch = _torch()
+    Cc, H, W = image.shape
+    nb = C.c_size_t()
+    _check(lib().lodge_dssim_scratch_size(int(W), int(H), int(Cc), C.byref(nb)))
+    if scratch is None or scratch.numel() * scratch.element_size() < nb.value:
+        scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=image.device)
+    _check(lib().lodge_dssim_grad(int(W), int(H), int(Cc), _ptr(image), _ptr(target), float(weight), _ptr(grad),
+                                  _ptr(loss), _ptr(scratch), C.c_size_t(scratch.numel()), _stream_ptr(stream)))
+    return scratch
 
 
 def lodge_keep_indices(score, threshold: float, idx, count, scratch=None, stream=None):

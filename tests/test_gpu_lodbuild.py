@@ -81,6 +81,27 @@ def test_l1_grad_kernel(L):
     assert float(loss.item()) == pytest.approx(l_o, rel=1e-5)
 
 
+@pytest.mark.parametrize("W,H", [(48, 32), (37, 23), (5, 3)])
+def test_dssim_kernel(L, W, H):
+    """lodge_dssim_grad against the oracle's SSIM map and adjoint: loss and gradient within FP32 rounding
+    of the float64 definition, added onto what grad already holds."""
+    import torch
+    rng = np.random.default_rng(74 + W)
+    x = rng.random((3, H, W)).astype(np.float32)
+    y = rng.random((3, H, W)).astype(np.float32)
+    base = (1e-3 * rng.normal(size=(3, H, W))).astype(np.float32)   # small: its FP32 rounding stays below 1e-10
+    tx, ty = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    grad = torch.from_numpy(base.copy()).cuda()
+    loss = torch.full((1,), 0.5, device="cuda")
+    L.lodge_dssim_grad(tx, ty, grad, 0.2, loss)
+    torch.cuda.synchronize()
+    l_o, g_o = oracle.dssim_grad(x, y)
+    assert float(loss.item()) == pytest.approx(0.5 + 0.2 * l_o, abs=2e-6)
+    got = grad.cpu().numpy().astype(np.float64) - base
+    ref = 0.2 * g_o
+    assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max() + 1e-9, np.abs(got - ref).max()
+
+
 @pytest.mark.parametrize("n", [0, 1, 4095, 4096, 4097, 100003])
 def test_keep_and_gather(L, n):
     import torch
@@ -142,11 +163,15 @@ def test_finetune_steps_vs_oracle(L, oracle64):
         torch.cuda.synchronize()
         dL = B.dL.cpu().numpy().astype(np.float64)
         loss, dL_o, g_o, img = oracle.finetune_grad(oracle64, pre, [3, 3], fv, d, 1, cams[view], targets[view], u,
-                                                    dL=dL)
-        # the GPU's sign decisions agree with the oracle's wherever the image is not within rounding of the
-        # target (where level 0 alone covers a pixel the GPU render equals its target exactly: sign 0)
+                                                    dL=dL, lam=B.lam)
+        # the GPU's dL/dimage ((1 - lambda) sign / n + lambda D-SSIM gradient) is the oracle's wherever the
+        # image is not within rounding of the target (where level 0 alone covers a pixel the GPU render
+        # equals its target exactly, and the L1 sign is 0)
+        _, dL_own, _, _ = oracle.finetune_grad(oracle64, pre, [3, 3], fv, d, 1, cams[view], targets[view], u,
+                                               lam=B.lam)
         far = np.abs(img - targets[view]) > 1e-5
-        assert np.mean((np.sign(dL) != np.sign(img - targets[view]))[far]) < 1e-3
+        dd = np.abs(dL - dL_own)[far]
+        assert np.mean(dd > 1e-3 * np.abs(dL_own).max()) < 1e-3
         row = 0
         for k, p in (("mean", 3), ("log_scale", 3), ("quat_raw", 4), ("opacity_logit", 1), ("sh", 48)):
             ref = np.asarray(g_o[k], np.float64).reshape(p, -1)
