@@ -239,6 +239,145 @@ def diff_section(n=1_000_000, views=8, width=1280, height=720, steps=3):
             "ms_per_step": round(ms, 3), "views_per_s": round(views * 1000.0 / ms, 2)}
 
 
+def visibility_section(dev, sc, chunk=27, n_pos=4, n_orient=3, width=1920, height=1080, threshold=0.02):
+    """Per-chunk visibility filtering of one chunk of the benchmark scene: its stored set rendered from
+    n_pos x n_orient views (positions about the chunk centre, random orientations), the importance walk
+    timed per view with events, then the pruning.  The compositing work of the same views (significant
+    pairs of an ordinary render) prices the walk against the VALU roofline."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2505_23158_amd import lodge as L
+    views = synth.chunk_views(sc.chunks, chunk, n_pos, n_orient, width, height)
+    sets = L.ChunkSets(dev)
+    R = L.Renderer(dev, width, height, max_active=8_000_000, max_instances=32_000_000)
+    score = torch.zeros(dev.total, dtype=torch.float32, device="cuda")
+    L.lodge_select_chunk(dev, sets, chunk, R.ws, R.sel)
+    torch.cuda.synchronize()
+    members = int(R.sel.count.item())
+    sig = 0.0
+    for cam in views:      # significant pairs of the same frames (an ordinary render of the chunk's set)
+        L.lodge_render(dev, R.sel, cam, R.ws, R.image, R.final_T, R.n_contrib)
+        info = R.info()
+        if L.lodge_check(R.ws)[0] != L.LODGE_OK:
+            raise SystemExit("visibility: workspace too small")
+        sig += info["pairs_blended"] + info["pixels_stopped"]
+    for cam in views[:2]:
+        L.lodge_importance(dev, R.sel, cam, R.ws, score)
+    score.zero_()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(views) + 1)]
+    stg = [[torch.cuda.Event(enable_timing=True) for _ in range(L.STAGE_EVENTS)] for _ in views]
+    for row in stg:            # torch creates the HIP event at its first record
+        for e in row:
+            e.record()
+    torch.cuda.synchronize()
+    ev[0].record()
+    for i, cam in enumerate(views):
+        L.lodge_importance(dev, R.sel, cam, R.ws, score, stage_events=stg[i])
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(len(views))]
+    walk_ms = [stg[i][3].elapsed_time(stg[i][4]) for i in range(len(views))]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    L.lodge_chunk_sets_prune(dev, sets, chunk, score, threshold)
+    e1.record()
+    L.lodge_select_chunk(dev, sets, chunk, R.ws, R.sel)
+    torch.cuda.synchronize()
+    kept = int(R.sel.count.item())
+    ops = OPS_PER_SIGNIFICANT_PAIR * sig
+    achieved = ops / (sum(walk_ms) * 1e-3) / 1e12
+    return {"workload": f"chunk {chunk} of the lod4 scene: its stored set, {len(views)} views {width}x{height}",
+            "members": members, "kept_at_threshold": kept, "threshold": threshold,
+            "ms_per_view": round(float(np.mean(ms)), 4), "views_per_s": round(1000.0 * len(ms) / sum(ms), 1),
+            "walk_ms_per_view": round(float(np.mean(walk_ms)), 4),
+            "prune_ms": round(e0.elapsed_time(e1), 4),
+            "roofline": {"kernel": "k_composite<true> (the importance walk)", "bound": "alu",
+                         "achieved": round(achieved, 2), "peak": VALU_PEAK_TOPS, "unit": "TVALU-op/s",
+                         "frac": round(achieved / VALU_PEAK_TOPS, 4)}}
+
+
+def thresholds_section(n_views=8, width=1920, height=1080):
+    """Greedy depth-threshold search on the lod3 scene (2M/500k/125k): every candidate set of thresholds
+    is a GPU LOD frame per view; also the two-threshold cost table (the analog of the paper's cost map)."""
+    import torch
+
+    import synth
+    from paper_2505_23158_amd import lodge as L
+    from paper_2505_23158_amd import thresholds as TH
+    sc = synth.config2_scene()
+    dev = L.Scene.from_synth(sc)
+    cams = synth.threshold_views(n_views, half_xy=100.0, width=width, height=height, seed=46)
+    ev = TH.CostEvaluator(dev, cams, max_instances=32_000_000)
+    cands = [5.0, 10.0, 15.0, 20.0, 30.0, 40.0, 60.0, 80.0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chosen, curves = TH.greedy_search(ev, cands, 3)
+    torch.cuda.synchronize()
+    t_search = time.perf_counter() - t0
+    n_eval = len(ev.cache)
+    grid = [10.0, 20.0, 40.0, 60.0, 80.0]
+    table = TH.cost_table(ev, grid, grid)
+    return {"workload": f"lod3 scene, {n_views} views {width}x{height}, candidates {cands}",
+            "chosen_m": chosen, "search_s": round(t_search, 3), "threshold_sets_evaluated": n_eval,
+            "frames_per_s": round(n_eval * n_views / t_search, 1),
+            "greedy_curves": [[(c, round(v, 2)) for c, v in cv] for cv in curves],
+            "cost_table": {"d1": grid, "d2": grid,
+                           "mean_gaussians_per_tile": [[None if v is None else round(v, 2) for v in row]
+                                                       for row in table]},
+            "as_given_cost": round(ev.cost(tuple(sc.d)), 2)}
+
+
+def lodbuild_section(n=1_000_000, width=1280, height=720, views=8, steps=20, d=(15.0,)):
+    """Construction of one coarser level over a 1M-Gaussian G^(0): one pruning (importance over the
+    training views) and fine-tuning steps (LOD render of levels 0..1 with d_1 scaled by the step's draw,
+    mean L1, adjoint of level 1 only, Adam), timed."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2505_23158_amd import lodge as L
+    from paper_2505_23158_amd import lodbuild as LB
+    sc = synth.diff_scene(n=n, n_views=views, width=width, height=height)
+    lv = sc.levels[0]
+    t = {"mean": lv.mean, "log_scale": lv.raw["log_scale"], "quat_raw": lv.raw["quat"],
+         "opacity_logit": lv.raw["opacity_logit"], "sh": lv.sh.reshape(-1, n)}
+    t = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in t.items()}
+    base = LB.level_from_raw(t["mean"], t["log_scale"], t["quat_raw"], t["opacity_logit"], t["sh"], 3, 0.0)
+    sc0 = L.Scene([base.scene_level()], [], None)
+    R0 = L.Renderer(sc0, width, height, max_active=n, max_instances=24_000_000)
+    targets = torch.empty((views, 3, height, width), device="cuda")
+    for v, cam in enumerate(sc.cameras):
+        R0.frame(cam, L.SELECT_ALL)
+        targets[v].copy_(R0.image)
+    del R0, sc0
+    B = LB.LodBuilder([base], d, sc.cameras, targets, max_active=2 * n, max_instances=48_000_000)
+    B.levels.append(LB.copy_with_filter(base, synth.filter_var(d[0])))
+    rng = np.random.default_rng(9)
+    draws = [(int(rng.integers(0, views)), float(rng.uniform(0.7, 1.3))) for _ in range(steps + 2)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.prune(1, 0.2 * 0.02)
+    torch.cuda.synchronize()
+    t_prune = time.perf_counter() - t0
+    kept = B.levels[1].n
+    for view, u in draws[:2]:
+        B.finetune_step(1, view, u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for view, u in draws[2:]:
+        B.finetune_step(1, view, u)
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / steps
+    st, na, ni = L.lodge_check(B.R.ws)
+    if st != L.LODGE_OK:
+        raise SystemExit(f"lodbuild: workspace too small ({na} active, {ni} instances)")
+    return {"workload": f"G^(0) of {n} Gaussians, level 1 at d_1 = {d[0]} m, {views} views {width}x{height}",
+            "prune_s": round(t_prune, 3), "kept_after_prune": kept, "ms_per_finetune_step": round(ms, 3),
+            "finetune_steps_per_s": round(1000.0 / ms, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,6 +394,13 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--no-paper-protocol", action="store_true", help="skip the median-of-7 pass")
+    ap.add_argument("--pack", action="store_true",
+                    help="render from the packed copy of the levels (lodge_scene_pack) instead of the parameter "
+                         "planes; it pays off when the storage order has no spatial locality (--permute)")
+    ap.add_argument("--permute", action="store_true",
+                    help="store every level in a seeded random order instead of the generator's Morton order")
+    ap.add_argument("--no-lod-build", action="store_true",
+                    help="skip the visibility-filtering, threshold-search and level-construction sections")
     ap.add_argument("--in-flight", type=int, default=3,
                     help="frames in flight for the throughput pass: one renderer (workspace, outputs) and one "
                          "stream each, frames handed out round robin")
@@ -279,7 +425,23 @@ def main():
     sc, desc, mode, (max_active, max_inst) = workload(args.workload, args.frames)
     cams = sc.cameras
     log(f"[bench] {desc['workload']}: generated in {time.perf_counter() - t0:.1f} s")
+    if args.permute:
+        import synth
+        rng = np.random.default_rng(12345)
+        sc.levels = [synth.permuted(lv, rng.permutation(lv.n)) for lv in sc.levels]
+        desc["storage_order"] = "seeded random permutation of every level"
     dev = L.Scene.from_synth(sc)
+    pack = None
+    if args.pack:
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        nbytes = dev.pack()
+        e1.record()
+        torch.cuda.synchronize()
+        pack = {"bytes": nbytes, "pack_ms": round(e0.elapsed_time(e1), 3)}
+        log(f"[bench] packed copy of the levels: {nbytes / 1e9:.2f} GB in {pack['pack_ms']:.1f} ms")
+    desc["projection_reads"] = "packed copy (lodge_scene_pack)" if pack else "parameter planes"
     R = L.Renderer(dev, cams[0].width, cams[0].height, max_active=max_active, max_instances=max_inst)
     F = max(1, args.in_flight)
     # frames in flight: renderer 0 is R; each has its own stream at the default priority
@@ -455,6 +617,19 @@ def main():
         diff = diff_section()
         log(f"[bench] differentiation {diff}")
 
+    visibility = thresholds = lodbuild = None
+    if not args.no_lod_build and args.workload == "large":
+        log("[bench] visibility filtering of one chunk")
+        visibility = visibility_section(dev, sc)
+        log(f"[bench] visibility {visibility}")
+    if not args.no_lod_build:
+        log("[bench] depth-threshold search")
+        thresholds = thresholds_section()
+        log(f"[bench] thresholds {thresholds}")
+        log("[bench] level construction")
+        lodbuild = lodbuild_section()
+        log(f"[bench] lodbuild {lodbuild}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host")
@@ -483,9 +658,13 @@ def main():
         "per_frame": {k: round(v, 1) for k, v in mean.items()},
         "stages": stages,
         "roofline": roofline,
+        "scene_pack": pack,
         "serving": serving,
         "differentiation": diff,
         "chunk_sets": chunk_sets,
+        "visibility_filtering": visibility,
+        "threshold_search": thresholds,
+        "level_construction": lodbuild,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -43,9 +43,11 @@ __device__ __forceinline__ float splat_alpha(const float4& geo, const float4& co
 }
 
 // The same decision as splat_alpha without branches: alpha (clamped at
-// kAlphaMax) and whether the pair counts; exp is evaluated either way.
-// amin is kAlphaMin, or +inf for a pixel that takes no more splats (every
-// finite alpha is then below it).
+// kAlphaMax) and whether the pair counts; exp is evaluated either way, so
+// the power threshold is not tested: a power below it gives
+// o exp(power) < e^-0.001 / 255, far enough below 1/255 for any rounding of
+// exp, and the alpha test rejects the pair.  amin is kAlphaMin, or +inf for
+// a pixel that takes no more splats (every finite alpha is then below it).
 __device__ __forceinline__ bool splat_keep(const float4& geo, const float4& col, float px, float py, float amin,
                                            float& alpha)
 {
@@ -53,7 +55,7 @@ __device__ __forceinline__ bool splat_keep(const float4& geo, const float4& col,
     const float power = splat_power(geo, col, px, py, dx, dy);
     const float og = col.y * __expf(power);
     alpha = fminf(og, kAlphaMax);
-    return !(power > 0.0f || power < col.z) && !(alpha < amin);
+    return !(power > 0.0f) && !(alpha < amin);
 }
 
 // Culling of a splat against a box of pixel centres, shared by the
