@@ -5,8 +5,15 @@ Workload (default, "large"): the 4-level 20M/5M/1.25M/300k-Gaussian scene on
 1 x 1 km with an 8 x 8 chunk grid and 15 m blend bands, rendered at
 1920 x 1080 along its 300-frame circular camera path, re-selecting the two
 nearest chunks and the active set every frame.  One step = one frame =
-lodge_select + lodge_render (chunk pair, selection, projection, binning,
+selection + lodge_render (chunk pair, selection, projection, binning,
 per-tile sort, compositing), inputs resident in HBM.  Prints ONE JSON line.
+
+The selection of "value" is the paper's runtime form: every chunk's active
+set is stored once (lodge_chunk_sets_build, at scene load), and each frame
+picks the two nearest chunks and reads their sets with the Eq. 4 weights
+(lodge_select_chunk_sets).  "per_frame_selection" times the same frames with
+the active set re-derived from every Gaussian's mean (lodge_select): the
+same ids, weights and images; "stages" and "roofline" come from that pass.
 
     python bench.py [--steps K] [--warmup W] [--workload large|lod|plain]
 
@@ -531,6 +538,27 @@ def main():
     log(f"[bench] {K} frames one after another in {el_serial:.3f} s -> {fps_serial:.1f} frames/s; stage ms " +
         ", ".join(f"{k}={v:.3f}" for k, v in stage_ms.items()))
 
+    # the paper's storage form: per-chunk active sets stored once (a scene-load step, untimed); a frame
+    # picks the two nearest chunks and reads their sets (the same ids and weights as the per-frame selection)
+    chunk_sets = None
+    sets = None
+    if mode == L.SELECT_CHUNKED:
+        sets = L.ChunkSets(dev)
+        for k in range(max(args.warmup, F)):
+            rens[k % F].frame(cams[frames[k % K]], mode, stream=streams[k % F], sets=sets)
+        torch.cuda.synchronize()
+        el_f, el_f_runs = repeated(throughput,
+                                   lambda cam, r, st: L.lodge_select_chunk_sets(dev, sets, cam, r.ws, r.sel, st))
+        el2, st2, fm2 = repeated(timed, lambda cam: L.lodge_select_chunk_sets(dev, sets, cam, R.ws, R.sel))
+        sets_bytes = 0.25 * sc.n_total + 8.0 * mean["n_selected"]   # two 16-bit words per 16 Gaussians + ids, w
+        chunk_sets = {"frames_per_s": round(K / el_f, 2), "ms_per_step": round(1000.0 * el_f / K, 4),
+                      "frames_in_flight": F, "repeats_s": el_f_runs,
+                      "serial": {"frames_per_s": round(K / el2, 2), "ms_per_step": round(1000.0 * el2 / K, 4)},
+                      "frame_ms_events": round(fm2, 4), "stage_ms": {k: round(v, 4) for k, v in st2.items()},
+                      "select_bytes": sets_bytes, "sets_bytes_resident": sets.bytes,
+                      "select_achieved_GBs": round(sets_bytes / (st2["select"] * 1e-3) / 1e9, 2)}
+        log(f"[bench] chunk sets: {chunk_sets}")
+
     # the paper's protocol: per frame the median of 7 timings, FPS = 1 / mean
     per = []
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -538,31 +566,13 @@ def main():
         ts = []
         for _ in range(7):
             e0.record()
-            R.frame(cams[k], mode)
+            R.frame(cams[k], mode, sets=sets)
             e1.record()
             e1.synchronize()
             ts.append(e0.elapsed_time(e1))
         per.append(statistics.median(ts))
     paper_fps = 1000.0 / float(np.mean(per)) if per else None
-
-    # the paper's storage form: per-chunk active sets stored once, a frame reads the two chunks' sets
-    chunk_sets = None
-    if mode == L.SELECT_CHUNKED:
-        sets = L.ChunkSets(dev)
-        for k in range(max(args.warmup, F)):
-            rens[k % F].frame(cams[frames[k % K]], mode, stream=streams[k % F], sets=sets)
-        torch.cuda.synchronize()
-        el_f, _ = repeated(throughput, lambda cam, r, st: L.lodge_select_chunk_sets(dev, sets, cam, r.ws, r.sel, st))
-        el2, st2, fm2 = repeated(timed, lambda cam: L.lodge_select_chunk_sets(dev, sets, cam, R.ws, R.sel))
-        sets_bytes = 0.25 * sc.n_total + 8.0 * mean["n_selected"]   # two 16-bit words per 16 Gaussians + ids, w
-        chunk_sets = {"frames_per_s": round(K / el_f, 2), "ms_per_step": round(1000.0 * el_f / K, 4),
-                      "frames_in_flight": F,
-                      "serial": {"frames_per_s": round(K / el2, 2), "ms_per_step": round(1000.0 * el2 / K, 4)},
-                      "frame_ms_events": round(fm2, 4), "stage_ms": {k: round(v, 4) for k, v in st2.items()},
-                      "select_bytes": sets_bytes, "sets_bytes_resident": sets.bytes,
-                      "select_achieved_GBs": round(sets_bytes / (st2["select"] * 1e-3) / 1e9, 2)}
-        log(f"[bench] chunk sets: {chunk_sets}")
-        del sets
+    del sets
 
     # roofline terms (algorithmic bytes / ops per launch, divided by live event durations)
     N = sc.n_total
@@ -636,24 +646,38 @@ def main():
         mo = {L.SELECT_ALL: oracle.ALL, L.SELECT_LOD_CAMERA: oracle.LOD_CAMERA, L.SELECT_CHUNKED: oracle.CHUNKED}[mode]
         cpu = cpu_baseline(sc, cams, mo, args.cpu_frames, args.cpu_reps, args.cpu_single_frames)
 
+    # value: the paper's runtime form (stored chunk sets) when the workload is chunked
+    if chunk_sets is not None:
+        v_fps, v_ms, v_runs = chunk_sets["frames_per_s"], chunk_sets["ms_per_step"], chunk_sets["repeats_s"]
+        v_serial = dict(chunk_sets["serial"], frame_ms_events=chunk_sets["frame_ms_events"])
+        desc["selection"] = "stored per-chunk active sets, two nearest chunks every frame (lodge_select_chunk_sets)"
+    else:
+        v_fps, v_ms, v_runs = round(fps, 2), round(1000.0 * elapsed / K, 4), elapsed_runs
+        v_serial = {"frames_per_s": round(fps_serial, 2), "ms_per_step": round(1000.0 * el_serial / K, 4),
+                    "frame_ms_events": round(frame_ms_events, 4)}
     out = {
         "metric": "frames/s and Gaussians composited/s at 1080p; serving p50/p99 latency",
-        "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
-        "ms_per_step": round(1000.0 * elapsed / K, 4), "higher_is_better": True, "scaling": "weak",
+        "value": v_fps, "unit": "frames/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": v_ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded generator, no trained weights)",
         "config": desc,
-        "gaussians_composited_per_s": round(mean["pairs_evaluated"] * fps, 1),
-        "gaussians_blended_per_s": round(mean["pairs_blended"] * fps, 1),
+        "gaussians_composited_per_s": round(mean["pairs_evaluated"] * v_fps, 1),
+        "gaussians_blended_per_s": round(mean["pairs_blended"] * v_fps, 1),
         "frames_in_flight": F,
         "timed_frames": frames,
-        "repeats_s": elapsed_runs,
-        "serial": {"frames_per_s": round(fps_serial, 2), "ms_per_step": round(1000.0 * el_serial / K, 4),
-                   "frame_ms_events": round(frame_ms_events, 4)},
+        "repeats_s": v_runs,
+        "serial": v_serial,
+        "per_frame_selection": {
+            "note": "the same frames with the active set re-derived from the Gaussians' means every frame "
+                    "(lodge_select); identical ids, weights and images; `stages` and `roofline` come from this pass",
+            "frames_per_s": round(fps, 2), "ms_per_step": round(1000.0 * elapsed / K, 4), "repeats_s": elapsed_runs,
+            "serial": {"frames_per_s": round(fps_serial, 2), "ms_per_step": round(1000.0 * el_serial / K, 4),
+                       "frame_ms_events": round(frame_ms_events, 4)}},
         "paper_protocol_fps": round(paper_fps, 2) if paper_fps else None,
         "paper_comparable": {
             "note": "the paper's FPS times one image at a time (FPS = 1 / mean render time, median of 7 per "
                     "image); `value` overlaps consecutive frames and is not comparable with it",
-            "fps_one_frame_at_a_time": round(fps_serial, 2),
+            "fps_one_frame_at_a_time": v_serial["frames_per_s"],
             "fps_paper_protocol": round(paper_fps, 2) if paper_fps else None},
         "per_frame": {k: round(v, 1) for k, v in mean.items()},
         "stages": stages,
