@@ -281,6 +281,23 @@ class Oracle:
                                 _p(binned.ranges), _p(val), _p(ids), _p(score), _p(amb))
         return score, amb
 
+    def pixel_weights(self, proj: Projection, binned: Binned, cam, x: int, y: int):
+        """Blending weights of pixel (x, y): (active indices, alpha T, list positions) of its blended entries
+        in blend order, and the list position of its first near-threshold decision."""
+        cap = max(1, int(binned.M))
+        act = np.empty(cap, np.uint32)
+        wt = np.empty(cap, self.dt)
+        pos = np.empty(cap, np.int64)
+        near = C.c_int64()
+        c = self.camera(cam)
+        val = binned.val if binned.M else np.zeros(1, np.uint32)
+        fn = self.lib.orc_pixel_weights
+        fn.restype = C.c_int64
+        m = fn(C.byref(c), _p(proj.uv), _p(proj.conic), _p(proj.o_eff), _p(proj.rgb), _p(binned.ranges), _p(val),
+               C.c_int32(x), C.c_int32(y), _p(act), _p(wt), _p(pos), C.c_int64(cap), C.byref(near))
+        assert m >= 0
+        return act[:m].copy(), wt[:m].copy(), pos[:m].copy(), int(near.value)
+
     def sh_basis(self, x, y, z):
         Y = np.empty(16, self.dt)
         self.lib.orc_sh_basis(self.real(x), self.real(y), self.real(z), _p(Y))
@@ -333,6 +350,13 @@ class Oracle:
             out["brute"] = self.composite_brute(proj, cam)
         self._keep.clear()
         return out
+
+    def view_lists(self, scene, ids, w, cam, s2d=0.3, compensate=True):
+        """project -> bin/sort for a given selection (ids, w) seen from cam."""
+        proj = self.project(scene, ids, w, cam, s2d, compensate)
+        binned = self.bin_sort(proj, cam)
+        self._keep.clear()
+        return proj, binned
 
     def view_importance(self, scene, ids, w, cam, score=None, amb=None, s2d=0.3, compensate=True):
         """project -> bin/sort -> importance for a given selection (ids, w) seen from cam."""

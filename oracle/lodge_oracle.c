@@ -836,6 +836,41 @@ void orc_importance(const orc_camera* cam, const real* uv, const real* conic, co
     free(pos); free(ta); free(tT); free(tc); free(tG);
 }
 
+/* The blending weights of one pixel (x, y) of the tiled lists: for each of
+ * its blended entries, in blend order, the active index and alpha T; at most
+ * cap of them are written; returns their number (-1 if cap is too small).
+ * *near_pos receives the list position of the pixel's first near-threshold
+ * decision (the list length if none).  Used to check importance scores of
+ * full-size frames at sampled pixels. */
+int64_t orc_pixel_weights(const orc_camera* cam, const real* uv, const real* conic, const real* o_eff, const real* rgb,
+                          const uint32_t* ranges, const uint32_t* vals, int32_t x, int32_t y, uint32_t* act,
+                          real* weight, int64_t* pos, int64_t cap, int64_t* near_pos)
+{
+    int32_t TX = (cam->width + TILE - 1) / TILE;
+    int32_t t = (y / TILE) * TX + (x / TILE);
+    const uint32_t* list = vals + ranges[2 * t];
+    int64_t len = (int64_t)ranges[2 * t + 1] - ranges[2 * t];
+    int64_t n = len > 0 ? len : 1;
+    int64_t* tp = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    real* ta = (real*)malloc(sizeof(real) * (size_t)n);
+    real* tT = (real*)malloc(sizeof(real) * (size_t)n);
+    int* tc = (int*)malloc(sizeof(int) * (size_t)n);
+    real* tG = (real*)malloc(sizeof(real) * (size_t)n);
+    pix_t S; memset(&S, 0, sizeof(S));
+    S.cap_trace = n; S.tr_pos = tp; S.tr_alpha = ta; S.tr_T = tT; S.tr_clamped = tc; S.tr_G = tG;
+    composite_pixel(list, len, (real)x + (real)0.5, (real)y + (real)0.5, uv, conic, o_eff, rgb, &S);
+    int64_t m = S.ntrace;
+    if (m <= cap)
+        for (int64_t j = 0; j < m; j++) {
+            act[j] = list[tp[j]];
+            weight[j] = ta[j] * tT[j];
+            pos[j] = tp[j];
+        }
+    *near_pos = S.first_near;
+    free(tp); free(ta); free(tT); free(tc); free(tG);
+    return m <= cap ? m : -1;
+}
+
 /* ------------------------------------------------------------------------ */
 /* adjoint (reverse mode by hand), used in the FP64 build                    */
 /* ------------------------------------------------------------------------ */

@@ -263,3 +263,51 @@ def test_build_levels_end_to_end(L):
     assert L.lodge_check(R.ws)[0] == L.LODGE_OK
     assert torch.isfinite(R.image).all()
     log(f"[lodbuild] built levels of {[lv.n for lv in B.levels]} Gaussians")
+
+
+def test_full_size_finetune_touches_only_rendered_level_l_gaussians(L):
+    """The construction workload the benchmark times (1M-Gaussian G^(0), level 1
+    at d_1 = 15 m, 1280x720): after a pruning round and two fine-tuning steps,
+    level 0 is unchanged bit for bit, every parameter is finite, and a level-1
+    Gaussian that neither step selected (nearer than that step's scaled d_1 to
+    its camera) keeps its parameters and zero Adam moments exactly."""
+    import torch
+    from paper_2505_23158_amd import lodbuild as LB
+    n, views, W, H, d = 1_000_000, 8, 1280, 720, (15.0,)
+    sc = synth.diff_scene(n=n, n_views=views, width=W, height=H)
+    lv = sc.levels[0]
+    t = {"mean": lv.mean, "log_scale": lv.raw["log_scale"], "quat_raw": lv.raw["quat"],
+         "opacity_logit": lv.raw["opacity_logit"], "sh": lv.sh.reshape(-1, n)}
+    t = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in t.items()}
+    base = LB.level_from_raw(t["mean"], t["log_scale"], t["quat_raw"], t["opacity_logit"], t["sh"], 3, 0.0)
+    sc0 = L.Scene([base.scene_level()], [], None)
+    R0 = L.Renderer(sc0, W, H, max_active=n, max_instances=24_000_000)
+    targets = torch.empty((views, 3, H, W), device="cuda")
+    for v, cam in enumerate(sc.cameras):
+        R0.frame(cam, L.SELECT_ALL)
+        targets[v].copy_(R0.image)
+    del R0, sc0
+    B = LB.LodBuilder([base], d, sc.cameras, targets, max_active=2 * n, max_instances=48_000_000)
+    B.levels.append(LB.copy_with_filter(base, synth.filter_var(d[0])))
+    lv0 = base.raw.clone()
+    B.prune(1, 0.2 * 0.02)
+    before = B.levels[1].raw.clone()
+    draws = [(2, 0.8), (5, 1.2)]
+    for view, u in draws:
+        B.finetune_step(1, view, u)
+    torch.cuda.synchronize()
+    assert L.lodge_check(B.R.ws)[0] == L.LODGE_OK
+    assert torch.equal(B.levels[0].raw, lv0)
+    raw = B.levels[1].raw
+    assert torch.isfinite(raw).all()
+    mean = before[0:3].cpu().numpy().astype(np.float64)
+    never = np.ones(B.levels[1].n, bool)
+    for view, u in draws:
+        pos = np.asarray(sc.cameras[view].pos, np.float64)
+        dd = float(np.float32(np.float32(d[0]) * np.float32(u)))
+        never &= np.linalg.norm(mean.T - pos, axis=1) < dd * (1 - 1e-5)
+    assert never.sum() > 0 and (~never).sum() > 0
+    idx = torch.from_numpy(np.flatnonzero(never)).cuda()
+    assert torch.equal(raw[:, idx], before[:, idx])
+    assert not B.levels[1].m[:, idx].any() and not B.levels[1].v[:, idx].any()
+    log(f"[lodbuild] full size: level 1 kept {B.levels[1].n} of {n}; {int(never.sum())} never selected, unchanged")

@@ -52,3 +52,19 @@ def test_greedy_search_and_cost_table_match_oracle(L, oracle32):
             else:
                 assert table[i][j] is None
     log(f"[thresholds] greedy choice {chosen}; {len(ev.cache)} threshold sets evaluated, all counts bit-exact")
+
+
+def test_full_size_instance_counts(L, oracle32):
+    """The lod3 scene at full size (2.625M Gaussians) and 1080p views: the tile
+    instances of LOD frames at two sets of switch distances, bit-exact against
+    the oracle (the integers the search compares)."""
+    from paper_2505_23158_amd import thresholds as TH
+    sc = synth.config2_scene()
+    cams = synth.threshold_views(2, half_xy=100.0, width=1920, height=1080, seed=47)
+    dev = L.Scene.from_synth(sc)
+    ev = TH.CostEvaluator(dev, cams, max_instances=32_000_000)
+    for d in ((20.0, 60.0), (10.0, 40.0)):
+        got = ev.instances(d)
+        ref = [oracle.lod_instances(oracle32, sc, d, 3, c) for c in cams]
+        assert got == ref, (d, got, ref)
+        log(f"[thresholds] full size d={d}: {got} instances per view")

@@ -1137,3 +1137,22 @@ def test_ssim_window_filter_by_brute_force_including_images_smaller_than_the_win
                             if 0 <= ii < H and 0 <= jj < W:
                                 ref[c, i, j] += w[a] * w[b] * img[c, ii, jj]
         assert np.allclose(got, ref, rtol=0, atol=1e-14), (H, W)
+
+
+def test_pixel_weights_sum_with_transmittance_to_one_and_bound_the_scores(oracle64, oracle32):
+    """A pixel's blending weights and its final transmittance sum to 1 (the
+    compositing identity); the importance score of every Gaussian is the
+    largest of its weights over the pixels."""
+    sc = synth.plain_scene(n=800, seed=27, width=40, height=24)
+    cam = sc.cameras[0]
+    for O, tol in ((oracle64, 1e-12), (oracle32, 2e-6)):
+        r = O.render(sc, cam, oracle.ALL)
+        best = np.zeros(sc.n_total)
+        for y in range(cam.height):
+            for x in range(cam.width):
+                act, wt, pos, near = O.pixel_weights(r["proj"], r["binned"], cam, x, y)
+                assert abs(float(np.sum(wt.astype(np.float64))) + float(r["final_T"][y, x]) - 1.0) <= tol
+                assert np.all(np.diff(pos) > 0)
+                np.maximum.at(best, r["ids"][act].astype(np.int64), wt.astype(np.float64))
+        score, _ = O.view_importance(sc, r["ids"], r["w"], cam)
+        assert np.array_equal(best.astype(O.dt), score)
