@@ -55,6 +55,16 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # 1-alpha, T(1-alpha), stop test, alpha*T, 3 colour FMAs = 25 lane-ops.  Pairs a bounding test can reject are not
 # counted: the compositor culls them per sub-quadrant, so they are not work the method has to do.
 OPS_PER_SIGNIFICANT_PAIR = 25
+# The adjoint's work per blended (pixel, splat) pair: alpha re-evaluated as above up to its test (18), then 1-alpha,
+# reciprocal (4 slots), T recovery, alpha*T, dC.c (3), dC/dalpha (2), the dC.S update, 3 colour gradients, the
+# opacity and exponent gradients (2), the conic gradient (6, the squares reused from the quadratic form) and the
+# mean gradient (6) = 30, and the nine gradients summed over the pixels (9): 57 lane-ops.
+ADJ_OPS_PER_BLENDED = 57
+# Projection adjoint bytes: the tile rect of every selected Gaussian (8); per visible one, reads of id, weight,
+# its 9 summed 2-D gradients, mean, scale, quaternion, opacity and 48 SH coefficients (280) and a read-add-write of
+# each gradient plane (mean 24, scale 24, quaternion 32, opacity 8, SH 384) = 752 at SH degree 3.
+ADJ_BYTES_PER_ACTIVE = 8
+ADJ_BYTES_PER_VISIBLE = 752
 CSRC = os.path.join(ROOT, "paper_2505_23158_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_lod4_1080p.txt")
 
@@ -241,9 +251,45 @@ def diff_section(n=1_000_000, views=8, width=1280, height=720, steps=3):
         step()
     torch.cuda.synchronize()
     ms = 1000.0 * (time.perf_counter() - t0) / steps
+
+    # the adjoint's two kernels timed live: each view rendered on its slot, then its backward with events
+    # around the compositing adjoint and the projection adjoint (grads into the renderer's own planes)
+    dr.activate()
+    comp_ms = proj_ms = 0.0
+    blended = visible = active = 0
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    for e in ev:            # torch creates the HIP event at its first record
+        e.record()
+    numel = 3 * width * height
+    for v, cam in enumerate(sc.cameras):
+        R = dr.slots[v]
+        R.frame(cam, L.SELECT_ALL)
+        info = R.info()
+        blended += info["pairs_blended"]
+        visible += info["n_visible"]
+        active += info["n_selected"]
+        dL = torch.sign(R.image - tgt[v]) / numel
+        dr._zero_grads()
+        L.lodge_render_backward(dr.scene, R.sel, cam, R.ws, R.final_T, R.n_contrib, dL, dr.g_act,
+                                stage_events=ev)
+        torch.cuda.synchronize()
+        comp_ms += ev[0].elapsed_time(ev[1])
+        proj_ms += ev[1].elapsed_time(ev[2])
+    comp_ops = ADJ_OPS_PER_BLENDED * blended
+    proj_bytes = ADJ_BYTES_PER_ACTIVE * active + ADJ_BYTES_PER_VISIBLE * visible
     return {"workload": f"1 level, {n} Gaussians, {views} views {width}x{height}, L1 loss, grads for mean, "
                         "log-scale, raw quaternion, opacity logit, SH",
-            "ms_per_step": round(ms, 3), "views_per_s": round(views * 1000.0 / ms, 2)}
+            "ms_per_step": round(ms, 3), "views_per_s": round(views * 1000.0 / ms, 2),
+            "per_view": {"composite_bwd_ms": round(comp_ms / views, 4), "project_bwd_ms": round(proj_ms / views, 4),
+                         "pairs_blended": blended // views, "n_visible": visible // views,
+                         "n_selected": active // views},
+            "roofline": {
+                "composite_bwd": {"bound": "alu", "achieved": round(comp_ops / (comp_ms * 1e-3) / 1e12, 3),
+                                  "peak": round(VALU_PEAK_TOPS, 2), "unit": "TVALU-op/s",
+                                  "frac": round(comp_ops / (comp_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4)},
+                "project_bwd": {"bound": "hbm", "achieved": round(proj_bytes / (proj_ms * 1e-3) / 1e9, 1),
+                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": round(proj_bytes / (proj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}}
 
 
 def visibility_section(dev, sc, chunk=27, n_pos=4, n_orient=3, width=1920, height=1080, threshold=0.02):

@@ -380,10 +380,13 @@ typedef struct {
  * gradients w.r.t. the activated parameters of every selected Gaussian
  * (grad_level >= 0: only Gaussians of that level, as the per-level
  * fine-tuning updates G_l alone).  Walks each pixel's list back to front
- * from n_contrib - 1, recovering the transmittance before each entry by
- * division T_k = T_{k+1} / (1 - alpha_k) from final_T instead of storing it.
+ * from n_contrib - 1, recovering the transmittance before each entry as
+ * T_k = T_{k+1} / (1 - alpha_k) from final_T instead of storing it (the
+ * division by the hardware reciprocal, within 1 ulp per entry).
  * ws must still hold the forward's intermediates (same scene, selection,
- * camera and options).  grads is an array of L entries.
+ * camera and options).  grads is an array of L entries.  opts->stage_events,
+ * when set, gets its first three events recorded on the stream: before the
+ * compositing adjoint, between it and the projection adjoint, and after.
  * Accumulation is a plain read-add-write per Gaussian (one thread owns each
  * selected Gaussian within a call), not an atomic: two calls that run at
  * the same time (different streams) into the same gradient planes race and

@@ -674,8 +674,8 @@ lodge_status lodge_render_backward(const lodge_scene* scene, const lodge_selecti
     // the forward's camera and options are still in ws; a given camera replaces it
     hipError_t e = hipSuccess;
     if (cam && (e = launch_set_camera(*cam, v, st)) != hipSuccess) return hip_fail(e, "lodge_render_backward: camera");
-    if ((e = launch_backward(scene->levels, *sel, v, final_T, n_contrib, dL_dimage, grad_level, grads, st)) !=
-        hipSuccess)
+    if ((e = launch_backward(scene->levels, *sel, v, final_T, n_contrib, dL_dimage, grad_level, grads, st,
+                             o.stage_events)) != hipSuccess)
         return hip_fail(e, "lodge_render_backward");
     return LODGE_OK;
 }

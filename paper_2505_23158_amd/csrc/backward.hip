@@ -13,9 +13,12 @@
 //                  T_k = T_{k+1} / (1 - alpha_k), rather than stored per pair.
 //                  With S_k the colour behind entry k (plus T_final * bg):
 //                    dC/dc_k = alpha_k T_k,  dC/dalpha_k = c_k T_k - S_k / (1 - alpha_k).
-//                  Per entry the quadrant's gradients are summed with a wave
-//                  reduction (only where some pixel contributed) and one
-//                  atomic add per wave.
+//                  The colour behind enters only through D = dC . S, so
+//                  dC/dalpha_k = T_k (dC . c_k) - D / (1 - alpha_k), one
+//                  reciprocal per pair.  Per entry the quadrant's nine
+//                  gradients are summed over the wave by a transposed
+//                  reduction (only where some pixel contributed) and added
+//                  with one atomic instruction of nine lanes.
 // k_project_bwd    one thread per visible active Gaussian: the chain rule from
 //                  (u, v, conic, o_eff, rgb) back through the 2-D filter, the
 //                  EWA covariance, the camera and the Eq. 3 filter to the
@@ -36,10 +39,64 @@ __global__ void k_bwd_setup(float* __restrict__ g2d, const uint32_t* __restrict_
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) g2d[i] = 0.0f;
 }
 
-__device__ __forceinline__ float wave_sum(float v)
+// Lane exchanges of the reduction below.  permlane32_swap / permlane16_swap
+// (gfx950) trade the upper half of the first operand with the lower half of
+// the second, per 64 and per 32 lanes; the sum of the two results is then
+// a + partner's a on the lower side and b + partner's b on the upper side.
+__device__ __forceinline__ float keep_half32(float a, float b)
 {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float keep_half16(float a, float b)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+template <int kCtrl>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xf, 0xf, false));
+}
+
+constexpr int kRowMirror = 0x140;       // lane i of 16 reads lane 15 - i
+constexpr int kRowHalfMirror = 0x141;   // lane i of 8 reads lane 7 - i
+constexpr int kQuadXor2 = 0x4e;         // quad_perm (2, 3, 0, 1)
+constexpr int kQuadXor1 = 0xb1;         // quad_perm (1, 0, 3, 2)
+
+// Wave sum of nine per-lane values, transposed: each halving step splits the
+// values between the two sides of a lane bit, each side keeping one part
+// plus its partner's copy of that part, so a step moves half as many values
+// as the one before (5 + 3 + 2 + 1 + 1 + 1 exchanges instead of 9 x 6).
+// Lane l ends with the total of value sum9_slot(l) (valid when below 9).
+__device__ __forceinline__ float wave_sum9(const float (&g)[9], uint32_t lane)
+{
+    float a[5];
+#pragma unroll
+    for (int j = 0; j < 4; j++) a[j] = keep_half32(g[j], g[5 + j]);   // bit 5: 0..4 | 5..8
+    a[4] = keep_half32(g[4], 0.0f);
+    float b[3];
+#pragma unroll
+    for (int j = 0; j < 2; j++) b[j] = keep_half16(a[j], a[3 + j]);   // bit 4: 0..2 | 3..4
+    b[2] = keep_half16(a[2], 0.0f);
+    const bool b3 = (lane >> 3) & 1u, b2 = (lane >> 2) & 1u;
+    float c[2];
+    c[0] = (b3 ? b[2] : b[0]) + dpp<kRowMirror>(b3 ? b[0] : b[2]);   // bit 3: 0..1 | 2
+    c[1] = (b3 ? 0.0f : b[1]) + dpp<kRowMirror>(b3 ? b[1] : 0.0f);
+    float d = (b2 ? c[1] : c[0]) + dpp<kRowHalfMirror>(b2 ? c[0] : c[1]);   // bit 2: 0 | 1
+    d += dpp<kQuadXor2>(d);
+    d += dpp<kQuadXor1>(d);
+    return d;
+}
+
+// The value whose total lane l holds after wave_sum9 (9 or more: none).
+__device__ __forceinline__ uint32_t sum9_slot(uint32_t lane)
+{
+    const uint32_t b5 = (lane >> 5) & 1u, b4 = (lane >> 4) & 1u, b3 = (lane >> 3) & 1u, b2 = (lane >> 2) & 1u;
+    const uint32_t low = 2u * b3 + b2, mid = 3u * b4 + low;
+    return (low < 3u && mid < 5u) ? 5u * b5 + mid : 9u;
 }
 
 __global__ __launch_bounds__(256) void k_composite_bwd(const FrameParams* __restrict__ fp,
@@ -82,7 +139,9 @@ __global__ __launch_bounds__(256) void k_composite_bwd(const FrameParams* __rest
         dC2 = dL[2 * HW + p];
     }
     const float* bg = fp->cam.bg;
-    float S0 = T * bg[0], S1 = T * bg[1], S2 = T * bg[2];   // colour behind the current entry
+    float D = T * ((dC0 * bg[0] + dC1 * bg[1]) + dC2 * bg[2]);   // dC . (colour behind the current entry)
+    const uint32_t slot = sum9_slot(lane);
+    const bool adds = (lane & 3u) == 0u && slot < 9u;
 
     // the quadrant's entries that any pixel blended lie in [0, end)
     uint32_t end = last;
@@ -112,50 +171,41 @@ __global__ __launch_bounds__(256) void k_composite_bwd(const FrameParams* __rest
         for (int jj = (int)__popcll(m) - 1; jj >= 0; jj--) {
             const uint32_t e = s_idx[wave][jj];
             const uint32_t kk = b0 + e;
-            float g[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-            bool contrib = false;
-            if (kk < last) {
-                const float4 geo = sa[e];
-                const float4 col = sb[e];
-                float dx, dy, G;
-                bool clamped = false;
-                const float alpha = splat_alpha(geo, col, px, py, dx, dy, G, clamped);
-                if (alpha >= 0.0f) {
-                    contrib = true;
-                    const float om = 1.0f - alpha;
-                    T = T / om;                       // transmittance before this entry
-                    const float4 gb = sc[e];
-                    const float c0 = col.w, c1 = gb.x, c2 = gb.y;
-                    const float wgt = alpha * T;
-                    g[6] = wgt * dC0;
-                    g[7] = wgt * dC1;
-                    g[8] = wgt * dC2;
-                    const float dalpha = dC0 * (c0 * T - S0 / om) + dC1 * (c1 * T - S1 / om) +
-                                         dC2 * (c2 * T - S2 / om);
-                    S0 += c0 * wgt;
-                    S1 += c1 * wgt;
-                    S2 += c2 * wgt;
-                    if (!clamped) {
-                        const float o = col.y;
-                        g[5] = dalpha * G;
-                        const float dpow = dalpha * o * G;
-                        // power = -A/2 dx^2 - C/2 dy^2 - B dx dy, staged as geo.z = -A/2, geo.w = -B, col.x = -C/2
-                        const float A = -2.0f * geo.z, B = -geo.w, C = -2.0f * col.x;
-                        g[2] = -0.5f * dx * dx * dpow;
-                        g[3] = -dx * dy * dpow;
-                        g[4] = -0.5f * dy * dy * dpow;
-                        g[0] = (-A * dx - B * dy) * dpow;
-                        g[1] = (-C * dy - B * dx) * dpow;
-                    }
-                }
-            }
+            // every lane evaluates the entry; those that did not blend it (past their last entry, or alpha
+            // below 1/255) keep T and D and give zero gradients through the selects
+            const float4 geo = sa[e];
+            const float4 col = sb[e];
+            const float4 gb = sc[e];
+            float dx, dy;
+            const float power = splat_power(geo, col, px, py, dx, dy);
+            const float G = __expf(power);
+            const float og = col.y * G;
+            const bool clamped = og > kAlphaMax;
+            const float alpha = clamped ? kAlphaMax : og;
+            const bool contrib = kk < last && !(power > 0.0f) && alpha >= kAlphaMin;
+            const float r = __builtin_amdgcn_rcpf(1.0f - alpha);
+            const float Tk = T * r;                   // transmittance before this entry
+            const float wgt = alpha * Tk;
+            const float cd = (dC0 * col.w + dC1 * gb.x) + dC2 * gb.y;
+            const float dalpha = Tk * cd - D * r;
+            T = contrib ? Tk : T;
+            D = contrib ? D + wgt * cd : D;
+            const float wc = contrib ? wgt : 0.0f;
+            float g[9];
+            g[6] = wc * dC0;
+            g[7] = wc * dC1;
+            g[8] = wc * dC2;
+            g[5] = contrib && !clamped ? dalpha * G : 0.0f;
+            const float dpow = g[5] * col.y;
+            // power = -A/2 dx^2 - C/2 dy^2 - B dx dy, staged as geo.z = -A/2, geo.w = -B, col.x = -C/2
+            g[2] = -0.5f * dx * dx * dpow;
+            g[3] = -dx * dy * dpow;
+            g[4] = -0.5f * dy * dy * dpow;
+            g[0] = (2.0f * geo.z * dx + geo.w * dy) * dpow;
+            g[1] = (2.0f * col.x * dy + geo.w * dx) * dpow;
             if (__ballot(contrib) != 0ull) {
-                float* dst = g2d + (size_t)s_a[wave][e] * kG2;
-#pragma unroll
-                for (int q = 0; q < 9; q++) {
-                    const float sum = wave_sum(g[q]);
-                    if (lane == 0 && sum != 0.0f) atomicAdd(dst + q, sum);
-                }
+                const float sum = wave_sum9(g, lane);
+                if (adds && sum != 0.0f) atomicAdd(g2d + (size_t)s_a[wave][e] * kG2 + slot, sum);
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -295,30 +345,50 @@ __global__ __launch_bounds__(256) void k_project_bwd(LevelsArg lv, GradsArg ga, 
         float dmu[3] = {0.0f, 0.0f, 0.0f};
 
         // ---- colour: rgb = max(0, sum_k sh_k Y_k(dir) + 1/2), dir = (mu - pos) / |mu - pos|
+        // Every index below is a compile-time constant (coefficients past the level's
+        // degree are zero and never loaded), so the basis stays in registers.
         const float d0 = mx - cam.pos[0], d1 = my - cam.pos[1], d2 = mz - cam.pos[2];
         const float dn = sqrtf((d0 * d0 + d1 * d1) + d2 * d2);
-        const float ux = d0 / dn, uy = d1 / dn, uz = d2 / dn;
+        const float idn = 1.0f / dn;
+        const float ux = d0 * idn, uy = d1 * idn, uz = d2 * idn;
         float Y[kMaxSh], dY[kMaxSh][3];
         sh_basis_grad(ux, uy, uz, Y, dY);
         const int nb = (L.sh_degree + 1) * (L.sh_degree + 1);
-        float ddir[3] = {0.0f, 0.0f, 0.0f};
+        float coef[kMaxSh][3];
+#pragma unroll
+        for (int k = 0; k < kMaxSh; k++)
+#pragma unroll
+            for (int ch = 0; ch < 3; ch++) coef[k][ch] = k < nb ? L.sh[((size_t)(k * 3 + ch)) * n + i] : 0.0f;
+        // the gradient reaches a channel only where its colour was not clamped at 0
+        float m[3];
+#pragma unroll
         for (int ch = 0; ch < 3; ch++) {
             float acc = 0.0f;
-            for (int k = 0; k < nb; k++) acc = acc + L.sh[((size_t)(k * 3 + ch)) * n + i] * Y[k];
-            if (!(acc + 0.5f > 0.0f) || grgb[ch] == 0.0f) continue;
-            for (int k = 0; k < nb; k++) {
-                const size_t idx = ((size_t)(k * 3 + ch)) * n + i;
-                if (G.sh) G.sh[idx] += grgb[ch] * Y[k];
-                const float c = grgb[ch] * L.sh[idx];
-                ddir[0] += c * dY[k][0];
-                ddir[1] += c * dY[k][1];
-                ddir[2] += c * dY[k][2];
+#pragma unroll
+            for (int k = 0; k < kMaxSh; k++) acc = acc + coef[k][ch] * Y[k];
+            m[ch] = acc + 0.5f > 0.0f ? grgb[ch] : 0.0f;
+        }
+        float ddir[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int k = 0; k < kMaxSh; k++) {
+            const float wk = (m[0] * coef[k][0] + m[1] * coef[k][1]) + m[2] * coef[k][2];
+            ddir[0] += wk * dY[k][0];
+            ddir[1] += wk * dY[k][1];
+            ddir[2] += wk * dY[k][2];
+        }
+        if (G.sh) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ch++) {
+                if (m[ch] == 0.0f) continue;
+#pragma unroll
+                for (int k = 0; k < kMaxSh; k++)
+                    if (k < nb) G.sh[((size_t)(k * 3 + ch)) * n + i] += m[ch] * Y[k];
             }
         }
         const float dot = ddir[0] * ux + ddir[1] * uy + ddir[2] * uz;
-        dmu[0] += (ddir[0] - ux * dot) / dn;
-        dmu[1] += (ddir[1] - uy * dot) / dn;
-        dmu[2] += (ddir[2] - uz * dot) / dn;
+        dmu[0] += (ddir[0] - ux * dot) * idn;
+        dmu[1] += (ddir[1] - uy * dot) * idn;
+        dmu[2] += (ddir[2] - uz * dot) * idn;
 
         // ---- opacity: o_eff = o w comp3 comp2
         if (G.opacity) G.opacity[i] += go_eff * w * comp3 * comp2;
@@ -326,13 +396,13 @@ __global__ __launch_bounds__(256) void k_project_bwd(LevelsArg lv, GradsArg ga, 
         const float dcomp2 = go_eff * op * w * comp3;
 
         // ---- conic (A, B, C) = (c, -b, a) / det, a = a0 + s2d, c = c0 + s2d
-        const float det2 = det * det;
-        float ga_ = gA * (-(cc * cc) / det2) + gB * (b * cc / det2) + gC * (-(b * b) / det2);
-        float gc_ = gA * (-(b * b) / det2) + gB * (b * aa / det2) + gC * (-(aa * aa) / det2);
-        float gb_ = gA * (2.0f * b * cc / det2) + gB * (-(aa * cc + b * b) / det2) + gC * (2.0f * aa * b / det2);
+        const float idet = 1.0f / det, idet2 = idet * idet;
+        float ga_ = (gA * (-(cc * cc)) + gB * (b * cc) + gC * (-(b * b))) * idet2;
+        float gc_ = (gA * (-(b * b)) + gB * (b * aa) + gC * (-(aa * aa))) * idet2;
+        float gb_ = (gA * (2.0f * b * cc) + gB * (-(aa * cc + b * b)) + gC * (2.0f * aa * b)) * idet2;
         if (compensate && det0 > 0.0f) {
-            const float ddet0 = dcomp2 / (2.0f * comp2 * det);
-            const float ddet = -dcomp2 * comp2 / (2.0f * det);
+            const float ddet0 = 0.5f * dcomp2 * idet / comp2;
+            const float ddet = -0.5f * dcomp2 * comp2 * idet;
             ga_ += ddet0 * c0 + ddet * cc;
             gc_ += ddet0 * a0 + ddet * aa;
             gb_ += -2.0f * b * (ddet0 + ddet);
@@ -363,17 +433,18 @@ __global__ __launch_bounds__(256) void k_project_bwd(LevelsArg lv, GradsArg ga, 
             dJ11 += dM[3 + c] * Wc[3 + c];
             dJ12 += dM[3 + c] * Wc[6 + c];
         }
-        const float tz2 = tz * tz, tz3 = tz2 * tz;
+        const float itz = 1.0f / tz, itz2 = itz * itz, itz3 = itz2 * itz;
+        const float fx2 = cam.fx * itz2, fy2 = cam.fy * itz2;   // f / tz^2
         float dtx = 0.0f, dty = 0.0f, dtz = 0.0f;
-        dtz += dJ00 * (-cam.fx / tz2) + dJ11 * (-cam.fy / tz2);
-        if (clx) dtz += dJ02 * (cam.fx * rx / tz2);
-        else { dtx += dJ02 * (-cam.fx / tz2); dtz += dJ02 * (2.0f * cam.fx * tx / tz3); }
-        if (cly) dtz += dJ12 * (cam.fy * ry / tz2);
-        else { dty += dJ12 * (-cam.fy / tz2); dtz += dJ12 * (2.0f * cam.fy * ty / tz3); }
-        dtx += gu * cam.fx / tz;
-        dtz += gu * (-cam.fx * tx / tz2);
-        dty += gv * cam.fy / tz;
-        dtz += gv * (-cam.fy * ty / tz2);
+        dtz += dJ00 * (-fx2) + dJ11 * (-fy2);
+        if (clx) dtz += dJ02 * (rx * fx2);
+        else { dtx += dJ02 * (-fx2); dtz += dJ02 * (2.0f * cam.fx * tx * itz3); }
+        if (cly) dtz += dJ12 * (ry * fy2);
+        else { dty += dJ12 * (-fy2); dtz += dJ12 * (2.0f * cam.fy * ty * itz3); }
+        dtx += gu * cam.fx * itz;
+        dtz += gu * (-tx * fx2);
+        dty += gv * cam.fy * itz;
+        dtz += gv * (-ty * fy2);
         for (int j = 0; j < 3; j++) dmu[j] += Wc[j] * dtx + Wc[3 + j] * dty + Wc[6 + j] * dtz;
 
         // ---- Sigma = R diag(v) R^T, v_j = s_j^2 + var, comp3 = sqrt(prod s_j^2 / v_j)
@@ -424,18 +495,25 @@ __global__ __launch_bounds__(256) void k_project_bwd(LevelsArg lv, GradsArg ga, 
 
 hipError_t launch_backward(const LevelsArg& lv, const lodge_selection& sel, const Views& v, const float* final_T,
                            const uint32_t* n_contrib, const float* dL_dimage, int32_t grad_level,
-                           const lodge_grads* grads, hipStream_t st)
+                           const lodge_grads* grads, hipStream_t st, void* const* events)
 {
+    auto mark = [&](int k) -> hipError_t {
+        return events ? hipEventRecord(static_cast<hipEvent_t>(events[k]), st) : hipSuccess;
+    };
     GradsArg ga{};
     for (int l = 0; l < lv.L; l++) ga.g[l] = grads[l];
     uint32_t blocks = std::min<uint32_t>(2048, std::max<uint32_t>(1, (v.max_active * (uint32_t)kG2 + 255) / 256));
     k_bwd_setup<<<blocks, 256, 0, st>>>(v.g2d, sel.count, sel.cap);
+    hipError_t e = mark(0);
+    if (e != hipSuccess) return e;
     k_composite_bwd<<<v.lay.T, 256, 0, st>>>(v.params, v.ranges, v.order, v.sorted, v.proj, final_T, n_contrib,
                                              dL_dimage, v.g2d, v.max_active);
+    if ((e = mark(1)) != hipSuccess) return e;
     blocks = std::min<uint32_t>(4096, std::max<uint32_t>(1, (v.max_active + 255) / 256));
     k_project_bwd<<<blocks, 256, 0, st>>>(lv, ga, grad_level, sel.ids, sel.w, sel.count, sel.cap, v.params, v.rect,
                                           v.g2d);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return mark(2);
 }
 
 }  // namespace lodge

@@ -216,7 +216,7 @@ hipError_t launch_composite(const Views& v, float* image, float* final_T, uint32
 hipError_t launch_importance(const Views& v, const uint32_t* sel_ids, float* score, hipStream_t st);
 hipError_t launch_backward(const LevelsArg& lv, const lodge_selection& sel, const Views& v, const float* final_T,
                            const uint32_t* n_contrib, const float* dL_dimage, int32_t grad_level,
-                           const lodge_grads* grads, hipStream_t st);
+                           const lodge_grads* grads, hipStream_t st, void* const* events = nullptr);
 // fills the packed copy of every level (layout in LevelDev)
 hipError_t launch_pack(const LevelsArg& lv, hipStream_t st);
 hipError_t launch_activate(int64_t n, const float* ls, const float* qr, const float* ol, float* s, float* q, float* o,

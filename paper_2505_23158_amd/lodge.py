@@ -180,6 +180,19 @@ def _stream_ptr(stream) -> Optional[int]:
     return stream.cuda_stream
 
 
+def _event_array(stage_events, n: int):
+    """hipEvent_t array of torch.cuda.Event objects.  torch creates an event's HIP handle at its first record(), so
+    each must have been recorded once."""
+    if stage_events is None:
+        return None
+    if len(stage_events) < n:
+        raise ValueError(f"stage_events: {n} events needed, {len(stage_events)} given")
+    handles = [e.cuda_event for e in stage_events]
+    if any(h == 0 for h in handles):
+        raise ValueError("stage_events: record() each event once before passing it (its HIP event is created then)")
+    return (C.c_void_p * len(handles))(*handles)
+
+
 def make_camera(cam) -> lodge_camera:
     """lodge_camera from any object with the synth.Camera fields."""
     c = lodge_camera()
@@ -358,9 +371,7 @@ def lodge_importance(scene: Scene, sel: Selection, cam, ws: Workspace, score, s2
     if score.numel() != scene.total or score.dtype != _torch().float32 or not score.is_contiguous():
         raise ValueError("score must be a contiguous float32 tensor of scene.total elements")
     cp, keep = _cam_arg(cam)
-    evs = None
-    if stage_events is not None:
-        evs = (C.c_void_p * STAGE_EVENTS)(*[e.cuda_event for e in stage_events])
+    evs = _event_array(stage_events, STAGE_EVENTS)
     opts = lodge_render_opts(s2d=s2d, compensate=int(compensate), stage_events=C.cast(evs, C.c_void_p) if evs else None)
     _check(lib().lodge_importance(scene.handle, C.byref(sel.desc), cp, C.byref(opts), C.byref(ws.desc),
                                   _ptr(score), _stream_ptr(stream)))
@@ -375,9 +386,7 @@ def lodge_render(scene: Scene, sel: Selection, cam, ws: Workspace, image, final_
                  compensate: bool = True, stream=None, stage_events=None):
     """stage_events: None or STAGE_EVENTS torch.cuda.Event objects recorded at the stage boundaries."""
     cp, keep = _cam_arg(cam)
-    evs = None
-    if stage_events is not None:
-        evs = (C.c_void_p * STAGE_EVENTS)(*[e.cuda_event for e in stage_events])
+    evs = _event_array(stage_events, STAGE_EVENTS)
     opts = lodge_render_opts(s2d=s2d, compensate=int(compensate), stage_events=C.cast(evs, C.c_void_p) if evs else None)
     _check(lib().lodge_render(scene.handle, C.byref(sel.desc), cp, C.byref(opts), C.byref(ws.desc), _ptr(image),
                               _ptr(final_T), _ptr(n_contrib), _stream_ptr(stream)))
@@ -425,9 +434,13 @@ def lodge_debug_views(ws: Workspace, n_instances: int):
 
 def lodge_render_backward(scene: Scene, sel: Selection, cam, ws: Workspace, final_T, n_contrib, dL_dimage,
                           grads: Sequence[dict], grad_level: int = -1, s2d: float = 0.3, compensate: bool = True,
-                          stream=None):
+                          stream=None, stage_events=None):
+    """stage_events: None or three torch.cuda.Event objects, recorded before the compositing adjoint, between it
+    and the projection adjoint, and after."""
     cp, keep = _cam_arg(cam)
-    opts = lodge_render_opts(s2d=s2d, compensate=int(compensate))
+    evs = _event_array(stage_events, 3)
+    opts = lodge_render_opts(s2d=s2d, compensate=int(compensate),
+                             stage_events=C.cast(evs, C.c_void_p) if evs else None)
     arr = (lodge_grads * len(scene.levels))()
     for i, g in enumerate(grads):
         for k in ("mean", "scale", "quat", "opacity", "sh"):
