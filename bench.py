@@ -60,11 +60,13 @@ OPS_PER_SIGNIFICANT_PAIR = 25
 # opacity and exponent gradients (2), the conic gradient (6, the squares reused from the quadratic form) and the
 # mean gradient (6) = 30, and the nine gradients summed over the pixels (9): 57 lane-ops.
 ADJ_OPS_PER_BLENDED = 57
-# Projection adjoint bytes: the tile rect of every selected Gaussian (8); per visible one, reads of id, weight,
-# its 9 summed 2-D gradients, mean, scale, quaternion, opacity and 48 SH coefficients (280) and a read-add-write of
-# each gradient plane (mean 24, scale 24, quaternion 32, opacity 8, SH 384) = 752 at SH degree 3.
+# Projection adjoint bytes: the tile rect of every selected Gaussian (8); the 9 summed 2-D gradients of every
+# visible one (36); for each with a non-zero 2-D gradient (the others have a zero gradient for every parameter),
+# reads of id, weight, mean, scale, quaternion, opacity and 48 SH coefficients (244) and a read-add-write of each
+# gradient plane (mean 24, scale 24, quaternion 32, opacity 8, SH 384) = 716 more at SH degree 3.
 ADJ_BYTES_PER_ACTIVE = 8
-ADJ_BYTES_PER_VISIBLE = 752
+ADJ_BYTES_PER_VISIBLE = 36
+ADJ_BYTES_PER_GRADIENT = 716
 CSRC = os.path.join(ROOT, "paper_2505_23158_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_lod4_1080p.txt")
 
@@ -256,7 +258,7 @@ def diff_section(n=1_000_000, views=8, width=1280, height=720, steps=3):
     # around the compositing adjoint and the projection adjoint (grads into the renderer's own planes)
     dr.activate()
     comp_ms = proj_ms = 0.0
-    blended = visible = active = 0
+    blended = visible = active = touched = 0
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     for e in ev:            # torch creates the HIP event at its first record
         e.record()
@@ -275,14 +277,16 @@ def diff_section(n=1_000_000, views=8, width=1280, height=720, steps=3):
         torch.cuda.synchronize()
         comp_ms += ev[0].elapsed_time(ev[1])
         proj_ms += ev[1].elapsed_time(ev[2])
+        g = dr.g_act[0]   # Gaussians with a non-zero gradient (a non-zero 2-D gradient reaches opacity or mean)
+        touched += int(((g["opacity"] != 0) | (g["mean"] != 0).any(0)).sum().item())
     comp_ops = ADJ_OPS_PER_BLENDED * blended
-    proj_bytes = ADJ_BYTES_PER_ACTIVE * active + ADJ_BYTES_PER_VISIBLE * visible
+    proj_bytes = ADJ_BYTES_PER_ACTIVE * active + ADJ_BYTES_PER_VISIBLE * visible + ADJ_BYTES_PER_GRADIENT * touched
     return {"workload": f"1 level, {n} Gaussians, {views} views {width}x{height}, L1 loss, grads for mean, "
                         "log-scale, raw quaternion, opacity logit, SH",
             "ms_per_step": round(ms, 3), "views_per_s": round(views * 1000.0 / ms, 2),
             "per_view": {"composite_bwd_ms": round(comp_ms / views, 4), "project_bwd_ms": round(proj_ms / views, 4),
                          "pairs_blended": blended // views, "n_visible": visible // views,
-                         "n_selected": active // views},
+                         "n_selected": active // views, "n_with_gradient": touched // views},
             "roofline": {
                 "composite_bwd": {"bound": "alu", "achieved": round(comp_ops / (comp_ms * 1e-3) / 1e12, 3),
                                   "peak": round(VALU_PEAK_TOPS, 2), "unit": "TVALU-op/s",

@@ -19,7 +19,8 @@
 //                  gradients are summed over the wave by a transposed
 //                  reduction (only where some pixel contributed) and added
 //                  with one atomic instruction of nine lanes.
-// k_project_bwd    one thread per visible active Gaussian: the chain rule from
+// k_project_bwd    one thread per visible active Gaussian whose 2-D gradient is
+//                  not zero: the chain rule from
 //                  (u, v, conic, o_eff, rgb) back through the 2-D filter, the
 //                  EWA covariance, the camera and the Eq. 3 filter to the
 //                  activated parameters; each Gaussian occurs once per frame,
@@ -277,6 +278,13 @@ __global__ __launch_bounds__(256) void k_project_bwd(LevelsArg lv, GradsArg ga, 
     for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < n_act; a += gridDim.x * blockDim.x) {
         const uint2 rc = rect[a];
         if ((rc.y & 0xffffu) <= (rc.x & 0xffffu)) continue;   // culled: empty rectangle
+        const float4* const g4 = reinterpret_cast<const float4*>(g2d + (size_t)a * kG2);
+        const float4 gq0 = g4[0], gq1 = g4[1], gq2 = g4[2];
+        // a Gaussian that no pixel blended (hidden, or below 1/255 everywhere) has a zero 2-D
+        // gradient and so a zero gradient for every parameter: nothing to read or add
+        if (gq0.x == 0.0f && gq0.y == 0.0f && gq0.z == 0.0f && gq0.w == 0.0f && gq1.x == 0.0f &&
+            gq1.y == 0.0f && gq1.z == 0.0f && gq1.w == 0.0f && gq2.x == 0.0f)
+            continue;
         const uint32_t gid = ids[a];
         int l = 0;
 #pragma unroll
@@ -287,9 +295,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(LevelsArg lv, GradsArg ga, 
         const lodge_grads& G = ga.g[l];
         const size_t n = L.n;
         const uint32_t i = gid - L.base;
-        const float* g = g2d + (size_t)a * kG2;
-        const float gu = g[0], gv = g[1], gA = g[2], gB = g[3], gC = g[4], go_eff = g[5];
-        const float grgb[3] = {g[6], g[7], g[8]};
+        const float gu = gq0.x, gv = gq0.y, gA = gq0.z, gB = gq0.w, gC = gq1.x, go_eff = gq1.y;
+        const float grgb[3] = {gq1.z, gq1.w, gq2.x};
 
         // ---- forward recomputation (as in the projection kernel)
         const float mx = L.mean[i], my = L.mean[n + i], mz = L.mean[2 * n + i];
