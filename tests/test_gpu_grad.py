@@ -266,3 +266,34 @@ def test_batched_views_equal_single_views(L):
         ref = p.grad
         err = float((gb - ref).abs().max())
         assert err <= 1e-5 * max(1.0, float(ref.abs().max())), err
+
+
+def test_zero_image_gradient_and_timed_backward(L):
+    """dL/dimage = 0 leaves every parameter gradient exactly zero (no Gaussian has a 2-D gradient, so the
+    projection adjoint adds nothing); a backward with stage events records them in order and gives the
+    gradients of one without, up to the order of the atomic sums; events never recorded are refused."""
+    import torch
+    sc = synth.check_scene(n=64, width=32, height=32)
+    cam = sc.cameras[0]
+    g0, _ = gpu_grads(L, sc, cam, L.SELECT_ALL, np.zeros((3, cam.height, cam.width)))
+    for k in PARAMS:
+        assert np.all(g0[0][k] == 0.0), k
+    dL = np.random.default_rng(21).normal(size=(3, cam.height, cam.width))
+    g1, _ = gpu_grads(L, sc, cam, L.SELECT_ALL, dL)
+    dev = L.Scene.from_synth(sc)
+    R = L.Renderer(dev, cam.width, cam.height)
+    R.frame(cam, L.SELECT_ALL)
+    grads = [{k: torch.zeros_like(t) for k, t in lv.items() if k in PARAMS} for lv in dev.levels]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    for e in ev:
+        e.record()
+    dL_d = torch.from_numpy(dL.astype(np.float32)).cuda()
+    L.lodge_render_backward(dev, R.sel, cam, R.ws, R.final_T, R.n_contrib, dL_d, grads, stage_events=ev)
+    torch.cuda.synchronize()
+    assert ev[0].elapsed_time(ev[1]) >= 0.0 and ev[1].elapsed_time(ev[2]) >= 0.0
+    for k in PARAMS:
+        ok, rel = rel_ok(grads[0][k].cpu().numpy(), g1[0][k], tol=1e-5)
+        assert ok, (k, rel)
+    fresh = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    with pytest.raises(ValueError):
+        L.lodge_render_backward(dev, R.sel, cam, R.ws, R.final_T, R.n_contrib, dL_d, grads, stage_events=fresh)
