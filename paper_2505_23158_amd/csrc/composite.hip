@@ -19,10 +19,10 @@
 // pixel skips; the wave then runs as many steps as the longest list, each
 // lane following its own, predicated, with the next entry read one step
 // ahead.  Per (pixel, splat): power = -1/2
-// (A dx^2 + C dy^2) - B dx dy; skip if power > 0 or below the splat's
-// threshold ln(1/(255 o)) - 1e-3 (alpha < 1/255 there); alpha = min(0.99,
-// o exp(power)); skip if alpha < 1/255; stop (without blending) once
-// T (1 - alpha) < 1e-4; else C += rgb alpha T, T *= 1 - alpha.  A splat
+// (A dx^2 + C dy^2) - B dx dy; alpha = min(0.99, o exp(power)); skip if
+// power > 0 or alpha < 1/255 (as is every power below the splat's threshold
+// ln(1/(255 o)) - 1e-3, which the culling uses); stop (without blending)
+// once T (1 - alpha) < 1e-4; else C += rgb alpha T, T *= 1 - alpha.  A splat
 // dropped for a sub-quadrant changes no decision: the tests keep every
 // splat that any of its pixels would not skip, with a margin above the
 // rounding of both computations.

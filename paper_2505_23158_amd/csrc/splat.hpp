@@ -27,27 +27,13 @@ __device__ __forceinline__ float splat_power(const float4& geo, const float4& co
     return __builtin_fmaf(dx, __builtin_fmaf(geo.w, dy, geo.z * dx), (col.x * dy) * dy);
 }
 
-// alpha of the splat at this pixel, or a negative value if it is skipped
-// (power > 0, power below the threshold, or alpha < 1/255).  G and the clamp
-// state are returned for the adjoint.
-__device__ __forceinline__ float splat_alpha(const float4& geo, const float4& col, float px, float py, float& dx,
-                                             float& dy, float& G, bool& clamped)
-{
-    const float power = splat_power(geo, col, px, py, dx, dy);
-    if (power > 0.0f || power < col.z) return -1.0f;
-    G = __expf(power);
-    const float og = col.y * G;
-    clamped = og > kAlphaMax;
-    const float alpha = clamped ? kAlphaMax : og;
-    return alpha < kAlphaMin ? -1.0f : alpha;
-}
-
-// The same decision as splat_alpha without branches: alpha (clamped at
-// kAlphaMax) and whether the pair counts; exp is evaluated either way, so
-// the power threshold is not tested: a power below it gives
-// o exp(power) < e^-0.001 / 255, far enough below 1/255 for any rounding of
-// exp, and the alpha test rejects the pair.  amin is kAlphaMin, or +inf for
-// a pixel that takes no more splats (every finite alpha is then below it).
+// Whether the pair counts, and its alpha (clamped at kAlphaMax), without
+// branches: the pair counts when power <= 0 and alpha >= amin.  exp is
+// evaluated either way, so the splat's power threshold is not tested: a
+// power below it gives o exp(power) < e^-0.001 / 255, far enough below
+// 1/255 for any rounding of exp, and the alpha test rejects the pair.  amin
+// is kAlphaMin, or +inf for a pixel that takes no more splats (every finite
+// alpha is then below it).
 __device__ __forceinline__ bool splat_keep(const float4& geo, const float4& col, float px, float py, float amin,
                                            float& alpha)
 {
