@@ -192,6 +192,22 @@ class LodBuilder:
         lv.activate()
         return graw
 
+    def eval_loss(self, l: int) -> float:
+        """The training loss of levels 0..l, (1 - lambda) mean L1 + lambda D-SSIM, averaged over the training
+        views rendered at the nominal switch distances (no parameter changes)."""
+        torch = L._torch()
+        n_px = 3 * self.W * self.H
+        total = torch.zeros(1, dtype=torch.float32, device="cuda")
+        for v, cam in enumerate(self.cams):
+            _, R = self.render(l, self.d, cam)
+            self.loss.zero_()
+            L.lodge_l1_grad(R.image, self.targets[v], self.dL, (1.0 - self.lam) / n_px, self.loss)
+            if self.lam:
+                self.ssim_scratch = L.lodge_dssim_grad(R.image, self.targets[v], self.dL, self.lam, self.loss,
+                                                       self.ssim_scratch)
+            total += self.loss
+        return float(total.item()) / len(self.cams)
+
     def importance(self, l: int):
         """Importance of every Gaussian of levels 0..l over the training views (LOD renders at the nominal
         switch distances); returns level l's slice of the score array."""

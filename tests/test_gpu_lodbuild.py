@@ -311,3 +311,31 @@ def test_full_size_finetune_touches_only_rendered_level_l_gaussians(L):
     assert torch.equal(raw[:, idx], before[:, idx])
     assert not B.levels[1].m[:, idx].any() and not B.levels[1].v[:, idx].any()
     log(f"[lodbuild] full size: level 1 kept {B.levels[1].n} of {n}; {int(never.sum())} never selected, unchanged")
+
+
+def test_finetuning_lowers_the_loss_of_a_pruned_level(L):
+    """The construction loop optimises: a level pruned hard renders the training views worse than G^(0)
+    does, and its fine-tuning steps (random view and d_l draw each, L1 + D-SSIM, adjoint of that level only,
+    Adam) bring the loss at the nominal switch distance down."""
+    import torch
+    from paper_2505_23158_amd import lodbuild as LB
+    base_raw, cams, d, _ = synth.lod_build_workload(n=2000, n_views=6, width=64, height=48, d=(4.0,), seed=66)
+    t = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in base_raw.items()}
+    base = LB.level_from_raw(t["mean"], t["log_scale"], t["quat_raw"], t["opacity_logit"], t["sh"], 3, 0.0)
+    sc0 = L.Scene([base.scene_level()], [], None)
+    R0 = L.Renderer(sc0, cams[0].width, cams[0].height)
+    targets = torch.empty((len(cams), 3, cams[0].height, cams[0].width), device="cuda")
+    for v, cam in enumerate(cams):
+        R0.frame(cam, L.SELECT_ALL)
+        targets[v].copy_(R0.image)
+    B = LB.LodBuilder([base], d, cams, targets)
+    B.levels.append(LB.copy_with_filter(base, synth.filter_var(d[0])))
+    s = B.importance(1)
+    B.prune(1, float(torch.quantile(s, 0.7)))
+    before = B.eval_loss(1)
+    rng = np.random.default_rng(5)
+    for _ in range(150):
+        B.finetune_step(1, int(rng.integers(0, len(cams))), float(rng.uniform(0.7, 1.3)))
+    after = B.eval_loss(1)
+    log(f"[lodbuild] pruned to {B.levels[1].n} of {base.n}; loss {before:.5f} -> {after:.5f}")
+    assert np.isfinite(after) and after < 0.9 * before, (before, after)
