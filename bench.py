@@ -31,6 +31,10 @@ stages, give "serial" and the stage times behind "stages" and "roofline".
 "paper_comparable" holds the figures comparable with the paper's FPS, which
 times one image at a time: the serial rate, and the paper's own protocol
 (median of 7 per image, FPS = 1 / mean time).
+
+Every roofline fraction is against the data-sheet peak ("frac") and against
+the rate this device reaches in a streaming read or copy, or in chains of
+dependent FMAs ("frac_of_measured", "measured_peaks").
 """
 from __future__ import annotations
 
@@ -386,6 +390,65 @@ def thresholds_section(n_views=8, width=1920, height=1080):
             "as_given_cost": round(ev.cost(tuple(sc.d)), 2)}
 
 
+def peaks_section(copy_mib=1024, reps=5):
+    """The device's achievable rates, measured: a streaming read and a streaming copy (HBM bytes moved per
+    second; the faster is the measured HBM peak) and chains of dependent FP32 FMAs (VALU lane-ops per second,
+    an FMA counted as one), timed with events; the roofline fractions are reported against these beside the
+    data-sheet peaks."""
+    import statistics as st
+
+    import torch
+
+    from paper_2505_23158_amd import lodge as L
+    src = torch.ones((copy_mib << 18,), dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    nbytes = src.numel() * 4
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(2):
+        L.lodge_microbench_copy(src, dst)
+    copies = []
+    for _ in range(reps):
+        e0.record()
+        for _ in range(4):
+            L.lodge_microbench_copy(src, dst)
+        e1.record()
+        torch.cuda.synchronize()
+        copies.append(2.0 * nbytes * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    if not bool(torch.equal(src, dst)):
+        raise SystemExit("microbench copy: wrong result")
+    del dst
+    sums = L.lodge_microbench_read(src)
+    reads = []
+    for _ in range(reps):
+        e0.record()
+        for _ in range(4):
+            L.lodge_microbench_read(src, sums)
+        e1.record()
+        torch.cuda.synchronize()
+        reads.append(nbytes * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    if float(sums.double().sum()) != float(src.numel()):   # every 1.0 of src read once
+        raise SystemExit("microbench read: wrong result")
+    del src, sums
+    blocks, iters = 8192, 4096
+    out = torch.empty((blocks * 256,), dtype=torch.float32, device="cuda")
+    L.lodge_microbench_fma(out, iters)
+    fmas = []
+    for _ in range(reps):
+        e0.record()
+        ops = L.lodge_microbench_fma(out, iters)
+        e1.record()
+        torch.cuda.synchronize()
+        fmas.append(ops / (e0.elapsed_time(e1) * 1e-3) / 1e12)
+    # x <- x + 1 from x = 0..7: every thread sums to 28 + 8 iters, exactly
+    if not bool((out == float(28 + 8 * iters)).all()):
+        raise SystemExit("microbench fma: wrong result")
+    read, copy = st.median(reads), st.median(copies)
+    return {"hbm_GBs": round(max(read, copy), 1), "hbm_read_GBs": round(read, 1), "hbm_copy_GBs": round(copy, 1),
+            "valu_fma_Tlane_ops": round(st.median(fmas), 2),
+            "hbm": f"the faster of a streaming read and a streaming copy of {copy_mib} MiB, median of {reps} x 4",
+            "fma": f"{blocks} x 256 threads x 8 chains x {iters} dependent FP32 FMAs, median of {reps}"}
+
+
 def lodbuild_section(n=1_000_000, width=1280, height=720, views=8, steps=20, d=(15.0,)):
     """Construction of one coarser level over a 1M-Gaussian G^(0): one pruning (importance over the
     training views) and fine-tuning steps (LOD render of levels 0..1 with d_1 scaled by the step's draw,
@@ -657,6 +720,16 @@ def main():
         s["traffic"] = traffic.get("k_" + n)
     roofline = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
                 "frac": d["frac"], "traffic": d["traffic"]}
+    # the same fractions against the rates this device reaches (streaming copy, dependent FMAs)
+    log("[bench] measured peaks (streaming read and copy, FMA chains)")
+    peaks = peaks_section()
+    measured = {"hbm": peaks["hbm_GBs"], "alu": peaks["valu_fma_Tlane_ops"]}
+    for s in stages.values():
+        if "bound" in s:
+            s["frac_of_measured"] = round(s["achieved"] / measured[s["bound"]], 4)
+    roofline["measured_peak"] = measured[roofline["bound"]]
+    roofline["frac_of_measured"] = round(roofline["achieved"] / measured[roofline["bound"]], 4)
+    log(f"[bench] measured peaks {peaks}")
 
     if args.calib_copy_mib:
         src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
@@ -675,12 +748,16 @@ def main():
     if not args.no_diff:
         log("[bench] differentiation, 8 views")
         diff = diff_section()
+        for r in diff["roofline"].values():
+            r["frac_of_measured"] = round(r["achieved"] / measured[r["bound"]], 4)
         log(f"[bench] differentiation {diff}")
 
     visibility = thresholds = lodbuild = None
     if not args.no_lod_build and args.workload == "large":
         log("[bench] visibility filtering of one chunk")
         visibility = visibility_section(dev, sc)
+        r = visibility["roofline"]
+        r["frac_of_measured"] = round(r["achieved"] / measured[r["bound"]], 4)
         log(f"[bench] visibility {visibility}")
     if not args.no_lod_build:
         log("[bench] depth-threshold search")
@@ -732,6 +809,7 @@ def main():
         "per_frame": {k: round(v, 1) for k, v in mean.items()},
         "stages": stages,
         "roofline": roofline,
+        "measured_peaks": peaks,
         "scene_pack": pack,
         "serving": serving,
         "differentiation": diff,

@@ -470,6 +470,36 @@ lodge_status lodge_keep_indices(int64_t n, const float* score, float threshold, 
 lodge_status lodge_gather_planes(int32_t planes, int64_t n_in, int64_t n_out, const float* in, const uint32_t* idx,
                                  const uint32_t* count, float* out, void* stream);
 
+/* ------------------------------------------------------ measurement helpers */
+
+/* Not part of the method: the device's achievable rates, against which the
+ * kernels' roofline fractions are reported beside the data-sheet peaks. */
+
+/* ASYNC.  Copies `bytes` (a multiple of 16) from src to dst (device, 16-byte
+ * aligned, not overlapping) with a coalesced streaming kernel: the HBM rate
+ * of a kernel that reads and writes once is 2 * bytes over its time.
+ * LODGE_ERR_INVALID_ARG for NULL or misaligned buffers. */
+lodge_status lodge_microbench_copy(const void* src, void* dst, size_t bytes, void* stream);
+
+/* The grid lodge_microbench_read uses for `bytes`: *blocks blocks of 256
+ * threads (out then needs *blocks x 256 floats). */
+lodge_status lodge_microbench_read_blocks(size_t bytes, uint32_t* blocks);
+
+/* ASYNC.  Reads `bytes` (a multiple of 16) of src (device, 16-byte aligned)
+ * with a coalesced streaming kernel of `blocks` blocks of 256 threads (the
+ * count lodge_microbench_read_blocks gives), each thread writing the sum of
+ * what it read to out[thread] (device, blocks x 256 floats): the HBM rate of
+ * a kernel that only reads is bytes over its time.  LODGE_ERR_INVALID_ARG for
+ * NULL or misaligned buffers or blocks == 0. */
+lodge_status lodge_microbench_read(const void* src, size_t bytes, float* out, uint32_t blocks, void* stream);
+
+/* ASYNC.  blocks x 256 threads, each running 8 independent chains of `iters`
+ * dependent FP32 FMAs x <- fma(x, a, b) from x = 0..7, and writing the sum of
+ * its chains to out[thread] (device, blocks x 256 floats): 8 * iters * 256 *
+ * blocks non-packed VALU lane-ops.  LODGE_ERR_INVALID_ARG for out == NULL or
+ * blocks == 0. */
+lodge_status lodge_microbench_fma(float* out, uint32_t blocks, uint32_t iters, float a, float b, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

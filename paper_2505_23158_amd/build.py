@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblodge.so")
 SOURCES = ["api.hip", "select.hip", "chunksets.hip", "project.hip", "bin.hip", "sort.hip", "composite.hip",
-           "backward.hip", "activate.hip", "noalloc.hip", "lodbuild.hip", "pack.hip"]
+           "backward.hip", "activate.hip", "noalloc.hip", "lodbuild.hip", "pack.hip", "microbench.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -136,6 +136,10 @@ def lib():
                                       vp]),
             "lodge_keep_indices": (st, [C.c_int64, vp, C.c_float, vp, vp, vp, C.c_size_t, vp]),
             "lodge_gather_planes": (st, [C.c_int32, C.c_int64, C.c_int64, vp, vp, vp, vp, vp]),
+            "lodge_microbench_copy": (st, [vp, vp, C.c_size_t, vp]),
+            "lodge_microbench_read_blocks": (st, [C.c_size_t, C.POINTER(C.c_uint32)]),
+            "lodge_microbench_read": (st, [vp, C.c_size_t, vp, C.c_uint32, vp]),
+            "lodge_microbench_fma": (st, [vp, C.c_uint32, C.c_uint32, C.c_float, C.c_float, vp]),
             "lodge_activate": (st, [C.c_int64, vp, vp, vp, vp, vp, vp, vp]),
             "lodge_activate_backward": (st, [C.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         }
@@ -158,7 +162,8 @@ EXPORTED = ["lodge_status_string", "lodge_last_error", "lodge_version", "lodge_s
             "lodge_check", "lodge_debug_views", "lodge_render_backward", "lodge_activate", "lodge_activate_backward",
             "lodge_render_static", "lodge_select_chunk", "lodge_importance", "lodge_chunk_sets_prune",
             "lodge_l1_grad", "lodge_adam", "lodge_keep_scratch_size", "lodge_keep_indices", "lodge_gather_planes",
-            "lodge_pack_size", "lodge_scene_pack", "lodge_dssim_scratch_size", "lodge_dssim_grad"]
+            "lodge_pack_size", "lodge_scene_pack", "lodge_dssim_scratch_size", "lodge_dssim_grad",
+            "lodge_microbench_copy", "lodge_microbench_read_blocks", "lodge_microbench_read", "lodge_microbench_fma"]
 STATIC_SCRATCH_BYTES = 256 << 20
 
 
@@ -560,3 +565,34 @@ class Renderer:
 
     def info(self, stream=None) -> dict:
         return lodge_frame_info_read(self.ws, stream)
+
+
+# --------------------------------------------------------------------------- measurement helpers
+
+def lodge_microbench_copy(src, dst, stream=None):
+    """Streaming device copy src -> dst (same-size contiguous CUDA tensors, 16-byte multiple)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst must have the same size in bytes")
+    _check(lib().lodge_microbench_copy(_ptr(src), _ptr(dst), C.c_size_t(nbytes), _stream_ptr(stream)))
+
+
+def lodge_microbench_read(src, out=None, stream=None):
+    """Streaming read of src (a contiguous CUDA tensor, 16-byte multiple); returns the per-thread sums tensor."""
+    torch = _torch()
+    nbytes = src.numel() * src.element_size()
+    blocks = C.c_uint32()
+    _check(lib().lodge_microbench_read_blocks(C.c_size_t(nbytes), C.byref(blocks)))
+    if out is None or out.numel() < blocks.value * 256:
+        out = torch.empty((blocks.value * 256,), dtype=torch.float32, device=src.device)
+    _check(lib().lodge_microbench_read(_ptr(src), C.c_size_t(nbytes), _ptr(out), blocks.value, _stream_ptr(stream)))
+    return out
+
+
+def lodge_microbench_fma(out, iters: int, a: float = 1.0, b: float = 1.0, stream=None):
+    """Chains of dependent FMAs: out is a float32 CUDA tensor of blocks x 256 elements; returns the lane-ops."""
+    n = int(out.numel())
+    if n == 0 or n % 256:
+        raise ValueError("out must hold a positive multiple of 256 floats")
+    _check(lib().lodge_microbench_fma(_ptr(out), n // 256, int(iters), float(a), float(b), _stream_ptr(stream)))
+    return 8 * int(iters) * n
