@@ -790,6 +790,8 @@ def main():
         "config": desc,
         "gaussians_composited_per_s": round(mean["pairs_evaluated"] * v_fps, 1),
         "gaussians_blended_per_s": round(mean["pairs_blended"] * v_fps, 1),
+        "active_gaussians_per_s": round(mean["n_selected"] * v_fps, 1),
+        "instances_per_s": round(mean["n_instances"] * v_fps, 1),
         "frames_in_flight": F,
         "timed_frames": frames,
         "repeats_s": v_runs,
