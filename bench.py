@@ -300,6 +300,28 @@ def diff_section(n=1_000_000, views=8, width=1280, height=720, steps=3):
                                 "frac": round(proj_bytes / (proj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}}
 
 
+def diff_cpu_baseline(n=1_000_000, views=8, width=1280, height=720):
+    """The oracle's differentiation as it stands, timed on one host thread: its FP64 forward of view 0 of the
+    differentiation workload, the L1 gradient of that image, and its FP64 adjoint (2-D gradients, then the
+    projection's chain rule to every parameter)."""
+    import numpy as np
+
+    import oracle
+    import synth
+    sc = synth.diff_scene(n=n, n_views=views, width=width, height=height)
+    tgt = synth.target_images(views, width, height)[0]
+    O = oracle.Oracle("f64")
+    cam = sc.cameras[0]
+    t0 = time.perf_counter()
+    fwd = O.render(sc, cam, oracle.ALL)
+    dL = np.sign(fwd["image"] - tgt) / tgt.size
+    g2 = O.grad2d(fwd["proj"], fwd["binned"], cam, dL)
+    O.project_grad(sc, fwd["ids"], fwd["w"], cam, g2, 0.3, True, -1)
+    dt = time.perf_counter() - t0
+    return {"value": round(1.0 / dt, 4), "unit": "views/s", "cores": 1, "kind": "oracle",
+            "sample": f"view 0 of the {views}, FP64 forward + L1 gradient + FP64 adjoint, {dt:.1f} s"}
+
+
 def visibility_section(dev, sc, chunk=27, n_pos=4, n_orient=3, width=1920, height=1080, threshold=0.02):
     """Per-chunk visibility filtering of one chunk of the benchmark scene: its stored set rendered from
     n_pos x n_orient views (positions about the chunk centre, random orientations), the importance walk
@@ -750,6 +772,9 @@ def main():
         diff = diff_section()
         for r in diff["roofline"].values():
             r["frac_of_measured"] = round(r["achieved"] / measured[r["bound"]], 4)
+        if not args.no_cpu_baseline:
+            log("[bench] timing the oracle's differentiation on the host")
+            diff["cpu_baseline"] = diff_cpu_baseline()
         log(f"[bench] differentiation {diff}")
 
     visibility = thresholds = lodbuild = None
