@@ -195,7 +195,8 @@ def serving_section(dev, n=256, rate=120.0, sweep=(1000.0, 3000.0, 10000.0)):
     """The served form on the resident scene: Poisson arrivals, mixed resolutions,
     per-slot graph replay; latency = completion - arrival (no device-to-host copy).
     The configured load (n requests at `rate`), then the same request mix at higher
-    rates on the same slots, to show where continuous batching saturates."""
+    rates on the same slots, to show where continuous batching saturates, and the
+    configured load with each image copied to pinned host memory (latency with it)."""
     import synth
     from paper_2505_23158_amd import lodge as L
     from paper_2505_23158_amd.serve import GpuBackend, Request, Scheduler
@@ -221,6 +222,13 @@ def serving_section(dev, n=256, rate=120.0, sweep=(1000.0, 3000.0, 10000.0)):
     base = run(rate)
     out = {"requests": n, "resolutions": ["640x360", "1280x720", "1920x1080"], "graph_replay": True, **base}
     out["saturation_sweep"] = [run(r) for r in sweep]
+    # the configured load again, each image also copied to a pinned host buffer: latency with the copy
+    be = GpuBackend(dev, L.SELECT_CHUNKED, SERVE_CAPS, use_graphs=True, copy_to_host=True)
+    pre = {res: be.prewarm(res, 4) for res in sorted(SERVE_CAPS)}
+    torch.cuda.synchronize()
+    d2h = run(rate)
+    out["with_device_to_host_copy"] = {k: d2h[k] for k in ("p50_ms", "p99_ms", "mean_ms", "frames_per_s",
+                                                           "peak_in_flight")}
     return out
 
 

@@ -213,12 +213,13 @@ class SimulatedBackend:
 
 
 class GpuBackend:
-    """Slots on the GPU: per-slot workspace, pinned camera, stream and graph."""
+    """Slots on the GPU: per-slot workspace, pinned camera, stream and graph.  copy_to_host: each frame's
+    image also goes to a pinned host buffer of its slot, and a request completes when that copy has."""
 
     MAX_GROWTHS = 4
 
     def __init__(self, scene, mode: int, caps: Dict[Tuple[int, int], Tuple[int, int]], use_graphs: bool = True,
-                 keep_images: bool = False):
+                 keep_images: bool = False, copy_to_host: bool = False):
         import torch
         from . import lodge as L
         self.torch, self.L = torch, L
@@ -226,6 +227,7 @@ class GpuBackend:
         self.caps = dict(caps)
         self.use_graphs = use_graphs
         self.keep_images = keep_images
+        self.copy_to_host = copy_to_host
         self.slots = []
         self.images: Dict[int, object] = {}
         self.outputs: Dict[int, dict] = {}
@@ -272,9 +274,10 @@ class GpuBackend:
             with torch.cuda.graph(graph, stream=stream):
                 R.frame(None, self.mode)
         done = torch.cuda.Event()
+        host = torch.empty((3, res[1], res[0]), dtype=torch.float32, pin_memory=True) if self.copy_to_host else None
         sid = len(self.slots)
         self.slots.append({"res": res, "R": R, "caps": caps, "stream": stream, "graph": graph, "done": done,
-                           "req": None, "growths": 0, "grown_bytes": 0})
+                           "req": None, "growths": 0, "grown_bytes": 0, "host": host})
         return sid
 
     def _render(self, s, cam):
@@ -284,6 +287,8 @@ class GpuBackend:
                 s["graph"].replay()
             else:
                 s["R"].frame(cam, self.mode, stream=s["stream"])
+            if s["host"] is not None:
+                s["host"].copy_(s["R"].image, non_blocking=True)
             s["done"].record()
 
     def launch(self, sid, req):

@@ -52,6 +52,22 @@ def test_graph_replays_follow_the_pinned_camera(env):
         assert torch.equal(be.images[k], ref), k
 
 
+def test_replies_copied_to_pinned_host_memory(env):
+    """copy_to_host: a request completes once its image is in its slot's pinned host buffer, which then holds
+    the image of that request (graph replays, the copy ordered after them on the slot's stream)."""
+    import torch
+    from paper_2505_23158_amd.serve import GpuBackend, Request
+    L, sc, dev = env
+    be = GpuBackend(dev, L.SELECT_CHUNKED, CAPS, use_graphs=True, copy_to_host=True)
+    sid = be.new_slot((640, 360))
+    assert be.slots[sid]["host"].is_pinned()
+    for k, cam in enumerate(synth.config3_path(3, 640, 360)):
+        be.launch(sid, Request(k, 0.0, cam))
+        while be.poll(sid) is None:
+            pass
+        assert torch.equal(be.slots[sid]["host"], alone(L, dev, cam).cpu()), k
+
+
 def test_mixed_concurrent_requests_equal_alone(env):
     import torch
     from paper_2505_23158_amd.serve import Request, serve
