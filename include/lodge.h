@@ -470,10 +470,11 @@ lodge_status lodge_keep_indices(int64_t n, const float* score, float threshold, 
 lodge_status lodge_gather_planes(int32_t planes, int64_t n_in, int64_t n_out, const float* in, const uint32_t* idx,
                                  const uint32_t* count, float* out, void* stream);
 
-/* ------------------------------------------------------ measurement helpers */
+/* ------------------------------------- measurement and verification helpers */
 
 /* Not part of the method: the device's achievable rates, against which the
- * kernels' roofline fractions are reported beside the data-sheet peaks. */
+ * kernels' roofline fractions are reported beside the data-sheet peaks, and
+ * the FP32 division and square root of the library's build. */
 
 /* ASYNC.  Copies `bytes` (a multiple of 16) from src to dst (device, 16-byte
  * aligned, not overlapping) with a coalesced streaming kernel: the HBM rate
@@ -492,6 +493,13 @@ lodge_status lodge_microbench_read_blocks(size_t bytes, uint32_t* blocks);
  * a kernel that only reads is bytes over its time.  LODGE_ERR_INVALID_ARG for
  * NULL or misaligned buffers or blocks == 0. */
 lodge_status lodge_microbench_read(const void* src, size_t bytes, float* out, uint32_t blocks, void* stream);
+
+/* ASYNC.  q[i] = a[i] / b[i] and r[i] = sqrt(a[i]) for i < n (device
+ * buffers), compiled with the library's flags.  The selection, tile
+ * rectangles and depth keys match an IEEE FP32 evaluation bit for bit only
+ * if these are correctly rounded; this call lets a test compare them with
+ * the host's.  LODGE_ERR_INVALID_ARG for a NULL buffer. */
+lodge_status lodge_fp32_div_sqrt(const float* a, const float* b, float* q, float* r, size_t n, void* stream);
 
 /* ASYNC.  blocks x 256 threads, each running 8 independent chains of `iters`
  * dependent FP32 FMAs x <- fma(x, a, b) from x = 0..7, and writing the sum of

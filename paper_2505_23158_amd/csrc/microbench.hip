@@ -1,6 +1,7 @@
-// Measurement helpers, not part of the method: the two rates the kernels'
-// roofline fractions are also reported against, measured on the device at
-// hand instead of taken from its data sheet.
+// Measurement and verification helpers, not part of the method: the rates
+// the kernels' roofline fractions are also reported against, measured on the
+// device at hand instead of taken from its data sheet, and the FP32 division
+// and square root the bit-exact stages rely on.
 //
 // k_stream_copy  a coalesced device copy, 16-byte non-temporal accesses, four
 //                loads per thread in flight before the stores: the HBM rate
@@ -12,6 +13,9 @@
 //                of them and enough waves to cover the FMA latency: the rate
 //                at which the SIMDs retire non-packed VALU lane-ops (one FMA
 //                counted as one).
+// k_div_sqrt     q = a / b and r = sqrt(a) per element, built with the
+//                library's flags: the selection, rectangles and depths match
+//                the oracle bit for bit only if both are correctly rounded.
 #include "lodge_internal.hpp"
 
 namespace lodge {
@@ -76,6 +80,15 @@ __global__ __launch_bounds__(kFmaThreads) void k_fma_chains(float* __restrict__ 
     out[t] = s;
 }
 
+__global__ __launch_bounds__(256) void k_div_sqrt(const float* __restrict__ a, const float* __restrict__ b,
+                                                  float* __restrict__ q, float* __restrict__ r, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        q[i] = a[i] / b[i];
+        r[i] = sqrtf(a[i]);
+    }
+}
+
 }  // namespace
 
 }  // namespace lodge
@@ -125,6 +138,17 @@ lodge_status lodge_microbench_read(const void* src, size_t bytes, float* out, ui
                                                                               bytes / 16);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "microbench_read");
+    return LODGE_OK;
+}
+
+lodge_status lodge_fp32_div_sqrt(const float* a, const float* b, float* q, float* r, size_t n, void* stream)
+{
+    if (n == 0) return LODGE_OK;
+    if (!a || !b || !q || !r) return fail(LODGE_ERR_INVALID_ARG, "fp32_div_sqrt: NULL buffer");
+    const uint32_t blocks = (uint32_t)std::min<size_t>((n + 255) / 256, 65536);
+    k_div_sqrt<<<blocks, 256, 0, static_cast<hipStream_t>(stream)>>>(a, b, q, r, n);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "fp32_div_sqrt");
     return LODGE_OK;
 }
 

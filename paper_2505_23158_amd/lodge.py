@@ -140,6 +140,7 @@ def lib():
             "lodge_microbench_read_blocks": (st, [C.c_size_t, C.POINTER(C.c_uint32)]),
             "lodge_microbench_read": (st, [vp, C.c_size_t, vp, C.c_uint32, vp]),
             "lodge_microbench_fma": (st, [vp, C.c_uint32, C.c_uint32, C.c_float, C.c_float, vp]),
+            "lodge_fp32_div_sqrt": (st, [vp, vp, vp, vp, C.c_size_t, vp]),
             "lodge_activate": (st, [C.c_int64, vp, vp, vp, vp, vp, vp, vp]),
             "lodge_activate_backward": (st, [C.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         }
@@ -163,7 +164,8 @@ EXPORTED = ["lodge_status_string", "lodge_last_error", "lodge_version", "lodge_s
             "lodge_render_static", "lodge_select_chunk", "lodge_importance", "lodge_chunk_sets_prune",
             "lodge_l1_grad", "lodge_adam", "lodge_keep_scratch_size", "lodge_keep_indices", "lodge_gather_planes",
             "lodge_pack_size", "lodge_scene_pack", "lodge_dssim_scratch_size", "lodge_dssim_grad",
-            "lodge_microbench_copy", "lodge_microbench_read_blocks", "lodge_microbench_read", "lodge_microbench_fma"]
+            "lodge_microbench_copy", "lodge_microbench_read_blocks", "lodge_microbench_read", "lodge_microbench_fma",
+            "lodge_fp32_div_sqrt"]
 STATIC_SCRATCH_BYTES = 256 << 20
 
 
@@ -596,3 +598,11 @@ def lodge_microbench_fma(out, iters: int, a: float = 1.0, b: float = 1.0, stream
         raise ValueError("out must hold a positive multiple of 256 floats")
     _check(lib().lodge_microbench_fma(_ptr(out), n // 256, int(iters), float(a), float(b), _stream_ptr(stream)))
     return 8 * int(iters) * n
+
+
+def lodge_fp32_div_sqrt(a, b, q, r, stream=None):
+    """q = a / b and r = sqrt(a) elementwise on the device (float32 CUDA tensors of one size)."""
+    n = int(a.numel())
+    if any(t.numel() != n or t.dtype != _torch().float32 for t in (b, q, r)):
+        raise ValueError("a, b, q, r: float32 tensors of one size")
+    _check(lib().lodge_fp32_div_sqrt(_ptr(a), _ptr(b), _ptr(q), _ptr(r), C.c_size_t(n), _stream_ptr(stream)))

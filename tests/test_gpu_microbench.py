@@ -45,3 +45,34 @@ def test_stream_read_sums_what_it_reads(L):
     sums = L.lodge_microbench_read(src)
     torch.cuda.synchronize()
     assert float(sums.double().sum()) == float(src.numel())
+
+
+def test_fp32_division_and_sqrt_are_correctly_rounded(L):
+    """The bit-exact stages (selection bounds, rectangles, depth keys) assume the device's FP32 division and
+    square root round correctly, as the host's IEEE ones do: 1.0e8 random operands (random signs and
+    mantissas, exponents in [-60, 60], so no result is subnormal or overflows), every quotient and root
+    equal bit for bit to numpy's."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(2505)
+    n = 1 << 24
+    mism_q = mism_r = 0
+    for chunk in range(6):
+        def draw():
+            exp = rng.integers(127 - 60, 127 + 61, size=n, dtype=np.uint32)
+            man = rng.integers(0, 1 << 23, size=n, dtype=np.uint32)
+            sgn = rng.integers(0, 2, size=n, dtype=np.uint32)
+            return ((sgn << 31) | (exp << 23) | man).view(np.float32)
+        a, b = draw(), draw()
+        da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+        dq, dr = torch.empty_like(da), torch.empty_like(da)
+        L.lodge_fp32_div_sqrt(da, db, dq, dr)
+        q_ref = a / b
+        with np.errstate(invalid="ignore"):
+            r_ref = np.sqrt(a)
+        q, r = dq.cpu().numpy(), dr.cpu().numpy()
+        mism_q += int(np.count_nonzero(q.view(np.uint32) != q_ref.view(np.uint32)))
+        neg = a < 0   # sqrt of a negative operand: NaN on both sides (payloads may differ)
+        ok_r = (r.view(np.uint32) == r_ref.view(np.uint32)) | (neg & np.isnan(r) & np.isnan(r_ref))
+        mism_r += int(np.count_nonzero(~ok_r))
+    assert mism_q == 0 and mism_r == 0, (mism_q, mism_r)
