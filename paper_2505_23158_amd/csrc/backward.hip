@@ -110,6 +110,10 @@ __global__ __launch_bounds__(256) void k_composite_bwd(const FrameParams* __rest
                                                        const float* __restrict__ dL, float* __restrict__ g2d,
                                                        uint32_t cap)
 {
+    // the adjoint matches the FP64 oracle within a tolerance, not bit for bit, so products and sums may
+    // fuse; the decisions that must equal the compositor's (power, alpha, which pixels blend) come from
+    // splat_power's explicit FMAs and plain comparisons, which contraction leaves as they are
+#pragma clang fp contract(fast)
     __shared__ float4 s_rec[4][3][64];     // per wave, by batch slot: geo, col, (g, b, -, -)
     __shared__ uint32_t s_a[4][64];        // active index of each slot
     __shared__ uint8_t s_idx[4][64];       // slots that reach the quadrant, in list order
@@ -271,6 +275,10 @@ __global__ __launch_bounds__(256) void k_project_bwd(LevelsArg lv, GradsArg ga, 
                                                      const FrameParams* __restrict__ fp,
                                                      const uint2* __restrict__ rect, const float* __restrict__ g2d)
 {
+    // products and sums may fuse here (the adjoint matches the FP64 oracle within a tolerance): the
+    // recomputed forward quantities then differ from the projection's by rounding, which only moves a
+    // Gaussian exactly on the Jacobian clamp to the other one-sided gradient
+#pragma clang fp contract(fast)
     const uint32_t n_act = min(*count, cap);
     const lodge_camera& cam = fp->cam;
     const float s2d = fp->s2d;
