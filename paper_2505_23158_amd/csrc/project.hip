@@ -9,12 +9,14 @@
 // are read; Gaussians behind the near plane stop there, the others read
 // scale, rotation and opacity.  Each active writes its depth, tile rectangle
 // and tile count (0 when culled), and each chunk writes its tile total (the
-// first level of the instance-offset scan).  A visible Gaussian writes its
+// first level of the instance-offset scan).  A visible Gaussian joins the
+// wave's LDS queue with its view direction and the geometry of its
 // compositing record (centre, conic, opacity, the power below which alpha
-// cannot reach 1/255, the half-extents of the ellipse where it can) and
-// joins the wave's LDS queue with its view direction.  Colour is evaluated
-// from the queue 64 at a time, so the 48 SH loads and the basis run with
-// every lane busy rather than on the few visible lanes of each chunk.
+// cannot reach 1/255, the half-extents of the ellipse where it can).  Colour
+// is evaluated from the queue 64 at a time, so the 48 SH loads and the basis
+// run with every lane busy rather than on the few visible lanes of each
+// chunk, and each record is then written whole, once (not its geometry
+// first and its colour into the same lines later).
 // The front/visible counters are reduced per block and added once.
 //
 // Built with -ffp-contract=off: the rectangle and depth (which decide tile
@@ -85,6 +87,7 @@ __device__ __forceinline__ int level_index(const LevelsArg& lv, uint32_t g)
 }
 
 constexpr int kQueue = 128;   // per-wave colour queue: < 64 left over + one chunk of 64
+constexpr int kQRows = 12;    // per queued Gaussian: view direction (3), then its record's geometry (9)
 
 // A float4 pointer every active lane holds the same value of, in scalar registers.
 __device__ __forceinline__ const float4* uniform_ptr4(const float4* p)
@@ -160,9 +163,11 @@ __device__ __forceinline__ void colour_batch(const LevelsArg& lv, const LevelDev
                 acc = acc + 0.5f;
                 rgb[ch] = acc > 0.0f ? acc : 0.0f;
             }
-            float* r = reinterpret_cast<float*>(proj + 3 * (size_t)a);
-            r[7] = rgb[0];
-            *reinterpret_cast<float2*>(r + 8) = make_float2(rgb[1], rgb[2]);
+            // the whole record at once: the geometry the projection queued, then the colour
+            const uint32_t k = lane;
+            proj[3 * (size_t)a] = make_float4(qd[3][k], qd[4][k], qd[5][k], qd[6][k]);
+            proj[3 * (size_t)a + 1] = make_float4(qd[7][k], qd[8][k], qd[9][k], rgb[0]);
+            proj[3 * (size_t)a + 2] = make_float4(rgb[1], rgb[2], qd[10][k], qd[11][k]);
         }
     }
 }
@@ -178,7 +183,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
 {
     __shared__ uint32_t s_cnt[2][4];
     __shared__ uint32_t s_qa[4][kQueue], s_qg[4][kQueue];
-    __shared__ float s_qd[4][3][kQueue];
+    __shared__ float s_qd[4][kQRows][kQueue];
     // the level table in LDS: a level picked at run time is then an LDS read,
     // not a memory round trip on every chunk and colour batch
     __shared__ LevelDev s_lv[LODGE_MAX_LEVELS];
@@ -344,11 +349,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
           }
         }
         if (a < n_act) {
-            if (visible) {
-                proj[3 * (size_t)a] = r0;
-                proj[3 * (size_t)a + 1] = r1;
-                proj[3 * (size_t)a + 2] = r2;
-            }
             depth[a] = dep;
             // culled: the canonical empty rect (the clamped bounds may be -1 and must not be packed)
             rect[a] = visible ? make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16))
@@ -375,6 +375,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             qd[0][p] = d0n;
             qd[1][p] = d1n;
             qd[2][p] = d2n;
+            qd[3][p] = r0.x;
+            qd[4][p] = r0.y;
+            qd[5][p] = r0.z;
+            qd[6][p] = r0.w;
+            qd[7][p] = r1.x;
+            qd[8][p] = r1.y;
+            qd[9][p] = r1.z;
+            qd[10][p] = r2.z;
+            qd[11][p] = r2.w;
         }
         qn += (uint32_t)__popcll(m);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -385,13 +394,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             // move the left-over entries to the front of the queue
             const uint32_t rem = qn - 64;
             uint32_t ta = 0, tg = 0;
-            float t0 = 0.0f, t1 = 0.0f, t2 = 0.0f;
+            float tq[kQRows];
+#pragma unroll
+            for (int q = 0; q < kQRows; q++) tq[q] = 0.0f;
             if (lane < rem) {
                 ta = qa[64 + lane];
                 tg = qg[64 + lane];
-                t0 = qd[0][64 + lane];
-                t1 = qd[1][64 + lane];
-                t2 = qd[2][64 + lane];
+#pragma unroll
+                for (int q = 0; q < kQRows; q++) tq[q] = qd[q][64 + lane];
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -399,9 +409,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             if (lane < rem) {
                 qa[lane] = ta;
                 qg[lane] = tg;
-                qd[0][lane] = t0;
-                qd[1][lane] = t1;
-                qd[2][lane] = t2;
+#pragma unroll
+                for (int q = 0; q < kQRows; q++) qd[q][lane] = tq[q];
             }
             qn = rem;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
