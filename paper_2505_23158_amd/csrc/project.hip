@@ -96,9 +96,10 @@ __device__ __forceinline__ const float4* uniform_ptr4(const float4* p)
 }
 
 // Colour of up to 64 queued Gaussians, one per lane (lanes >= cnt idle):
-// degree-3 real SH at the view direction, + 0.5, clamped at 0; written into
-// the record's colour fields.  kPacked: the coefficients come from the
-// level's packed copy (one contiguous run per Gaussian) instead of its planes.
+// degree-3 real SH at the view direction, + 0.5, clamped at 0; each lane
+// then writes its Gaussian's whole record, the queued geometry with the
+// colour.  kPacked: the coefficients come from the level's packed copy (one
+// contiguous run per Gaussian) instead of its planes.
 template <bool kPacked>
 __device__ __forceinline__ void colour_batch(const LevelsArg& lv, const LevelDev* s_lv, const uint32_t* qa,
                                              const uint32_t* qg,
