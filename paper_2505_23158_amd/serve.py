@@ -274,7 +274,13 @@ class GpuBackend:
             with torch.cuda.graph(graph, stream=stream):
                 R.frame(None, self.mode)
         done = torch.cuda.Event()
-        host = torch.empty((3, res[1], res[0]), dtype=torch.float32, pin_memory=True) if self.copy_to_host else None
+        host = None
+        if self.copy_to_host:
+            host = torch.empty((3, res[1], res[0]), dtype=torch.float32, pin_memory=True)
+            # the first copy into a fresh pinned buffer pays a one-time cost: take it here, not in a request
+            with torch.cuda.stream(stream):
+                host.copy_(R.image, non_blocking=True)
+            stream.synchronize()
         sid = len(self.slots)
         self.slots.append({"res": res, "R": R, "caps": caps, "stream": stream, "graph": graph, "done": done,
                            "req": None, "growths": 0, "grown_bytes": 0, "host": host})
