@@ -38,6 +38,17 @@ def test_plain_config(L, oracle32):
     full_parity(oracle32, sc, dev(L, sc), sc.cameras[0], oracle.ALL, "plain-10k")
 
 
+@pytest.mark.parametrize("s2d,compensate", [(0.0, True), (0.0, False), (1.0, True)])
+def test_screen_filter_variance(L, oracle32, s2d, compensate):
+    """The renderer's 2-D filter is an option of the boundary: off (the plain
+    EWA projection, where thin splats come close to a singular covariance and
+    some are culled by det <= 0), and wider than the default, with and without
+    the opacity compensation."""
+    sc = synth.plain_scene(n=8000, seed=43, width=192, height=144)
+    full_parity(oracle32, sc, dev(L, sc), sc.cameras[0], oracle.ALL, f"plain-s2d{s2d}-comp{int(compensate)}",
+                s2d=s2d, compensate=compensate)
+
+
 def test_plain_ragged_edges(L, oracle32):
     sc = synth.plain_scene(n=6000, seed=41, width=200, height=120)
     full_parity(oracle32, sc, dev(L, sc), sc.cameras[0], oracle.ALL, "plain-ragged-200x120")
