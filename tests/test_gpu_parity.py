@@ -49,6 +49,17 @@ def test_screen_filter_variance(L, oracle32, s2d, compensate):
                 s2d=s2d, compensate=compensate)
 
 
+def test_background_behind_partly_transparent_pixels(L, oracle32):
+    """A non-zero background shows through each pixel in proportion to the
+    transmittance left after its last blended splat (C + T_final bg)."""
+    import dataclasses
+    sc = synth.plain_scene(n=3000, seed=44, width=160, height=96)
+    cam = dataclasses.replace(sc.cameras[0], bg=(0.2, 0.4, 0.6))
+    g, r = full_parity(oracle32, sc, dev(L, sc), cam, oracle.ALL, "plain-bg")
+    T = g["final_T"]
+    assert (T > 0.5).any() and (T < 0.5).any()   # both mostly-background and mostly-covered pixels
+
+
 def test_plain_ragged_edges(L, oracle32):
     sc = synth.plain_scene(n=6000, seed=41, width=200, height=120)
     full_parity(oracle32, sc, dev(L, sc), sc.cameras[0], oracle.ALL, "plain-ragged-200x120")
