@@ -60,6 +60,31 @@ def test_background_behind_partly_transparent_pixels(L, oracle32):
     assert (T > 0.5).any() and (T < 0.5).any()   # both mostly-background and mostly-covered pixels
 
 
+@pytest.mark.parametrize("deg", [0, 1, 2])
+def test_sh_degrees_below_three(L, oracle32, deg):
+    """Colour from fewer SH bands: only the level's (d + 1)^2 coefficients
+    enter the sum."""
+    lv = synth.gaussians(4000, (45, deg), synth._cube(5.0), -3.0, 0.5, sh_degree=deg)
+    sc = Scene(levels=[lv], d=[])
+    cam = synth.look_at((3, -2, -14), (0, 0, 0), (0, -1, 0), 176, 112)
+    full_parity(oracle32, sc, dev(L, sc), cam, oracle.ALL, f"plain-sh{deg}")
+
+
+def test_levels_of_different_sh_degrees(L, oracle32):
+    """Three LOD levels with SH degrees 3, 1 and 0 in one frame: the colour
+    pass takes each queued Gaussian's coefficients from its own level."""
+    lvs = [synth.gaussians(6000, (46, 0), synth._cube(12.0), -3.0, 0.5, sh_degree=3),
+           synth.gaussians(3000, (46, 1), synth._cube(12.0), -3.0 + np.log(2.0), 0.5, sh_degree=1),
+           synth.gaussians(1500, (46, 2), synth._cube(12.0), -3.0 + 2 * np.log(2.0), 0.5, sh_degree=0)]
+    sc = Scene(levels=lvs, d=[12.0, 18.0])
+    cam = synth.look_at((0, 0, -14), (0, 0, 0), (0, -1, 0), 208, 128)
+    g, r = full_parity(oracle32, sc, dev(L, sc), cam, oracle.LOD_CAMERA, "lod-mixed-sh")
+    # every level contributes to the frame
+    bases = np.cumsum([0] + [lv.n for lv in lvs])
+    for l in range(3):
+        assert ((r["ids"] >= bases[l]) & (r["ids"] < bases[l + 1])).any(), f"level {l} selects nothing"
+
+
 def test_plain_ragged_edges(L, oracle32):
     sc = synth.plain_scene(n=6000, seed=41, width=200, height=120)
     full_parity(oracle32, sc, dev(L, sc), sc.cameras[0], oracle.ALL, "plain-ragged-200x120")
