@@ -85,6 +85,21 @@ def test_levels_of_different_sh_degrees(L, oracle32):
         assert ((r["ids"] >= bases[l]) & (r["ids"] < bases[l + 1])).any(), f"level {l} selects nothing"
 
 
+def test_gaussians_at_the_near_plane(L, oracle32):
+    """Gaussians from 0.1 to 0.7 m in front of the camera (near plane 0.2 m):
+    those behind it are culled, those just past it project to large splats,
+    and many sit outside the Jacobian clamp (|x/z| above lim_x)."""
+    def near_means(rng, m):
+        return np.stack([rng.uniform(-0.35, 0.35, m), rng.uniform(-0.25, 0.25, m), rng.uniform(0.1, 0.7, m)])
+    sc = Scene(levels=[synth.gaussians(1500, (47, 0), near_means, -5.0, 0.5),
+                       synth.gaussians(40, (47, 1), near_means, -3.0, 0.3)], d=[1000.0])
+    cam = synth.look_at((0, 0, 0), (0, 0, 1), (0, -1, 0), 256, 192)
+    g, r = full_parity(oracle32, sc, dev(L, sc), cam, oracle.ALL, "near-plane", max_instances=1_000_000)
+    z = np.concatenate([lv.mean[2] for lv in sc.levels])
+    x = np.concatenate([lv.mean[0] for lv in sc.levels])
+    assert (z <= cam.znear).sum() > 100 and (np.abs(x / z) > cam.lim_x).sum() > 100
+
+
 def test_plain_ragged_edges(L, oracle32):
     sc = synth.plain_scene(n=6000, seed=41, width=200, height=120)
     full_parity(oracle32, sc, dev(L, sc), sc.cameras[0], oracle.ALL, "plain-ragged-200x120")
