@@ -100,6 +100,19 @@ def test_gaussians_at_the_near_plane(L, oracle32):
     assert (z <= cam.znear).sum() > 100 and (np.abs(x / z) > cam.lim_x).sum() > 100
 
 
+def test_opaque_stack_stops_most_pixels(L, oracle32):
+    """6000 wide Gaussians of opacity 0.97: most pixels reach T < 1e-4 on the
+    next splat and stop there, so the stop decision, the last contributor and
+    the quadrant waves' early exit carry the image."""
+    lv = synth.gaussians(6000, (48, 0), synth._cube(4.0), -1.5, 0.3)
+    lv.opacity[:] = np.float32(0.97)
+    sc = Scene(levels=[lv], d=[])
+    cam = synth.look_at((0, 0, -12), (0, 0, 0), (0, -1, 0), 160, 128)
+    g, r = full_parity(oracle32, sc, dev(L, sc), cam, oracle.ALL, "opaque-stack")
+    assert (r["final_T"] < 1e-3).mean() > 0.5
+    assert g["final_T"].min() >= np.float32(1e-4)   # a pixel stops before T falls below the threshold
+
+
 def test_plain_ragged_edges(L, oracle32):
     sc = synth.plain_scene(n=6000, seed=41, width=200, height=120)
     full_parity(oracle32, sc, dev(L, sc), sc.cameras[0], oracle.ALL, "plain-ragged-200x120")
