@@ -93,6 +93,17 @@ def test_larger_scene_vs_fp64_adjoint(L, oracle32, oracle64):
     check_against_oracle(L, oracle32, oracle64, sc, sc.cameras[0], oracle.ALL, 6, label="plain-4000")
 
 
+def test_levels_of_different_sh_degrees_vs_fp64_adjoint(L, oracle32, oracle64):
+    """LOD levels with SH degrees 3, 1 and 0: each level's SH gradient has
+    only its own (d + 1)^2 bands."""
+    lvs = [synth.gaussians(2000, (63, 0), synth._cube(8.0), -2.5, 0.5, sh_degree=3),
+           synth.gaussians(1000, (63, 1), synth._cube(8.0), -2.5 + np.log(2.0), 0.5, sh_degree=1),
+           synth.gaussians(500, (63, 2), synth._cube(8.0), -2.5 + 2 * np.log(2.0), 0.5, sh_degree=0)]
+    sc = Scene(levels=lvs, d=[9.0, 13.0])
+    cam = synth.look_at((0, 0, -10), (0, 0, 0), (0, -1, 0), 96, 72)
+    check_against_oracle(L, oracle32, oracle64, sc, cam, oracle.LOD_CAMERA, 8, label="lod-mixed-sh")
+
+
 def test_chunked_two_levels_level_mask(L, oracle32, oracle64):
     sc = synth.lod_city_scene(counts=(6000, 1500), half_xy=12.0, d=(4.0,), grid=2, spacing=6.0, chunk_z=1.0,
                               band=2.0, seed=62)
