@@ -45,34 +45,35 @@ def as64(sc):
     return Scene(levels=out, d=sc.d, chunks=sc.chunks)
 
 
-def gpu_grads(L, sc, cam, mode, dL, grad_level=-1):
+def gpu_grads(L, sc, cam, mode, dL, grad_level=-1, s2d=0.3, compensate=True):
     import torch
     dev = L.Scene.from_synth(sc)
     R = L.Renderer(dev, cam.width, cam.height)
-    R.frame(cam, mode)
+    R.frame(cam, mode, s2d=s2d, compensate=compensate)
     grads = [{k: torch.zeros_like(t) for k, t in lv.items() if k in PARAMS} for lv in dev.levels]
     L.lodge_render_backward(dev, R.sel, cam, R.ws, R.final_T, R.n_contrib,
-                            torch.from_numpy(dL.astype(np.float32)).cuda(), grads, grad_level=grad_level)
+                            torch.from_numpy(dL.astype(np.float32)).cuda(), grads, grad_level=grad_level,
+                            s2d=s2d, compensate=compensate)
     torch.cuda.synchronize()
     return [{k: v.cpu().numpy() for k, v in g.items()} for g in grads], R
 
 
-def masked_dL(O32, sc, cam, mode, seed):
+def masked_dL(O32, sc, cam, mode, seed, s2d=0.3, compensate=True):
     """Seeded dL/dimage, zero at pixels where the FP32 oracle records a
     near-threshold decision (there two correct renderers may take different
     traces, and so have different gradients)."""
-    r = O32.render(sc, cam, mode)
+    r = O32.render(sc, cam, mode, s2d=s2d, compensate=compensate)
     rng = np.random.default_rng(seed)
     dL = rng.normal(size=(3, cam.height, cam.width))
     dL[:, r["near"] > 0] = 0.0
     return dL
 
 
-def check_against_oracle(L, O32, O64, sc, cam, mode, seed, grad_level=-1, label=""):
+def check_against_oracle(L, O32, O64, sc, cam, mode, seed, grad_level=-1, label="", s2d=0.3, compensate=True):
     log(f"[grad] {label}: {cam.width}x{cam.height}, {sc.n_total} Gaussians, grad_level={grad_level}")
-    dL = masked_dL(O32, sc, cam, mode, seed)
-    g_gpu, _ = gpu_grads(L, sc, cam, mode, dL, grad_level)
-    _, _, g_ref = O64.render_grad(as64(sc), cam, mode, dL, grad_level=grad_level)
+    dL = masked_dL(O32, sc, cam, mode, seed, s2d, compensate)
+    g_gpu, _ = gpu_grads(L, sc, cam, mode, dL, grad_level, s2d, compensate)
+    _, _, g_ref = O64.render_grad(as64(sc), cam, mode, dL, s2d=s2d, compensate=compensate, grad_level=grad_level)
     for l in range(len(sc.levels)):
         for k in PARAMS:
             nsh = (sc.levels[l].sh_degree + 1) ** 2
@@ -91,6 +92,15 @@ def test_check_scene_vs_fp64_adjoint(L, oracle32, oracle64, var):
 def test_larger_scene_vs_fp64_adjoint(L, oracle32, oracle64):
     sc = synth.plain_scene(n=4000, seed=61, width=96, height=80)
     check_against_oracle(L, oracle32, oracle64, sc, sc.cameras[0], oracle.ALL, 6, label="plain-4000")
+
+
+@pytest.mark.parametrize("s2d,compensate", [(0.3, False), (1.0, True)])
+def test_render_options_vs_fp64_adjoint(L, oracle32, oracle64, s2d, compensate):
+    """The adjoint follows the forward's options: the opacity compensation
+    off (no factor to differentiate), and a wider screen filter."""
+    sc = synth.plain_scene(n=3000, seed=64, width=80, height=64)
+    check_against_oracle(L, oracle32, oracle64, sc, sc.cameras[0], oracle.ALL, 9,
+                         label=f"plain-s2d{s2d}-comp{int(compensate)}", s2d=s2d, compensate=compensate)
 
 
 def test_levels_of_different_sh_degrees_vs_fp64_adjoint(L, oracle32, oracle64):
